@@ -1,0 +1,179 @@
+"""Benchmark: one step = create the flow problem from device-resident inputs
+(validation + device layout), solve the maximum preflow by push-relabel with
+global relabeling, extract the minimal source side (vertex and net bitmaps
+into device memory), release the handle.
+
+Workload: the large single flow -- 1,000,000 vertices, 2,000,000 nets with
+Zipf(2.2) sizes clamped to [2, 1000] (about 7.4 M pins), unit net weights,
+sources / sinks = the 1 % of vertices with the smallest / largest splitmix64
+hash of (seed, vertex).  Synthetic, seeded.
+
+Prints one JSON line (rank 0).  value = pins per second of whole steps.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--vertices", type=int, default=1_000_000)
+    ap.add_argument("--nets", type=int, default=2_000_000)
+    ap.add_argument("--size-hi", type=int, default=1000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="do not time kernels with HIP events during the timed steps")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the max-flow path is single-device, see DESIGN.md for how it would shard",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2201_01556_amd import hyperflow, inputs
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    hyperflow.load_library()
+
+    _log("generating input")
+    hg = inputs.zipf_hypergraph(args.seed, args.vertices, args.nets, size_hi=args.size_hi)
+    P, V, E = hg.num_pins, hg.num_vertices, hg.num_nets
+    arrays = [torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+              for a in (hg.net_offsets, hg.pins, hg.net_weights, hg.sources, hg.sinks)]
+    vs = torch.zeros(V, dtype=torch.uint8, device=dev)
+    ns = torch.zeros(E, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+
+    def step(profile):
+        opts = hyperflow.Options(profile=1 if profile else 0)
+        h = hyperflow.flow_problem_create(V, *arrays, options=opts, stream=stream)
+        try:
+            F = hyperflow.maxflow_solve(h, stream)
+            hyperflow.mincut_source_side(h, V, E, vs, ns, stream)
+            st = hyperflow.flow_problem_stats(h)
+            kt = hyperflow.flow_problem_kernel_times(h) if profile else None
+        finally:
+            hyperflow.flow_problem_destroy(h)
+        return F, st, kt
+
+    profile = not args.no_profile
+    for i in range(args.warmup):
+        _log(f"warmup {i}")
+        step(profile)
+    torch.cuda.synchronize()
+    times, kts, stats = [], [], []
+    F = None
+    for i in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F, st, kt = step(profile)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        times.append(dt)
+        kts.append(kt)
+        stats.append(st)
+        _log(f"step {i}: {dt * 1e3:.2f} ms flow={F} rounds={st['rounds']} "
+             f"gr={st['global_relabels']} syncs={st['host_syncs']}")
+    total = sum(times)
+    ms_per_step = 1e3 * total / args.steps
+    value = P * args.steps / total
+
+    roofline = None
+    kernels = None
+    if profile:
+        agg = {}
+        for kt in kts:
+            for k in kt:
+                a = agg.setdefault(k["kernel"], dict(launches=0, ms=0.0, bytes=0.0))
+                a["launches"] += k["launches"]
+                a["ms"] += k["ms"]
+                a["bytes"] += k["bytes"]
+        kernels = {k: dict(launches=v["launches"], ms=round(v["ms"] / args.steps, 4),
+                           avg_us=round(1e3 * v["ms"] / max(v["launches"], 1), 3),
+                           bytes_per_launch=(v["bytes"] / max(v["launches"], 1)))
+                   for k, v in agg.items() if v["launches"]}
+        # dominant kernel with a device byte count
+        cand = {k: v for k, v in agg.items() if v["launches"] and v["bytes"] > 0}
+        if cand:
+            dom = max(cand, key=lambda k: cand[k]["ms"])
+            d = cand[dom]
+            bpl = d["bytes"] / d["launches"]
+            avg_s = d["ms"] / d["launches"] / 1e3
+            achieved = bpl / avg_s / 1e9
+            roofline = dict(kernel=dom, bound="hbm", achieved=round(achieved, 3),
+                            peak=HBM_PEAK_GBS, unit="GB/s",
+                            frac=round(achieved / HBM_PEAK_GBS, 6), traffic=None,
+                            bytes_per_launch=bpl, avg_launch_us=round(avg_s * 1e6, 3),
+                            share_of_step=round(d["ms"] / args.steps / ms_per_step, 4))
+
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+        _log("cpu baseline (oracle, one thread)")
+        t0 = time.perf_counter()
+        ref = oracle.maxflow(hg)
+        dt = time.perf_counter() - t0
+        cpu = dict(value=P / dt, unit="pins/s", cores=1, kind="oracle",
+                   sample="the full workload once: explicit-Lawler FIFO push-relabel solve "
+                          "plus source-side BFS, single thread", seconds=round(dt, 3))
+        parity = bool(F == ref.flow and
+                      np.array_equal(vs.cpu().numpy(), ref.vertex_side) and
+                      np.array_equal(ns.cpu().numpy(), ref.net_side))
+
+    st = stats[-1]
+    out = {
+        "metric": "pins/s per max-flow solve (create + solve + source-side cut)",
+        "value": value,
+        "unit": "pins/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"zipf single flow: {V} vertices, {E} nets, Zipf(2.2) sizes "
+                        f"clamped to [2,{args.size_hi}], unit weights, 1% hash-selected "
+                        f"sources and sinks",
+            "seed": args.seed, "pins": P, "flow_value": F,
+            "rounds": st["rounds"], "tail_rounds": st["tail_rounds"],
+            "global_relabels": st["global_relabels"], "host_syncs": st["host_syncs"],
+            "profiled_steps": profile,
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity_vs_oracle": parity,
+        "kernels": kernels,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,232 @@
+/*
+ * hyperflow.h -- C ABI of the MI355X (gfx950) hypergraph max-flow / min-cut
+ * library (libhyperflow.so).
+ *
+ * Problem (paper: section "Preliminaries", paragraphs "Flows" and "Flows on
+ * Hypergraphs"; section "Network Construction"): given a hypergraph
+ * H = (V, E, w) with integer net weights w(e) >= 1, a source set S and a
+ * sink set T of vertices, compute
+ *
+ *   F = min over X with S <= X <= V \ T of  sum of w(e) over nets e that
+ *       have a pin in X and a pin outside X,
+ *
+ * which equals the maximum flow of the Lawler expansion (every net e becomes
+ * e_in -> e_out with capacity w(e); every pin u has infinite arcs
+ * u -> e_in and e_out -> u), with S contracted into one source and T into one
+ * sink.  Nets holding both a source and a sink pin are always cut and count
+ * in F; single-pin and empty nets never count.
+ *
+ * Method (paper, section "Parallel Maximum Flow Algorithm"): synchronous
+ * rounds of push-relabel over a compacted frontier of active nodes, with
+ * exact global relabeling by reverse residual BFS from the sinks; the
+ * arcs (u, e_in) carry capacity w(e) during the preflow (paragraph
+ * "Restricting Capacities").  The solve stops at a maximum preflow; the
+ * source side is the forward residual BFS of the uncapped network seeded
+ * with the sources and every non-terminal node that still holds excess
+ * (paragraph "Source-Side Cut").  The reported side is the unique
+ * inclusion-minimal minimum cut, so results do not depend on the schedule.
+ *
+ * All capacities, flows and labels are exact int32; the flow value is int64.
+ *
+ * Memory kinds: mem_kind 0 = host pointers, 1 = device pointers (for example
+ * torch.Tensor.data_ptr() of a CUDA/HIP tensor on the current device).
+ * Streams: hip_stream is a hipStream_t (NULL = the null stream).  Every call
+ * is stream-ordered on that stream and returns after its results are ready.
+ *
+ * Ownership: the caller owns every buffer it passes; create copies the
+ * inputs into library-owned device memory, released by destroy.  Outputs are
+ * written into caller buffers only when the call returns FP_OK.
+ *
+ * Threads: a handle must not be used by two threads at once.  Different
+ * handles are independent.
+ */
+#ifndef HYPERFLOW_H
+#define HYPERFLOW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fp_problem fp_problem; /* opaque, library-owned */
+
+typedef enum {
+  FP_OK = 0,
+  FP_ERR_INVALID = -1,  /* malformed input (see flow_problem_create)          */
+  FP_ERR_OVERFLOW = -2, /* sum of net weights exceeds INT32_MAX, or the
+                           network does not fit 31-bit node ids            */
+  FP_ERR_STATE = -3,    /* call not valid in the handle's current state     */
+  FP_ERR_DEVICE = -4,   /* HIP runtime error or a failed internal check     */
+  FP_ERR_OOM = -5,      /* device allocation failed                         */
+  FP_ERR_ABORTED = -6   /* round budget exhausted before the flow was found */
+} fp_status;
+
+/* Tuning and debugging knobs.  A NULL pointer, or 0 in a field, selects the
+ * default.  None of them changes any result. */
+typedef struct {
+  int32_t relabel_factor_x16; /* global relabel once (factor/16) * N relabels
+                                 accumulated since the last one (N = number of
+                                 network nodes); default 16 = once per N     */
+  int32_t round_budget;       /* stop with FP_ERR_ABORTED after this many
+                                 discharge rounds in one solve; 0 = no limit */
+  int32_t debug_checks;       /* 1 = verify preflow and labelling invariants
+                                 after every round (slow; test use)          */
+  int32_t tail_threshold;     /* frontier size at or below which a single
+                                 workgroup runs the rounds; default 4096     */
+  int32_t group_lanes;        /* lanes per small frontier node: 4, 8 or 16;
+                                 default 8                                   */
+  int32_t big_degree;         /* nodes with more arcs go wave-per-node;
+                                 default 32                                  */
+  int32_t profile;            /* 1 = time every kernel launch with HIP events
+                                 (see flow_problem_kernel_times)            */
+  int32_t reserved[9];
+} fp_options;
+
+/* Counters of the last solve (cumulative over warm-started solves). */
+typedef struct {
+  int64_t rounds;           /* discharge rounds                              */
+  int64_t tail_rounds;      /* of which run by the single-workgroup loop     */
+  int64_t relabels;         /* relabel operations                            */
+  int64_t global_relabels;  /* reverse-BFS global relabels                   */
+  int64_t bfs_levels;       /* BFS levels over all global relabels and cuts  */
+  int64_t restarts;         /* termination checks that found active nodes    */
+  int64_t host_syncs;       /* host round trips                              */
+  int64_t flow_value;       /* current flow value                            */
+  int64_t reserved[8];
+} fp_stats;
+
+/*
+ * flow_problem_create: validate the hypergraph and terminals, copy them to
+ * the device and build the device layout (net CSR, vertex incidence CSR).
+ *
+ *   num_vertices  |V| >= 1
+ *   num_nets      |E| >= 0
+ *   net_offsets   |E|+1 int32; net_offsets[0] = 0, nondecreasing; the pins
+ *                 of net e are pins[net_offsets[e] .. net_offsets[e+1])
+ *   pins          net_offsets[|E|] vertex ids in [0, |V|), no vertex twice
+ *                 inside one net
+ *   net_weights   |E| int32, each >= 1, sum <= INT32_MAX
+ *   sources       num_sources >= 1 vertex ids (repeats allowed)
+ *   sinks         num_sinks >= 1 vertex ids, disjoint from the sources
+ *   mem_kind      memory kind of all input pointers (0 host, 1 device)
+ *   opts          NULL for defaults
+ *   out           receives the handle on FP_OK, NULL otherwise
+ *
+ * Errors: FP_ERR_INVALID for any violated condition above, FP_ERR_OVERFLOW
+ * for too large weights or sizes, FP_ERR_OOM, FP_ERR_DEVICE.  A failed
+ * create leaves nothing allocated.
+ */
+fp_status flow_problem_create(int32_t num_vertices, int32_t num_nets,
+                              const int32_t *net_offsets, const int32_t *pins,
+                              const int32_t *net_weights, const int32_t *sources,
+                              int32_t num_sources, const int32_t *sinks,
+                              int32_t num_sinks, int32_t mem_kind,
+                              const fp_options *opts, void *hip_stream,
+                              fp_problem **out);
+
+/*
+ * maxflow_solve: push-relabel to a maximum preflow of the current S, T
+ * (paper, section "Synchronous Parallel Push-Relabel" with the terminating
+ * global relabel of section "A Bug in the Synchronous Algorithm").  The
+ * first call starts from the zero flow; after flow_problem_pierce it
+ * continues from the previous flow and labels (warm start, paragraph
+ * "Maintain Distance Labels").
+ *
+ *   flow_value  host out: maximum flow value = minimum cut weight
+ *
+ * Errors: FP_ERR_ABORTED when opts->round_budget is exhausted (the handle
+ * then holds a valid preflow and may be solved again), FP_ERR_DEVICE.
+ */
+fp_status maxflow_solve(fp_problem *problem, void *hip_stream, int64_t *flow_value);
+
+/*
+ * mincut_source_side: minimal source side of the minimum cut after a solve
+ * (paper, paragraph "Source-Side Cut"; forward BFS ignores the (u, e_in)
+ * capacity restriction as the paragraph "Restricting Capacities" states).
+ *
+ *   mem_kind     memory kind of the two output buffers
+ *   vertex_side  |V| bytes: 1 if the vertex is in the minimal source side
+ *   net_side     |E| bytes or NULL: bit 0 = e_in reachable from the source
+ *                side (the net has a pin in it), bit 1 = e_out reachable
+ *                (every pin of a non-empty net is in it)
+ *
+ * Errors: FP_ERR_STATE before a successful solve, FP_ERR_DEVICE (an
+ * internal check found a sink reachable, i.e. the preflow was not maximum).
+ */
+fp_status mincut_source_side(fp_problem *problem, void *hip_stream, int32_t mem_kind,
+                             uint8_t *vertex_side, uint8_t *net_side);
+
+/*
+ * flow_batch_solve: solve many independent problems in one persistent
+ * launch (one workgroup per problem, largest first), with the same device
+ * arithmetic as maxflow_solve.  Problems may differ in size.
+ *
+ *   problems     count handles created on the current device
+ *   skip         count bytes or NULL; skip[i] != 0 leaves problem i alone
+ *                and reports flow_values[i] = -1
+ *   flow_values  host out, count entries
+ *
+ * After FP_OK every solved handle behaves as after maxflow_solve
+ * (mincut_source_side may be called on it).
+ */
+fp_status flow_batch_solve(fp_problem *const *problems, int32_t count,
+                           const uint8_t *skip, void *hip_stream,
+                           int64_t *flow_values);
+
+/*
+ * flow_problem_pierce: turn vertices into terminals for the next solve of an
+ * incremental sequence (paper, section "Flow-Based Refinement", algorithm
+ * "FlowCutter Core"; paragraphs "Sink-Side Piercing" and "Maintain Distance
+ * Labels").  side 0: every vertex of the current minimal source side plus
+ * the given vertices becomes a source; side 1: every vertex of the current
+ * maximal sink side (vertices that reach a sink in the residual network)
+ * plus the given vertices becomes a sink, and excess held by new sinks is
+ * added to the flow value.  Flows are kept.
+ *
+ *   vertices  n host vertex ids (none may lie on the opposite terminal side)
+ *
+ * Errors: FP_ERR_STATE before a solve, FP_ERR_INVALID.
+ */
+fp_status flow_problem_pierce(fp_problem *problem, int32_t side, const int32_t *vertices,
+                              int32_t n, void *hip_stream);
+
+/* Counters of the handle (host out). */
+fp_status flow_problem_stats(const fp_problem *problem, fp_stats *out);
+
+/*
+ * Per-kernel timing when opts->profile = 1: for up to max_kinds kernel kinds
+ * writes the kernel name, launch count, summed milliseconds (HIP events on
+ * the launch stream) and algorithmic bytes moved (counted on the device).
+ * Returns the number of kinds, or a negative fp_status.
+ */
+int32_t flow_problem_kernel_times(const fp_problem *problem, int32_t max_kinds,
+                                  const char **names, int64_t *launches,
+                                  double *milliseconds, double *bytes);
+
+/*
+ * flow_problem_export_state: copy the current flow state to host buffers
+ * (any pointer may be NULL), for certificates and tests.
+ *
+ *   f_in    |P| ints: flow on (u, e_in) of each pin slot (net-CSR order)
+ *   f_out   |P| ints: flow on (e_out, u) of each pin slot
+ *   f_b     |E| ints: flow on (e_in, e_out)
+ *   labels  |V| + 2|E| ints: distance labels of vertices, then e_in / e_out
+ *           of each net interleaved (e_in of net e at |V| + 2e)
+ *   excess  same layout as labels
+ */
+fp_status flow_problem_export_state(fp_problem *problem, void *hip_stream, int32_t *f_in,
+                                    int32_t *f_out, int32_t *f_b, int32_t *labels,
+                                    int32_t *excess);
+
+/* Release all device memory of the handle.  NULL is ignored. */
+void flow_problem_destroy(fp_problem *problem);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *fp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HYPERFLOW_H */

@@ -1,0 +1,192 @@
+// C ABI entry points (include/hyperflow.h): argument checks, error strings
+// and handle lifetime; the work is done in hf_build.hip / hf_solve.hip.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "hf_host.h"
+
+namespace hf {
+
+static thread_local std::string g_last_error;
+
+void set_error(const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+}
+
+fp_status hip_fail(hipError_t e, const char* what) {
+  set_error("%s: HIP error %d (%s)", what, (int)e, hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? FP_ERR_OOM : FP_ERR_DEVICE;
+}
+
+}  // namespace hf
+
+using namespace hf;
+
+#pragma GCC visibility push(default)
+extern "C" {
+
+const char* fp_last_error(void) { return g_last_error.c_str(); }
+
+fp_status flow_problem_create(int32_t num_vertices, int32_t num_nets, const int32_t* net_offsets,
+                              const int32_t* pins, const int32_t* net_weights,
+                              const int32_t* sources, int32_t num_sources, const int32_t* sinks,
+                              int32_t num_sinks, int32_t mem_kind, const fp_options* opts,
+                              void* hip_stream, fp_problem** out) {
+  g_last_error.clear();
+  if (!out) {
+    set_error("out is NULL");
+    return FP_ERR_INVALID;
+  }
+  *out = nullptr;
+  if (num_vertices < 1 || num_nets < 0) {
+    set_error("need num_vertices >= 1 and num_nets >= 0 (got %d, %d)", num_vertices, num_nets);
+    return FP_ERR_INVALID;
+  }
+  if (num_sources < 1 || num_sinks < 1) {
+    set_error("source and sink sets must be nonempty (got %d, %d)", num_sources, num_sinks);
+    return FP_ERR_INVALID;
+  }
+  if (!net_offsets || !sources || !sinks || (num_nets > 0 && !net_weights)) {
+    set_error("NULL input pointer");
+    return FP_ERR_INVALID;
+  }
+  if (mem_kind != 0 && mem_kind != 1) {
+    set_error("mem_kind must be 0 (host) or 1 (device), got %d", mem_kind);
+    return FP_ERR_INVALID;
+  }
+  if ((long long)num_sources + num_sinks >= (1ll << 31)) {
+    set_error("too many terminals");
+    return FP_ERR_OVERFLOW;
+  }
+  fp_problem* pb = new (std::nothrow) fp_problem();
+  if (!pb) {
+    set_error("host allocation failed");
+    return FP_ERR_OOM;
+  }
+  hipGetDevice(&pb->device);
+  pb->V = num_vertices;
+  pb->E = num_nets;
+  pb->opt = resolve_options(opts);
+  fp_status st = build_problem(pb, net_offsets, pins, net_weights, sources, num_sources, sinks,
+                               num_sinks, mem_kind, static_cast<hipStream_t>(hip_stream));
+  if (st != FP_OK) {
+    hipStreamSynchronize(static_cast<hipStream_t>(hip_stream));
+    release_problem(pb);
+    delete pb;
+    return st;
+  }
+  *out = pb;
+  return FP_OK;
+}
+
+fp_status maxflow_solve(fp_problem* problem, void* hip_stream, int64_t* flow_value) {
+  g_last_error.clear();
+  if (!problem || !flow_value) {
+    set_error("NULL argument");
+    return problem ? FP_ERR_INVALID : FP_ERR_STATE;
+  }
+  int64_t f = 0;
+  fp_status st = solve_problem(problem, static_cast<hipStream_t>(hip_stream), &f);
+  if (st == FP_OK) *flow_value = f;
+  return st;
+}
+
+fp_status mincut_source_side(fp_problem* problem, void* hip_stream, int32_t mem_kind,
+                             uint8_t* vertex_side, uint8_t* net_side) {
+  g_last_error.clear();
+  if (!problem) {
+    set_error("NULL handle");
+    return FP_ERR_STATE;
+  }
+  if (!vertex_side || (mem_kind != 0 && mem_kind != 1)) {
+    set_error("vertex_side must be non-NULL and mem_kind 0 or 1");
+    return FP_ERR_INVALID;
+  }
+  return cut_problem(problem, static_cast<hipStream_t>(hip_stream), mem_kind, vertex_side,
+                     net_side);
+}
+
+fp_status flow_batch_solve(fp_problem* const* problems, int32_t count, const uint8_t* skip,
+                           void* hip_stream, int64_t* flow_values) {
+  g_last_error.clear();
+  if (count < 0 || (count > 0 && (!problems || !flow_values))) {
+    set_error("invalid batch arguments");
+    return FP_ERR_INVALID;
+  }
+  for (int32_t i = 0; i < count; ++i)
+    if (!problems[i]) {
+      set_error("problem %d is NULL", i);
+      return FP_ERR_INVALID;
+    }
+  return batch_solve(problems, count, skip, static_cast<hipStream_t>(hip_stream), flow_values);
+}
+
+fp_status flow_problem_pierce(fp_problem* problem, int32_t side, const int32_t* vertices,
+                              int32_t n, void* hip_stream) {
+  g_last_error.clear();
+  if (!problem) {
+    set_error("NULL handle");
+    return FP_ERR_STATE;
+  }
+  if ((side != 0 && side != 1) || n < 0 || (n > 0 && !vertices)) {
+    set_error("invalid pierce arguments");
+    return FP_ERR_INVALID;
+  }
+  return pierce_problem(problem, side, vertices, n, static_cast<hipStream_t>(hip_stream));
+}
+
+fp_status flow_problem_stats(const fp_problem* problem, fp_stats* out) {
+  if (!problem || !out) {
+    set_error("NULL argument");
+    return FP_ERR_INVALID;
+  }
+  *out = problem->st;
+  return FP_OK;
+}
+
+int32_t flow_problem_kernel_times(const fp_problem* problem, int32_t max_kinds, const char** names,
+                                  int64_t* launches, double* milliseconds, double* bytes) {
+  if (!problem) return FP_ERR_STATE;
+  int32_t n = 0;
+  for (int k = 0; k < KK_COUNT && n < max_kinds; ++k, ++n) {
+    if (names) names[n] = kernel_kind_name(k);
+    if (launches) launches[n] = problem->k_launches[k];
+    if (milliseconds) milliseconds[n] = problem->k_ms[k];
+    if (bytes) {
+      const int c = kernel_kind_class(k);
+      bytes[n] = c >= 0 ? (double)problem->ctl_h->bytes[c] : 0.0;
+    }
+  }
+  return n;
+}
+
+fp_status flow_problem_export_state(fp_problem* problem, void* hip_stream, int32_t* f_in,
+                                    int32_t* f_out, int32_t* f_b, int32_t* labels,
+                                    int32_t* excess) {
+  g_last_error.clear();
+  if (!problem) {
+    set_error("NULL handle");
+    return FP_ERR_STATE;
+  }
+  return export_state(problem, static_cast<hipStream_t>(hip_stream), f_in, f_out, f_b, labels,
+                      excess);
+}
+
+void flow_problem_destroy(fp_problem* problem) {
+  if (!problem) return;
+  hipSetDevice(problem->device);
+  hipDeviceSynchronize();
+  release_problem(problem);
+  delete problem;
+}
+
+}  // extern "C"
+#pragma GCC visibility pop

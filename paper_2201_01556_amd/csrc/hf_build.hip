@@ -1,0 +1,478 @@
+// Problem creation: copy the inputs to the device, validate them and build
+// the device layout (net CSR as given, vertex incidence CSR by a counting
+// sort with per-vertex ordering by pin slot, terminal roles, per-net terminal
+// flags).  Every step runs on the device.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <algorithm>
+
+#include "hf_host.h"
+
+namespace hf {
+
+// ---------------------------------------------------------------------------
+// validation / layout kernels (thread per element, grid-stride)
+// ---------------------------------------------------------------------------
+
+__global__ void k_check_nets(Dev g, unsigned long long* wsum) {
+  unsigned long long s = 0;
+  int err = 0;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < g.E; e += gridDim.x * blockDim.x) {
+    const int lo = g.net_off[e], hi = g.net_off[e + 1];
+    if (hi < lo || lo < 0 || hi > g.P) err |= ERR_BUILD_OFFSETS;
+    if (e == 0 && lo != 0) err |= ERR_BUILD_OFFSETS;
+    const int we = g.w[e];
+    if (we < 1) err |= ERR_BUILD_WEIGHT;
+    else s += (unsigned long long)we;
+  }
+  if (err) atomicOr(&g.ctl->err, err);
+  if (s) atomicAdd(wsum, s);
+}
+
+__global__ void k_count_pins(Dev g, int32_t* cnt) {
+  int err = 0;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < g.P; p += gridDim.x * blockDim.x) {
+    const int u = g.pin_v[p];
+    if (u < 0 || u >= g.V) err |= ERR_BUILD_PIN;
+    else atomicAdd(&cnt[u + 1], 1);
+  }
+  if (err) atomicOr(&g.ctl->err, err);
+}
+
+__global__ void k_roles(Dev g, const int32_t* S, int nS, const int32_t* T, int nT) {
+  int err = 0;
+  const int n = nS + nT;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const bool src = i < nS;
+    const int v = src ? S[i] : T[i - nS];
+    if (v < 0 || v >= g.V) err |= ERR_BUILD_TERMINAL;
+    else atomicOr(&g.role[v], src ? 1 : 2);
+  }
+  if (err) atomicOr(&g.ctl->err, err);
+}
+
+__global__ void k_role_check(Dev g) {
+  int err = 0;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.V; v += gridDim.x * blockDim.x)
+    if (g.role[v] == 3) err |= ERR_BUILD_ST;
+  if (err) atomicOr(&g.ctl->err, err);
+}
+
+// inclusive scan, three passes over tiles of 2048 ints
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 8;
+constexpr int kScanTile = kScanThreads * kScanPer;
+
+__device__ int block_excl_scan(int v, int* sh_wave, int* total) {
+  // inclusive within the wave
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) sh_wave[wid] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+      const int t = sh_wave[i];
+      sh_wave[i] = run;
+      run += t;
+    }
+    *total = run;
+  }
+  __syncthreads();
+  return sh_wave[wid] + incl - v;
+}
+
+__global__ void k_scan_tiles(int32_t* a, int n, int32_t* bsum) {
+  __shared__ int sh_wave[kScanThreads / 64];
+  __shared__ int total;
+  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+  int loc[kScanPer];
+  int run = 0;
+#pragma unroll
+  for (int j = 0; j < kScanPer; ++j) {
+    const int i = base + j;
+    run += (i < n) ? a[i] : 0;
+    loc[j] = run;
+  }
+  const int off = block_excl_scan(run, sh_wave, &total);
+#pragma unroll
+  for (int j = 0; j < kScanPer; ++j) {
+    const int i = base + j;
+    if (i < n) a[i] = loc[j] + off;
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// exclusive scan of the tile sums, one block
+__global__ void k_scan_sums(int32_t* bsum, int nb) {
+  __shared__ int sh_wave[kScanThreads / 64];
+  __shared__ int total;
+  int carry = 0;
+  for (int base = 0; base < nb; base += blockDim.x) {
+    const int i = base + threadIdx.x;
+    const int v = i < nb ? bsum[i] : 0;
+    const int ex = block_excl_scan(v, sh_wave, &total);
+    __syncthreads();
+    if (i < nb) bsum[i] = carry + ex;
+    carry += total;
+    __syncthreads();
+  }
+}
+
+__global__ void k_scan_add(int32_t* a, int n, const int32_t* bsum) {
+  const int add = bsum[blockIdx.x];
+  const int base = blockIdx.x * kScanTile;
+  for (int j = threadIdx.x; j < kScanTile; j += blockDim.x) {
+    const int i = base + j;
+    if (i < n) a[i] += add;
+  }
+}
+
+__global__ void k_scatter(Dev g, int32_t* cursor) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < g.P; p += gridDim.x * blockDim.x) {
+    // net of pin slot p: last e with net_off[e] <= p
+    int lo = 0, hi = g.E;  // answer in [0, E)
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (g.net_off[mid] <= p) lo = mid;
+      else hi = mid;
+    }
+    const int u = g.pin_v[p];
+    const int pos = atomicAdd(&cursor[u], 1);
+    const_cast<int2*>(g.vinc)[pos] = make_int2(lo, p);
+    const int r = g.role[u];
+    if (r) atomicOr(&g.nflag[lo], r);
+  }
+}
+
+// sort each vertex's incidences by pin slot (deterministic layout), then a
+// repeated net in one list means a vertex appears twice in that net
+__global__ void k_sort_incidences(Dev g) {
+  int err = 0;
+  int2* inc = const_cast<int2*>(g.vinc);
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.V; v += gridDim.x * blockDim.x) {
+    const int lo = g.vtx_off[v], hi = g.vtx_off[v + 1];
+    const int n = hi - lo;
+    int2* a = inc + lo;
+    if (n <= 16) {
+      for (int i = 1; i < n; ++i) {
+        const int2 t = a[i];
+        int j = i - 1;
+        while (j >= 0 && a[j].y > t.y) {
+          a[j + 1] = a[j];
+          --j;
+        }
+        a[j + 1] = t;
+      }
+    } else {
+      // heapsort by .y
+      for (int start = n / 2 - 1; start >= 0; --start) {
+        int r = start;
+        for (;;) {
+          int c = 2 * r + 1;
+          if (c >= n) break;
+          if (c + 1 < n && a[c + 1].y > a[c].y) ++c;
+          if (a[r].y >= a[c].y) break;
+          const int2 t = a[r];
+          a[r] = a[c];
+          a[c] = t;
+          r = c;
+        }
+      }
+      for (int end = n - 1; end > 0; --end) {
+        const int2 t = a[0];
+        a[0] = a[end];
+        a[end] = t;
+        int r = 0;
+        for (;;) {
+          int c = 2 * r + 1;
+          if (c >= end) break;
+          if (c + 1 < end && a[c + 1].y > a[c].y) ++c;
+          if (a[r].y >= a[c].y) break;
+          const int2 t2 = a[r];
+          a[r] = a[c];
+          a[c] = t2;
+          r = c;
+        }
+      }
+    }
+    for (int i = 1; i < n; ++i)
+      if (a[i].x == a[i - 1].x) err |= ERR_BUILD_DUP;
+  }
+  if (err) atomicOr(&g.ctl->err, err);
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Carve {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    T* p = reinterpret_cast<T*>(base + off);
+    off += align_up(count * sizeof(T) + 1);
+    return p;
+  }
+};
+
+static int grid_for(long long n, int threads = 256, int cap = 4096) {
+  long long b = (n + threads - 1) / threads;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (int)b;
+}
+
+fp_options resolve_options(const fp_options* o) {
+  fp_options r{};
+  if (o) r = *o;
+  if (r.relabel_factor_x16 <= 0) r.relabel_factor_x16 = 16;
+  if (r.tail_threshold <= 0) r.tail_threshold = 4096;
+  if (r.group_lanes != 4 && r.group_lanes != 8 && r.group_lanes != 16) r.group_lanes = 8;
+  if (r.big_degree <= 0) r.big_degree = 32;
+  return r;
+}
+
+fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_t* pins,
+                        const int32_t* net_weights, const int32_t* sources, int32_t nS,
+                        const int32_t* sinks, int32_t nT, int32_t mem_kind, hipStream_t s) {
+  hipError_t he;
+  const int32_t V = pb->V, E = pb->E;
+  // number of pins
+  int32_t P = 0;
+  if (mem_kind == 0) {
+    P = net_offsets[E];
+  } else {
+    he = hipMemcpyAsync(&P, net_offsets + E, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (he != hipSuccess) return hip_fail(he, "reading net_offsets[num_nets]");
+    he = hipStreamSynchronize(s);
+    if (he != hipSuccess) return hip_fail(he, "reading net_offsets[num_nets]");
+  }
+  if (P < 0) {
+    set_error("net_offsets[num_nets] = %d is negative", P);
+    return FP_ERR_INVALID;
+  }
+  if (P > 0 && pins == nullptr) {
+    set_error("pins is NULL but the nets hold %d pins", P);
+    return FP_ERR_INVALID;
+  }
+  const long long NB = ((long long)V + 1) & ~1ll;
+  const long long N = NB + 2ll * E;
+  if (N + 4 >= (1ll << 31) || 2ll * P >= (1ll << 31)) {
+    set_error("network too large for 31-bit ids (V=%d E=%d P=%d)", V, E, P);
+    return FP_ERR_OVERFLOW;
+  }
+  pb->P = P;
+  pb->NB = (int32_t)NB;
+  pb->N = (int32_t)N;
+  pb->nS = nS;
+  pb->nT = nT;
+
+  // one device pool for the whole handle
+  size_t bytes = 0;
+  auto add = [&](size_t n) { bytes += align_up(n + 1); };
+  add((E + 1) * 4ull);        // net_off
+  add(P * 4ull);              // pin_v
+  add(E * 4ull);              // w
+  add((V + 1) * 4ull);        // vtx_off
+  add(P * 8ull);              // vinc
+  add(V * 4ull);              // role
+  add(E * 4ull);              // nflag
+  add((nS + nT) * 4ull);      // terminal lists (build input copy)
+  add(2ull * P * 4ull);       // fpin
+  add(E * 4ull);              // fb
+  add(N * 4ull);              // d
+  add(N * 4ull);              // x
+  add(N * 4ull);              // stamp
+  add(4ull * N * 4ull);       // frontier lists
+  add(N * 8ull);              // left
+  add(sizeof(Ctl));           // ctl
+  add(64);                    // scratch for the weight sum
+  he = hipMalloc(&pb->pool, bytes);
+  if (he != hipSuccess) {
+    pb->pool = nullptr;
+    set_error("hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(he));
+    return FP_ERR_OOM;
+  }
+  Carve c{static_cast<char*>(pb->pool)};
+  Dev& g = pb->dev;
+  g.V = V;
+  g.E = E;
+  g.P = P;
+  g.NB = (int32_t)NB;
+  g.N = (int32_t)N;
+  g.nT = nT;
+  g.big_deg = pb->opt.big_degree;
+  int32_t* net_off = c.take<int32_t>(E + 1);
+  int32_t* pin_v = c.take<int32_t>(P);
+  int32_t* w = c.take<int32_t>(E);
+  int32_t* vtx_off = c.take<int32_t>(V + 1);
+  int2* vinc = c.take<int2>(P);
+  g.role = c.take<int32_t>(V);
+  g.nflag = c.take<int32_t>(E);
+  int32_t* terms = c.take<int32_t>(nS + nT);
+  g.fpin = c.take<int32_t>(2ull * P);
+  g.fb = c.take<int32_t>(E);
+  g.d = c.take<int32_t>(N);
+  g.x = c.take<int32_t>(N);
+  g.stamp = c.take<int32_t>(N);
+  int32_t* lists = c.take<int32_t>(4ull * N);
+  g.list[0][0] = lists;
+  g.list[0][1] = lists + N;
+  g.list[1][0] = lists + 2 * N;
+  g.list[1][1] = lists + 3 * N;
+  g.left = c.take<int2>(N);
+  g.ctl = c.take<Ctl>(1);
+  unsigned long long* wsum = c.take<unsigned long long>(1);
+  g.net_off = net_off;
+  g.pin_v = pin_v;
+  g.w = w;
+  g.vtx_off = vtx_off;
+  g.vinc = vinc;
+  g.tlist = terms + nS;
+
+  const hipMemcpyKind kind = mem_kind == 0 ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  he = hipMemcpyAsync(net_off, net_offsets, (E + 1) * 4ull, kind, s);
+  if (he == hipSuccess && P) he = hipMemcpyAsync(pin_v, pins, P * 4ull, kind, s);
+  if (he == hipSuccess && E) he = hipMemcpyAsync(w, net_weights, E * 4ull, kind, s);
+  if (he == hipSuccess) he = hipMemcpyAsync(terms, sources, nS * 4ull, kind, s);
+  if (he == hipSuccess) he = hipMemcpyAsync(terms + nS, sinks, nT * 4ull, kind, s);
+  if (he == hipSuccess) he = hipMemsetAsync(g.ctl, 0, sizeof(Ctl), s);
+  if (he == hipSuccess) he = hipMemsetAsync(wsum, 0, 8, s);
+  if (he == hipSuccess) he = hipMemsetAsync(vtx_off, 0, (V + 1) * 4ull, s);
+  if (he == hipSuccess) he = hipMemsetAsync(g.role, 0, V * 4ull, s);
+  if (he == hipSuccess && E) he = hipMemsetAsync(g.nflag, 0, E * 4ull, s);
+  if (he != hipSuccess) return hip_fail(he, "copying inputs");
+
+  // validation
+  if (E) k_check_nets<<<grid_for(E), 256, 0, s>>>(g, wsum);
+  if (P) k_count_pins<<<grid_for(P), 256, 0, s>>>(g, vtx_off);
+  k_roles<<<grid_for(nS + nT), 256, 0, s>>>(g, terms, nS, terms + nS, nT);
+  k_role_check<<<grid_for(V), 256, 0, s>>>(g);
+  int32_t err = 0;
+  unsigned long long wtot = 0;
+  he = hipMemcpyAsync(&err, &g.ctl->err, 4, hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess) he = hipMemcpyAsync(&wtot, wsum, 8, hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  if (he != hipSuccess) return hip_fail(he, "validating inputs");
+  if (err & ERR_BUILD_OFFSETS) {
+    set_error("net_offsets must start at 0 and be nondecreasing up to the pin count");
+    return FP_ERR_INVALID;
+  }
+  if (err & ERR_BUILD_WEIGHT) {
+    set_error("net weights must be >= 1");
+    return FP_ERR_INVALID;
+  }
+  if (err & ERR_BUILD_PIN) {
+    set_error("pin ids must lie in [0, num_vertices)");
+    return FP_ERR_INVALID;
+  }
+  if (err & ERR_BUILD_TERMINAL) {
+    set_error("source and sink ids must lie in [0, num_vertices)");
+    return FP_ERR_INVALID;
+  }
+  if (err & ERR_BUILD_ST) {
+    set_error("a vertex is both a source and a sink");
+    return FP_ERR_INVALID;
+  }
+  if (wtot > 0x7fffffffull) {
+    set_error("sum of net weights %llu exceeds INT32_MAX", wtot);
+    return FP_ERR_OVERFLOW;
+  }
+
+  // vertex incidence CSR: counts -> offsets
+  const int ntiles = (V + kScanTile - 1) / kScanTile;
+  int32_t* bsum = g.x;  // scratch
+  if (V) {
+    k_scan_tiles<<<ntiles, kScanThreads, 0, s>>>(vtx_off + 1, V, bsum);
+    k_scan_sums<<<1, kScanThreads, 0, s>>>(bsum, ntiles);
+    k_scan_add<<<ntiles, kScanThreads, 0, s>>>(vtx_off + 1, V, bsum);
+  }
+  int32_t* cursor = g.stamp;  // scratch
+  he = hipMemcpyAsync(cursor, vtx_off, V * 4ull, hipMemcpyDeviceToDevice, s);
+  if (he != hipSuccess) return hip_fail(he, "building incidences");
+  if (P) k_scatter<<<grid_for(P), 256, 0, s>>>(g, cursor);
+  k_sort_incidences<<<grid_for(V), 256, 0, s>>>(g);
+  he = hipMemcpyAsync(&err, &g.ctl->err, 4, hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  if (he == hipSuccess) he = hipGetLastError();
+  if (he != hipSuccess) return hip_fail(he, "building incidences");
+  if (err & ERR_BUILD_DUP) {
+    set_error("a vertex appears twice in one net");
+    return FP_ERR_INVALID;
+  }
+  he = hipHostMalloc((void**)&pb->ctl_h, sizeof(Ctl), hipHostMallocDefault);
+  if (he != hipSuccess) {
+    pb->ctl_h = nullptr;
+    return hip_fail(he, "allocating the pinned control block");
+  }
+  memset(pb->ctl_h, 0, sizeof(Ctl));
+  return FP_OK;
+}
+
+// pin state {r_in, f_out} -> separate flow arrays; labels / excess without
+// the padding node between vertices and nets
+__global__ void k_export(Dev g, int32_t* f_in, int32_t* f_out, int32_t* lab, int32_t* exc) {
+  const int n = max(g.P, g.V + 2 * g.E);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    if (i < g.P) {
+      const int2 ep = g.vinc[i];
+      f_in[ep.y] = g.w[ep.x] - g.fpin[2 * ep.y];
+      f_out[ep.y] = g.fpin[2 * ep.y + 1];
+    }
+    if (i < g.V + 2 * g.E) {
+      const int src = i < g.V ? i : i - g.V + g.NB;
+      lab[i] = g.d[src];
+      exc[i] = g.x[src];
+    }
+  }
+}
+
+fp_status export_state(fp_problem* pb, hipStream_t s, int32_t* f_in, int32_t* f_out,
+                       int32_t* f_b, int32_t* labels, int32_t* excess) {
+  if (!pb->inited) {
+    set_error("no flow state before the first solve");
+    return FP_ERR_STATE;
+  }
+  Dev& g = pb->dev;
+  const size_t P = g.P, M = (size_t)g.V + 2ull * g.E;
+  int32_t* tmp = nullptr;
+  hipError_t he = hipMalloc(&tmp, (2 * P + 2 * M + 2) * sizeof(int32_t));
+  if (he != hipSuccess) return hip_fail(he, "export buffer");
+  int32_t *dfi = tmp, *dfo = tmp + P, *dl = tmp + 2 * P, *dx = tmp + 2 * P + M;
+  k_export<<<grid_for((long long)std::max(P, M)), 256, 0, s>>>(g, dfi, dfo, dl, dx);
+  he = hipGetLastError();
+  if (he == hipSuccess && f_in && P) he = hipMemcpyAsync(f_in, dfi, P * 4, hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess && f_out && P) he = hipMemcpyAsync(f_out, dfo, P * 4, hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess && f_b && g.E) he = hipMemcpyAsync(f_b, g.fb, g.E * 4ull, hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess && labels) he = hipMemcpyAsync(labels, dl, M * 4, hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess && excess) he = hipMemcpyAsync(excess, dx, M * 4, hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  hipFree(tmp);
+  if (he != hipSuccess) return hip_fail(he, "exporting state");
+  return FP_OK;
+}
+
+void release_problem(fp_problem* pb) {
+  if (!pb) return;
+  for (auto& t : pb->pending) {
+    hipEventDestroy(t.a);
+    hipEventDestroy(t.b);
+  }
+  for (auto e : pb->free_events) hipEventDestroy(e);
+  if (pb->pool) hipFree(pb->pool);
+  if (pb->ctl_h) hipHostFree(pb->ctl_h);
+  pb->pool = nullptr;
+  pb->ctl_h = nullptr;
+}
+
+}  // namespace hf

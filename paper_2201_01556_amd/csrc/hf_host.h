@@ -1,0 +1,92 @@
+// Host-side state of a flow problem handle and internal entry points.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "hf_device.h"
+#include "hyperflow.h"
+
+namespace hf {
+
+// kernel kinds for per-launch timing
+enum KernelKind : int {
+  KK_INIT = 0,
+  KK_GR_RESET,
+  KK_BFS_REV,
+  KK_BFS_REV_LOOP,
+  KK_GATHER,
+  KK_PUSH,
+  KK_APPLY,
+  KK_ROUND_LOOP,
+  KK_CUT_SEED,
+  KK_BFS_FWD,
+  KK_BFS_FWD_LOOP,
+  KK_CUT_OUT,
+  KK_CHECK,
+  KK_BATCH,
+  KK_COUNT
+};
+
+const char* kernel_kind_name(int k);
+// device byte-counter class of a kernel kind (-1: none)
+int kernel_kind_class(int k);
+
+struct Timer {
+  int kind;
+  hipEvent_t a, b;
+};
+
+}  // namespace hf
+
+struct fp_problem {
+  int device = 0;
+  int32_t V = 0, E = 0, P = 0, NB = 0, N = 0;
+  int32_t nS = 0, nT = 0;
+  fp_options opt{};
+  hf::Dev dev{};
+  void* pool = nullptr;
+  hf::Ctl* ctl_h = nullptr;  // pinned host mirror of the control block
+  int32_t epoch = 1;         // stamp value of the next round / BFS
+  bool inited = false;
+  bool solved = false;
+  fp_stats st{};
+  // profiling
+  std::vector<hf::Timer> pending;
+  std::vector<hipEvent_t> free_events;
+  int64_t k_launches[hf::KK_COUNT] = {};
+  double k_ms[hf::KK_COUNT] = {};
+  unsigned long long bytes_at_sync[hf::KC_N] = {};
+  double k_bytes[hf::KK_COUNT] = {};
+};
+
+namespace hf {
+
+void set_error(const char* fmt, ...);
+fp_status hip_fail(hipError_t e, const char* what);
+
+// defaults filled in
+fp_options resolve_options(const fp_options* o);
+
+fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_t* pins,
+                        const int32_t* net_weights, const int32_t* sources, int32_t nS,
+                        const int32_t* sinks, int32_t nT, int32_t mem_kind,
+                        hipStream_t s);
+fp_status solve_problem(fp_problem* pb, hipStream_t s, int64_t* flow);
+fp_status cut_problem(fp_problem* pb, hipStream_t s, int32_t mem_kind, uint8_t* vside,
+                      uint8_t* nside);
+fp_status batch_solve(fp_problem* const* pbs, int32_t count, const uint8_t* skip,
+                      hipStream_t s, int64_t* flows);
+fp_status pierce_problem(fp_problem* pb, int32_t side, const int32_t* vertices, int32_t n,
+                         hipStream_t s);
+fp_status export_state(fp_problem* pb, hipStream_t s, int32_t* f_in, int32_t* f_out,
+                       int32_t* f_b, int32_t* labels, int32_t* excess);
+void release_problem(fp_problem* pb);
+
+// profiling helpers
+void prof_begin(fp_problem* pb, int kind, hipStream_t s, Timer* t);
+void prof_end(fp_problem* pb, Timer* t, hipStream_t s);
+void prof_collect(fp_problem* pb);
+
+}  // namespace hf

@@ -1,0 +1,331 @@
+"""ctypes binding of ``libhyperflow.so`` (C ABI in ``include/hyperflow.h``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Inputs may be numpy arrays (host memory) or torch CUDA/HIP tensors
+(device memory, passed by ``data_ptr()``); PyTorch is used only for device
+memory and streams.  There is no fallback: if the library is missing the
+first call raises.
+
+The C entry points are exposed under their own names
+(``flow_problem_create``, ``maxflow_solve``, ``mincut_source_side``,
+``flow_batch_solve``, ``flow_problem_pierce``, ``flow_problem_stats``,
+``flow_problem_kernel_times``, ``flow_problem_destroy``, ``fp_last_error``)
+plus a small :class:`FlowProblem` owner class.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhyperflow.so")
+
+FP_OK = 0
+STATUS = {
+    0: "FP_OK",
+    -1: "FP_ERR_INVALID",
+    -2: "FP_ERR_OVERFLOW",
+    -3: "FP_ERR_STATE",
+    -4: "FP_ERR_DEVICE",
+    -5: "FP_ERR_OOM",
+    -6: "FP_ERR_ABORTED",
+}
+
+
+class HyperflowError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+        super().__init__(f"{self.name}: {message}")
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("relabel_factor_x16", ctypes.c_int32),
+        ("round_budget", ctypes.c_int32),
+        ("debug_checks", ctypes.c_int32),
+        ("tail_threshold", ctypes.c_int32),
+        ("group_lanes", ctypes.c_int32),
+        ("big_degree", ctypes.c_int32),
+        ("profile", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 9),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("rounds", ctypes.c_int64),
+        ("tail_rounds", ctypes.c_int64),
+        ("relabels", ctypes.c_int64),
+        ("global_relabels", ctypes.c_int64),
+        ("bfs_levels", ctypes.c_int64),
+        ("restarts", ctypes.c_int64),
+        ("host_syncs", ctypes.c_int64),
+        ("flow_value", ctypes.c_int64),
+        ("reserved", ctypes.c_int64 * 8),
+    ]
+
+
+EXPORTED = [
+    "flow_problem_create",
+    "maxflow_solve",
+    "mincut_source_side",
+    "flow_batch_solve",
+    "flow_problem_pierce",
+    "flow_problem_stats",
+    "flow_problem_kernel_times",
+    "flow_problem_export_state",
+    "flow_problem_destroy",
+    "fp_last_error",
+]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the HIP library (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: build it with `python -m paper_2201_01556_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    i32 = ctypes.c_int32
+    lib.flow_problem_create.argtypes = [i32, i32, vp, vp, vp, vp, i32, vp, i32, i32,
+                                        ctypes.POINTER(Options), vp, ctypes.POINTER(vp)]
+    lib.flow_problem_create.restype = ctypes.c_int
+    lib.maxflow_solve.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.maxflow_solve.restype = ctypes.c_int
+    lib.mincut_source_side.argtypes = [vp, vp, i32, vp, vp]
+    lib.mincut_source_side.restype = ctypes.c_int
+    lib.flow_batch_solve.argtypes = [ctypes.POINTER(vp), i32, vp, vp, vp]
+    lib.flow_batch_solve.restype = ctypes.c_int
+    lib.flow_problem_pierce.argtypes = [vp, i32, vp, i32, vp]
+    lib.flow_problem_pierce.restype = ctypes.c_int
+    lib.flow_problem_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    lib.flow_problem_stats.restype = ctypes.c_int
+    lib.flow_problem_kernel_times.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_char_p),
+                                              vp, vp, vp]
+    lib.flow_problem_kernel_times.restype = i32
+    lib.flow_problem_export_state.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.flow_problem_export_state.restype = ctypes.c_int
+    lib.flow_problem_destroy.argtypes = [vp]
+    lib.flow_problem_destroy.restype = None
+    lib.fp_last_error.argtypes = []
+    lib.fp_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def fp_last_error() -> str:
+    return load_library().fp_last_error().decode()
+
+
+def _check(status: int):
+    if status != FP_OK:
+        raise HyperflowError(status, fp_last_error())
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available() and torch.cuda.is_initialized():
+                return torch.cuda.current_stream().cuda_stream
+        except ImportError:
+            pass
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _is_device_tensor(a) -> bool:
+    return hasattr(a, "is_cuda") and bool(a.is_cuda)
+
+
+def _ptr(a, dtype):
+    """(pointer, memkind, keepalive) of an int32 / uint8 array or tensor."""
+    if _is_device_tensor(a):
+        import torch
+        want = {np.int32: torch.int32, np.uint8: torch.uint8}[dtype]
+        if a.dtype != want or not a.is_contiguous():
+            raise TypeError(f"device tensor must be contiguous {want}")
+        return a.data_ptr(), 1, a
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    return arr.ctypes.data, 0, arr
+
+
+def flow_problem_create(num_vertices, net_offsets, pins, net_weights, sources, sinks,
+                        options: Options | None = None, stream=None):
+    """Create a problem handle; inputs all host (numpy) or all device (torch)."""
+    lib = load_library()
+    args = [_ptr(a, np.int32) for a in (net_offsets, pins, net_weights, sources, sinks)]
+    kinds = {k for _, k, _ in args}
+    if len(kinds) != 1:
+        raise TypeError("inputs must be all host arrays or all device tensors")
+    mem_kind = kinds.pop()
+    num_nets = len(net_offsets) - 1
+    h = ctypes.c_void_p()
+    st = lib.flow_problem_create(int(num_vertices), int(num_nets), args[0][0], args[1][0],
+                                 args[2][0], args[3][0], len(sources), args[4][0], len(sinks),
+                                 mem_kind, ctypes.byref(options) if options else None,
+                                 _stream_ptr(stream), ctypes.byref(h))
+    _check(st)
+    return h
+
+
+def maxflow_solve(handle, stream=None) -> int:
+    f = ctypes.c_int64()
+    _check(load_library().maxflow_solve(handle, _stream_ptr(stream), ctypes.byref(f)))
+    return int(f.value)
+
+
+def mincut_source_side(handle, num_vertices, num_nets, vertex_side=None, net_side=None,
+                       stream=None, want_nets=True):
+    """Minimal source side.  With no output buffers given, returns host numpy
+    arrays (vertex_side, net_side); device tensors are filled in place."""
+    lib = load_library()
+    if vertex_side is None:
+        vertex_side = np.zeros(max(num_vertices, 1), dtype=np.uint8)
+        if want_nets and net_side is None:
+            net_side = np.zeros(max(num_nets, 1), dtype=np.uint8)
+    vp, vk, _ = _ptr(vertex_side, np.uint8)
+    np_ = None
+    if net_side is not None:
+        np_, nk, _ = _ptr(net_side, np.uint8)
+        if nk != vk:
+            raise TypeError("vertex_side and net_side must be in the same memory")
+    _check(lib.mincut_source_side(handle, _stream_ptr(stream), vk, vp, np_))
+    if vk == 0:
+        vs = np.asarray(vertex_side)[:num_vertices]
+        ns = np.asarray(net_side)[:num_nets] if net_side is not None else None
+        return vs, ns
+    return vertex_side, net_side
+
+
+def flow_batch_solve(handles, skip=None, stream=None) -> np.ndarray:
+    lib = load_library()
+    n = len(handles)
+    arr = (ctypes.c_void_p * max(n, 1))(*[h.value if isinstance(h, ctypes.c_void_p) else h
+                                          for h in handles])
+    flows = np.zeros(max(n, 1), dtype=np.int64)
+    sk = None
+    if skip is not None:
+        skip_arr = np.ascontiguousarray(skip, dtype=np.uint8)
+        sk = skip_arr.ctypes.data
+    _check(lib.flow_batch_solve(arr, n, sk, _stream_ptr(stream), flows.ctypes.data))
+    return flows[:n]
+
+
+def flow_problem_pierce(handle, side: int, vertices, stream=None):
+    v = np.ascontiguousarray(vertices, dtype=np.int32)
+    _check(load_library().flow_problem_pierce(handle, int(side), v.ctypes.data, len(v),
+                                              _stream_ptr(stream)))
+
+
+def flow_problem_stats(handle) -> dict:
+    s = Stats()
+    _check(load_library().flow_problem_stats(handle, ctypes.byref(s)))
+    return {k: int(getattr(s, k)) for k, _ in Stats._fields_ if k != "reserved"}
+
+
+def flow_problem_kernel_times(handle) -> list:
+    lib = load_library()
+    n = 32
+    names = (ctypes.c_char_p * n)()
+    launches = np.zeros(n, dtype=np.int64)
+    ms = np.zeros(n, dtype=np.float64)
+    by = np.zeros(n, dtype=np.float64)
+    k = lib.flow_problem_kernel_times(handle, n, names, launches.ctypes.data, ms.ctypes.data,
+                                      by.ctypes.data)
+    if k < 0:
+        _check(k)
+    return [dict(kernel=names[i].decode(), launches=int(launches[i]), ms=float(ms[i]),
+                 bytes=float(by[i])) for i in range(k)]
+
+
+def flow_problem_export_state(handle, num_vertices, num_nets, num_pins, stream=None):
+    """Host copies of the flow state: dict with f_in, f_out (per pin slot),
+    f_b (per net), labels and excess (vertices, then e_in / e_out of each
+    net interleaved)."""
+    P, E, M = num_pins, num_nets, num_vertices + 2 * num_nets
+    out = dict(f_in=np.zeros(max(P, 1), np.int32), f_out=np.zeros(max(P, 1), np.int32),
+               f_b=np.zeros(max(E, 1), np.int32), labels=np.zeros(max(M, 1), np.int32),
+               excess=np.zeros(max(M, 1), np.int32))
+    _check(load_library().flow_problem_export_state(
+        handle, _stream_ptr(stream), out["f_in"].ctypes.data, out["f_out"].ctypes.data,
+        out["f_b"].ctypes.data, out["labels"].ctypes.data, out["excess"].ctypes.data))
+    out["f_in"], out["f_out"] = out["f_in"][:P], out["f_out"][:P]
+    out["f_b"] = out["f_b"][:E]
+    out["labels"], out["excess"] = out["labels"][:M], out["excess"][:M]
+    return out
+
+
+def flow_problem_destroy(handle):
+    if handle:
+        load_library().flow_problem_destroy(handle)
+
+
+class FlowProblem:
+    """Owner of one problem handle."""
+
+    def __init__(self, num_vertices, net_offsets, pins, net_weights, sources, sinks,
+                 options: Options | None = None, stream=None, **opts):
+        if options is None and opts:
+            options = Options(**opts)
+        self.num_vertices = int(num_vertices)
+        self.num_nets = len(net_offsets) - 1
+        self.stream = stream
+        self.handle = flow_problem_create(num_vertices, net_offsets, pins, net_weights,
+                                          sources, sinks, options, stream)
+
+    @classmethod
+    def from_hypergraph(cls, hg, device: bool = False, **opts):
+        arrays = (hg.net_offsets, hg.pins, hg.net_weights, hg.sources, hg.sinks)
+        if device:
+            import torch
+            arrays = tuple(torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrays)
+            torch.cuda.synchronize()
+        return cls(hg.num_vertices, *arrays, **opts)
+
+    def solve(self) -> int:
+        return maxflow_solve(self.handle, self.stream)
+
+    def source_side(self, vertex_side=None, net_side=None):
+        return mincut_source_side(self.handle, self.num_vertices, self.num_nets, vertex_side,
+                                  net_side, self.stream)
+
+    def pierce(self, side: int, vertices):
+        flow_problem_pierce(self.handle, side, vertices, self.stream)
+
+    def stats(self) -> dict:
+        return flow_problem_stats(self.handle)
+
+    def export_state(self, num_pins: int) -> dict:
+        return flow_problem_export_state(self.handle, self.num_vertices, self.num_nets,
+                                         num_pins, self.stream)
+
+    def kernel_times(self) -> list:
+        return flow_problem_kernel_times(self.handle)
+
+    def close(self):
+        if self.handle:
+            flow_problem_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
