@@ -73,14 +73,25 @@ typedef struct {
   int32_t debug_checks;       /* 1 = verify preflow and labelling invariants
                                  after every round (slow; test use)          */
   int32_t tail_threshold;     /* frontier size at or below which a single
-                                 workgroup runs the rounds; default 4096     */
+                                 workgroup runs the rounds; default 1024     */
   int32_t group_lanes;        /* lanes per small frontier node: 4, 8 or 16;
                                  default 8                                   */
   int32_t big_degree;         /* nodes with more arcs go wave-per-node;
                                  default 32                                  */
   int32_t profile;            /* 1 = time every kernel launch with HIP events
                                  (see flow_problem_kernel_times)            */
-  int32_t reserved[9];
+  int32_t gr_interval;        /* also relabel globally after this many rounds
+                                 since the last global relabel; default 64,
+                                 -1 = only by relabel count and stale flow  */
+  int32_t stale_rounds;       /* also relabel globally once the flow value
+                                 stayed unchanged for this many rounds with a
+                                 small frontier (paper, paragraph "Avoid
+                                 Pushing Flow Back"); default 500, -1 = off  */
+  int32_t bottom_up_min;      /* reverse-BFS levels with at least this many
+                                 nodes are expanded without atomics and the
+                                 next level is collected by a sweep over the
+                                 labels; default N/128, -1 = never          */
+  int32_t reserved[6];
 } fp_options;
 
 /* Counters of the last solve (cumulative over warm-started solves). */

@@ -208,6 +208,21 @@ __global__ void k_sort_incidences(Dev g) {
   if (err) atomicOr(&g.ctl->err, err);
 }
 
+// bit v of the bitmap: node v has more than big_deg arcs (vertex: incident
+// nets; net node: pins plus the bridge); padding nodes are never big
+__global__ void k_bigbits(Dev g, uint32_t* bits) {
+  const int words = (g.N + 31) >> 5;
+  for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < words; w += gridDim.x * blockDim.x) {
+    uint32_t m = 0;
+    for (int b = 0; b < 32; ++b) {
+      const int v = (w << 5) + b;
+      if (v >= g.N || (v >= g.V && v < g.NB)) continue;
+      if (deg_of(g, v) > g.big_deg) m |= 1u << b;
+    }
+    bits[w] = m;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -236,9 +251,13 @@ fp_options resolve_options(const fp_options* o) {
   fp_options r{};
   if (o) r = *o;
   if (r.relabel_factor_x16 <= 0) r.relabel_factor_x16 = 16;
-  if (r.tail_threshold <= 0) r.tail_threshold = 4096;
+  if (r.tail_threshold <= 0) r.tail_threshold = 1024;
   if (r.group_lanes != 4 && r.group_lanes != 8 && r.group_lanes != 16) r.group_lanes = 8;
   if (r.big_degree <= 0) r.big_degree = 32;
+  if (r.gr_interval == 0) r.gr_interval = 64;
+  if (r.gr_interval < 0) r.gr_interval = 0;
+  if (r.stale_rounds == 0) r.stale_rounds = 500;
+  if (r.stale_rounds < 0) r.stale_rounds = 0;
   return r;
 }
 
@@ -271,6 +290,8 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
     set_error("network too large for 31-bit ids (V=%d E=%d P=%d)", V, E, P);
     return FP_ERR_OVERFLOW;
   }
+  if (pb->opt.bottom_up_min == 0) pb->opt.bottom_up_min = (int32_t)std::max<long long>(N / 128, 1024);
+  if (pb->opt.bottom_up_min < 0) pb->opt.bottom_up_min = 0;
   pb->P = P;
   pb->NB = (int32_t)NB;
   pb->N = (int32_t)N;
@@ -293,8 +314,12 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
   add(N * 4ull);              // d
   add(N * 4ull);              // x
   add(N * 4ull);              // stamp
-  add(4ull * N * 4ull);       // frontier lists
-  add(N * 8ull);              // left
+  add(2ull * (V + 2ull * E + N) * 4ull);  // frontier lists, two parities
+  add(N * 4ull);              // cand
+  add(N * 4ull);              // dx[0]
+  add(N * 4ull);              // dx[1]
+  add(((N + 31) / 32) * 4ull); // big-node bitmap
+  add(N);                     // seen bytes
   add(sizeof(Ctl));           // ctl
   add(64);                    // scratch for the weight sum
   he = hipMalloc(&pb->pool, bytes);
@@ -325,12 +350,21 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
   g.d = c.take<int32_t>(N);
   g.x = c.take<int32_t>(N);
   g.stamp = c.take<int32_t>(N);
-  int32_t* lists = c.take<int32_t>(4ull * N);
-  g.list[0][0] = lists;
-  g.list[0][1] = lists + N;
-  g.list[1][0] = lists + 2 * N;
-  g.list[1][1] = lists + 3 * N;
-  g.left = c.take<int2>(N);
+  int32_t* lists = c.take<int32_t>(2ull * (V + 2ull * E + N));
+  for (int par = 0; par < 2; ++par) {
+    // capacities: small vertices V, small e_in E, small e_out E, big N
+    g.list[par][0] = lists;
+    g.list[par][1] = lists + V;
+    g.list[par][2] = lists + V + E;
+    g.list[par][3] = lists + V + 2ll * E;
+    lists += V + 2ll * E + N;
+  }
+  g.cand = c.take<int32_t>(N);
+  g.dx[0] = c.take<int32_t>(N);
+  g.dx[1] = c.take<int32_t>(N);
+  uint32_t* bigbits = c.take<uint32_t>((N + 31) / 32);
+  g.bigbits = bigbits;
+  g.seen = c.take<uint8_t>(N);
   g.ctl = c.take<Ctl>(1);
   unsigned long long* wsum = c.take<unsigned long long>(1);
   g.net_off = net_off;
@@ -338,7 +372,6 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
   g.w = w;
   g.vtx_off = vtx_off;
   g.vinc = vinc;
-  g.tlist = terms + nS;
 
   const hipMemcpyKind kind = mem_kind == 0 ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
   he = hipMemcpyAsync(net_off, net_offsets, (E + 1) * 4ull, kind, s);
@@ -402,6 +435,7 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
   if (he != hipSuccess) return hip_fail(he, "building incidences");
   if (P) k_scatter<<<grid_for(P), 256, 0, s>>>(g, cursor);
   k_sort_incidences<<<grid_for(V), 256, 0, s>>>(g);
+  k_bigbits<<<grid_for((N + 31) / 32), 256, 0, s>>>(g, bigbits);
   he = hipMemcpyAsync(&err, &g.ctl->err, 4, hipMemcpyDeviceToHost, s);
   if (he == hipSuccess) he = hipStreamSynchronize(s);
   if (he == hipSuccess) he = hipGetLastError();
@@ -432,7 +466,7 @@ __global__ void k_export(Dev g, int32_t* f_in, int32_t* f_out, int32_t* lab, int
     if (i < g.V + 2 * g.E) {
       const int src = i < g.V ? i : i - g.V + g.NB;
       lab[i] = g.d[src];
-      exc[i] = g.x[src];
+      exc[i] = g.x[src] + g.dx[0][src] + g.dx[1][src];
     }
   }
 }

@@ -6,8 +6,8 @@
 // never built.  Node ids:
 //   v            in [0, V)      hypernode
 //   NB + 2e                     e_in  of net e     (NB = V rounded up to even,
-//   NB + 2e + 1                 e_out of net e      so (e_in, e_out) labels and
-//                                                   excesses form an int2)
+//   NB + 2e + 1                 e_out of net e      so (e_in, e_out) labels form
+//                                                   an aligned int2)
 // Source and sink sets are contracted: a net with a source pin receives w(e)
 // units into e_in at initialisation (its contracted source arc, capped at
 // w(e)); sinks keep label 0 and absorb whatever is pushed into them.
@@ -22,14 +22,19 @@
 //   e_out -> u      infinite          e_out -> e_in   fb
 //
 // One discharge round (paper section "Synchronous Parallel Push-Relabel") is
-// split into two phases with a device-wide ordering point between them:
-//   push   every frontier node u with label k = d(u) < N and excess X pushes
-//          along arcs admissible under the round-start labels
-//          (residual > 0 and d(v) = k - 1) and distributes X over them in arc
-//          order; it records cand = 1 + min label over the arcs that stay
-//          residual after its own pushes.  Admissibility is antisymmetric in
-//          the labels, so each arc pair has a single writer per round and no
-//          winning criterion is needed.
+// two phases with an ordering point between them:
+//   push   every frontier node u first folds the excess it received in the
+//          previous round (dx[prev]) into x[u].  If its label k = d(u) < N it
+//          pushes along arcs admissible under the round-start labels
+//          (residual > 0 and d(v) = k - 1), distributing its excess over them
+//          in arc order; received amounts go to dx[cur][v] (the "excess
+//          differences aggregated in a second array" of the paper), so no
+//          node ever reads an excess that is still changing and rounds are
+//          deterministic.  A node left with excess records
+//          cand = 1 + min label over the arcs that stay residual after its own
+//          pushes.  Admissibility is antisymmetric in the labels, so each arc
+//          pair has a single writer per round and no winning criterion is
+//          needed.
 //   apply  a node left with excess is relabelled to
 //          min(cand, d(u) + 2 if something was pushed into u this round, N).
 //          Pushes into u come from nodes labelled d(u) + 1 and are the only
@@ -37,8 +42,10 @@
 //          (d(a) <= d(b) + 1 on every residual arc), which rules out the
 //          push-relabel conflict described in section "A Bug in the
 //          Synchronous Algorithm".
-// Frontier = nodes pushed into (deduplicated by a per-round stamp) plus nodes
-// relabelled below N, compacted with wave ballots (paragraph "Active Nodes").
+// Frontier of the next round = nodes pushed into (deduplicated by a
+// per-round stamp) plus nodes relabelled below N (paragraph "Active Nodes").
+// Appends are staged per wave in LDS and flushed with one global atomic per
+// batch.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -47,12 +54,13 @@ namespace hf {
 
 constexpr int kWave = 64;
 constexpr int kInf = 0x7fffffff;
+constexpr int kQCap = 128;  // LDS staging entries per wave and list
 
 // error bits reported through Ctl::err
 enum : int32_t {
-  ERR_LABEL = 1,        // a relabel did not raise the label
-  ERR_SINK_REACHED = 2, // forward cut BFS reached a sink
-  ERR_INVARIANT = 4,    // debug invariant check failed
+  ERR_LABEL = 1,         // a relabel did not raise the label
+  ERR_SINK_REACHED = 2,  // forward cut BFS reached a sink
+  ERR_INVARIANT = 4,     // debug invariant check failed
   ERR_BUILD_PIN = 16,
   ERR_BUILD_OFFSETS = 32,
   ERR_BUILD_WEIGHT = 64,
@@ -72,15 +80,20 @@ enum : int {
   KC_N = 8
 };
 
+// A frontier is four lists: small vertices, small e_in, small e_out (nodes
+// with at most big_deg arcs, processed by groups of G lanes) and big nodes of
+// any kind (processed by whole waves).  Splitting by kind keeps every wave
+// item on one code path.
+constexpr int kNL = 4;
+constexpr int kBigList = 3;
+
 struct Ctl {
-  int32_t fcnt[3][2];  // round frontier counts, ring by epoch % 3, [small, big]
-  int32_t lcnt[3];     // leftover (relabel) list counts, ring by epoch % 3
-  int32_t bcnt[3][2];  // BFS level counts, ring by level % 3
+  int32_t fcnt[3][kNL];  // round frontier counts, ring by epoch % 3
+  int32_t bcnt[3][kNL];  // BFS level counts, ring by level % 3
   int32_t err;
   int32_t loop_rounds;  // rounds run by the last single-workgroup round loop
   int32_t loop_levels;  // levels run by the last single-workgroup BFS loop
   int32_t loop_exit;
-  int32_t pad0;
   unsigned long long flow;      // flow value (into sinks)
   unsigned long long relabels;  // relabel operations
   unsigned long long bytes[KC_N];
@@ -96,14 +109,16 @@ struct Dev {
   const int2* vinc;        // P   {net, pin slot}, per vertex sorted by slot
   int32_t* role;           // V   0 free, 1 source, 2 sink
   int32_t* nflag;          // E   bit0 has a source pin, bit1 has a sink pin
-  int32_t* tlist;          // sinks (capacity V)
   int32_t* fpin;           // 2P  {r_in, f_out}
   int32_t* fb;             // E
   int32_t* d;              // N   labels
-  int32_t* x;              // N   excess
+  int32_t* x;              // N   excess (written by the node itself)
+  int32_t* dx[2];          // N   excess received in a round, by round parity
+  int32_t* cand;           // N   relabel candidate of a node left with excess, -1 = none
   int32_t* stamp;          // N
-  int32_t* list[2][2];     // [parity][small, big], capacity N each
-  int2* left;              // N   {node, cand}
+  const uint32_t* bigbits; // ceil(N/32) words: bit v set when node v has more than big_deg arcs
+  uint8_t* seen;           // N   reverse BFS: 1 once a node has a label (hint, see label_rev)
+  int32_t* list[2][kNL];   // [parity][list]: capacities V, E, E, N
   Ctl* ctl;
 };
 
@@ -112,17 +127,8 @@ struct Dev {
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
-
-// Aggregated append: every active lane calls it; lanes with pred get
-// consecutive slots from one atomic per wave.
-__device__ __forceinline__ int wave_append(int32_t* cnt, bool pred) {
-  const unsigned long long m = __ballot(pred);
-  if (m == 0ull) return 0;
-  const int leader = __builtin_ctzll(m);
-  int base = 0;
-  if (lane_id() == leader) base = atomicAdd(cnt, __popcll(m));
-  base = __shfl(base, leader);
-  return base + __popcll(m & ((1ull << lane_id()) - 1ull));
+__device__ __forceinline__ unsigned long long lanemask_lt() {
+  return (1ull << lane_id()) - 1ull;
 }
 
 // Sum over the wave, one atomic.  The whole wave must be active.
@@ -149,30 +155,181 @@ __device__ __forceinline__ int g_min(int v) {
   return v;
 }
 
-template <int G>
-__device__ __forceinline__ uint32_t g_sum(uint32_t v) {
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
-  return v;
-}
-
 __device__ __forceinline__ int deg_of(const Dev& g, int v) {
   if (v < g.V) return g.vtx_off[v + 1] - g.vtx_off[v];
   const int e = (v - g.NB) >> 1;
   return g.net_off[e + 1] - g.net_off[e] + 1;
 }
 
-// Append v (if pred) to the small or big list of a frontier.
-__device__ __forceinline__ void push_frontier(const Dev& g, int32_t* cnt2, int32_t* ls,
-                                              int32_t* lb, int v, bool pred) {
-  bool big = false;
-  if (pred) big = deg_of(g, v) > g.big_deg;
-  const int is = wave_append(&cnt2[0], pred && !big);
-  const int ib = wave_append(&cnt2[1], pred && big);
-  if (pred) {
-    if (big) lb[ib] = v;
-    else ls[is] = v;
+// ---------------------------------------------------------------------------
+// block-level LDS staging of list appends
+//
+// Appends to a global list reserve space with an atomic on one counter, and
+// same-address atomics serialise across the whole chip.  A workgroup
+// therefore stages its appends in LDS (wave-aggregated LDS atomics) and
+// reserves global space once per flush.  Flushes happen at block-uniform
+// points: when the staging area may not hold the next tile's appends, and at
+// the end of a phase.  A wave whose appends do not fit any more writes the
+// excess straight to the global list (one global atomic for that wave).
+// ---------------------------------------------------------------------------
+
+constexpr int kBCap = 4096;                    // staged entries per list and block
+constexpr int kBQWords = kNL * kBCap + 2 * kNL;  // LDS words of one block queue
+
+typedef __attribute__((address_space(3))) int32_t lds_int;
+
+struct BlockQ {
+  lds_int* buf;         // [kNL][kBCap]
+  lds_int* n;           // [kNL] staged counts (may exceed kBCap after overflow)
+  lds_int* base;        // [kNL] global base of the current flush
+  int32_t* gcnt;        // global counts [kNL]
+  int32_t* dst[kNL];    // global lists
+};
+
+__device__ __forceinline__ int lds_add(lds_int* p, int v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Block-uniform: every thread of the workgroup calls it.
+__device__ __forceinline__ BlockQ bq_bind(lds_int* lds, int32_t* gcnt, int32_t* const lists[kNL]) {
+  BlockQ q;
+  q.buf = lds;
+  q.n = lds + kNL * kBCap;
+  q.base = lds + kNL * kBCap + kNL;
+  q.gcnt = gcnt;
+#pragma unroll
+  for (int k = 0; k < kNL; ++k) q.dst[k] = lists[k];
+  __syncthreads();  // earlier users of the area are done with it
+  if (threadIdx.x < kNL) q.n[threadIdx.x] = 0;
+  __syncthreads();
+  return q;
+}
+
+// Called by all active lanes of a wave.
+__device__ __forceinline__ void bq_push1(const BlockQ& q, int k, int v, bool pred) {
+  const unsigned long long m = __ballot(pred);
+  if (m == 0ull) return;
+  const int cnt = __popcll(m);
+  const int leader = __builtin_ctzll(m);
+  int pos = 0;
+  if (lane_id() == leader) pos = lds_add(q.n + k, cnt);
+  pos = __shfl(pos, leader);
+  const int rank = __popcll(m & lanemask_lt());
+  const int room = max(0, kBCap - pos);
+  if (cnt <= room) {
+    if (pred) q.buf[k * kBCap + pos + rank] = v;
+    return;
   }
+  int gb = 0;
+  if (lane_id() == leader) gb = atomicAdd(&q.gcnt[k], cnt - room);
+  gb = __shfl(gb, leader);
+  if (pred) {
+    if (rank < room) q.buf[k * kBCap + pos + rank] = v;
+    else q.dst[k][gb + rank - room] = v;
+  }
+}
+
+__device__ __forceinline__ bool is_big(const Dev& g, int v) {
+  return (g.bigbits[v >> 5] >> (v & 31)) & 1u;
+}
+
+// list of a node: big nodes together, small ones by kind
+__device__ __forceinline__ int list_of(const Dev& g, int v) {
+  if (is_big(g, v)) return kBigList;
+  return v < g.V ? 0 : 1 + ((v - g.NB) & 1);
+}
+
+// Stage v (if pred) into its list.  Called by all active lanes.
+__device__ __forceinline__ void qpush(const Dev& g, const BlockQ& q, int v, bool pred) {
+  const int k = pred ? list_of(g, v) : -1;
+#pragma unroll
+  for (int j = 0; j < kNL; ++j) bq_push1(q, j, v, k == j);
+}
+
+// Block-uniform: move the staged entries to the global lists.
+__device__ __forceinline__ void bq_flush(const BlockQ& q) {
+  __syncthreads();
+  if (threadIdx.x < kNL) {
+    const int k = threadIdx.x;
+    const int c = min((int)q.n[k], kBCap);
+    q.base[k] = c ? atomicAdd(&q.gcnt[k], c) : 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kNL; ++k) {
+    const int c = min((int)q.n[k], kBCap);
+    const int b = q.base[k];
+    for (int i = threadIdx.x; i < c; i += blockDim.x) q.dst[k][b + i] = q.buf[k * kBCap + i];
+  }
+  __syncthreads();
+  if (threadIdx.x < kNL) q.n[threadIdx.x] = 0;
+  __syncthreads();
+}
+
+// Block-uniform: flush unless `reserve` more entries per list still fit.
+__device__ __forceinline__ void bq_tile_end(const BlockQ& q, int reserve) {
+  __syncthreads();
+  int mx = 0;
+#pragma unroll
+  for (int k = 0; k < kNL; ++k) mx = max(mx, (int)q.n[k]);
+  __syncthreads();  // every thread has read the counts before anyone appends
+  if (mx > kBCap - reserve) bq_flush(q);
+}
+
+// Four values selected by a runtime index without a local array (which would
+// live in scratch memory).
+struct Quad {
+  int v0, v1, v2, v3;
+  __device__ __forceinline__ int operator[](int k) const {
+    return k == 0 ? v0 : (k == 1 ? v1 : (k == 2 ? v2 : v3));
+  }
+};
+
+__device__ __forceinline__ Quad load_counts(const int32_t* c) {
+  return Quad{c[0], c[1], c[2], c[3]};
+}
+
+// Exclusive prefix of four counts: start of each list in the concatenation
+// and the total.
+struct Prefix4 {
+  Quad start;
+  int total;
+  __device__ __forceinline__ explicit Prefix4(const Quad& n) {
+    start = Quad{0, n.v0, n.v0 + n.v1, n.v0 + n.v1 + n.v2};
+    total = start.v3 + n.v3;
+  }
+  // list holding concatenated index i
+  __device__ __forceinline__ int list_of(int i) const {
+    return (i >= start.v1) + (i >= start.v2) + (i >= start.v3);
+  }
+};
+
+// Item layout of a frontier or BFS level: for each small list, groups of G
+// lanes take one node each (64/G nodes per wave item); then one big node per
+// wave item.
+template <int G>
+struct Items {
+  Quad n;
+  Quad start;  // first item of each list
+  int end;
+  __device__ __forceinline__ explicit Items(const int32_t* cnt) {
+    constexpr int NPW = kWave / G;
+    n = load_counts(cnt);
+    const int i0 = (n.v0 + NPW - 1) / NPW, i1 = (n.v1 + NPW - 1) / NPW,
+              i2 = (n.v2 + NPW - 1) / NPW;
+    start = Quad{0, i0, i0 + i1, i0 + i1 + i2};
+    end = start.v3 + n.v3;
+  }
+  __device__ __forceinline__ int total() const { return end; }
+  __device__ __forceinline__ int list_of_item(int it) const {
+    return (it >= start.v1) + (it >= start.v2) + (it >= start.v3);
+  }
+};
+
+// Node i of a frontier given as kNL lists with prefix p.
+__device__ __forceinline__ int frontier_node(const Dev& g, int par, const Prefix4& p, int i) {
+  const int k = p.list_of(i);
+  return g.list[par][k][i - p.start[k]];
 }
 
 // Round-scoped stamp: true for exactly one caller per (v, epoch).
@@ -182,10 +339,11 @@ __device__ __forceinline__ bool stamp_first(const Dev& g, int v, int epoch) {
 }
 
 struct RoundArgs {
-  int epoch;   // unique id of this round
-  int cur3;    // epoch % 3
-  int nxt3;    // (epoch + 1) % 3
-  int nxtp;    // (epoch + 1) % 2
+  int epoch;  // unique id of this round
+  int cur3;   // epoch % 3
+  int nxt3;   // (epoch + 1) % 3
+  int cur;    // epoch % 2: list parity of this round, dx buffer written
+  int nxt;    // (epoch + 1) % 2
 };
 
 __device__ __forceinline__ RoundArgs round_args(int epoch) {
@@ -193,27 +351,48 @@ __device__ __forceinline__ RoundArgs round_args(int epoch) {
   a.epoch = epoch;
   a.cur3 = epoch % 3;
   a.nxt3 = (epoch + 1) % 3;
-  a.nxtp = (epoch + 1) & 1;
+  a.cur = epoch & 1;
+  a.nxt = a.cur ^ 1;
   return a;
 }
 
-__device__ __forceinline__ void mark_pushed(const Dev& g, const RoundArgs& ra, int v, bool pred) {
-  bool fresh = false;
-  if (pred) fresh = stamp_first(g, v, ra.epoch);
-  push_frontier(g, g.ctl->fcnt[ra.nxt3], g.list[ra.nxtp][0], g.list[ra.nxtp][1], v, fresh);
+__device__ __forceinline__ BlockQ round_queue(const Dev& g, const RoundArgs& ra, lds_int* lds) {
+  return bq_bind(lds, g.ctl->fcnt[ra.nxt3], g.list[ra.nxt]);
 }
 
-// End of a node's push scan: give up the pushed excess; a node left with
-// excess goes to the relabel list with its candidate label.
+// push received by v: amount into dx[cur][v] and v into the next frontier
+__device__ __forceinline__ void deliver(const Dev& g, const RoundArgs& ra, const BlockQ& q, int v,
+                                        uint32_t amount) {
+  bool fresh = false;
+  if (amount) {
+    atomicAdd(&g.dx[ra.cur][v], (int)amount);
+    fresh = stamp_first(g, v, ra.epoch);
+  }
+  qpush(g, q, v, fresh);
+}
+
+// Excess at the start of the round: x plus what arrived last round.
+__device__ __forceinline__ int take_excess(const Dev& g, const RoundArgs& ra, int u, int gl) {
+  const int xv = g.x[u];
+  const int dv = g.dx[ra.nxt][u];  // previous round's buffer (parity of epoch - 1)
+  const int X = xv + dv;
+  if (dv != 0 && gl == 0) {
+    g.x[u] = X;
+    g.dx[ra.nxt][u] = 0;
+  }
+  return X;
+}
+
+// End of a node's push scan.
 template <int G>
-__device__ __forceinline__ void finish_push(const Dev& g, const RoundArgs& ra, int u,
-                                            uint32_t X, uint32_t pushed, int cand, int gl,
-                                            bool active) {
-  if (active && gl == 0 && pushed > 0u) atomicSub(&g.x[u], (int)pushed);
+__device__ __forceinline__ void finish_push(const Dev& g, int u, uint32_t X, uint32_t pushed,
+                                            int cand, int gl, bool active) {
+  if (active && gl == 0 && pushed > 0u) g.x[u] = (int)(X - pushed);
   const bool left = active && pushed < X;
-  if (left) cand = g_min<G>(cand);
-  const int slot = wave_append(&g.ctl->lcnt[ra.cur3], left && gl == 0);
-  if (left && gl == 0) g.left[slot] = make_int2(u, cand);
+  if (left) {
+    cand = g_min<G>(cand);
+    if (gl == 0) g.cand[u] = cand;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -221,21 +400,21 @@ __device__ __forceinline__ void finish_push(const Dev& g, const RoundArgs& ra, i
 // ---------------------------------------------------------------------------
 
 template <int G>
-__device__ void push_vertex(const Dev& g, const RoundArgs& ra, int u, bool has, int gl,
-                            uint32_t& nbytes) {
+__device__ void push_vertex(const Dev& g, const RoundArgs& ra, const BlockQ& q, int u, bool has,
+                            int gl, uint32_t& nbytes) {
   int k = 0, X = 0, beg = 0, end = 0;
   if (has) {
     k = g.d[u];
-    X = g.x[u];
+    X = take_excess(g, ra, u, gl);
     beg = g.vtx_off[u];
     end = g.vtx_off[u + 1];
+    nbytes += 20;
   }
   const bool active = has && k < g.N && X > 0;
   const uint32_t UX = active ? (uint32_t)X : 0u;
   uint32_t carry = 0;
   int cand = kInf;
   if (active) {
-    nbytes += 16;
     for (int base = beg; base < end; base += G) {
       const int i = base + gl;
       const bool valid = i < end;
@@ -260,16 +439,10 @@ __device__ void push_vertex(const Dev& g, const RoundArgs& ra, int u, bool has, 
       const uint32_t give = min(want, UX - used);
       const uint32_t g1 = a1 ? min(give, r1) : 0u;
       const uint32_t g2 = give - g1;
-      if (g1) {
-        g.fpin[2 * p] = (int)(r1 - g1);
-        atomicAdd(&g.x[g.NB + 2 * e], (int)g1);
-      }
-      if (g2) {
-        g.fpin[2 * p + 1] = (int)(r2 - g2);
-        atomicAdd(&g.x[g.NB + 2 * e + 1], (int)g2);
-      }
-      mark_pushed(g, ra, g.NB + 2 * e, g1 > 0u);
-      mark_pushed(g, ra, g.NB + 2 * e + 1, g2 > 0u);
+      if (g1) g.fpin[2 * p] = (int)(r1 - g1);
+      if (g2) g.fpin[2 * p + 1] = (int)(r2 - g2);
+      deliver(g, ra, q, g.NB + 2 * e, g1);
+      deliver(g, ra, q, g.NB + 2 * e + 1, g2);
       if (valid) {
         if (r1 > g1) cand = min(cand, dl.x + 1);
         if (r2 > g2) cand = min(cand, dl.y + 1);
@@ -278,17 +451,18 @@ __device__ void push_vertex(const Dev& g, const RoundArgs& ra, int u, bool has, 
       if (carry >= UX) break;
     }
   }
-  finish_push<G>(g, ra, u, UX, carry, cand, gl, active);
+  finish_push<G>(g, u, UX, carry, cand, gl, active);
 }
 
 template <int G>
-__device__ void push_ein(const Dev& g, const RoundArgs& ra, int node, bool has, int gl,
-                         uint32_t& nbytes) {
+__device__ void push_ein(const Dev& g, const RoundArgs& ra, const BlockQ& q, int node, bool has,
+                         int gl, uint32_t& nbytes) {
   const int e = (node - g.NB) >> 1;
   int k = 0, X = 0;
   if (has) {
     k = g.d[node];
-    X = g.x[node];
+    X = take_excess(g, ra, node, gl);
+    nbytes += 12;
   }
   const bool active = has && k < g.N && X > 0;
   const uint32_t UX = active ? (uint32_t)X : 0u;
@@ -298,15 +472,12 @@ __device__ void push_ein(const Dev& g, const RoundArgs& ra, int node, bool has, 
     const int we = g.w[e];
     const int fbv = g.fb[e];
     const int dout = g.d[node + 1];
-    nbytes += 32;
+    nbytes += 20;
     const uint32_t rb = (uint32_t)(we - fbv);
     const bool ab = rb > 0u && dout == k - 1;
     const uint32_t gb = ab ? min(rb, UX) : 0u;
-    if (gb && gl == 0) {
-      g.fb[e] = fbv + (int)gb;
-      atomicAdd(&g.x[node + 1], (int)gb);
-    }
-    mark_pushed(g, ra, node + 1, gb > 0u && gl == 0);
+    if (gb && gl == 0) g.fb[e] = fbv + (int)gb;
+    deliver(g, ra, q, node + 1, gl == 0 ? gb : 0u);
     carry = gb;
     if (rb > gb) cand = dout + 1;
     if (carry < UX) {
@@ -329,36 +500,34 @@ __device__ void push_ein(const Dev& g, const RoundArgs& ra, int node, bool has, 
         if (gl == 0) excl = 0u;
         const uint32_t used = min(carry + excl, UX);
         const uint32_t give = min(want, UX - used);
-        if (give) {
-          g.fpin[2 * i] = rin + (int)give;
-          atomicAdd(&g.x[u], (int)give);
-        }
-        mark_pushed(g, ra, u, give > 0u);
+        if (give) g.fpin[2 * i] = rin + (int)give;
+        deliver(g, ra, q, u, give);
         if (valid && r > give) cand = min(cand, du + 1);
         carry = min(carry + __shfl(incl, G - 1, G), UX);
         if (carry >= UX) break;
       }
     }
   }
-  finish_push<G>(g, ra, node, UX, carry, cand, gl, active);
+  finish_push<G>(g, node, UX, carry, cand, gl, active);
 }
 
 template <int G>
-__device__ void push_eout(const Dev& g, const RoundArgs& ra, int node, bool has, int gl,
-                          uint32_t& nbytes, unsigned long long& to_sink) {
+__device__ void push_eout(const Dev& g, const RoundArgs& ra, const BlockQ& q, int node, bool has,
+                          int gl, uint32_t& nbytes, unsigned long long& to_sink) {
   const int e = (node - g.NB) >> 1;
   int k = 0, X = 0;
   if (has) {
     k = g.d[node];
-    X = g.x[node];
+    X = take_excess(g, ra, node, gl);
+    nbytes += 12;
   }
   const bool active = has && k < g.N && X > 0;
   const uint32_t UX = active ? (uint32_t)X : 0u;
   uint32_t carry = 0;
   int cand = kInf;
   if (active) {
-    nbytes += 16;
     const int beg = g.net_off[e], end = g.net_off[e + 1];
+    nbytes += 8;
     // pins first: the arcs e_out -> u are infinite, so the first admissible
     // pin takes all remaining excess
     for (int base = beg; base < end; base += G) {
@@ -381,9 +550,8 @@ __device__ void push_eout(const Dev& g, const RoundArgs& ra, int node, bool has,
         g.fpin[2 * i + 1] += (int)give;
         nbytes += 8;
         if (du == 0) to_sink += give;  // only sinks carry label 0
-        else atomicAdd(&g.x[u], (int)give);
       }
-      mark_pushed(g, ra, u, give > 0u && du != 0);
+      deliver(g, ra, q, u, du != 0 ? give : 0u);
       if (valid) cand = min(cand, du + 1);
       carry = min(carry + __shfl(incl, G - 1, G), UX);
       if (carry >= UX) break;
@@ -394,98 +562,108 @@ __device__ void push_eout(const Dev& g, const RoundArgs& ra, int node, bool has,
       nbytes += 8;
       const bool ab = rb > 0 && din == k - 1;
       const uint32_t gb = ab ? min((uint32_t)rb, UX - carry) : 0u;
-      if (gb && gl == 0) {
-        g.fb[e] = rb - (int)gb;
-        atomicAdd(&g.x[node - 1], (int)gb);
-      }
-      mark_pushed(g, ra, node - 1, gb > 0u && gl == 0);
+      if (gb && gl == 0) g.fb[e] = rb - (int)gb;
+      deliver(g, ra, q, node - 1, gl == 0 ? gb : 0u);
       carry += gb;
       if ((uint32_t)rb > gb) cand = min(cand, din + 1);
     }
   }
-  finish_push<G>(g, ra, node, UX, carry, cand, gl, active);
+  finish_push<G>(g, node, UX, carry, cand, gl, active);
 }
 
 template <int G>
-__device__ __forceinline__ void push_node(const Dev& g, const RoundArgs& ra, int v, bool has,
-                                          int gl, uint32_t& nbytes,
+__device__ __forceinline__ void push_node(const Dev& g, const RoundArgs& ra, const BlockQ& q, int v,
+                                          bool has, int gl, uint32_t& nbytes,
                                           unsigned long long& to_sink) {
   // kind is wave-divergent only across groups; each branch is group-uniform
-  if (!has || v < g.V) push_vertex<G>(g, ra, v, has, gl, nbytes);
-  else if (((v - g.NB) & 1) == 0) push_ein<G>(g, ra, v, has, gl, nbytes);
-  else push_eout<G>(g, ra, v, has, gl, nbytes, to_sink);
+  if (!has || v < g.V) push_vertex<G>(g, ra, q, v, has, gl, nbytes);
+  else if (((v - g.NB) & 1) == 0) push_ein<G>(g, ra, q, v, has, gl, nbytes);
+  else push_eout<G>(g, ra, q, v, has, gl, nbytes, to_sink);
 }
 
 // Work items of a frontier: small nodes in groups of G lanes (64/G nodes per
-// wave item), then big nodes one per wave item.
+// wave item), then big nodes one per wave item.  A workgroup takes tiles of
+// one item per wave (block-uniform loop, so the staging area can be flushed
+// between tiles).
 template <int G>
-__device__ void phase_push(const Dev& g, int epoch, int w0, int wstride, int kc) {
+__device__ void phase_push(const Dev& g, int epoch, int tile0, int tstride, int kc, lds_int* lds) {
   const RoundArgs ra = round_args(epoch);
-  if (w0 == 0 && lane_id() == 0) {
-    // ring slots no one reads in this round: next round's append targets
-    g.ctl->fcnt[(epoch + 2) % 3][0] = 0;
-    g.ctl->fcnt[(epoch + 2) % 3][1] = 0;
-    g.ctl->lcnt[ra.nxt3] = 0;
+  if (tile0 == 0 && threadIdx.x < kNL) {
+    // ring slot that nobody reads this round: the next round's append target
+    g.ctl->fcnt[(epoch + 2) % 3][threadIdx.x] = 0;
   }
-  const int ns = g.ctl->fcnt[ra.cur3][0];
-  const int nb = g.ctl->fcnt[ra.cur3][1];
-  const int cur = epoch & 1;
-  const int32_t* ls = g.list[cur][0];
-  const int32_t* lb = g.list[cur][1];
+  const BlockQ q = round_queue(g, ra, lds);
+  const Items<G> its(g.ctl->fcnt[ra.cur3]);
   constexpr int NPW = kWave / G;
-  const int nsi = (ns + NPW - 1) / NPW;
-  const int total = nsi + nb;
+  const int total = its.total();
+  const int wpb = blockDim.x >> 6, wid = threadIdx.x >> 6;
+  const int ntiles = (total + wpb - 1) / wpb;
   const int lane = lane_id();
   uint32_t nbytes = 0;
   uint32_t nitems = 0;
   unsigned long long to_sink = 0;
-  for (int it = w0; it < total; it += wstride) {
-    if (it < nsi) {
-      const int idx = it * NPW + lane / G;
-      const bool has = idx < ns;
-      const int v = has ? ls[idx] : 0;
-      nitems += has && (lane % G) == 0;
-      push_node<G>(g, ra, v, has, lane % G, nbytes, to_sink);
-    } else {
-      const int v = lb[it - nsi];
-      nitems += lane == 0;
-      push_node<kWave>(g, ra, v, true, lane, nbytes, to_sink);
+  for (int tile = tile0; tile < ntiles; tile += tstride) {
+    const int it = tile * wpb + wid;
+    if (it < total) {
+      const int k = its.list_of_item(it);
+      if (k < kBigList) {
+        const int idx = (it - its.start[k]) * NPW + lane / G;
+        const bool has = idx < its.n[k];
+        const int v = has ? g.list[ra.cur][k][idx] : 0;
+        nitems += has && (lane % G) == 0;
+        if (k == 0) push_vertex<G>(g, ra, q, v, has, lane % G, nbytes);
+        else if (k == 1) push_ein<G>(g, ra, q, v, has, lane % G, nbytes);
+        else push_eout<G>(g, ra, q, v, has, lane % G, nbytes, to_sink);
+      } else {
+        const int v = g.list[ra.cur][kBigList][it - its.start[kBigList]];
+        nitems += lane == 0;
+        push_node<kWave>(g, ra, q, v, true, lane, nbytes, to_sink);
+      }
     }
+    bq_tile_end(q, kBCap / 2);
   }
+  bq_flush(q);
   wave_add_u64(&g.ctl->flow, to_sink);
   wave_add_u64(&g.ctl->bytes[kc], (unsigned long long)nbytes + 4ull * nitems);
   wave_add_u64(&g.ctl->items[kc], nitems);
 }
 
-// Apply phase: relabel nodes left with excess; thread per entry.
-__device__ void phase_apply(const Dev& g, int epoch, int t0, int tstride, int kc) {
+// Apply phase over the same frontier: relabel nodes left with excess; thread
+// per node, small list then big list, tiles of one node per thread.
+__device__ void phase_apply(const Dev& g, int epoch, int tile0, int tstride, int kc, lds_int* lds) {
   const RoundArgs ra = round_args(epoch);
-  const int n = g.ctl->lcnt[ra.cur3];
+  const BlockQ q = round_queue(g, ra, lds);
+  const Prefix4 pre(load_counts(g.ctl->fcnt[ra.cur3]));
+  const int n = pre.total;
+  const int ntiles = (n + blockDim.x - 1) / blockDim.x;
   unsigned long long nrel = 0;
   uint32_t nbytes = 0;
-  // t0 is wave-aligned and tstride a multiple of 64, so lanes of a wave run
-  // the same iterations (needed by the ballots in push_frontier)
-  for (int base = t0 - lane_id(); base < n; base += tstride) {
-    const int i = base + lane_id();
-    const bool has = i < n;
-    int v = 0;
+  for (int tile = tile0; tile < ntiles; tile += tstride) {
+    const int i = tile * blockDim.x + threadIdx.x;
     bool app = false;
-    if (has) {
-      const int2 en = g.left[i];
-      v = en.x;
-      const int k = g.d[v];
-      const bool rec = g.stamp[v] == ra.epoch;
-      int nd = en.y;
-      if (rec) nd = min(nd, k + 2);
-      nd = min(nd, g.N);
-      if (nd <= k) atomicOr(&g.ctl->err, ERR_LABEL);
-      g.d[v] = nd;
-      nrel += 1;
-      nbytes += 20;
-      app = !rec && nd < g.N;
+    int v = 0;
+    if (i < n) {
+      v = frontier_node(g, ra.cur, pre, i);
+      const int c = g.cand[v];
+      nbytes += 8;
+      if (c >= 0) {
+        g.cand[v] = -1;
+        const int k = g.d[v];
+        const bool rec = g.stamp[v] == ra.epoch;
+        int nd = c;
+        if (rec) nd = min(nd, k + 2);
+        nd = min(nd, g.N);
+        if (nd <= k) atomicOr(&g.ctl->err, ERR_LABEL);
+        g.d[v] = nd;
+        nrel += 1;
+        nbytes += 12;
+        app = !rec && nd < g.N;
+      }
     }
-    push_frontier(g, g.ctl->fcnt[ra.nxt3], g.list[ra.nxtp][0], g.list[ra.nxtp][1], v, app);
+    qpush(g, q, v, app);
+    bq_tile_end(q, (int)blockDim.x);
   }
+  bq_flush(q);
   wave_add_u64(&g.ctl->relabels, nrel);
   wave_add_u64(&g.ctl->bytes[kc], nbytes);
   wave_add_u64(&g.ctl->items[kc], nrel);
@@ -495,106 +673,291 @@ __device__ void phase_apply(const Dev& g, int epoch, int t0, int tstride, int kc
 // reverse residual BFS from the sinks (global relabel) over the capped network
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ bool visit_rev(const Dev& g, int v, int lvl) {
-  if (g.d[v] != g.N) return false;
-  return atomicCAS(&g.d[v], g.N, lvl) == g.N;
+// Label v with lvl if it is unlabelled.  `seen` mirrors "labelled" in a
+// byte map small enough to stay in L2, so the common case (already labelled)
+// costs no label load; a stale 0 only repeats an identical store.  With
+// kClaim the first writer wins by compare-and-swap on the label and reports
+// it; otherwise a plain store (all writers store the same value).
+template <bool kClaim>
+__device__ __forceinline__ bool label_rev(const Dev& g, int v, int lvl) {
+  if (g.seen[v]) return false;
+  if (!kClaim) {
+    g.d[v] = lvl;
+    g.seen[v] = 1;
+    return false;
+  }
+  if (atomicCAS(&g.d[v], g.N, lvl) != g.N) return false;
+  g.seen[v] = 1;
+  return true;
 }
 
-template <int G>
-__device__ void bfs_rev_node(const Dev& g, int x, bool has, int gl, int lvl, int32_t* cnt2,
-                             int32_t* ls, int32_t* lb, uint32_t& nbytes) {
-  // lvl = label to give to newly reached nodes
-  const bool isv = has && x < g.V;
-  const bool isnet = has && x >= g.NB;
-  if (!has || isv) {
-    int beg = 0, end = 0;
-    if (isv) {
-      beg = g.vtx_off[x];
-      end = g.vtx_off[x + 1];
+// ---------------------------------------------------------------------------
+// arc-parallel BFS levels
+//
+// A workgroup takes a tile of up to blockDim frontier nodes, computes their
+// arc counts and an exclusive prefix sum in LDS, and then every thread takes
+// one arc per step (locating its node by binary search in the prefix), so
+// all loads of a step are independent and nodes of any degree are spread
+// over the whole workgroup.  Arc 0 of a net node is its bridge.
+// ---------------------------------------------------------------------------
+
+constexpr int kMaxBlock = 1024;
+constexpr int kTileWords = 3 * kMaxBlock + 1 + 32;  // node, beg, off[+1], wave sums
+
+struct ArcTile {
+  lds_int* node;
+  lds_int* beg;
+  lds_int* off;
+  lds_int* wsum;
+};
+
+__device__ __forceinline__ ArcTile arc_tile(lds_int* lds) {
+  ArcTile t;
+  t.node = lds;
+  t.beg = lds + kMaxBlock;
+  t.off = lds + 2 * kMaxBlock;
+  t.wsum = lds + 3 * kMaxBlock + 1;
+  return t;
+}
+
+// Block-uniform exclusive prefix sum of one int per thread; returns the
+// thread's offset, *total gets the sum (same in every thread).
+__device__ __forceinline__ int block_excl_scan(int v, lds_int* wsum, int* total) {
+  const int lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int incl = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int t = __shfl_up(incl, o);
+    if (lane >= o) incl += t;
+  }
+  __syncthreads();  // wsum is free (previous readers are done)
+  if (lane == kWave - 1) wsum[wid] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int i = 0; i < nw; ++i) {
+      const int t = wsum[i];
+      wsum[i] = run;
+      run += t;
     }
-    for (int base = beg; base < end; base += G) {
-      const int i = base + gl;
-      const bool valid = i < end;
-      bool vin = false, vout = false;
-      int e = 0;
-      if (valid) {
-        const int2 ep = g.vinc[i];
-        e = ep.x;
-        const int2 dl = *reinterpret_cast<const int2*>(g.d + g.NB + 2 * e);
-        nbytes += 16;
-        if (dl.y == g.N) vout = atomicCAS(&g.d[g.NB + 2 * e + 1], g.N, lvl) == g.N;
-        if (dl.x == g.N) {
-          const int rin = g.fpin[2 * ep.y];
-          const int we = g.w[e];
-          nbytes += 8;
-          if (we - rin > 0) vin = atomicCAS(&g.d[g.NB + 2 * e], g.N, lvl) == g.N;
+    wsum[nw] = run;
+  }
+  __syncthreads();
+  *total = wsum[nw];
+  return wsum[wid] + incl - v;
+}
+
+// Block-uniform: load tile `tile` of the frontier into LDS; returns the arc
+// count of the tile and the node count in *nt_out.
+__device__ __forceinline__ int load_arc_tile(const Dev& g, const ArcTile& t, int par,
+                                             const Prefix4& pre, int tile, int* nt_out) {
+  const int nf = pre.total;
+  const int first = tile * blockDim.x;
+  const int nt = min((int)blockDim.x, nf - first);
+  int deg = 0, beg = 0, v = 0;
+  if ((int)threadIdx.x < nt) {
+    v = frontier_node(g, par, pre, first + threadIdx.x);
+    if (v < g.V) {
+      beg = g.vtx_off[v];
+      deg = g.vtx_off[v + 1] - beg;
+    } else {
+      const int e = (v - g.NB) >> 1;
+      beg = g.net_off[e];
+      deg = g.net_off[e + 1] - beg + 1;
+    }
+  }
+  int total = 0;
+  const int o = block_excl_scan(deg, t.wsum, &total);
+  if ((int)threadIdx.x < nt) {
+    t.node[threadIdx.x] = v;
+    t.beg[threadIdx.x] = beg;
+    t.off[threadIdx.x] = o;
+  }
+  if (threadIdx.x == 0) t.off[nt] = total;
+  __syncthreads();
+  *nt_out = nt;
+  return total;
+}
+
+// index k of the tile node owning arc a: largest k with off[k] <= a
+__device__ __forceinline__ int arc_owner(const ArcTile& t, int nt, int a) {
+  int lo = 0, hi = nt;  // off[lo] <= a < off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (t.off[mid] <= a) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// One level of the reverse BFS (labels level+1), arc-parallel.
+template <bool kClaim>
+__device__ void phase_bfs_rev_lb(const Dev& g, int level, int tile0, int tstride, int kc,
+                                 lds_int* lds) {
+  const int c3 = level % 3, n3 = (level + 1) % 3, z3 = (level + 2) % 3;
+  if (tile0 == 0 && threadIdx.x < kNL) g.ctl->bcnt[z3][threadIdx.x] = 0;
+  const int cp = level & 1, np = (level + 1) & 1;
+  const BlockQ q = bq_bind(lds, g.ctl->bcnt[n3], g.list[np]);
+  const ArcTile t = arc_tile(lds + kBQWords);
+  const Prefix4 pre(load_counts(g.ctl->bcnt[c3]));
+  const int ntiles = (pre.total + blockDim.x - 1) / blockDim.x;
+  const int lvl = level + 1;
+  uint32_t nbytes = 0, narcs = 0;
+  for (int tile = tile0; tile < ntiles; tile += tstride) {
+    int nt = 0;
+    const int A = load_arc_tile(g, t, cp, pre, tile, &nt);
+    for (int a0 = 0; a0 < A; a0 += blockDim.x) {
+      const int a = a0 + threadIdx.x;
+      int t1 = 0, t2 = 0;
+      bool v1 = false, v2 = false;
+      if (a < A) {
+        const int k = arc_owner(t, nt, a);
+        const int x = t.node[k];
+        const int j = a - t.off[k];
+        const int b = t.beg[k];
+        ++narcs;
+        if (x < g.V) {
+          const int2 ep = g.vinc[b + j];
+          const int e = ep.x;
+          t1 = g.NB + 2 * e;
+          t2 = t1 + 1;
+          const uint16_t sb = *reinterpret_cast<const uint16_t*>(g.seen + t1);
+          nbytes += 10;
+          if (!(sb >> 8)) v2 = label_rev<kClaim>(g, t2, lvl);  // e_out -> x infinite
+          if (!(sb & 0xff) && g.w[e] - g.fpin[2 * ep.y] > 0)   // e_in -> x reverse
+            v1 = label_rev<kClaim>(g, t1, lvl);
+        } else {
+          const int e = (x - g.NB) >> 1;
+          const bool in = ((x - g.NB) & 1) == 0;
+          if (j == 0) {  // bridge
+            const int fbv = g.fb[e];
+            nbytes += 8;
+            t1 = in ? x + 1 : x - 1;
+            if (in ? fbv > 0 : g.w[e] - fbv > 0) v1 = label_rev<kClaim>(g, t1, lvl);
+          } else {
+            const int i = b + j - 1;
+            t1 = g.pin_v[i];
+            const int f = g.fpin[2 * i + (in ? 0 : 1)];  // r_in (u->e_in) or f_out (u->e_out)
+            nbytes += 9;
+            if (f > 0) v1 = label_rev<kClaim>(g, t1, lvl);
+          }
         }
       }
-      push_frontier(g, cnt2, ls, lb, g.NB + 2 * e, vin);
-      push_frontier(g, cnt2, ls, lb, g.NB + 2 * e + 1, vout);
-    }
-  } else if (isnet) {
-    const int e = (x - g.NB) >> 1;
-    const bool in = ((x - g.NB) & 1) == 0;
-    const int beg = g.net_off[e], end = g.net_off[e + 1];
-    const int we = g.w[e];
-    const int fbv = g.fb[e];
-    nbytes += 16;
-    bool vb = false;
-    if (gl == 0) {
-      if (in) vb = fbv > 0 && visit_rev(g, x + 1, lvl);       // e_out -> e_in residual fb
-      else vb = we - fbv > 0 && visit_rev(g, x - 1, lvl);     // e_in -> e_out residual w - fb
-    }
-    push_frontier(g, cnt2, ls, lb, in ? x + 1 : x - 1, vb);
-    for (int base = beg; base < end; base += G) {
-      const int i = base + gl;
-      const bool valid = i < end;
-      bool vu = false;
-      int u = 0;
-      if (valid) {
-        u = g.pin_v[i];
-        const int f = g.fpin[2 * i + (in ? 0 : 1)];  // r_in (u->e_in) or f_out (u->e_out)
-        nbytes += 12;
-        if (f > 0) vu = visit_rev(g, u, lvl);
+      if (kClaim) {
+        qpush(g, q, t1, v1);
+        qpush(g, q, t2, v2);
+        bq_tile_end(q, 2 * blockDim.x);
       }
-      push_frontier(g, cnt2, ls, lb, u, vu);
     }
+    __syncthreads();  // the tile area is rewritten by the next tile
   }
+  if (kClaim) bq_flush(q);
+  wave_add_u64(&g.ctl->bytes[kc], (unsigned long long)nbytes + 12ull * narcs);
+  wave_add_u64(&g.ctl->items[kc], narcs);
+}
+
+// One level of the forward BFS of the uncapped network, arc-parallel.
+__device__ void phase_bfs_fwd_lb(const Dev& g, int level, int ep, int tile0, int tstride, int kc,
+                                 lds_int* lds) {
+  const int c3 = level % 3, n3 = (level + 1) % 3, z3 = (level + 2) % 3;
+  if (tile0 == 0 && threadIdx.x < kNL) g.ctl->bcnt[z3][threadIdx.x] = 0;
+  const int cp = level & 1, np = (level + 1) & 1;
+  const BlockQ q = bq_bind(lds, g.ctl->bcnt[n3], g.list[np]);
+  const ArcTile t = arc_tile(lds + kBQWords);
+  const Prefix4 pre(load_counts(g.ctl->bcnt[c3]));
+  const int ntiles = (pre.total + blockDim.x - 1) / blockDim.x;
+  uint32_t nbytes = 0, narcs = 0;
+  for (int tile = tile0; tile < ntiles; tile += tstride) {
+    int nt = 0;
+    const int A = load_arc_tile(g, t, cp, pre, tile, &nt);
+    for (int a0 = 0; a0 < A; a0 += blockDim.x) {
+      const int a = a0 + threadIdx.x;
+      int t1 = 0, t2 = 0;
+      bool v1 = false, v2 = false;
+      if (a < A) {
+        const int k = arc_owner(t, nt, a);
+        const int x = t.node[k];
+        const int j = a - t.off[k];
+        const int b = t.beg[k];
+        ++narcs;
+        if (x < g.V) {
+          const int2 ep2 = g.vinc[b + j];
+          t1 = g.NB + 2 * ep2.x;
+          t2 = t1 + 1;
+          nbytes += 12;
+          v1 = stamp_first(g, t1, ep);                                 // x -> e_in (uncapped)
+          if (g.fpin[2 * ep2.y + 1] > 0) v2 = stamp_first(g, t2, ep);  // x -> e_out reverse
+        } else {
+          const int e = (x - g.NB) >> 1;
+          const bool in = ((x - g.NB) & 1) == 0;
+          if (j == 0) {  // bridge
+            const int fbv = g.fb[e];
+            nbytes += 8;
+            t1 = in ? x + 1 : x - 1;
+            if (in ? fbv < g.w[e] : fbv > 0) v1 = stamp_first(g, t1, ep);
+          } else {
+            const int i = b + j - 1;
+            t1 = g.pin_v[i];
+            nbytes += 8;
+            if (in) {
+              if (g.w[e] - g.fpin[2 * i] > 0) v1 = stamp_first(g, t1, ep);  // e_in -> u reverse
+            } else {
+              const int r = g.role[t1];
+              if (r == 2) atomicOr(&g.ctl->err, ERR_SINK_REACHED);
+              else if (r == 0) v1 = stamp_first(g, t1, ep);  // e_out -> u infinite
+            }
+          }
+        }
+      }
+      qpush(g, q, t1, v1);
+      qpush(g, q, t2, v2);
+      bq_tile_end(q, 2 * blockDim.x);
+    }
+    __syncthreads();  // the tile area is rewritten by the next tile
+  }
+  bq_flush(q);
+  wave_add_u64(&g.ctl->bytes[kc], (unsigned long long)nbytes + 12ull * narcs);
+  wave_add_u64(&g.ctl->items[kc], narcs);
 }
 
 template <int G>
-__device__ void phase_bfs_rev(const Dev& g, int level, int w0, int wstride, int kc) {
-  // frontier of level `level` -> label level+1
-  const int c3 = level % 3, n3 = (level + 1) % 3, z3 = (level + 2) % 3;
-  if (w0 == 0 && lane_id() == 0) {
-    g.ctl->bcnt[z3][0] = 0;
-    g.ctl->bcnt[z3][1] = 0;
-  }
-  const int ns = g.ctl->bcnt[c3][0];
-  const int nb = g.ctl->bcnt[c3][1];
-  const int cp = level & 1, np = (level + 1) & 1;
-  constexpr int NPW = kWave / G;
-  const int nsi = (ns + NPW - 1) / NPW;
-  const int total = nsi + nb;
-  const int lane = lane_id();
-  uint32_t nbytes = 0, nitems = 0;
-  for (int it = w0; it < total; it += wstride) {
-    if (it < nsi) {
-      const int idx = it * NPW + lane / G;
-      const bool has = idx < ns;
-      const int v = has ? g.list[cp][0][idx] : 0;
-      nitems += has && (lane % G) == 0;
-      bfs_rev_node<G>(g, v, has, lane % G, level + 1, g.ctl->bcnt[n3], g.list[np][0],
-                      g.list[np][1], nbytes);
-    } else {
-      const int v = g.list[cp][1][it - nsi];
-      nitems += lane == 0;
-      bfs_rev_node<kWave>(g, v, true, lane, level + 1, g.ctl->bcnt[n3], g.list[np][0],
-                          g.list[np][1], nbytes);
+__device__ void phase_bfs_rev(const Dev& g, int level, int tile0, int tstride, int kc,
+                              lds_int* lds) {
+  phase_bfs_rev_lb<true>(g, level, tile0, tstride, kc, lds);
+}
+
+// Large levels run in two steps without claiming atomics: expand the level
+// from its list, labelling unlabelled in-neighbours with plain stores (every
+// writer stores the same value), then collect the next level by one sweep
+// over the labels.
+template <int G>
+__device__ void phase_bfs_rev_expand(const Dev& g, int level, int tile0, int tstride, int kc,
+                                     lds_int* lds) {
+  phase_bfs_rev_lb<false>(g, level, tile0, tstride, kc, lds);
+}
+
+// Sweep tiles: 2 nodes per thread, so a tile appends at most 2 * blockDim
+// entries per list.
+__device__ __forceinline__ int sweep_tiles(const Dev& g) {
+  const int ts = 2 * blockDim.x;
+  return (g.N + ts - 1) / ts;
+}
+
+__device__ void phase_bfs_collect(const Dev& g, int level, int tile0, int tstride, lds_int* lds) {
+  // nodes labelled level+1 become the list of level+1
+  const int n3 = (level + 1) % 3, np = (level + 1) & 1;
+  const BlockQ q = bq_bind(lds, g.ctl->bcnt[n3], g.list[np]);
+  const int lab = level + 1;
+  const int ntiles = sweep_tiles(g);
+  for (int tile = tile0; tile < ntiles; tile += tstride) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int v = (2 * tile + j) * blockDim.x + threadIdx.x;
+      qpush(g, q, v, v < g.N && g.d[v] == lab);
     }
+    bq_tile_end(q, 2 * blockDim.x);
   }
-  wave_add_u64(&g.ctl->bytes[kc], (unsigned long long)nbytes + 4ull * nitems);
-  wave_add_u64(&g.ctl->items[kc], nitems);
+  bq_flush(q);
 }
 
 // ---------------------------------------------------------------------------
@@ -602,98 +965,9 @@ __device__ void phase_bfs_rev(const Dev& g, int level, int w0, int wstride, int 
 // ---------------------------------------------------------------------------
 
 template <int G>
-__device__ void bfs_fwd_node(const Dev& g, int x, bool has, int gl, int ep, int32_t* cnt2,
-                             int32_t* ls, int32_t* lb, uint32_t& nbytes) {
-  const bool isv = has && x < g.V;
-  const bool isnet = has && x >= g.NB;
-  if (!has || isv) {
-    int beg = 0, end = 0;
-    if (isv) {
-      beg = g.vtx_off[x];
-      end = g.vtx_off[x + 1];
-    }
-    for (int base = beg; base < end; base += G) {
-      const int i = base + gl;
-      const bool valid = i < end;
-      bool vin = false, vout = false;
-      int e = 0;
-      if (valid) {
-        const int2 ep2 = g.vinc[i];
-        e = ep2.x;
-        nbytes += 12;
-        vin = stamp_first(g, g.NB + 2 * e, ep);                    // u -> e_in (uncapped)
-        if (g.fpin[2 * ep2.y + 1] > 0) vout = stamp_first(g, g.NB + 2 * e + 1, ep);
-      }
-      push_frontier(g, cnt2, ls, lb, g.NB + 2 * e, vin);
-      push_frontier(g, cnt2, ls, lb, g.NB + 2 * e + 1, vout);
-    }
-  } else if (isnet) {
-    const int e = (x - g.NB) >> 1;
-    const bool in = ((x - g.NB) & 1) == 0;
-    const int beg = g.net_off[e], end = g.net_off[e + 1];
-    const int we = g.w[e];
-    const int fbv = g.fb[e];
-    nbytes += 16;
-    bool vb = false;
-    if (gl == 0) {
-      if (in) vb = fbv < we && stamp_first(g, x + 1, ep);   // bridge residual
-      else vb = fbv > 0 && stamp_first(g, x - 1, ep);       // reverse bridge
-    }
-    push_frontier(g, cnt2, ls, lb, in ? x + 1 : x - 1, vb);
-    for (int base = beg; base < end; base += G) {
-      const int i = base + gl;
-      const bool valid = i < end;
-      bool vu = false;
-      int u = 0;
-      if (valid) {
-        u = g.pin_v[i];
-        nbytes += 8;
-        if (in) {
-          const int rin = g.fpin[2 * i];
-          if (we - rin > 0) vu = stamp_first(g, u, ep);       // e_in -> u reverse
-        } else {
-          const int r = g.role[u];
-          if (r == 2) atomicOr(&g.ctl->err, ERR_SINK_REACHED);
-          else if (r == 0) vu = stamp_first(g, u, ep);        // e_out -> u infinite
-        }
-      }
-      push_frontier(g, cnt2, ls, lb, u, vu);
-    }
-  }
-}
-
-template <int G>
-__device__ void phase_bfs_fwd(const Dev& g, int level, int ep, int w0, int wstride, int kc) {
-  const int c3 = level % 3, n3 = (level + 1) % 3, z3 = (level + 2) % 3;
-  if (w0 == 0 && lane_id() == 0) {
-    g.ctl->bcnt[z3][0] = 0;
-    g.ctl->bcnt[z3][1] = 0;
-  }
-  const int ns = g.ctl->bcnt[c3][0];
-  const int nb = g.ctl->bcnt[c3][1];
-  const int cp = level & 1, np = (level + 1) & 1;
-  constexpr int NPW = kWave / G;
-  const int nsi = (ns + NPW - 1) / NPW;
-  const int total = nsi + nb;
-  const int lane = lane_id();
-  uint32_t nbytes = 0, nitems = 0;
-  for (int it = w0; it < total; it += wstride) {
-    if (it < nsi) {
-      const int idx = it * NPW + lane / G;
-      const bool has = idx < ns;
-      const int v = has ? g.list[cp][0][idx] : 0;
-      nitems += has && (lane % G) == 0;
-      bfs_fwd_node<G>(g, v, has, lane % G, ep, g.ctl->bcnt[n3], g.list[np][0], g.list[np][1],
-                      nbytes);
-    } else {
-      const int v = g.list[cp][1][it - nsi];
-      nitems += lane == 0;
-      bfs_fwd_node<kWave>(g, v, true, lane, ep, g.ctl->bcnt[n3], g.list[np][0],
-                          g.list[np][1], nbytes);
-    }
-  }
-  wave_add_u64(&g.ctl->bytes[kc], (unsigned long long)nbytes + 4ull * nitems);
-  wave_add_u64(&g.ctl->items[kc], nitems);
+__device__ void phase_bfs_fwd(const Dev& g, int level, int ep, int tile0, int tstride, int kc,
+                              lds_int* lds) {
+  phase_bfs_fwd_lb(g, level, ep, tile0, tstride, kc, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -705,11 +979,8 @@ __device__ void phase_bfs_fwd(const Dev& g, int level, int ep, int w0, int wstri
 __device__ void phase_init(const Dev& g, int t0, int tstride) {
   if (t0 == 0) {
     Ctl* c = g.ctl;
-    for (int i = 0; i < 3; ++i) {
-      c->fcnt[i][0] = c->fcnt[i][1] = 0;
-      c->bcnt[i][0] = c->bcnt[i][1] = 0;
-      c->lcnt[i] = 0;
-    }
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < kNL; ++k) c->fcnt[i][k] = c->bcnt[i][k] = 0;
     c->err = 0;
     c->flow = 0ull;
     c->relabels = 0ull;
@@ -724,6 +995,9 @@ __device__ void phase_init(const Dev& g, int t0, int tstride) {
     }
     if (i < g.N) {
       g.stamp[i] = -1;
+      g.cand[i] = -1;
+      g.dx[0][i] = 0;
+      g.dx[1][i] = 0;
       int xv = 0;
       if (i >= g.NB) {
         const int e = (i - g.NB) >> 1;
@@ -740,76 +1014,109 @@ __device__ void phase_init(const Dev& g, int t0, int tstride) {
 // Global relabel, step 1: labels N for free nodes, 0 for sinks, N+1 for
 // sources and padding; sinks form BFS level 0.  Round counters are cleared
 // (the frontier is rebuilt by phase_gather).
-__device__ void phase_gr_reset(const Dev& g, int t0, int tstride) {
-  if (t0 == 0) {
+__device__ void phase_gr_reset(const Dev& g, int tile0, int tstride, lds_int* lds) {
+  if (tile0 == 0 && threadIdx.x == 0) {
     Ctl* c = g.ctl;
-    for (int i = 0; i < 3; ++i) {
-      c->fcnt[i][0] = c->fcnt[i][1] = 0;
-      c->lcnt[i] = 0;
-    }
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < kNL; ++k) c->fcnt[i][k] = 0;
   }
-  for (int base = t0 - lane_id(); base < g.N; base += tstride) {
-    const int v = base + lane_id();
-    bool seed = false;
-    if (v < g.N) {
-      int lab = g.N;
-      if (v < g.V) {
-        const int r = g.role[v];
-        lab = r == 1 ? g.N + 1 : (r == 2 ? 0 : g.N);
-        seed = r == 2;
-      } else if (v < g.NB) {
-        lab = g.N + 1;
+  const BlockQ q = bq_bind(lds, g.ctl->bcnt[0], g.list[0]);
+  const int ntiles = sweep_tiles(g);
+  for (int tile = tile0; tile < ntiles; tile += tstride) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int v = (2 * tile + j) * blockDim.x + threadIdx.x;
+      bool seed = false;
+      if (v < g.N) {
+        int lab = g.N;
+        if (v < g.V) {
+          const int r = g.role[v];
+          lab = r == 1 ? g.N + 1 : (r == 2 ? 0 : g.N);
+          seed = r == 2;
+        } else if (v < g.NB) {
+          lab = g.N + 1;
+        }
+        g.d[v] = lab;
+        g.seen[v] = lab != g.N;
       }
-      g.d[v] = lab;
+      qpush(g, q, v, seed);
     }
-    push_frontier(g, g.ctl->bcnt[0], g.list[0][0], g.list[0][1], v, seed);
+    bq_tile_end(q, 2 * blockDim.x);
   }
+  bq_flush(q);
 }
 
-// Global relabel, step 3: frontier = non-terminal nodes with excess and a
-// label below N.  BFS counters are cleared for the next BFS.
-__device__ void phase_gather(const Dev& g, int epoch, int t0, int tstride) {
+// Global relabel, step 3: fold outstanding excess deltas; frontier =
+// non-terminal nodes with excess and a label below N; stale relabel
+// candidates dropped.  BFS counters are cleared for the next BFS.
+__device__ void phase_gather(const Dev& g, int epoch, int tile0, int tstride, lds_int* lds) {
   const int c3 = epoch % 3, cp = epoch & 1;
-  if (t0 == 0) {
-    for (int i = 0; i < 3; ++i) g.ctl->bcnt[i][0] = g.ctl->bcnt[i][1] = 0;
+  if (tile0 == 0 && threadIdx.x == 0) {
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < kNL; ++k) g.ctl->bcnt[i][k] = 0;
   }
-  for (int base = t0 - lane_id(); base < g.N; base += tstride) {
-    const int v = base + lane_id();
-    bool act = false;
-    if (v < g.N && (v >= g.NB || (v < g.V && g.role[v] == 0)))
-      act = g.x[v] > 0 && g.d[v] < g.N;
-    push_frontier(g, g.ctl->fcnt[c3], g.list[cp][0], g.list[cp][1], v, act);
+  const BlockQ q = bq_bind(lds, g.ctl->fcnt[c3], g.list[cp]);
+  const int ntiles = sweep_tiles(g);
+  for (int tile = tile0; tile < ntiles; tile += tstride) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int v = (2 * tile + j) * blockDim.x + threadIdx.x;
+      bool act = false;
+      if (v < g.N) {
+        const int a = g.dx[0][v], b = g.dx[1][v];
+        int xv = g.x[v];
+        if (a | b) {
+          xv += a + b;
+          g.x[v] = xv;
+          g.dx[0][v] = 0;
+          g.dx[1][v] = 0;
+        }
+        if (g.cand[v] >= 0) g.cand[v] = -1;
+        if (v >= g.NB || (v < g.V && g.role[v] == 0)) act = xv > 0 && g.d[v] < g.N;
+      }
+      qpush(g, q, v, act);
+    }
+    bq_tile_end(q, 2 * blockDim.x);
   }
+  bq_flush(q);
 }
 
 // Cut BFS seeds: sources (marked, nothing to expand: their only arcs are the
 // contracted source arcs into e_in), e_in of nets with a source pin, and
 // every non-terminal node holding excess.
-__device__ void phase_cut_seed(const Dev& g, int ep, int t0, int tstride) {
-  for (int base = t0 - lane_id(); base < g.N; base += tstride) {
-    const int v = base + lane_id();
-    bool seed = false;
-    if (v < g.N) {
-      if (v < g.V) {
-        const int r = g.role[v];
-        if (r == 1) g.stamp[v] = ep;
-        else if (r == 0 && g.x[v] > 0) seed = true;
-      } else if (v >= g.NB) {
-        const int e = (v - g.NB) >> 1;
-        const bool in = ((v - g.NB) & 1) == 0;
-        seed = g.x[v] > 0 || (in && (g.nflag[e] & 1));
+__device__ void phase_cut_seed(const Dev& g, int ep, int tile0, int tstride, lds_int* lds) {
+  const BlockQ q = bq_bind(lds, g.ctl->bcnt[0], g.list[0]);
+  const int ntiles = sweep_tiles(g);
+  for (int tile = tile0; tile < ntiles; tile += tstride) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int v = (2 * tile + j) * blockDim.x + threadIdx.x;
+      bool seed = false;
+      if (v < g.N) {
+        if (v < g.V) {
+          const int r = g.role[v];
+          if (r == 1) g.stamp[v] = ep;
+          else if (r == 0 && g.x[v] > 0) seed = true;
+        } else if (v >= g.NB) {
+          const int e = (v - g.NB) >> 1;
+          const bool in = ((v - g.NB) & 1) == 0;
+          seed = g.x[v] > 0 || (in && (g.nflag[e] & 1));
+        }
+        if (seed) g.stamp[v] = ep;
       }
-      if (seed) g.stamp[v] = ep;
+      qpush(g, q, v, seed);
     }
-    push_frontier(g, g.ctl->bcnt[0], g.list[0][0], g.list[0][1], v, seed);
+    bq_tile_end(q, 2 * blockDim.x);
   }
+  bq_flush(q);
 }
 
 // Write the side bitmaps and clear BFS counters.
 __device__ void phase_cut_out(const Dev& g, int ep, uint8_t* vside, uint8_t* nside, int t0,
                               int tstride) {
   if (t0 == 0) {
-    for (int i = 0; i < 3; ++i) g.ctl->bcnt[i][0] = g.ctl->bcnt[i][1] = 0;
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < kNL; ++k) g.ctl->bcnt[i][k] = 0;
   }
   const int n = max(g.V, g.E);
   for (int i = t0; i < n; i += tstride) {
@@ -825,24 +1132,26 @@ __device__ void phase_cut_out(const Dev& g, int ep, uint8_t* vside, uint8_t* nsi
   }
 }
 
-// Debug: preflow feasibility and label validity on every residual arc of the
-// capped network.  Thread per pin / net / vertex.
+// Debug: preflow feasibility (excess = inflow - outflow >= 0, capacities) and
+// label validity on every residual arc of the capped network, after a
+// completed round.  Thread per vertex / net / pin.
+__device__ __forceinline__ long long excess_of(const Dev& g, int v) {
+  return (long long)g.x[v] + g.dx[0][v] + g.dx[1][v];
+}
+
 __device__ void phase_check(const Dev& g, int t0, int tstride) {
   const int n = max(g.P, max(g.E, g.V));
   bool bad = false;
   for (int i = t0; i < n; i += tstride) {
     if (i < g.V) {
       const int r = g.role[i];
-      const int xv = g.x[i];
-      if (r == 0 && xv < 0) bad = true;
       if (r == 0) {
-        // excess equals inflow - outflow
         long long s = 0;
         for (int j = g.vtx_off[i]; j < g.vtx_off[i + 1]; ++j) {
           const int2 ep = g.vinc[j];
           s += (long long)g.fpin[2 * ep.y + 1] - (long long)(g.w[ep.x] - g.fpin[2 * ep.y]);
         }
-        if (s != xv) bad = true;
+        if (s != excess_of(g, i) || s < 0) bad = true;
       }
     }
     if (i < g.E) {
@@ -853,16 +1162,13 @@ __device__ void phase_check(const Dev& g, int t0, int tstride) {
         sin += we - g.fpin[2 * p];
         sout += g.fpin[2 * p + 1];
       }
-      if (sin - fbv != g.x[g.NB + 2 * i]) bad = true;
-      if (fbv - sout != g.x[g.NB + 2 * i + 1]) bad = true;
-      if (g.x[g.NB + 2 * i] < 0 || g.x[g.NB + 2 * i + 1] < 0) bad = true;
+      const long long xin = excess_of(g, g.NB + 2 * i), xout = excess_of(g, g.NB + 2 * i + 1);
+      if (sin - fbv != xin || fbv - sout != xout || xin < 0 || xout < 0) bad = true;
       const int din = g.d[g.NB + 2 * i], dout = g.d[g.NB + 2 * i + 1];
       if (din < g.N && fbv < we && din > dout + 1) bad = true;
       if (dout < g.N && fbv > 0 && dout > din + 1) bad = true;
     }
     if (i < g.P) {
-      // pin arcs: find the net by the vertex side entry (pins are scanned
-      // through vinc for the net id)
       const int2 ep = g.vinc[i];
       const int e = ep.x, p = ep.y;
       const int u = g.pin_v[p];
@@ -878,7 +1184,7 @@ __device__ void phase_check(const Dev& g, int t0, int tstride) {
         if (du < g.N && fout > 0 && du > dout + 1) bad = true;      // u -> e_out
         if (din < g.N && we - rin > 0 && din > du + 1) bad = true;  // e_in -> u
       }
-      if (dout < g.N && r != 1 && dout > du + 1) bad = true;        // e_out -> u
+      if (dout < g.N && r != 1 && dout > du + 1) bad = true;  // e_out -> u
     }
   }
   if (bad) atomicOr(&g.ctl->err, ERR_INVARIANT);

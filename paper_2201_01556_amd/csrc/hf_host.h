@@ -26,6 +26,7 @@ enum KernelKind : int {
   KK_CUT_OUT,
   KK_CHECK,
   KK_BATCH,
+  KK_BFS_COLLECT,
   KK_COUNT
 };
 

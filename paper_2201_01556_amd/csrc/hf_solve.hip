@@ -7,29 +7,37 @@
 // paper observes (paragraph "Avoid Pushing Flow Back") costs no launches and
 // no host round trips.  Both paths call the same phase functions.
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "hf_host.h"
 
 namespace hf {
 
-constexpr int kThreads = 256;    // device-wide kernels
-constexpr int kLoopThreads = 1024;  // single-workgroup loops
-constexpr int kMaxBlocks = 2048;
+constexpr int kThreads = 256;  // plain element-wise kernels
+constexpr int kBlock = 1024;   // frontier, sweep and single-workgroup kernels
+constexpr int kMaxFrontierBlocks = 512;
+constexpr int kMaxSweepBlocks = 256;
 constexpr long long kRoundGuard = 200000000ll;  // rounds per solve before giving up
 
 __device__ __forceinline__ int ld_vol(const int32_t* p) {
-  return __atomic_load_n(p, __ATOMIC_RELAXED);
+  return *reinterpret_cast<const volatile int32_t*>(p);
 }
 __device__ __forceinline__ unsigned long long ld_vol64(const unsigned long long* p) {
-  return __atomic_load_n(p, __ATOMIC_RELAXED);
+  return *reinterpret_cast<const volatile unsigned long long*>(p);
 }
 
-// ordering point inside one workgroup: all global writes of the workgroup
-// become visible to all its waves (L1 is invalidated by the agent fence)
-__device__ __forceinline__ void wg_sync() {
-  __threadfence();
-  __syncthreads();
+__device__ __forceinline__ int count_all(const int32_t* c) {
+  int n = 0;
+#pragma unroll
+  for (int k = 0; k < kNL; ++k) n += c[k];
+  return n;
+}
+__device__ __forceinline__ int count_all_vol(const int32_t* c) {
+  int n = 0;
+#pragma unroll
+  for (int k = 0; k < kNL; ++k) n += ld_vol(c + k);
+  return n;
 }
 
 __device__ __forceinline__ int gwave() { return (blockIdx.x * blockDim.x + threadIdx.x) >> 6; }
@@ -37,37 +45,61 @@ __device__ __forceinline__ int gwaves() { return (gridDim.x * blockDim.x) >> 6; 
 __device__ __forceinline__ int gthread() { return blockIdx.x * blockDim.x + threadIdx.x; }
 __device__ __forceinline__ int gthreads() { return gridDim.x * blockDim.x; }
 
+// LDS staging area of the workgroup's list appends
+#define HF_QUEUE_LDS __shared__ int32_t hf_bq[kBQWords + kTileWords]; lds_int* const lds = (lds_int*)hf_bq
+
 __global__ void __launch_bounds__(kThreads) k_init(Dev g) { phase_init(g, gthread(), gthreads()); }
 
-__global__ void __launch_bounds__(kThreads) k_gr_reset(Dev g) {
-  phase_gr_reset(g, gthread(), gthreads());
+__global__ void __launch_bounds__(kBlock) k_gr_reset(Dev g) {
+  HF_QUEUE_LDS;
+  phase_gr_reset(g, blockIdx.x, gridDim.x, lds);
+}
+
+// One level of the reverse BFS.  A level holding at least `big_min` nodes
+// is only expanded here (plain stores) and k_bfs_collect lists the next
+// level; smaller levels claim and list new nodes directly.  Both kernels read
+// the same count, so they agree on the mode.
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_bfs_rev(Dev g, int level, int big_min) {
+  HF_QUEUE_LDS;
+  const int c3 = level % 3;
+  const int nf = count_all(g.ctl->bcnt[c3]);
+  if (nf >= big_min) phase_bfs_rev_expand<G>(g, level, blockIdx.x, gridDim.x, KC_BFS_REV, lds);
+  else phase_bfs_rev<G>(g, level, blockIdx.x, gridDim.x, KC_BFS_REV, lds);
+}
+
+__global__ void __launch_bounds__(kBlock) k_bfs_collect(Dev g, int level, int big_min) {
+  HF_QUEUE_LDS;
+  const int c3 = level % 3;
+  const int nf = count_all(g.ctl->bcnt[c3]);
+  if (nf >= big_min) phase_bfs_collect(g, level, blockIdx.x, gridDim.x, lds);
+}
+
+__global__ void __launch_bounds__(kBlock) k_gather(Dev g, int epoch) {
+  HF_QUEUE_LDS;
+  phase_gather(g, epoch, blockIdx.x, gridDim.x, lds);
 }
 
 template <int G>
-__global__ void __launch_bounds__(kThreads) k_bfs_rev(Dev g, int level) {
-  phase_bfs_rev<G>(g, level, gwave(), gwaves(), KC_BFS_REV);
+__global__ void __launch_bounds__(kBlock) k_push(Dev g, int epoch) {
+  HF_QUEUE_LDS;
+  phase_push<G>(g, epoch, blockIdx.x, gridDim.x, KC_PUSH, lds);
 }
 
-__global__ void __launch_bounds__(kThreads) k_gather(Dev g, int epoch) {
-  phase_gather(g, epoch, gthread(), gthreads());
+__global__ void __launch_bounds__(kBlock) k_apply(Dev g, int epoch) {
+  HF_QUEUE_LDS;
+  phase_apply(g, epoch, blockIdx.x, gridDim.x, KC_APPLY, lds);
 }
 
-template <int G>
-__global__ void __launch_bounds__(kThreads) k_push(Dev g, int epoch) {
-  phase_push<G>(g, epoch, gwave(), gwaves(), KC_PUSH);
-}
-
-__global__ void __launch_bounds__(kThreads) k_apply(Dev g, int epoch) {
-  phase_apply(g, epoch, gthread(), gthreads(), KC_APPLY);
-}
-
-__global__ void __launch_bounds__(kThreads) k_cut_seed(Dev g, int ep) {
-  phase_cut_seed(g, ep, gthread(), gthreads());
+__global__ void __launch_bounds__(kBlock) k_cut_seed(Dev g, int ep) {
+  HF_QUEUE_LDS;
+  phase_cut_seed(g, ep, blockIdx.x, gridDim.x, lds);
 }
 
 template <int G>
-__global__ void __launch_bounds__(kThreads) k_bfs_fwd(Dev g, int level, int ep) {
-  phase_bfs_fwd<G>(g, level, ep, gwave(), gwaves(), KC_BFS_FWD);
+__global__ void __launch_bounds__(kBlock) k_bfs_fwd(Dev g, int level, int ep) {
+  HF_QUEUE_LDS;
+  phase_bfs_fwd<G>(g, level, ep, blockIdx.x, gridDim.x, KC_BFS_FWD, lds);
 }
 
 __global__ void __launch_bounds__(kThreads) k_cut_out(Dev g, int ep, uint8_t* vs, uint8_t* ns) {
@@ -78,30 +110,45 @@ __global__ void __launch_bounds__(kThreads) k_check(Dev g) {
   phase_check(g, gthread(), gthreads());
 }
 
-// Rounds inside one workgroup.  Stops when the frontier is empty, exceeds
-// `cap`, `max_rounds` rounds ran, or the relabel count reached
-// `relabel_limit` (a global relabel is due).
+// Rounds inside one workgroup.  All waves of the workgroup share one CU, so
+// a workgroup barrier orders their global memory traffic; no device-scope
+// fence (which would write back and invalidate the L2) is needed.  Stops when
+// the frontier is empty (1), exceeds `cap` (2), `max_rounds` rounds ran (3),
+// the relabel count reached `relabel_limit` (4), or the flow value did not
+// change for `stale_limit` rounds (5).  The exit tests read values that no
+// wave writes between the barrier and the test, so every wave takes the same
+// decision.
 template <int G>
-__global__ void __launch_bounds__(kLoopThreads) k_round_loop(Dev g, int epoch0, int max_rounds,
-                                                             int cap,
-                                                             unsigned long long relabel_limit) {
-  const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+__global__ void __launch_bounds__(kBlock) k_round_loop(Dev g, int epoch0, int max_rounds, int cap,
+                                                       unsigned long long relabel_limit,
+                                                       int stale_limit) {
+  HF_QUEUE_LDS;
   int epoch = epoch0;
   int r = 0;
   int why = 0;
+  int stale = 0;
+  unsigned long long last_flow = ld_vol64(&g.ctl->flow);
   for (;;) {
     const int c3 = epoch % 3;
-    const int nf = ld_vol(&g.ctl->fcnt[c3][0]) + ld_vol(&g.ctl->fcnt[c3][1]);
+    const int nf = count_all_vol(g.ctl->fcnt[c3]);
+    const unsigned long long fl = ld_vol64(&g.ctl->flow);
+    if (fl != last_flow) {
+      last_flow = fl;
+      stale = 0;
+    }
     if (nf == 0) { why = 1; break; }
     if (nf > cap) { why = 2; break; }
     if (r >= max_rounds) { why = 3; break; }
     if (ld_vol64(&g.ctl->relabels) >= relabel_limit) { why = 4; break; }
-    phase_push<G>(g, epoch, wv, nw, KC_LOOP_ROUNDS);
-    wg_sync();
-    phase_apply(g, epoch, threadIdx.x, blockDim.x, KC_LOOP_ROUNDS);
-    wg_sync();
+    if (stale_limit > 0 && stale >= stale_limit) { why = 5; break; }
+    __syncthreads();  // every wave has read the counters before they change
+    phase_push<G>(g, epoch, 0, 1, KC_LOOP_ROUNDS, lds);
+    __syncthreads();
+    phase_apply(g, epoch, 0, 1, KC_LOOP_ROUNDS, lds);
+    __syncthreads();
     ++epoch;
     ++r;
+    ++stale;
   }
   if (threadIdx.x == 0) {
     g.ctl->loop_rounds = r;
@@ -111,16 +158,17 @@ __global__ void __launch_bounds__(kLoopThreads) k_round_loop(Dev g, int epoch0, 
 
 // BFS levels inside one workgroup (reverse when ep < 0, forward otherwise).
 template <int G>
-__global__ void __launch_bounds__(kLoopThreads) k_bfs_loop(Dev g, int level0, int cap, int ep) {
-  const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+__global__ void __launch_bounds__(kBlock) k_bfs_loop(Dev g, int level0, int cap, int ep) {
+  HF_QUEUE_LDS;
   int level = level0;
   for (;;) {
     const int c3 = level % 3;
-    const int nf = ld_vol(&g.ctl->bcnt[c3][0]) + ld_vol(&g.ctl->bcnt[c3][1]);
+    const int nf = count_all_vol(g.ctl->bcnt[c3]);
     if (nf == 0 || nf > cap) break;
-    if (ep < 0) phase_bfs_rev<G>(g, level, wv, nw, KC_LOOP_BFS);
-    else phase_bfs_fwd<G>(g, level, ep, wv, nw, KC_LOOP_BFS);
-    wg_sync();
+    __syncthreads();
+    if (ep < 0) phase_bfs_rev<G>(g, level, 0, 1, KC_LOOP_BFS, lds);
+    else phase_bfs_fwd<G>(g, level, ep, 0, 1, KC_LOOP_BFS, lds);
+    __syncthreads();
     ++level;
   }
   if (threadIdx.x == 0) g.ctl->loop_levels = level - level0;
@@ -137,11 +185,11 @@ static int sweep_grid(long long n) {
   return (int)b;
 }
 
-// grid for a frontier phase with `items` wave items (unknown: use the cap)
-static int frontier_grid(long long items) {
-  long long b = (items + (kThreads / 64) - 1) / (kThreads / 64);
-  if (b < 64) b = 64;
-  if (b > kMaxBlocks) b = kMaxBlocks;
+// grid for a sweep over n nodes (tiles of 2 * kBlock nodes)
+static int sweep_blocks(long long n) {
+  long long b = (n + 2 * kBlock - 1) / (2 * kBlock);
+  if (b < 1) b = 1;
+  if (b > kMaxSweepBlocks) b = kMaxSweepBlocks;
   return (int)b;
 }
 
@@ -158,13 +206,37 @@ struct Launch {
   }
 };
 
-static fp_status sync_ctl(fp_problem* pb, hipStream_t s) {
+static long long host_count(const int32_t* c) {
+  long long n = 0;
+  for (int k = 0; k < kNL; ++k) n += c[k];
+  return n;
+}
+
+static bool trace_on() {
+  static const bool on = [] {
+    const char* e = getenv("HYPERFLOW_TRACE");
+    return e && e[0] && e[0] != '0';
+  }();
+  return on;
+}
+
+static fp_status sync_ctl(fp_problem* pb, hipStream_t s, const char* what = "") {
   hipError_t he = hipGetLastError();
   if (he == hipSuccess)
     he = hipMemcpyAsync(pb->ctl_h, pb->dev.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s);
   if (he == hipSuccess) he = hipStreamSynchronize(s);
   if (he != hipSuccess) return hip_fail(he, "solver step");
   pb->st.host_syncs++;
+  if (trace_on()) {
+    const Ctl* c = pb->ctl_h;
+    const int c3 = pb->epoch % 3;
+    fprintf(stderr,
+            "[hyperflow] %-10s epoch=%d rounds=%lld flow=%llu frontier=%d/%d/%d/%d bfs=%d|%d|%d "
+            "relabels=%llu loop=%d/%d/%d\n",
+            what, pb->epoch, (long long)pb->st.rounds, c->flow, c->fcnt[c3][0], c->fcnt[c3][1],
+            c->fcnt[c3][2], c->fcnt[c3][3], host_count(c->bcnt[0]), host_count(c->bcnt[1]),
+            host_count(c->bcnt[2]), c->relabels, c->loop_rounds, c->loop_levels, c->loop_exit);
+  }
   if (pb->opt.profile) prof_collect(pb);
   return FP_OK;
 }
@@ -179,30 +251,34 @@ static fp_status run_bfs(fp_problem* pb, hipStream_t s, int ep, int* levels_out)
   if (st) return st;
   for (;;) {
     const int c3 = level % 3;
-    const long long nf = (long long)pb->ctl_h->bcnt[c3][0] + pb->ctl_h->bcnt[c3][1];
+    const long long nf = host_count(pb->ctl_h->bcnt[c3]);
     if (nf == 0) break;
     if (nf <= cap && !pb->opt.debug_checks) {
       {
         Launch L(pb, s, ep < 0 ? KK_BFS_REV_LOOP : KK_BFS_FWD_LOOP);
-        k_bfs_loop<G><<<1, kLoopThreads, 0, s>>>(g, level, cap, ep);
+        k_bfs_loop<G><<<1, kBlock, 0, s>>>(g, level, cap, ep);
       }
-      st = sync_ctl(pb, s);
+      st = sync_ctl(pb, s, "bfs-loop");
       if (st) return st;
       level += pb->ctl_h->loop_levels;
     } else {
-      const int steps = 4;
-      const int grid = frontier_grid(nf);
+      const int steps = 8;
+      const int big_min = pb->opt.bottom_up_min > 0 ? pb->opt.bottom_up_min : (1 << 30);
       for (int i = 0; i < steps; ++i) {
         if (ep < 0) {
-          Launch L(pb, s, KK_BFS_REV);
-          k_bfs_rev<G><<<grid, kThreads, 0, s>>>(g, level + i);
+          {
+            Launch L(pb, s, KK_BFS_REV);
+            k_bfs_rev<G><<<kMaxFrontierBlocks, kBlock, 0, s>>>(g, level + i, big_min);
+          }
+          Launch L(pb, s, KK_BFS_COLLECT);
+          k_bfs_collect<<<sweep_blocks(g.N), kBlock, 0, s>>>(g, level + i, big_min);
         } else {
           Launch L(pb, s, KK_BFS_FWD);
-          k_bfs_fwd<G><<<grid, kThreads, 0, s>>>(g, level + i, ep);
+          k_bfs_fwd<G><<<kMaxFrontierBlocks, kBlock, 0, s>>>(g, level + i, ep);
         }
       }
       level += steps;
-      st = sync_ctl(pb, s);
+      st = sync_ctl(pb, s, "bfs");
       if (st) return st;
     }
   }
@@ -215,18 +291,18 @@ static fp_status global_relabel(fp_problem* pb, hipStream_t s) {
   Dev& g = pb->dev;
   {
     Launch L(pb, s, KK_GR_RESET);
-    k_gr_reset<<<sweep_grid(g.N), kThreads, 0, s>>>(g);
+    k_gr_reset<<<sweep_blocks(g.N), kBlock, 0, s>>>(g);
   }
   int levels = 0;
   fp_status st = run_bfs<G>(pb, s, -1, &levels);
   if (st) return st;
   {
     Launch L(pb, s, KK_GATHER);
-    k_gather<<<sweep_grid(g.N), kThreads, 0, s>>>(g, pb->epoch);
+    k_gather<<<sweep_blocks(g.N), kBlock, 0, s>>>(g, pb->epoch);
   }
   pb->st.global_relabels++;
   pb->st.bfs_levels += levels;
-  return sync_ctl(pb, s);
+  return sync_ctl(pb, s, "gather");
 }
 
 static fp_status debug_check(fp_problem* pb, hipStream_t s) {
@@ -258,9 +334,17 @@ static fp_status solve_impl(fp_problem* pb, hipStream_t s, int64_t* flow) {
   }
   st = global_relabel<G>(pb, s);
   if (st) return st;
+  // global relabel triggers (paper: "after linear push and relabel work",
+  // and the stale-flow rule of paragraph "Avoid Pushing Flow Back")
   const unsigned long long budget =
       (unsigned long long)((double)g.N * pb->opt.relabel_factor_x16 / 16.0) + 1ull;
+  const int gr_interval = pb->opt.gr_interval;
+  const int stale_limit = pb->opt.stale_rounds;
+  constexpr long long kStaleFrontier = 1500;  // "only few active nodes" (paper)
   unsigned long long rel_at_gr = pb->ctl_h->relabels;
+  unsigned long long last_flow = pb->ctl_h->flow;
+  long long stale = 0;
+  long long rounds_since_gr = 0;
   bool fresh_gr = true;  // frontier was just gathered by a global relabel
   const int cap = pb->opt.tail_threshold;
   const int rounds_per_sync = pb->opt.debug_checks ? 1 : 8;
@@ -271,17 +355,21 @@ static fp_status solve_impl(fp_problem* pb, hipStream_t s, int64_t* flow) {
       return FP_ERR_DEVICE;
     }
     const int c3 = pb->epoch % 3;
-    const long long nf = (long long)pb->ctl_h->fcnt[c3][0] + pb->ctl_h->fcnt[c3][1];
+    const long long nf = host_count(pb->ctl_h->fcnt[c3]);
+    bool do_gr = false;
     if (nf == 0) {
       if (fresh_gr) break;
-      // apparent termination: confirm with exact labels, restart if active
-      // nodes remain (paper, section "A Bug in the Synchronous Algorithm")
+      // apparent termination: confirm with exact labels and restart if
+      // active nodes remain (paper, section "A Bug in the Synchronous
+      // Algorithm")
       st = global_relabel<G>(pb, s);
       if (st) return st;
-      rel_at_gr = pb->ctl_h->relabels;
-      fresh_gr = true;
       const int c3b = pb->epoch % 3;
-      if (pb->ctl_h->fcnt[c3b][0] + pb->ctl_h->fcnt[c3b][1] > 0) pb->st.restarts++;
+      if (host_count(pb->ctl_h->fcnt[c3b]) > 0) pb->st.restarts++;
+      rel_at_gr = pb->ctl_h->relabels;
+      rounds_since_gr = 0;
+      stale = 0;
+      fresh_gr = true;
       continue;
     }
     if (rounds_this_solve > kRoundGuard) {
@@ -293,49 +381,69 @@ static fp_status solve_impl(fp_problem* pb, hipStream_t s, int64_t* flow) {
       return FP_ERR_ABORTED;
     }
     fresh_gr = false;
+    int ran = 0;
     if (nf <= cap && !pb->opt.debug_checks) {
-      int max_rounds = 1 << 16;  // per launch; the host loop continues
+      long long max_rounds = 1 << 16;  // per launch; the host loop continues
+      if (gr_interval > 0) max_rounds = std::min<long long>(max_rounds, gr_interval - rounds_since_gr);
       if (pb->opt.round_budget > 0)
-        max_rounds = (int)std::min<int64_t>(max_rounds, pb->opt.round_budget - rounds_this_solve);
+        max_rounds = std::min<long long>(max_rounds, pb->opt.round_budget - rounds_this_solve);
+      max_rounds = std::max<long long>(max_rounds, 1);
+      const int stale_left = stale_limit > 0 ? (int)std::max<long long>(1, stale_limit - stale) : 0;
       {
         Launch L(pb, s, KK_ROUND_LOOP);
-        k_round_loop<G><<<1, kLoopThreads, 0, s>>>(g, pb->epoch, max_rounds, cap,
-                                                  rel_at_gr + budget);
+        k_round_loop<G><<<1, kBlock, 0, s>>>(g, pb->epoch, (int)max_rounds, cap,
+                                                  rel_at_gr + budget, stale_left);
       }
-      st = sync_ctl(pb, s);
+      st = sync_ctl(pb, s, "loop");
       if (st) return st;
-      const int r = pb->ctl_h->loop_rounds;
-      pb->epoch += r;
-      pb->st.rounds += r;
-      pb->st.tail_rounds += r;
-      rounds_this_solve += r;
+      ran = pb->ctl_h->loop_rounds;
+      pb->st.tail_rounds += ran;
+      if (pb->ctl_h->loop_exit == 5) do_gr = true;
     } else {
-      const int grid = frontier_grid(nf);
+      // later rounds of the batch may hold larger frontiers than the
+      // count known now, so the batch uses the full grid
+      const int grid = kMaxFrontierBlocks;
       for (int i = 0; i < rounds_per_sync; ++i) {
         {
           Launch L(pb, s, KK_PUSH);
-          k_push<G><<<grid, kThreads, 0, s>>>(g, pb->epoch);
+          k_push<G><<<grid, kBlock, 0, s>>>(g, pb->epoch + i);
         }
         {
           Launch L(pb, s, KK_APPLY);
-          k_apply<<<grid, kThreads, 0, s>>>(g, pb->epoch);
+          k_apply<<<grid, kBlock, 0, s>>>(g, pb->epoch + i);
         }
-        pb->epoch++;
       }
-      pb->st.rounds += rounds_per_sync;
-      rounds_this_solve += rounds_per_sync;
+      ran = rounds_per_sync;
       if (pb->opt.debug_checks) {
         st = debug_check(pb, s);
         if (st) return st;
       } else {
-        st = sync_ctl(pb, s);
+        st = sync_ctl(pb, s, "rounds");
         if (st) return st;
       }
     }
-    if (pb->ctl_h->relabels - rel_at_gr >= budget) {
+    pb->epoch += ran;
+    pb->st.rounds += ran;
+    rounds_this_solve += ran;
+    rounds_since_gr += ran;
+    // stale-flow bookkeeping for device-wide rounds (the loop kernel keeps
+    // its own count and reports exit 5)
+    if (pb->ctl_h->flow != last_flow) {
+      last_flow = pb->ctl_h->flow;
+      stale = 0;
+    } else if (nf < kStaleFrontier) {
+      stale += ran;
+    }
+    if (stale_limit > 0 && stale >= stale_limit) do_gr = true;
+    if (pb->ctl_h->relabels - rel_at_gr >= budget) do_gr = true;
+    if (gr_interval > 0 && rounds_since_gr >= gr_interval) do_gr = true;
+    if (do_gr) {
       st = global_relabel<G>(pb, s);
       if (st) return st;
       rel_at_gr = pb->ctl_h->relabels;
+      rounds_since_gr = 0;
+      stale = 0;
+      last_flow = pb->ctl_h->flow;
       fresh_gr = true;
     }
   }
@@ -364,7 +472,7 @@ static fp_status cut_impl(fp_problem* pb, hipStream_t s, uint8_t* vs, uint8_t* n
   const int ep = pb->epoch++;
   {
     Launch L(pb, s, KK_CUT_SEED);
-    k_cut_seed<<<sweep_grid(g.N), kThreads, 0, s>>>(g, ep);
+    k_cut_seed<<<sweep_blocks(g.N), kBlock, 0, s>>>(g, ep);
   }
   int levels = 0;
   fp_status st = run_bfs<G>(pb, s, ep, &levels);
@@ -392,7 +500,7 @@ fp_status cut_problem(fp_problem* pb, hipStream_t s, int32_t mem_kind, uint8_t* 
   uint8_t* vs = vside;
   uint8_t* ns = nside;
   if (mem_kind == 0) {  // stage in the relabel list memory (8N bytes >= V + E)
-    vs = reinterpret_cast<uint8_t*>(pb->dev.left);
+    vs = reinterpret_cast<uint8_t*>(pb->dev.list[1][kBigList]);  // 4N bytes >= V + E, free after the BFS
     ns = nside ? vs + pb->V : nullptr;
   }
   fp_status st;
@@ -439,7 +547,7 @@ const char* kernel_kind_name(int k) {
   static const char* names[KK_COUNT] = {
       "init",      "gr_reset", "bfs_rev",       "bfs_rev_loop", "gather",
       "push",      "apply",    "round_loop",    "cut_seed",     "bfs_fwd",
-      "bfs_fwd_loop", "cut_out", "check",       "batch"};
+      "bfs_fwd_loop", "cut_out", "check",       "batch",        "bfs_collect"};
   return (k >= 0 && k < KK_COUNT) ? names[k] : "?";
 }
 

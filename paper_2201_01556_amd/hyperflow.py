@@ -50,7 +50,10 @@ class Options(ctypes.Structure):
         ("group_lanes", ctypes.c_int32),
         ("big_degree", ctypes.c_int32),
         ("profile", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 9),
+        ("gr_interval", ctypes.c_int32),
+        ("stale_rounds", ctypes.c_int32),
+        ("bottom_up_min", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 6),
     ]
 
 
