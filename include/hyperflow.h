@@ -75,13 +75,13 @@ typedef struct {
   int32_t tail_threshold;     /* frontier size at or below which a single
                                  workgroup runs the rounds; default 1024     */
   int32_t group_lanes;        /* lanes per small frontier node: 4, 8 or 16;
-                                 default 8                                   */
+                                 default 4                                   */
   int32_t big_degree;         /* nodes with more arcs go wave-per-node;
                                  default 32                                  */
   int32_t profile;            /* 1 = time every kernel launch with HIP events
                                  (see flow_problem_kernel_times)            */
   int32_t gr_interval;        /* also relabel globally after this many rounds
-                                 since the last global relabel; default 64,
+                                 since the last global relabel; default 16,
                                  -1 = only by relabel count and stale flow  */
   int32_t stale_rounds;       /* also relabel globally once the flow value
                                  stayed unchanged for this many rounds with a
@@ -91,7 +91,10 @@ typedef struct {
                                  nodes are expanded without atomics and the
                                  next level is collected by a sweep over the
                                  labels; default N/128, -1 = never          */
-  int32_t reserved[6];
+  int32_t bfs_arc_parallel;   /* 1 = BFS levels split work per arc (prefix sum
+                                 over the level's arc counts) instead of per
+                                 node; default 0                             */
+  int32_t reserved[5];
 } fp_options;
 
 /* Counters of the last solve (cumulative over warm-started solves). */

@@ -252,9 +252,9 @@ fp_options resolve_options(const fp_options* o) {
   if (o) r = *o;
   if (r.relabel_factor_x16 <= 0) r.relabel_factor_x16 = 16;
   if (r.tail_threshold <= 0) r.tail_threshold = 1024;
-  if (r.group_lanes != 4 && r.group_lanes != 8 && r.group_lanes != 16) r.group_lanes = 8;
+  if (r.group_lanes != 4 && r.group_lanes != 8 && r.group_lanes != 16) r.group_lanes = 4;
   if (r.big_degree <= 0) r.big_degree = 32;
-  if (r.gr_interval == 0) r.gr_interval = 64;
+  if (r.gr_interval == 0) r.gr_interval = 16;
   if (r.gr_interval < 0) r.gr_interval = 0;
   if (r.stale_rounds == 0) r.stale_rounds = 500;
   if (r.stale_rounds < 0) r.stale_rounds = 0;
@@ -319,7 +319,7 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
   add(N * 4ull);              // dx[0]
   add(N * 4ull);              // dx[1]
   add(((N + 31) / 32) * 4ull); // big-node bitmap
-  add(N);                     // seen bytes
+  add(((N + 31) / 32) * 4ull); // labelled hint bitmap
   add(sizeof(Ctl));           // ctl
   add(64);                    // scratch for the weight sum
   he = hipMalloc(&pb->pool, bytes);
@@ -364,7 +364,8 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
   g.dx[1] = c.take<int32_t>(N);
   uint32_t* bigbits = c.take<uint32_t>((N + 31) / 32);
   g.bigbits = bigbits;
-  g.seen = c.take<uint8_t>(N);
+  g.seen = c.take<uint32_t>((N + 31) / 32);
+  g.bfs_arc = pb->opt.bfs_arc_parallel;
   g.ctl = c.take<Ctl>(1);
   unsigned long long* wsum = c.take<unsigned long long>(1);
   g.net_off = net_off;

@@ -101,7 +101,7 @@ struct Ctl {
 };
 
 struct Dev {
-  int32_t V, E, P, NB, N, nT, big_deg, pad;
+  int32_t V, E, P, NB, N, nT, big_deg, bfs_arc;  // bfs_arc: arc-parallel BFS levels
   const int32_t* net_off;  // E+1
   const int32_t* pin_v;    // P
   const int32_t* w;        // E
@@ -117,7 +117,7 @@ struct Dev {
   int32_t* cand;           // N   relabel candidate of a node left with excess, -1 = none
   int32_t* stamp;          // N
   const uint32_t* bigbits; // ceil(N/32) words: bit v set when node v has more than big_deg arcs
-  uint8_t* seen;           // N   reverse BFS: 1 once a node has a label (hint, see label_rev)
+  uint32_t* seen;          // ceil(N/32) words: reverse BFS hint "node has a label" (see label_rev)
   int32_t* list[2][kNL];   // [parity][list]: capacities V, E, E, N
   Ctl* ctl;
 };
@@ -673,22 +673,135 @@ __device__ void phase_apply(const Dev& g, int epoch, int tile0, int tstride, int
 // reverse residual BFS from the sinks (global relabel) over the capped network
 // ---------------------------------------------------------------------------
 
-// Label v with lvl if it is unlabelled.  `seen` mirrors "labelled" in a
-// byte map small enough to stay in L2, so the common case (already labelled)
-// costs no label load; a stale 0 only repeats an identical store.  With
-// kClaim the first writer wins by compare-and-swap on the label and reports
-// it; otherwise a plain store (all writers store the same value).
+// The "labelled" hint of the reverse BFS is a bitmap small enough to stay in
+// the L2, so checking an arc whose tail is already labelled costs no access
+// to the large label array.  Bits are set with a plain read-modify-write; a
+// bit lost to a concurrent update only sends a later check to the label
+// itself, which stays the source of truth.
+__device__ __forceinline__ bool seen_bit(const Dev& g, int v) {
+  return (g.seen[v >> 5] >> (v & 31)) & 1u;
+}
+__device__ __forceinline__ void set_seen(const Dev& g, int v) {
+  g.seen[v >> 5] |= 1u << (v & 31);
+}
+
+// Label v with lvl if it is unlabelled.  With kClaim the first writer wins
+// by compare-and-swap on the label and reports it; otherwise a plain store
+// (all writers of a level store the same value).
 template <bool kClaim>
 __device__ __forceinline__ bool label_rev(const Dev& g, int v, int lvl) {
-  if (g.seen[v]) return false;
+  if (seen_bit(g, v)) return false;
   if (!kClaim) {
+    if (g.d[v] != g.N) return false;
     g.d[v] = lvl;
-    g.seen[v] = 1;
+    set_seen(g, v);
     return false;
   }
   if (atomicCAS(&g.d[v], g.N, lvl) != g.N) return false;
-  g.seen[v] = 1;
+  set_seen(g, v);
   return true;
+}
+
+// Node-grouped reverse BFS: G lanes per small node, a wave per big node.
+template <int G, bool kClaim>
+__device__ void bfs_rev_node(const Dev& g, const BlockQ& q, int x, bool has, int gl, int lvl,
+                             uint32_t& nbytes) {
+  const bool isv = has && x < g.V;
+  const bool isnet = has && x >= g.NB;
+  if (!has || isv) {
+    int beg = 0, end = 0;
+    if (isv) {
+      beg = g.vtx_off[x];
+      end = g.vtx_off[x + 1];
+    }
+    for (int base = beg; base < end; base += G) {
+      const int i = base + gl;
+      const bool valid = i < end;
+      bool vin = false, vout = false;
+      int t1 = 0;
+      if (valid) {
+        const int2 ep = g.vinc[i];
+        t1 = g.NB + 2 * ep.x;
+        // bits of e_in and e_out share a word (NB and 2e are even)
+        const uint32_t sw = g.seen[t1 >> 5] >> (t1 & 31);
+        nbytes += 12;
+        if (!(sw & 2u)) vout = label_rev<kClaim>(g, t1 + 1, lvl);  // e_out -> x infinite
+        if (!(sw & 1u) && g.w[ep.x] - g.fpin[2 * ep.y] > 0)        // e_in -> x reverse
+          vin = label_rev<kClaim>(g, t1, lvl);
+      }
+      if (kClaim) {
+        qpush(g, q, t1, vin);
+        qpush(g, q, t1 + 1, vout);
+      }
+    }
+  } else if (isnet) {
+    const int e = (x - g.NB) >> 1;
+    const bool in = ((x - g.NB) & 1) == 0;
+    const int we = g.w[e];
+    const int fbv = g.fb[e];
+    int beg = g.net_off[e], end = g.net_off[e + 1];
+    // in-arcs of e_out from pins carry flow(e_out, u) > 0; their sum is the
+    // outflow fb - excess(e_out), so a net without outflow skips its pins
+    if (!in && fbv == g.x[x] + g.dx[0][x] + g.dx[1][x]) end = beg;
+    nbytes += 16;
+    bool vb = false;
+    if (gl == 0) {
+      if (in) vb = fbv > 0 && label_rev<kClaim>(g, x + 1, lvl);    // e_out -> e_in residual fb
+      else vb = we - fbv > 0 && label_rev<kClaim>(g, x - 1, lvl);  // e_in -> e_out residual w - fb
+    }
+    if (kClaim) qpush(g, q, in ? x + 1 : x - 1, vb);
+    for (int base = beg; base < end; base += G) {
+      const int i = base + gl;
+      const bool valid = i < end;
+      bool vu = false;
+      int u = 0;
+      if (valid) {
+        u = g.pin_v[i];
+        const int f = g.fpin[2 * i + (in ? 0 : 1)];  // r_in (u->e_in) or f_out (u->e_out)
+        nbytes += 12;
+        if (f > 0) vu = label_rev<kClaim>(g, u, lvl);
+      }
+      if (kClaim) qpush(g, q, u, vu);
+    }
+  }
+}
+
+template <int G, bool kClaim>
+__device__ void phase_bfs_rev_node(const Dev& g, int level, int tile0, int tstride, int kc,
+                                   lds_int* lds) {
+  // frontier of level `level` -> label level+1
+  const int c3 = level % 3, n3 = (level + 1) % 3, z3 = (level + 2) % 3;
+  if (tile0 == 0 && threadIdx.x < kNL) g.ctl->bcnt[z3][threadIdx.x] = 0;
+  const int cp = level & 1, np = (level + 1) & 1;
+  const BlockQ q = bq_bind(lds, g.ctl->bcnt[n3], g.list[np]);
+  const Items<G> its(g.ctl->bcnt[c3]);
+  constexpr int NPW = kWave / G;
+  const int total = its.total();
+  const int wpb = blockDim.x >> 6, wid = threadIdx.x >> 6;
+  const int ntiles = (total + wpb - 1) / wpb;
+  const int lane = lane_id();
+  uint32_t nbytes = 0, nitems = 0;
+  for (int tile = tile0; tile < ntiles; tile += tstride) {
+    const int it = tile * wpb + wid;
+    if (it < total) {
+      const int k = its.list_of_item(it);
+      if (k < kBigList) {
+        const int idx = (it - its.start[k]) * NPW + lane / G;
+        const bool has = idx < its.n[k];
+        const int v = has ? g.list[cp][k][idx] : 0;
+        nitems += has && (lane % G) == 0;
+        bfs_rev_node<G, kClaim>(g, q, v, has, lane % G, level + 1, nbytes);
+      } else {
+        const int v = g.list[cp][kBigList][it - its.start[kBigList]];
+        nitems += lane == 0;
+        bfs_rev_node<kWave, kClaim>(g, q, v, true, lane, level + 1, nbytes);
+      }
+    }
+    if (kClaim) bq_tile_end(q, kBCap / 2);
+  }
+  if (kClaim) bq_flush(q);
+  wave_add_u64(&g.ctl->bytes[kc], (unsigned long long)nbytes + 4ull * nitems);
+  wave_add_u64(&g.ctl->items[kc], nitems);
 }
 
 // ---------------------------------------------------------------------------
@@ -821,10 +934,10 @@ __device__ void phase_bfs_rev_lb(const Dev& g, int level, int tile0, int tstride
           const int e = ep.x;
           t1 = g.NB + 2 * e;
           t2 = t1 + 1;
-          const uint16_t sb = *reinterpret_cast<const uint16_t*>(g.seen + t1);
-          nbytes += 10;
-          if (!(sb >> 8)) v2 = label_rev<kClaim>(g, t2, lvl);  // e_out -> x infinite
-          if (!(sb & 0xff) && g.w[e] - g.fpin[2 * ep.y] > 0)   // e_in -> x reverse
+          const uint32_t sw = g.seen[t1 >> 5] >> (t1 & 31);
+          nbytes += 12;
+          if (!(sw & 2u)) v2 = label_rev<kClaim>(g, t2, lvl);  // e_out -> x infinite
+          if (!(sw & 1u) && g.w[e] - g.fpin[2 * ep.y] > 0)     // e_in -> x reverse
             v1 = label_rev<kClaim>(g, t1, lvl);
         } else {
           const int e = (x - g.NB) >> 1;
@@ -923,7 +1036,8 @@ __device__ void phase_bfs_fwd_lb(const Dev& g, int level, int ep, int tile0, int
 template <int G>
 __device__ void phase_bfs_rev(const Dev& g, int level, int tile0, int tstride, int kc,
                               lds_int* lds) {
-  phase_bfs_rev_lb<true>(g, level, tile0, tstride, kc, lds);
+  if (g.bfs_arc) phase_bfs_rev_lb<true>(g, level, tile0, tstride, kc, lds);
+  else phase_bfs_rev_node<G, true>(g, level, tile0, tstride, kc, lds);
 }
 
 // Large levels run in two steps without claiming atomics: expand the level
@@ -933,7 +1047,8 @@ __device__ void phase_bfs_rev(const Dev& g, int level, int tile0, int tstride, i
 template <int G>
 __device__ void phase_bfs_rev_expand(const Dev& g, int level, int tile0, int tstride, int kc,
                                      lds_int* lds) {
-  phase_bfs_rev_lb<false>(g, level, tile0, tstride, kc, lds);
+  if (g.bfs_arc) phase_bfs_rev_lb<false>(g, level, tile0, tstride, kc, lds);
+  else phase_bfs_rev_node<G, false>(g, level, tile0, tstride, kc, lds);
 }
 
 // Sweep tiles: 2 nodes per thread, so a tile appends at most 2 * blockDim
@@ -1037,13 +1152,25 @@ __device__ void phase_gr_reset(const Dev& g, int tile0, int tstride, lds_int* ld
           lab = g.N + 1;
         }
         g.d[v] = lab;
-        g.seen[v] = lab != g.N;
       }
       qpush(g, q, v, seed);
     }
     bq_tile_end(q, 2 * blockDim.x);
   }
   bq_flush(q);
+  // labelled hint: sinks, sources and padding start labelled
+  const int words = (g.N + 31) >> 5;
+  for (int w = tile0 * blockDim.x + threadIdx.x; w < words; w += tstride * blockDim.x) {
+    uint32_t m = 0;
+    const int v0 = w << 5;
+    if (v0 < g.NB) {
+      for (int b = 0; b < 32; ++b) {
+        const int v = v0 + b;
+        if (v >= g.V ? v < g.NB : g.role[v] != 0) m |= 1u << b;
+      }
+    }
+    g.seen[w] = m;
+  }
 }
 
 // Global relabel, step 3: fold outstanding excess deltas; frontier =

@@ -53,7 +53,8 @@ class Options(ctypes.Structure):
         ("gr_interval", ctypes.c_int32),
         ("stale_rounds", ctypes.c_int32),
         ("bottom_up_min", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 6),
+        ("bfs_arc_parallel", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
     ]
 
 
