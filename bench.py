@@ -37,8 +37,9 @@ def main():
     ap.add_argument("--nets", type=int, default=2_000_000)
     ap.add_argument("--size-hi", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-profile", action="store_true",
-                    help="do not time kernels with HIP events during the timed steps")
+    ap.add_argument("--profile", type=int, default=2,
+                    help="HIP-event timing inside the timed steps: 0 off, 1 every kernel, "
+                         "2 only the reverse-BFS level kernel (the dominant one)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -68,7 +69,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step(profile):
-        opts = hyperflow.Options(profile=1 if profile else 0)
+        opts = hyperflow.Options(profile=profile)
         h = hyperflow.flow_problem_create(V, *arrays, options=opts, stream=stream)
         try:
             F = hyperflow.maxflow_solve(h, stream)
@@ -79,7 +80,7 @@ def main():
             hyperflow.flow_problem_destroy(h)
         return F, st, kt
 
-    profile = not args.no_profile
+    profile = args.profile
     for i in range(args.warmup):
         _log(f"warmup {i}")
         step(profile)

@@ -78,8 +78,9 @@ typedef struct {
                                  default 4                                   */
   int32_t big_degree;         /* nodes with more arcs go wave-per-node;
                                  default 32                                  */
-  int32_t profile;            /* 1 = time every kernel launch with HIP events
-                                 (see flow_problem_kernel_times)            */
+  int32_t profile;            /* 1 = time every kernel launch with HIP events,
+                                 2 = only the reverse-BFS level kernel (see
+                                 flow_problem_kernel_times)                  */
   int32_t gr_interval;        /* also relabel globally after this many rounds
                                  since the last global relabel; default 16,
                                  -1 = only by relabel count and stale flow  */

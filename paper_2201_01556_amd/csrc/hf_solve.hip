@@ -198,7 +198,9 @@ struct Launch {
   hipStream_t s;
   Timer t;
   bool on;
-  Launch(fp_problem* p, hipStream_t st, int kind) : pb(p), s(st), on(p->opt.profile != 0) {
+  // profile 1: every kernel; profile 2: only the reverse-BFS level kernel
+  Launch(fp_problem* p, hipStream_t st, int kind)
+      : pb(p), s(st), on(p->opt.profile == 1 || (p->opt.profile == 2 && kind == KK_BFS_REV)) {
     if (on) prof_begin(pb, kind, s, &t);
   }
   ~Launch() {
