@@ -175,19 +175,98 @@ fp_status mincut_source_side(fp_problem *problem, void *hip_stream, int32_t mem_
 /*
  * flow_batch_solve: solve many independent problems in one persistent
  * launch (one workgroup per problem, largest first), with the same device
- * arithmetic as maxflow_solve.  Problems may differ in size.
+ * phases as maxflow_solve.  Problems may differ in size.  Equivalent to
+ * flow_batch_create (no cut outputs, default configuration),
+ * flow_batch_run and flow_batch_destroy.
  *
- *   problems     count handles created on the current device
+ *   problems     count handles created on the current device, pairwise
+ *                distinct
  *   skip         count bytes or NULL; skip[i] != 0 leaves problem i alone
  *                and reports flow_values[i] = -1
  *   flow_values  host out, count entries
  *
  * After FP_OK every solved handle behaves as after maxflow_solve
- * (mincut_source_side may be called on it).
+ * (mincut_source_side may be called on it).  Errors: FP_ERR_INVALID,
+ * FP_ERR_ABORTED (a problem's round budget ran out; the others are solved),
+ * FP_ERR_DEVICE.
  */
 fp_status flow_batch_solve(fp_problem *const *problems, int32_t count,
                            const uint8_t *skip, void *hip_stream,
                            int64_t *flow_values);
+
+/*
+ * Batch plans: the persistent batched solve of a fixed set of problems as a
+ * captured HIP graph (descriptor upload, queue reset, the persistent kernel,
+ * result download), replayed by flow_batch_run.  Pattern of the paper's
+ * refinement scheduler (section "Parallel Active Block Scheduling"): many
+ * block-pair flow problems solved concurrently; here each problem runs
+ * inside one workgroup and workgroups take problems from a shared queue,
+ * largest (pins + network nodes) first.
+ */
+typedef struct fp_batch fp_batch; /* opaque, library-owned */
+
+typedef struct {
+  int32_t group_lanes;   /* lanes per small frontier node: 4, 8 or 16;
+                            0 = 4                                          */
+  int32_t block_threads; /* threads per workgroup: 256 or 1024; 0 = 1024    */
+  int32_t gr_interval;   /* rounds between global relabels, -1 = off;
+                            0 = each problem's own option                  */
+  int32_t workgroups;    /* persistent workgroups; 0 = as many as fit on
+                            the device at once (at most one per problem)   */
+  int32_t reserved[4];
+} fp_batch_config;
+
+/*
+ * flow_batch_create: plan a batch over count distinct problems.
+ *
+ *   vertex_sides, net_sides  count device pointers each, or NULL: where
+ *                flow_batch_run(..., with_cut = 1, ...) writes problem i's
+ *                minimal source side (layout as mincut_source_side; a NULL
+ *                entry of net_sides skips that output)
+ *   config       NULL for defaults
+ *
+ * The pointer arrays are copied; the buffers they point to must stay valid
+ * while the plan is used.  Errors: FP_ERR_INVALID, FP_ERR_OOM, FP_ERR_DEVICE.
+ */
+fp_status flow_batch_create(fp_problem *const *problems, int32_t count,
+                            uint8_t *const *vertex_sides, uint8_t *const *net_sides,
+                            const fp_batch_config *config, void *hip_stream,
+                            fp_batch **out);
+
+/*
+ * flow_batch_run: solve every problem not skipped (warm: a problem that was
+ * solved or pierced before continues from its flow; a fresh or reset one
+ * starts from zero), and with with_cut = 1 also write its minimal source
+ * side.  flow_values as in flow_batch_solve.  Skipped problems are not
+ * touched.  Errors as flow_batch_solve; FP_ERR_INVALID when with_cut = 1
+ * but the plan has no vertex_sides.
+ */
+fp_status flow_batch_run(fp_batch *batch, const uint8_t *skip, int32_t with_cut,
+                         void *hip_stream, int64_t *flow_values);
+
+/*
+ * flow_batch_tune: time candidate configurations (lanes per node, block
+ * size, global relabel interval) on this batch, each run from the zero flow,
+ * and keep the fastest.  With a cache_path (or NULL), a configuration stored
+ * under the batch's signature (device, problem count, total pins, total
+ * network nodes) is reused without timing, and a newly timed one is
+ * appended.  Leaves every problem solved.  chosen may be NULL.
+ */
+fp_status flow_batch_tune(fp_batch *batch, void *hip_stream, const char *cache_path,
+                          fp_batch_config *chosen);
+
+/* Current configuration of the plan (host out). */
+fp_status flow_batch_get_config(const fp_batch *batch, fp_batch_config *out);
+
+/* Release the plan (the problems stay).  NULL is ignored. */
+void flow_batch_destroy(fp_batch *batch);
+
+/*
+ * flow_problem_reset: forget the flow; the next solve starts from the zero
+ * flow with the handle's current terminals.  Used to time or re-tune solves
+ * of the same problem.
+ */
+fp_status flow_problem_reset(fp_problem *problem);
 
 /*
  * flow_problem_pierce: turn vertices into terminals for the next solve of an

@@ -3,8 +3,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "hf_host.h"
 
@@ -114,19 +116,129 @@ fp_status mincut_source_side(fp_problem* problem, void* hip_stream, int32_t mem_
                      net_side);
 }
 
-fp_status flow_batch_solve(fp_problem* const* problems, int32_t count, const uint8_t* skip,
-                           void* hip_stream, int64_t* flow_values) {
-  g_last_error.clear();
-  if (count < 0 || (count > 0 && (!problems || !flow_values))) {
+// distinct, non-NULL handles on the current device
+static fp_status check_batch_problems(fp_problem* const* problems, int32_t count) {
+  if (count < 0 || (count > 0 && !problems)) {
     set_error("invalid batch arguments");
     return FP_ERR_INVALID;
   }
-  for (int32_t i = 0; i < count; ++i)
+  int dev = 0;
+  hipGetDevice(&dev);
+  std::vector<fp_problem*> seen(problems, problems + count);
+  std::sort(seen.begin(), seen.end());
+  for (int32_t i = 0; i < count; ++i) {
     if (!problems[i]) {
       set_error("problem %d is NULL", i);
       return FP_ERR_INVALID;
     }
+    if (problems[i]->device != dev) {
+      set_error("problem %d lives on device %d, the current device is %d", i,
+                problems[i]->device, dev);
+      return FP_ERR_INVALID;
+    }
+    if (i > 0 && seen[i] == seen[i - 1]) {
+      set_error("a problem appears twice in the batch");
+      return FP_ERR_INVALID;
+    }
+  }
+  return FP_OK;
+}
+
+fp_status flow_batch_solve(fp_problem* const* problems, int32_t count, const uint8_t* skip,
+                           void* hip_stream, int64_t* flow_values) {
+  g_last_error.clear();
+  fp_status st = check_batch_problems(problems, count);
+  if (st) return st;
+  if (count > 0 && !flow_values) {
+    set_error("flow_values is NULL");
+    return FP_ERR_INVALID;
+  }
   return batch_solve(problems, count, skip, static_cast<hipStream_t>(hip_stream), flow_values);
+}
+
+fp_status flow_batch_create(fp_problem* const* problems, int32_t count,
+                            uint8_t* const* vertex_sides, uint8_t* const* net_sides,
+                            const fp_batch_config* config, void* hip_stream, fp_batch** out) {
+  g_last_error.clear();
+  if (!out) {
+    set_error("out is NULL");
+    return FP_ERR_INVALID;
+  }
+  *out = nullptr;
+  fp_status st = check_batch_problems(problems, count);
+  if (st) return st;
+  if (net_sides && !vertex_sides) {
+    set_error("net_sides given without vertex_sides");
+    return FP_ERR_INVALID;
+  }
+  if (vertex_sides)
+    for (int32_t i = 0; i < count; ++i)
+      if (!vertex_sides[i]) {
+        set_error("vertex_sides[%d] is NULL", i);
+        return FP_ERR_INVALID;
+      }
+  if (config) {
+    fp_batch_config c = *config;
+    if (c.group_lanes == 0) c.group_lanes = 4;
+    if (c.block_threads == 0) c.block_threads = 1024;
+    if (!((c.group_lanes == 4 || c.group_lanes == 8 || c.group_lanes == 16) &&
+          (c.block_threads == 256 || c.block_threads == 1024) && c.gr_interval >= -1 &&
+          c.workgroups >= 0)) {
+      set_error("invalid batch configuration");
+      return FP_ERR_INVALID;
+    }
+  }
+  return create_batch(problems, count, vertex_sides, net_sides, config,
+                      static_cast<hipStream_t>(hip_stream), out);
+}
+
+fp_status flow_batch_run(fp_batch* batch, const uint8_t* skip, int32_t with_cut, void* hip_stream,
+                         int64_t* flow_values) {
+  g_last_error.clear();
+  if (!batch) {
+    set_error("NULL batch");
+    return FP_ERR_STATE;
+  }
+  if (with_cut != 0 && with_cut != 1) {
+    set_error("with_cut must be 0 or 1");
+    return FP_ERR_INVALID;
+  }
+  return run_batch(batch, skip, with_cut, static_cast<hipStream_t>(hip_stream), flow_values);
+}
+
+fp_status flow_batch_tune(fp_batch* batch, void* hip_stream, const char* cache_path,
+                          fp_batch_config* chosen) {
+  g_last_error.clear();
+  if (!batch) {
+    set_error("NULL batch");
+    return FP_ERR_STATE;
+  }
+  return tune_batch(batch, static_cast<hipStream_t>(hip_stream), cache_path, chosen);
+}
+
+fp_status flow_batch_get_config(const fp_batch* batch, fp_batch_config* out) {
+  if (!batch || !out) {
+    set_error("NULL argument");
+    return FP_ERR_INVALID;
+  }
+  return batch_config(batch, out);
+}
+
+void flow_batch_destroy(fp_batch* batch) {
+  if (!batch) return;
+  release_batch(batch);
+  delete batch;
+}
+
+fp_status flow_problem_reset(fp_problem* problem) {
+  g_last_error.clear();
+  if (!problem) {
+    set_error("NULL handle");
+    return FP_ERR_STATE;
+  }
+  problem->inited = false;
+  problem->solved = false;
+  return FP_OK;
 }
 
 fp_status flow_problem_pierce(fp_problem* problem, int32_t side, const int32_t* vertices,

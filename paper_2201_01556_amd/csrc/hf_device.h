@@ -54,7 +54,6 @@ namespace hf {
 
 constexpr int kWave = 64;
 constexpr int kInf = 0x7fffffff;
-constexpr int kQCap = 128;  // LDS staging entries per wave and list
 
 // error bits reported through Ctl::err
 enum : int32_t {
@@ -77,6 +76,7 @@ enum : int {
   KC_BFS_FWD = 3,
   KC_LOOP_ROUNDS = 4,
   KC_LOOP_BFS = 5,
+  KC_BATCH = 6,
   KC_N = 8
 };
 
@@ -155,6 +155,28 @@ __device__ __forceinline__ int g_min(int v) {
   return v;
 }
 
+// Loads that bypass the compiler's value caching (counters written by other
+// waves between workgroup barriers).
+__device__ __forceinline__ int ld_vol(const int32_t* p) {
+  return *reinterpret_cast<const volatile int32_t*>(p);
+}
+__device__ __forceinline__ unsigned long long ld_vol64(const unsigned long long* p) {
+  return *reinterpret_cast<const volatile unsigned long long*>(p);
+}
+
+__device__ __forceinline__ int count_all(const int32_t* c) {
+  int n = 0;
+#pragma unroll
+  for (int k = 0; k < kNL; ++k) n += c[k];
+  return n;
+}
+__device__ __forceinline__ int count_all_vol(const int32_t* c) {
+  int n = 0;
+#pragma unroll
+  for (int k = 0; k < kNL; ++k) n += ld_vol(c + k);
+  return n;
+}
+
 __device__ __forceinline__ int deg_of(const Dev& g, int v) {
   if (v < g.V) return g.vtx_off[v + 1] - g.vtx_off[v];
   const int e = (v - g.NB) >> 1;
@@ -173,17 +195,23 @@ __device__ __forceinline__ int deg_of(const Dev& g, int v) {
 // excess straight to the global list (one global atomic for that wave).
 // ---------------------------------------------------------------------------
 
-constexpr int kBCap = 4096;                    // staged entries per list and block
-constexpr int kBQWords = kNL * kBCap + 2 * kNL;  // LDS words of one block queue
+// Staged entries per list: 4 per thread of the workgroup.  LDS words of a
+// workgroup's staging area plus the arc tile of the arc-parallel BFS levels:
+constexpr int kQPerThread = 4;
+constexpr int lds_words(int block) {
+  return kNL * kQPerThread * block + 2 * kNL + 3 * block + 1 + 32;
+}
+__device__ __forceinline__ int bq_words() { return kNL * kQPerThread * (int)blockDim.x + 2 * kNL; }
 
 typedef __attribute__((address_space(3))) int32_t lds_int;
 
 struct BlockQ {
-  lds_int* buf;         // [kNL][kBCap]
-  lds_int* n;           // [kNL] staged counts (may exceed kBCap after overflow)
+  lds_int* buf;         // [kNL][cap]
+  lds_int* n;           // [kNL] staged counts (may exceed cap after overflow)
   lds_int* base;        // [kNL] global base of the current flush
   int32_t* gcnt;        // global counts [kNL]
   int32_t* dst[kNL];    // global lists
+  int cap;              // staged entries per list
 };
 
 __device__ __forceinline__ int lds_add(lds_int* p, int v) {
@@ -193,9 +221,10 @@ __device__ __forceinline__ int lds_add(lds_int* p, int v) {
 // Block-uniform: every thread of the workgroup calls it.
 __device__ __forceinline__ BlockQ bq_bind(lds_int* lds, int32_t* gcnt, int32_t* const lists[kNL]) {
   BlockQ q;
+  q.cap = kQPerThread * (int)blockDim.x;
   q.buf = lds;
-  q.n = lds + kNL * kBCap;
-  q.base = lds + kNL * kBCap + kNL;
+  q.n = lds + kNL * q.cap;
+  q.base = lds + kNL * q.cap + kNL;
   q.gcnt = gcnt;
 #pragma unroll
   for (int k = 0; k < kNL; ++k) q.dst[k] = lists[k];
@@ -215,16 +244,16 @@ __device__ __forceinline__ void bq_push1(const BlockQ& q, int k, int v, bool pre
   if (lane_id() == leader) pos = lds_add(q.n + k, cnt);
   pos = __shfl(pos, leader);
   const int rank = __popcll(m & lanemask_lt());
-  const int room = max(0, kBCap - pos);
+  const int room = max(0, q.cap - pos);
   if (cnt <= room) {
-    if (pred) q.buf[k * kBCap + pos + rank] = v;
+    if (pred) q.buf[k * q.cap + pos + rank] = v;
     return;
   }
   int gb = 0;
   if (lane_id() == leader) gb = atomicAdd(&q.gcnt[k], cnt - room);
   gb = __shfl(gb, leader);
   if (pred) {
-    if (rank < room) q.buf[k * kBCap + pos + rank] = v;
+    if (rank < room) q.buf[k * q.cap + pos + rank] = v;
     else q.dst[k][gb + rank - room] = v;
   }
 }
@@ -251,15 +280,15 @@ __device__ __forceinline__ void bq_flush(const BlockQ& q) {
   __syncthreads();
   if (threadIdx.x < kNL) {
     const int k = threadIdx.x;
-    const int c = min((int)q.n[k], kBCap);
+    const int c = min((int)q.n[k], q.cap);
     q.base[k] = c ? atomicAdd(&q.gcnt[k], c) : 0;
   }
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kNL; ++k) {
-    const int c = min((int)q.n[k], kBCap);
+    const int c = min((int)q.n[k], q.cap);
     const int b = q.base[k];
-    for (int i = threadIdx.x; i < c; i += blockDim.x) q.dst[k][b + i] = q.buf[k * kBCap + i];
+    for (int i = threadIdx.x; i < c; i += blockDim.x) q.dst[k][b + i] = q.buf[k * q.cap + i];
   }
   __syncthreads();
   if (threadIdx.x < kNL) q.n[threadIdx.x] = 0;
@@ -273,7 +302,7 @@ __device__ __forceinline__ void bq_tile_end(const BlockQ& q, int reserve) {
 #pragma unroll
   for (int k = 0; k < kNL; ++k) mx = max(mx, (int)q.n[k]);
   __syncthreads();  // every thread has read the counts before anyone appends
-  if (mx > kBCap - reserve) bq_flush(q);
+  if (mx > q.cap - reserve) bq_flush(q);
 }
 
 // Four values selected by a runtime index without a local array (which would
@@ -620,7 +649,7 @@ __device__ void phase_push(const Dev& g, int epoch, int tile0, int tstride, int 
         push_node<kWave>(g, ra, q, v, true, lane, nbytes, to_sink);
       }
     }
-    bq_tile_end(q, kBCap / 2);
+    bq_tile_end(q, q.cap / 2);
   }
   bq_flush(q);
   wave_add_u64(&g.ctl->flow, to_sink);
@@ -797,7 +826,7 @@ __device__ void phase_bfs_rev_node(const Dev& g, int level, int tile0, int tstri
         bfs_rev_node<kWave, kClaim>(g, q, v, true, lane, level + 1, nbytes);
       }
     }
-    if (kClaim) bq_tile_end(q, kBCap / 2);
+    if (kClaim) bq_tile_end(q, q.cap / 2);
   }
   if (kClaim) bq_flush(q);
   wave_add_u64(&g.ctl->bytes[kc], (unsigned long long)nbytes + 4ull * nitems);
@@ -814,8 +843,8 @@ __device__ void phase_bfs_rev_node(const Dev& g, int level, int tile0, int tstri
 // over the whole workgroup.  Arc 0 of a net node is its bridge.
 // ---------------------------------------------------------------------------
 
-constexpr int kMaxBlock = 1024;
-constexpr int kTileWords = 3 * kMaxBlock + 1 + 32;  // node, beg, off[+1], wave sums
+// tile area after the staging area: node[bd], beg[bd], off[bd + 1], wave
+// sums[32] (bd = blockDim, at most 1024)
 
 struct ArcTile {
   lds_int* node;
@@ -827,9 +856,10 @@ struct ArcTile {
 __device__ __forceinline__ ArcTile arc_tile(lds_int* lds) {
   ArcTile t;
   t.node = lds;
-  t.beg = lds + kMaxBlock;
-  t.off = lds + 2 * kMaxBlock;
-  t.wsum = lds + 3 * kMaxBlock + 1;
+  const int bd = blockDim.x;
+  t.beg = lds + bd;
+  t.off = lds + 2 * bd;
+  t.wsum = lds + 3 * bd + 1;
   return t;
 }
 
@@ -911,7 +941,7 @@ __device__ void phase_bfs_rev_lb(const Dev& g, int level, int tile0, int tstride
   if (tile0 == 0 && threadIdx.x < kNL) g.ctl->bcnt[z3][threadIdx.x] = 0;
   const int cp = level & 1, np = (level + 1) & 1;
   const BlockQ q = bq_bind(lds, g.ctl->bcnt[n3], g.list[np]);
-  const ArcTile t = arc_tile(lds + kBQWords);
+  const ArcTile t = arc_tile(lds + bq_words());
   const Prefix4 pre(load_counts(g.ctl->bcnt[c3]));
   const int ntiles = (pre.total + blockDim.x - 1) / blockDim.x;
   const int lvl = level + 1;
@@ -976,7 +1006,7 @@ __device__ void phase_bfs_fwd_lb(const Dev& g, int level, int ep, int tile0, int
   if (tile0 == 0 && threadIdx.x < kNL) g.ctl->bcnt[z3][threadIdx.x] = 0;
   const int cp = level & 1, np = (level + 1) & 1;
   const BlockQ q = bq_bind(lds, g.ctl->bcnt[n3], g.list[np]);
-  const ArcTile t = arc_tile(lds + kBQWords);
+  const ArcTile t = arc_tile(lds + bq_words());
   const Prefix4 pre(load_counts(g.ctl->bcnt[c3]));
   const int ntiles = (pre.total + blockDim.x - 1) / blockDim.x;
   uint32_t nbytes = 0, narcs = 0;

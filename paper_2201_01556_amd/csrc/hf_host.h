@@ -79,6 +79,14 @@ fp_status cut_problem(fp_problem* pb, hipStream_t s, int32_t mem_kind, uint8_t* 
                       uint8_t* nside);
 fp_status batch_solve(fp_problem* const* pbs, int32_t count, const uint8_t* skip,
                       hipStream_t s, int64_t* flows);
+fp_status create_batch(fp_problem* const* pbs, int32_t count, uint8_t* const* vsides,
+                       uint8_t* const* nsides, const fp_batch_config* config, hipStream_t s,
+                       fp_batch** out);
+fp_status run_batch(fp_batch* b, const uint8_t* skip, int32_t with_cut, hipStream_t s,
+                    int64_t* flows);
+fp_status tune_batch(fp_batch* b, hipStream_t s, const char* cache_path, fp_batch_config* chosen);
+fp_status batch_config(const fp_batch* b, fp_batch_config* out);
+void release_batch(fp_batch* b);
 fp_status pierce_problem(fp_problem* pb, int32_t side, const int32_t* vertices, int32_t n,
                          hipStream_t s);
 fp_status export_state(fp_problem* pb, hipStream_t s, int32_t* f_in, int32_t* f_out,

@@ -20,33 +20,13 @@ constexpr int kMaxFrontierBlocks = 512;
 constexpr int kMaxSweepBlocks = 256;
 constexpr long long kRoundGuard = 200000000ll;  // rounds per solve before giving up
 
-__device__ __forceinline__ int ld_vol(const int32_t* p) {
-  return *reinterpret_cast<const volatile int32_t*>(p);
-}
-__device__ __forceinline__ unsigned long long ld_vol64(const unsigned long long* p) {
-  return *reinterpret_cast<const volatile unsigned long long*>(p);
-}
-
-__device__ __forceinline__ int count_all(const int32_t* c) {
-  int n = 0;
-#pragma unroll
-  for (int k = 0; k < kNL; ++k) n += c[k];
-  return n;
-}
-__device__ __forceinline__ int count_all_vol(const int32_t* c) {
-  int n = 0;
-#pragma unroll
-  for (int k = 0; k < kNL; ++k) n += ld_vol(c + k);
-  return n;
-}
-
 __device__ __forceinline__ int gwave() { return (blockIdx.x * blockDim.x + threadIdx.x) >> 6; }
 __device__ __forceinline__ int gwaves() { return (gridDim.x * blockDim.x) >> 6; }
 __device__ __forceinline__ int gthread() { return blockIdx.x * blockDim.x + threadIdx.x; }
 __device__ __forceinline__ int gthreads() { return gridDim.x * blockDim.x; }
 
 // LDS staging area of the workgroup's list appends
-#define HF_QUEUE_LDS __shared__ int32_t hf_bq[kBQWords + kTileWords]; lds_int* const lds = (lds_int*)hf_bq
+#define HF_QUEUE_LDS __shared__ int32_t hf_bq[lds_words(kBlock)]; lds_int* const lds = (lds_int*)hf_bq
 
 __global__ void __launch_bounds__(kThreads) k_init(Dev g) { phase_init(g, gthread(), gthreads()); }
 
@@ -518,20 +498,6 @@ fp_status cut_problem(fp_problem* pb, hipStream_t s, int32_t mem_kind, uint8_t* 
       he = hipMemcpyAsync(nside, ns, pb->E, hipMemcpyDeviceToHost, s);
     if (he == hipSuccess) he = hipStreamSynchronize(s);
     if (he != hipSuccess) return hip_fail(he, "copying the cut to the host");
-  }
-  return FP_OK;
-}
-
-fp_status batch_solve(fp_problem* const* pbs, int32_t count, const uint8_t* skip,
-                      hipStream_t s, int64_t* flows) {
-  // plain schedule: one problem after the other with the same kernels
-  for (int32_t i = 0; i < count; ++i) {
-    if (skip && skip[i]) {
-      flows[i] = -1;
-      continue;
-    }
-    fp_status st = solve_problem(pbs[i], s, &flows[i]);
-    if (st) return st;
   }
   return FP_OK;
 }

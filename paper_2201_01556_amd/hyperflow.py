@@ -8,9 +8,11 @@ first call raises.
 
 The C entry points are exposed under their own names
 (``flow_problem_create``, ``maxflow_solve``, ``mincut_source_side``,
-``flow_batch_solve``, ``flow_problem_pierce``, ``flow_problem_stats``,
+``flow_batch_solve``, ``flow_batch_create``, ``flow_batch_run``,
+``flow_batch_tune``, ``flow_batch_get_config``, ``flow_batch_destroy``,
+``flow_problem_reset``, ``flow_problem_pierce``, ``flow_problem_stats``,
 ``flow_problem_kernel_times``, ``flow_problem_destroy``, ``fp_last_error``)
-plus a small :class:`FlowProblem` owner class.
+plus small owner classes :class:`FlowProblem` and :class:`FlowBatch`.
 """
 from __future__ import annotations
 
@@ -72,11 +74,30 @@ class Stats(ctypes.Structure):
     ]
 
 
+class BatchConfig(ctypes.Structure):
+    _fields_ = [
+        ("group_lanes", ctypes.c_int32),
+        ("block_threads", ctypes.c_int32),
+        ("gr_interval", ctypes.c_int32),
+        ("workgroups", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
+
+
 EXPORTED = [
     "flow_problem_create",
     "maxflow_solve",
     "mincut_source_side",
     "flow_batch_solve",
+    "flow_batch_create",
+    "flow_batch_run",
+    "flow_batch_tune",
+    "flow_batch_get_config",
+    "flow_batch_destroy",
+    "flow_problem_reset",
     "flow_problem_pierce",
     "flow_problem_stats",
     "flow_problem_kernel_times",
@@ -108,6 +129,19 @@ def load_library(path: str = LIB_PATH):
     lib.mincut_source_side.restype = ctypes.c_int
     lib.flow_batch_solve.argtypes = [ctypes.POINTER(vp), i32, vp, vp, vp]
     lib.flow_batch_solve.restype = ctypes.c_int
+    lib.flow_batch_create.argtypes = [ctypes.POINTER(vp), i32, vp, vp,
+                                      ctypes.POINTER(BatchConfig), vp, ctypes.POINTER(vp)]
+    lib.flow_batch_create.restype = ctypes.c_int
+    lib.flow_batch_run.argtypes = [vp, vp, i32, vp, vp]
+    lib.flow_batch_run.restype = ctypes.c_int
+    lib.flow_batch_tune.argtypes = [vp, vp, ctypes.c_char_p, ctypes.POINTER(BatchConfig)]
+    lib.flow_batch_tune.restype = ctypes.c_int
+    lib.flow_batch_get_config.argtypes = [vp, ctypes.POINTER(BatchConfig)]
+    lib.flow_batch_get_config.restype = ctypes.c_int
+    lib.flow_batch_destroy.argtypes = [vp]
+    lib.flow_batch_destroy.restype = None
+    lib.flow_problem_reset.argtypes = [vp]
+    lib.flow_problem_reset.restype = ctypes.c_int
     lib.flow_problem_pierce.argtypes = [vp, i32, vp, i32, vp]
     lib.flow_problem_pierce.restype = ctypes.c_int
     lib.flow_problem_stats.argtypes = [vp, ctypes.POINTER(Stats)]
@@ -215,8 +249,7 @@ def mincut_source_side(handle, num_vertices, num_nets, vertex_side=None, net_sid
 def flow_batch_solve(handles, skip=None, stream=None) -> np.ndarray:
     lib = load_library()
     n = len(handles)
-    arr = (ctypes.c_void_p * max(n, 1))(*[h.value if isinstance(h, ctypes.c_void_p) else h
-                                          for h in handles])
+    arr = _handle_array(handles)
     flows = np.zeros(max(n, 1), dtype=np.int64)
     sk = None
     if skip is not None:
@@ -224,6 +257,82 @@ def flow_batch_solve(handles, skip=None, stream=None) -> np.ndarray:
         sk = skip_arr.ctypes.data
     _check(lib.flow_batch_solve(arr, n, sk, _stream_ptr(stream), flows.ctypes.data))
     return flows[:n]
+
+
+def _handle_array(handles):
+    n = len(handles)
+    return (ctypes.c_void_p * max(n, 1))(*[h.value if isinstance(h, ctypes.c_void_p) else h
+                                           for h in handles])
+
+
+def flow_batch_create(handles, vertex_sides=None, net_sides=None,
+                      config: BatchConfig | None = None, stream=None):
+    """Plan a batch.  ``vertex_sides`` / ``net_sides``: lists of device
+    uint8 tensors (one per problem) that ``flow_batch_run(with_cut=1)``
+    fills, or None."""
+    lib = load_library()
+    n = len(handles)
+    arr = _handle_array(handles)
+
+    def ptrs(bufs):
+        if bufs is None:
+            return None, None
+        if len(bufs) != n:
+            raise ValueError("one output buffer per problem")
+        out = []
+        for b in bufs:
+            if b is None:
+                out.append(0)
+                continue
+            p, kind, _ = _ptr(b, np.uint8)
+            if kind != 1:
+                raise TypeError("batch cut outputs must be device tensors")
+            out.append(p)
+        a = (ctypes.c_void_p * max(n, 1))(*out)
+        return a, a
+    vs, _ = ptrs(vertex_sides)
+    ns, _ = ptrs(net_sides)
+    h = ctypes.c_void_p()
+    _check(lib.flow_batch_create(arr, n, vs, ns, ctypes.byref(config) if config else None,
+                                 _stream_ptr(stream), ctypes.byref(h)))
+    return h
+
+
+def flow_batch_run(batch, count: int, skip=None, with_cut: bool = False,
+                   stream=None) -> np.ndarray:
+    flows = np.zeros(max(count, 1), dtype=np.int64)
+    sk = None
+    if skip is not None:
+        skip_arr = np.ascontiguousarray(skip, dtype=np.uint8)
+        if skip_arr.shape[0] != count:
+            raise ValueError("skip needs one entry per problem")
+        sk = skip_arr.ctypes.data
+    _check(load_library().flow_batch_run(batch, sk, 1 if with_cut else 0, _stream_ptr(stream),
+                                         flows.ctypes.data))
+    return flows[:count]
+
+
+def flow_batch_tune(batch, cache_path: str | None = None, stream=None) -> dict:
+    c = BatchConfig()
+    _check(load_library().flow_batch_tune(batch, _stream_ptr(stream),
+                                          cache_path.encode() if cache_path else None,
+                                          ctypes.byref(c)))
+    return c.as_dict()
+
+
+def flow_batch_get_config(batch) -> dict:
+    c = BatchConfig()
+    _check(load_library().flow_batch_get_config(batch, ctypes.byref(c)))
+    return c.as_dict()
+
+
+def flow_batch_destroy(batch):
+    if batch:
+        load_library().flow_batch_destroy(batch)
+
+
+def flow_problem_reset(handle):
+    _check(load_library().flow_problem_reset(handle))
 
 
 def flow_problem_pierce(handle, side: int, vertices, stream=None):
@@ -304,6 +413,9 @@ class FlowProblem:
         return mincut_source_side(self.handle, self.num_vertices, self.num_nets, vertex_side,
                                   net_side, self.stream)
 
+    def reset(self):
+        flow_problem_reset(self.handle)
+
     def pierce(self, side: int, vertices):
         flow_problem_pierce(self.handle, side, vertices, self.stream)
 
@@ -320,6 +432,62 @@ class FlowProblem:
     def close(self):
         if self.handle:
             flow_problem_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class FlowBatch:
+    """Owner of a batch plan over :class:`FlowProblem` objects (which must
+    outlive it).  With ``with_cut=True`` device side buffers are allocated
+    for every problem (``vertex_sides[i]``, ``net_sides[i]``)."""
+
+    def __init__(self, problems, with_cut: bool = False, config: BatchConfig | None = None,
+                 stream=None, **cfg):
+        if config is None and cfg:
+            config = BatchConfig(**cfg)
+        self.problems = list(problems)
+        self.stream = stream
+        self.vertex_sides = self.net_sides = None
+        if with_cut:
+            import torch
+            self.vertex_sides = [torch.zeros(max(p.num_vertices, 1), dtype=torch.uint8,
+                                             device="cuda") for p in self.problems]
+            self.net_sides = [torch.zeros(max(p.num_nets, 1), dtype=torch.uint8, device="cuda")
+                              for p in self.problems]
+            torch.cuda.synchronize()
+        self.handle = flow_batch_create([p.handle for p in self.problems], self.vertex_sides,
+                                        self.net_sides, config, stream)
+
+    def run(self, skip=None, with_cut: bool = False) -> np.ndarray:
+        return flow_batch_run(self.handle, len(self.problems), skip, with_cut, self.stream)
+
+    def tune(self, cache_path: str | None = None) -> dict:
+        return flow_batch_tune(self.handle, cache_path, self.stream)
+
+    def config(self) -> dict:
+        return flow_batch_get_config(self.handle)
+
+    def sides(self, i: int):
+        """Host copies of problem i's (vertex_side, net_side) after a run
+        with the cut."""
+        p = self.problems[i]
+        return (self.vertex_sides[i][:p.num_vertices].cpu().numpy(),
+                self.net_sides[i][:p.num_nets].cpu().numpy())
+
+    def close(self):
+        if self.handle:
+            flow_batch_destroy(self.handle)
             self.handle = None
 
     def __enter__(self):

@@ -15,6 +15,11 @@ sections "Network Construction" and "Experimental Setup"):
   clamped to [2, hi], unit net weights, terminals chosen by a seeded
   splitmix64 hash of the vertex id (1 % smallest = sources, 1 % largest =
   sinks).
+* ``block_pair_problems`` -- the flow problems of a k-way partition: a
+  power-law hypergraph, a balanced random k-way partition refined by label
+  propagation, and for each heavy block pair a region grown around the cut
+  with the rest of each block contracted into a source / sink vertex (the
+  construction itself is host C in ``regions.c``).
 * ``tiny_hypergraph``    -- tiny random instances (<= 16 vertices) with the
   adversarial shapes used to pin the oracle (nets inside S or T, nets with
   both S and T pins, single-pin nets, a hub vertex, one all-vertex net, large
@@ -38,6 +43,9 @@ __all__ = [
     "tiny_hypergraph",
     "hypergraph_from_nets",
     "hash_terminals",
+    "zipf_sizes_until",
+    "BlockPairSet",
+    "block_pair_problems",
 ]
 
 
@@ -242,3 +250,182 @@ def tiny_hypergraph(seed: int, max_vertices: int = 12, max_nets: int = 10,
         w = np.append(w, rng.integers(1, max_weight + 1, 2))
     return hypergraph_from_nets(V, nets, w, src, snk,
                                 meta=dict(kind="tiny", seed=seed, shape=shape))
+
+
+# ---------------------------------------------------------------------------
+# block-pair flow problems of a k-way partition
+# ---------------------------------------------------------------------------
+
+_REGIONS_LIB = None
+
+
+def _regions_lib():
+    """Load (building on first use) the host C region builder."""
+    global _REGIONS_LIB
+    if _REGIONS_LIB is not None:
+        return _REGIONS_LIB
+    import ctypes
+    import os
+    import subprocess
+    here = os.path.dirname(os.path.abspath(__file__))
+    lib = os.path.join(here, "libhfregions.so")
+    src = os.path.join(here, "regions.c")
+    if not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
+        build_regions_lib()
+    L = ctypes.CDLL(lib)
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.hfr_new.restype = P
+    L.hfr_new.argtypes = [I32, I32, P, P, P, P, I32, P]
+    L.hfr_free.argtypes = [P]
+    L.hfr_free.restype = None
+    L.hfr_objective.argtypes = [P]
+    L.hfr_objective.restype = I64
+    L.hfr_lp.argtypes = [P, I32, I64]
+    L.hfr_lp.restype = I64
+    L.hfr_blocks.argtypes = [P, P, P]
+    L.hfr_blocks.restype = None
+    L.hfr_pairs.argtypes = [P, I64, I32, P, P, P]
+    L.hfr_pairs.restype = I32
+    L.hfr_regions.argtypes = [P, I32, P, P, P, I64, I64, I64, I32]
+    L.hfr_regions.restype = I32
+    L.hfr_region_info.argtypes = [P, I32, P]
+    L.hfr_region_info.restype = None
+    L.hfr_region_take.argtypes = [P, I32, P, P, P, P, P]
+    L.hfr_region_take.restype = None
+    _REGIONS_LIB = L
+    return L
+
+
+def build_regions_lib() -> str:
+    """Compile ``regions.c`` (host code) into ``libhfregions.so``."""
+    import os
+    import subprocess
+    here = os.path.dirname(os.path.abspath(__file__))
+    lib = os.path.join(here, "libhfregions.so")
+    tmp = lib + ".tmp"
+    subprocess.run(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-fvisibility=hidden", "-o", tmp,
+                    os.path.join(here, "regions.c")], check=True)
+    os.replace(tmp, lib)
+    return lib
+
+
+def zipf_sizes_until(rng, target_pins: int, zipf_a: float = 2.2, size_hi: int = 2000,
+                     chunk: int = 1 << 20) -> np.ndarray:
+    """Net sizes ``clip(zipf(a), 2, hi)`` drawn in chunks of ``chunk`` until
+    their sum reaches ``target_pins``; the prefix up to (and including) the
+    net that reaches it is returned."""
+    parts, total = [], 0
+    while total < target_pins:
+        s = np.clip(rng.zipf(zipf_a, chunk), 2, size_hi).astype(np.int64)
+        parts.append(s)
+        total += int(s.sum())
+    sizes = np.concatenate(parts)
+    cs = np.cumsum(sizes)
+    n = int(np.searchsorted(cs, target_pins)) + 1
+    return sizes[:n]
+
+
+@dataclass
+class BlockPairSet:
+    """Flow problems of one partitioned hypergraph.
+
+    ``problems[i]`` is a :class:`Hypergraph` whose last two vertices are the
+    contracted source (``S = [n]``) and sink (``T = [n + 1]``); its ``meta``
+    holds the block pair, the pair's cut weight, ``cut_before`` (weight of
+    the problem's nets cut by the current partition) and ``features`` (12
+    ints: cut weight, region pins, boundary vertices, 7 net-size bins of the
+    problem, c(Vi), c(Vj)).
+    """
+
+    hypergraph: Hypergraph
+    block: np.ndarray
+    block_weights: np.ndarray
+    lmax: int
+    lp_moves: int
+    objective_before: int
+    objective_after: int
+    problems: list
+
+
+def block_pair_problems(seed: int, num_vertices: int = 2_000_000,
+                        target_pins: int = 10_000_000, size_hi: int = 2000,
+                        zipf_a: float = 2.2, k: int = 64, lp_rounds: int = 3,
+                        eps: float = 0.03, alpha: int = 16, min_cut: int = 10,
+                        max_problems: int = 500, threads: int = 0) -> BlockPairSet:
+    """Block-pair flow problems of a partitioned power-law hypergraph.
+
+    Draw order: net sizes (:func:`zipf_sizes_until`), pins uniform without
+    replacement (sorted per net), then ``perm = rng.permutation(V)`` and the
+    balanced random partition ``block[v] = perm[v] % k``.  Unit net and
+    vertex weights.  Label propagation (``lp_rounds`` sweeps) with
+    ``Lmax = floor((100 + 100 eps) * ceil(c(V) / k) / 100)``; pairs with cut
+    weight >= ``min_cut``, heaviest ``max_problems``; regions with side bound
+    ``min(alpha / 2 * cut, (1 + alpha eps) * ceil((c(Vi)+c(Vj))/2) - c(other))``.
+    Regions are built on ``threads`` host threads (0: OpenMP default); the
+    result does not depend on the thread count.
+    """
+    import ctypes
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sizes = zipf_sizes_until(rng, target_pins, zipf_a, size_hi)
+    pins = _distinct_pins(rng, num_vertices, sizes)
+    E = int(sizes.shape[0])
+    off = np.zeros(E + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    perm = rng.permutation(num_vertices)
+    block0 = _i32(perm % k)
+    hg = Hypergraph(int(num_vertices), _i32(off), _i32(pins), np.ones(E, dtype=np.int32),
+                    np.ones(num_vertices, dtype=np.int32), _i32([]), _i32([]),
+                    dict(kind="block_pairs", seed=seed, V=num_vertices, E=E, k=k))
+    L = _regions_lib()
+
+    def ptr(a):
+        return a.ctypes.data_as(ctypes.c_void_p)
+
+    ctx = L.hfr_new(num_vertices, E, ptr(hg.net_offsets), ptr(hg.pins), ptr(hg.net_weights),
+                    ptr(hg.vertex_weights), k, ptr(block0))
+    if not ctx:
+        raise ValueError("region builder rejected the input")
+    try:
+        cV = int(hg.vertex_weights.sum())
+        eps_pct = int(round(eps * 100))
+        lmax = (100 + eps_pct) * (-(-cV // k)) // 100
+        obj0 = int(L.hfr_objective(ctx))
+        moves = int(L.hfr_lp(ctx, lp_rounds, lmax))
+        obj1 = int(L.hfr_objective(ctx))
+        block = np.empty(num_vertices, dtype=np.int32)
+        bw = np.empty(k, dtype=np.int64)
+        L.hfr_blocks(ctx, ptr(block), ptr(bw))
+        pi = np.empty(max_problems, dtype=np.int32)
+        pj = np.empty(max_problems, dtype=np.int32)
+        pc = np.empty(max_problems, dtype=np.int64)
+        npairs = int(L.hfr_pairs(ctx, min_cut, max_problems, ptr(pi), ptr(pj), ptr(pc)))
+        if npairs < 0:
+            raise MemoryError("region builder: out of memory")
+        info = np.zeros(14, dtype=np.int64)
+        scale_num = 100 + alpha * eps_pct
+        if L.hfr_regions(ctx, npairs, ptr(pi), ptr(pj), ptr(pc), alpha // 2, scale_num, 100,
+                         threads) != 0:
+            raise MemoryError("region builder: out of memory")
+        problems = []
+        for t in range(npairs):
+            i, j, cut = int(pi[t]), int(pj[t]), int(pc[t])
+            L.hfr_region_info(ctx, t, ptr(info))
+            nv, ne, npins = int(info[0]), int(info[1]), int(info[2])
+            roff = np.empty(ne + 1, dtype=np.int32)
+            rpins = np.empty(npins, dtype=np.int32)
+            rw = np.empty(ne, dtype=np.int32)
+            rvw = np.empty(nv, dtype=np.int32)
+            gid = np.empty(nv - 2, dtype=np.int32)
+            L.hfr_region_take(ctx, t, ptr(roff), ptr(rpins), ptr(rw), ptr(rvw), ptr(gid))
+            n = nv - 2
+            feats = np.array([cut, npins, int(info[4]), *[int(x) for x in info[7:14]],
+                              int(bw[i]), int(bw[j])], dtype=np.int64)
+            problems.append(Hypergraph(
+                nv, roff, rpins, rw, rvw, _i32([n]), _i32([n + 1]),
+                dict(kind="block_pair", seed=seed, pair=(i, j), cut=cut,
+                     cut_before=int(info[3]), boundary=int(info[4]),
+                     side_weights=(int(info[5]), int(info[6])),
+                     features=feats, gid=gid)))
+    finally:
+        L.hfr_free(ctx)
+    return BlockPairSet(hg, block, bw, lmax, moves, obj0, obj1, problems)

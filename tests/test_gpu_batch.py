@@ -1,0 +1,262 @@
+"""GPU parity of the batch API (flow_batch_solve and batch plans) against
+the CPU oracle, through the C ABI.
+
+A batch runs the same device phases as the single-problem path under a
+different schedule, so flow values and minimal source sides must match the
+oracle bit-exactly for every configuration.  The persistent one-workgroup-
+per-problem kernel is switched off in the library (its first GPU run ended
+in a memory fault whose cause is not found yet); the plans then run their
+problems one after another, and these tests check that schedule.
+"""
+import os
+import sys
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_2201_01556_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-batch] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def hf():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2201_01556_amd import hyperflow
+    hyperflow.load_library()
+    return hyperflow
+
+
+def uneven_set(n, seed0=0):
+    """Uniform hypergraphs of different sizes (uneven batch)."""
+    out = []
+    for i in range(n):
+        V = 200 + 300 * (i % 7)
+        out.append(inputs.uniform_hypergraph(seed0 + i, num_vertices=V,
+                                             num_nets=int(1.5 * V), num_sources=V // 20,
+                                             num_sinks=V // 20))
+    return out
+
+
+@pytest.fixture(scope="module")
+def small_pairs():
+    return inputs.block_pair_problems(0, num_vertices=20000, target_pins=100000, k=8,
+                                      max_problems=50)
+
+
+def _oracle_all(oracle_mod, hgs):
+    return [oracle_mod.maxflow(h) for h in hgs]
+
+
+def _check_sides(batch, hgs, refs, tag):
+    for i, (h, r) in enumerate(zip(hgs, refs)):
+        vs, ns = batch.sides(i)
+        bad = np.nonzero(vs.astype(bool) != r.vertex_side.astype(bool))[0]
+        assert bad.size == 0, f"{tag} problem {i}: {bad.size} vertex sides differ"
+        badn = np.nonzero(ns != r.net_side)[0]
+        assert badn.size == 0, f"{tag} problem {i}: {badn.size} net sides differ"
+
+
+def test_batch_solve_uneven_vs_oracle(hf, oracle_mod):
+    hgs = uneven_set(40)
+    refs = _oracle_all(oracle_mod, hgs)
+    probs = [hf.FlowProblem.from_hypergraph(h) for h in hgs]
+    try:
+        _say("flow_batch_solve, 40 uneven problems")
+        flows = hf.flow_batch_solve([p.handle for p in probs])
+        assert list(flows) == [r.flow for r in refs]
+        # a batch-solved handle behaves as after maxflow_solve
+        for i in (0, 13, 39):
+            vs, ns = probs[i].source_side()
+            assert (vs.astype(bool) == refs[i].vertex_side.astype(bool)).all()
+            assert (ns == refs[i].net_side).all()
+            assert probs[i].solve() == refs[i].flow  # warm re-solve
+    finally:
+        for p in probs:
+            p.close()
+
+
+@pytest.mark.parametrize("lanes,block", [(4, 1024), (8, 1024), (16, 1024), (4, 256),
+                                         (8, 256), (16, 256)])
+def test_batch_plan_configs_with_cut(hf, oracle_mod, lanes, block):
+    hgs = uneven_set(24, seed0=100)
+    refs = _oracle_all(oracle_mod, hgs)
+    probs = [hf.FlowProblem.from_hypergraph(h) for h in hgs]
+    try:
+        _say(f"plan lanes={lanes} block={block}")
+        with hf.FlowBatch(probs, with_cut=True, group_lanes=lanes, block_threads=block) as b:
+            flows = b.run(with_cut=True)
+            assert list(flows) == [r.flow for r in refs]
+            _check_sides(b, hgs, refs, f"lanes={lanes} block={block}")
+    finally:
+        for p in probs:
+            p.close()
+
+
+@pytest.mark.parametrize("gr", [-1, 1, 8, 64])
+def test_batch_relabel_intervals(hf, oracle_mod, gr):
+    hgs = uneven_set(12, seed0=200)
+    refs = _oracle_all(oracle_mod, hgs)
+    probs = [hf.FlowProblem.from_hypergraph(h) for h in hgs]
+    try:
+        _say(f"gr_interval={gr}")
+        with hf.FlowBatch(probs, with_cut=True, gr_interval=gr, workgroups=5) as b:
+            flows = b.run(with_cut=True)
+            assert list(flows) == [r.flow for r in refs]
+            _check_sides(b, hgs, refs, f"gr={gr}")
+    finally:
+        for p in probs:
+            p.close()
+
+
+def test_batch_block_pairs_vs_oracle(hf, oracle_mod, small_pairs):
+    hgs = small_pairs.problems
+    refs = _oracle_all(oracle_mod, hgs)
+    probs = [hf.FlowProblem.from_hypergraph(h) for h in hgs]
+    try:
+        _say(f"{len(hgs)} block-pair problems")
+        with hf.FlowBatch(probs, with_cut=True) as b:
+            flows = b.run(with_cut=True)
+            assert list(flows) == [r.flow for r in refs]
+            _check_sides(b, hgs, refs, "block pairs")
+            for h, f in zip(hgs, flows):
+                assert 0 <= f <= h.meta["cut_before"]
+            # replay of the captured graph: warm problems finish at once
+            flows2 = b.run(with_cut=True)
+            assert list(flows2) == list(flows)
+            _check_sides(b, hgs, refs, "block pairs replay")
+    finally:
+        for p in probs:
+            p.close()
+
+
+def test_batch_skip_and_reset(hf, oracle_mod):
+    hgs = uneven_set(10, seed0=300)
+    refs = _oracle_all(oracle_mod, hgs)
+    probs = [hf.FlowProblem.from_hypergraph(h) for h in hgs]
+    try:
+        skip = np.zeros(10, dtype=np.uint8)
+        skip[[1, 4, 9]] = 1
+        with hf.FlowBatch(probs, with_cut=True) as b:
+            flows = b.run(skip=skip, with_cut=True)
+            for i in range(10):
+                assert flows[i] == (-1 if skip[i] else refs[i].flow)
+            # skipped problems were left alone: still unsolved
+            with pytest.raises(hf.HyperflowError):
+                probs[1].source_side()
+            flows = b.run(with_cut=True)
+            assert list(flows) == [r.flow for r in refs]
+            for p in probs:
+                p.reset()
+            flows = b.run(with_cut=True)
+            assert list(flows) == [r.flow for r in refs]
+            _check_sides(b, hgs, refs, "after reset")
+    finally:
+        for p in probs:
+            p.close()
+
+
+def test_batch_tune_and_cache(hf, oracle_mod):
+    hgs = uneven_set(16, seed0=400)
+    refs = _oracle_all(oracle_mod, hgs)
+    probs = [hf.FlowProblem.from_hypergraph(h) for h in hgs]
+    try:
+        with tempfile.TemporaryDirectory() as d:
+            cache = os.path.join(d, "tune.txt")
+            with hf.FlowBatch(probs, with_cut=True) as b:
+                cfg = b.tune(cache)
+                assert cfg["group_lanes"] in (4, 8, 16)
+                assert cfg["block_threads"] in (256, 1024)
+                assert b.config() == cfg
+                flows = b.run(with_cut=True)
+                assert list(flows) == [r.flow for r in refs]
+                _check_sides(b, hgs, refs, "tuned")
+            with open(cache) as f:
+                assert len(f.read().strip().splitlines()) == 1
+            with hf.FlowBatch(probs) as b2:
+                assert b2.tune(cache) == cfg  # from the cache
+            with open(cache) as f:
+                assert len(f.read().strip().splitlines()) == 1
+    finally:
+        for p in probs:
+            p.close()
+
+
+@pytest.mark.skip(reason="persistent batch kernel switched off: its first GPU run ended in a "
+                         "memory access fault whose cause has not been found")
+def test_persistent_batch_kernel():
+    """Placeholder for the persistent kernel's own parity runs."""
+
+
+def test_batch_errors(hf):
+    hgs = uneven_set(3, seed0=500)
+    probs = [hf.FlowProblem.from_hypergraph(h, round_budget=1) for h in hgs]
+    try:
+        with pytest.raises(hf.HyperflowError) as ei:
+            hf.flow_batch_solve([probs[0].handle, probs[0].handle])
+        assert ei.value.name == "FP_ERR_INVALID"
+        with pytest.raises(hf.HyperflowError) as ei:
+            hf.FlowBatch(probs, block_threads=512)
+        assert ei.value.name == "FP_ERR_INVALID"
+        with hf.FlowBatch(probs) as b:
+            with pytest.raises(hf.HyperflowError) as ei:
+                b.run(with_cut=True)  # planned without side buffers
+            assert ei.value.name == "FP_ERR_INVALID"
+            with pytest.raises(hf.HyperflowError) as ei:
+                b.run()
+            assert ei.value.name == "FP_ERR_ABORTED"
+        assert len(hf.flow_batch_solve([])) == 0
+    finally:
+        for p in probs:
+            p.close()
+
+
+def _cut_weight(hg, side):
+    off = hg.net_offsets.astype(np.int64)
+    sizes = np.diff(off)
+    inside = side[hg.pins].astype(np.int64)
+    net_of = np.repeat(np.arange(hg.num_nets), sizes)
+    cnt = np.bincount(net_of, weights=inside, minlength=hg.num_nets)
+    cut = (cnt > 0) & (cnt < sizes)
+    return int(hg.net_weights[cut].sum())
+
+
+@pytest.mark.slow
+def test_batch_full_block_pairs_sampled(hf, oracle_mod):
+    """The 2M-vertex, 10M-pin, k=64 instance as the benchmark runs it: all
+    500 problems in one plan with the cut; every problem's side is a
+    minimum cut certificate (cut weight = flow <= cut before), and sampled
+    problems match the oracle exactly."""
+    import torch
+    _say("building the 10M-pin block-pair set")
+    bp = inputs.block_pair_problems(0)
+    hgs = bp.problems
+    _say(f"{len(hgs)} problems, creating on the device")
+    probs = [hf.FlowProblem.from_hypergraph(h, device=True) for h in hgs]
+    try:
+        with hf.FlowBatch(probs, with_cut=True) as b:
+            _say("batched solve + cut")
+            flows = b.run(with_cut=True)
+            torch.cuda.synchronize()
+            for i, h in enumerate(hgs):
+                vs, _ = b.sides(i)
+                assert vs[h.sources[0]] == 1 and vs[h.sinks[0]] == 0
+                assert _cut_weight(h, vs) == flows[i], f"problem {i}"
+                assert 0 <= flows[i] <= h.meta["cut_before"]
+            for i in (0, 137, len(hgs) - 1):
+                _say(f"oracle on problem {i}")
+                r = oracle_mod.maxflow(hgs[i])
+                vs, ns = b.sides(i)
+                assert flows[i] == r.flow
+                assert (vs.astype(bool) == r.vertex_side.astype(bool)).all()
+                assert (ns == r.net_side).all()
+    finally:
+        for p in probs:
+            p.close()
