@@ -195,13 +195,16 @@ fp_status flow_batch_solve(fp_problem *const *problems, int32_t count,
                            int64_t *flow_values);
 
 /*
- * Batch plans: the persistent batched solve of a fixed set of problems as a
- * captured HIP graph (descriptor upload, queue reset, the persistent kernel,
- * result download), replayed by flow_batch_run.  Pattern of the paper's
- * refinement scheduler (section "Parallel Active Block Scheduling"): many
- * block-pair flow problems solved concurrently; here each problem runs
- * inside one workgroup and workgroups take problems from a shared queue,
- * largest (pins + network nodes) first.
+ * Batch plans: many independent problems solved concurrently, the pattern of
+ * the paper's refinement scheduler (section "Parallel Active Block
+ * Scheduling").  Problems are taken from a shared queue, largest (pins +
+ * network nodes) first, by `streams` host workers, each driving the
+ * single-problem path on a HIP stream of its own, so the kernels and host
+ * round trips of different problems overlap.  (A persistent kernel that
+ * runs each problem inside one workgroup, replayed from a captured HIP
+ * graph, is built but switched off: its first GPU run ended in a memory
+ * access fault whose cause has not been found; block_threads and workgroups
+ * only apply to it.)
  */
 typedef struct fp_batch fp_batch; /* opaque, library-owned */
 
@@ -213,7 +216,8 @@ typedef struct {
                             0 = each problem's own option                  */
   int32_t workgroups;    /* persistent workgroups; 0 = as many as fit on
                             the device at once (at most one per problem)   */
-  int32_t reserved[4];
+  int32_t streams;       /* concurrent workers (streams), 1..64; 0 = 4      */
+  int32_t reserved[3];
 } fp_batch_config;
 
 /*
@@ -245,9 +249,9 @@ fp_status flow_batch_run(fp_batch *batch, const uint8_t *skip, int32_t with_cut,
                          void *hip_stream, int64_t *flow_values);
 
 /*
- * flow_batch_tune: time candidate configurations (lanes per node, block
- * size, global relabel interval) on this batch, each run from the zero flow,
- * and keep the fastest.  With a cache_path (or NULL), a configuration stored
+ * flow_batch_tune: time candidate configurations (number of streams, lanes
+ * per node, global relabel interval) on this batch, each run from the zero
+ * flow, and keep the fastest.  With a cache_path (or NULL), a configuration stored
  * under the batch's signature (device, problem count, total pins, total
  * network nodes) is reused without timing, and a newly timed one is
  * appended.  Leaves every problem solved.  chosen may be NULL.

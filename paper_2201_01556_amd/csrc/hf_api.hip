@@ -181,9 +181,10 @@ fp_status flow_batch_create(fp_problem* const* problems, int32_t count,
     fp_batch_config c = *config;
     if (c.group_lanes == 0) c.group_lanes = 4;
     if (c.block_threads == 0) c.block_threads = 1024;
+    if (c.streams == 0) c.streams = 4;
     if (!((c.group_lanes == 4 || c.group_lanes == 8 || c.group_lanes == 16) &&
           (c.block_threads == 256 || c.block_threads == 1024) && c.gr_interval >= -1 &&
-          c.workgroups >= 0)) {
+          c.workgroups >= 0 && c.streams >= 1 && c.streams <= 64)) {
       set_error("invalid batch configuration");
       return FP_ERR_INVALID;
     }

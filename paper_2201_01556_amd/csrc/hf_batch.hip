@@ -9,14 +9,20 @@
 //
 // That persistent path is switched off (kPersistentBatch): its first GPU run
 // ended in a memory access fault whose cause has not been found.  Until it
-// is, a plan runs its problems one after another with the single-problem
-// path (same device phases, device-wide kernels and single-workgroup tail
-// loops), which gives the same results.
+// is, a plan runs its problems concurrently with the single-problem path
+// (same device phases, device-wide kernels and single-workgroup tail loops):
+// `streams` host workers take problems from a shared queue, largest first,
+// and drive each on a HIP stream of their own, so the kernels and host
+// round trips of different problems overlap.  Results are identical.
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "hf_host.h"
@@ -294,6 +300,7 @@ struct fp_batch {
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   fp_batch_config exec_cfg[2]{};
   int cus = 0;
+  std::vector<hipStream_t> workers;  // streams of the concurrent schedule
 };
 
 namespace hf {
@@ -305,13 +312,14 @@ static fp_batch_config resolve_batch_config(const fp_batch_config* c) {
   if (c) r = *c;
   if (r.group_lanes == 0) r.group_lanes = 4;
   if (r.block_threads == 0) r.block_threads = 1024;
+  if (r.streams == 0) r.streams = 4;
   return r;
 }
 
 static bool batch_config_valid(const fp_batch_config& c) {
   return (c.group_lanes == 4 || c.group_lanes == 8 || c.group_lanes == 16) &&
          (c.block_threads == 256 || c.block_threads == 1024) && c.gr_interval >= -1 &&
-         c.workgroups >= 0;
+         c.workgroups >= 0 && c.streams >= 1 && c.streams <= 64;
 }
 
 static void drop_graphs(fp_batch* b) {
@@ -324,6 +332,8 @@ static void drop_graphs(fp_batch* b) {
 
 void release_batch(fp_batch* b) {
   drop_graphs(b);
+  for (hipStream_t w : b->workers) (void)hipStreamDestroy(w);
+  b->workers.clear();
   if (b->cap) (void)hipStreamDestroy(b->cap);
   if (b->dmem) (void)hipFree(b->dmem);
   if (b->hmem) (void)hipHostFree(b->hmem);
@@ -489,14 +499,18 @@ static fp_status batch_graph(fp_batch* b, int with_cut, hipGraphExec_t* exec) {
 
 // One replay: fill the parameters from the handles, launch, read results.
 // `force_init` starts every problem from the zero flow (tuning).
-// Problems one after another with the single-problem path.
-static fp_status batch_sequential(fp_batch* b, const uint8_t* skip, int32_t with_cut,
+// Problems spread over `streams` workers, each a host thread driving the
+// single-problem path on its own stream; problems are taken from a shared
+// counter in the plan's order (largest first).  The batch configuration's
+// lanes per node and relabel interval apply to every problem for the run.
+static fp_status batch_concurrent(fp_batch* b, const uint8_t* skip, int32_t with_cut,
                                   bool force_init, hipStream_t s, int64_t* flows, float* ms) {
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (ms) {
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
-    (void)hipEventRecord(e0, s);
+  const int nw = std::max(1, std::min<int>(b->cfg.streams, b->count));
+  while ((int)b->workers.size() < nw) {
+    hipStream_t w = nullptr;
+    hipError_t he = hipStreamCreateWithFlags(&w, hipStreamNonBlocking);
+    if (he != hipSuccess) return hip_fail(he, "creating a batch stream");
+    b->workers.push_back(w);
   }
   std::vector<uint8_t*> vs, ns;
   if (with_cut) {
@@ -509,42 +523,75 @@ static fp_status batch_sequential(fp_batch* b, const uint8_t* skip, int32_t with
                      hipMemcpyDeviceToHost);
     if (he != hipSuccess) return hip_fail(he, "reading the batch side pointers");
   }
+  // work queued on the caller's stream comes first
+  hipEvent_t ready = nullptr;
+  hipError_t he = hipEventCreateWithFlags(&ready, hipEventDisableTiming);
+  if (he == hipSuccess) he = hipEventRecord(ready, s);
+  for (int w = 0; w < nw && he == hipSuccess; ++w) he = hipStreamWaitEvent(b->workers[w], ready, 0);
+  if (he != hipSuccess) {
+    if (ready) (void)hipEventDestroy(ready);
+    return hip_fail(he, "ordering the batch after the caller's stream");
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  std::atomic<int32_t> next{0};
+  std::atomic<bool> stop{false};
+  std::mutex mu;
   fp_status first = FP_OK;
-  for (int32_t k = 0; k < b->count; ++k) {
-    const int32_t i = b->order[k];
-    if (skip && skip[i]) {
-      if (flows) flows[i] = -1;
-      continue;
+  std::string first_msg;
+  const fp_batch_config cfg = b->cfg;
+  auto worker = [&](int w) {
+    (void)hipSetDevice(b->device);
+    hipStream_t ws = b->workers[w];
+    for (;;) {
+      if (stop.load()) return;
+      const int32_t k = next.fetch_add(1);
+      if (k >= b->count) return;
+      const int32_t i = b->order[k];
+      if (skip && skip[i]) {
+        if (flows) flows[i] = -1;
+        continue;
+      }
+      fp_problem* pb = b->pbs[i];
+      if (force_init) {
+        pb->inited = false;
+        pb->solved = false;
+      }
+      const fp_options saved = pb->opt;
+      pb->opt.group_lanes = cfg.group_lanes;
+      if (cfg.gr_interval != 0) pb->opt.gr_interval = cfg.gr_interval;
+      int64_t f = -1;
+      fp_status st = solve_problem(pb, ws, &f);
+      if (st == FP_OK && with_cut) st = cut_problem(pb, ws, 1, vs[i], b->has_ns ? ns[i] : nullptr);
+      pb->opt = saved;
+      if (flows) flows[i] = st == FP_OK ? f : -1;
+      if (st != FP_OK) {
+        std::lock_guard<std::mutex> lock(mu);
+        if (first == FP_OK || (st == FP_ERR_DEVICE && first != FP_ERR_DEVICE)) {
+          first = st;
+          first_msg = std::string("problem ") + std::to_string(i) + ": " + fp_last_error();
+        }
+        if (st == FP_ERR_DEVICE) stop.store(true);  // the device state is not usable
+      }
     }
-    fp_problem* pb = b->pbs[i];
-    if (force_init) {
-      pb->inited = false;
-      pb->solved = false;
-    }
-    int64_t f = -1;
-    fp_status st = solve_problem(pb, s, &f);
-    if (st == FP_OK && with_cut)
-      st = cut_problem(pb, s, 1, vs[i], b->has_ns ? ns[i] : nullptr);
-    if (flows) flows[i] = st == FP_OK ? f : -1;
-    if (st != FP_OK && first == FP_OK) {
-      if (st == FP_ERR_DEVICE) return st;  // the device state is not usable
-      first = st;
-    }
+  };
+  if (nw == 1) {
+    worker(0);
+  } else {
+    std::vector<std::thread> pool;
+    pool.reserve(nw);
+    for (int w = 0; w < nw; ++w) pool.emplace_back(worker, w);
+    for (auto& t : pool) t.join();
   }
-  if (ms) {
-    hipError_t he = hipEventRecord(e1, s);
-    if (he == hipSuccess) he = hipEventSynchronize(e1);
-    if (he == hipSuccess) he = hipEventElapsedTime(ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (he != hipSuccess) return hip_fail(he, "timing the batch");
-  }
+  (void)hipEventDestroy(ready);
+  if (ms)
+    *ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (first != FP_OK) set_error("%s", first_msg.c_str());
   return first;
 }
 
 static fp_status batch_replay(fp_batch* b, const uint8_t* skip, int32_t with_cut, bool force_init,
                               hipStream_t s, int64_t* flows, float* ms) {
-  if (!kPersistentBatch) return batch_sequential(b, skip, with_cut, force_init, s, flows, ms);
+  if (!kPersistentBatch) return batch_concurrent(b, skip, with_cut, force_init, s, flows, ms);
   hipGraphExec_t exec = nullptr;
   fp_status st = batch_graph(b, with_cut ? 1 : 0, &exec);
   if (st) return st;
@@ -660,15 +707,16 @@ static bool cache_lookup(const char* path, const std::string& sig, fp_batch_conf
   FILE* f = fopen(path, "r");
   if (!f) return false;
   char key[256];
-  int g = 0, bs = 0, gr = 0, wg = 0;
+  int g = 0, bs = 0, gr = 0, wg = 0, ns = 0;
   bool found = false;
-  while (fscanf(f, "%255s %d %d %d %d", key, &g, &bs, &gr, &wg) == 5) {
+  while (fscanf(f, "%255s %d %d %d %d %d", key, &g, &bs, &gr, &wg, &ns) == 6) {
     if (sig == key) {  // the last entry for a signature wins
       *c = fp_batch_config{};
       c->group_lanes = g;
       c->block_threads = bs;
       c->gr_interval = gr;
       c->workgroups = wg;
+      c->streams = ns;
       found = batch_config_valid(*c);
     }
   }
@@ -680,8 +728,8 @@ static void cache_store(const char* path, const std::string& sig, const fp_batch
   if (!path) return;
   FILE* f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "%s %d %d %d %d\n", sig.c_str(), c.group_lanes, c.block_threads, c.gr_interval,
-          c.workgroups);
+  fprintf(f, "%s %d %d %d %d %d\n", sig.c_str(), c.group_lanes, c.block_threads, c.gr_interval,
+          c.workgroups, c.streams);
   fclose(f);
 }
 
@@ -713,18 +761,34 @@ fp_status tune_batch(fp_batch* b, hipStream_t s, const char* cache_path, fp_batc
     }
     return FP_OK;
   };
-  // lanes per node and block size at the base relabel interval, then the
-  // relabel interval for the best of those
-  const int lanes[3] = {4, 8, 16};
-  const int blocks[2] = {1024, 256};
-  for (int bs : blocks)
-    for (int g : lanes) {
+  // one knob at a time, each from the best so far: concurrency (streams;
+  // block size for the persistent kernel), lanes per node, relabel interval
+  if (kPersistentBatch) {
+    const int blocks[2] = {1024, 256};
+    for (int bs : blocks) {
       fp_batch_config c = base;
-      c.group_lanes = g;
       c.block_threads = bs;
       fp_status st = trial(c);
       if (st) return st;
     }
+  } else {
+    const int streams[5] = {1, 2, 4, 8, 16};
+    for (int ns : streams) {
+      fp_batch_config c = base;
+      c.streams = ns;
+      fp_status st = trial(c);
+      if (st) return st;
+    }
+  }
+  const int lanes[3] = {4, 8, 16};
+  const fp_batch_config conc = best;
+  for (int g : lanes) {
+    fp_batch_config c = conc;
+    c.group_lanes = g;
+    if (c.group_lanes == conc.group_lanes) continue;
+    fp_status st = trial(c);
+    if (st) return st;
+  }
   const int intervals[4] = {8, 16, 32, 64};
   const fp_batch_config shape = best;
   for (int gr : intervals) {

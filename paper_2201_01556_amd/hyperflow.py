@@ -80,7 +80,8 @@ class BatchConfig(ctypes.Structure):
         ("block_threads", ctypes.c_int32),
         ("gr_interval", ctypes.c_int32),
         ("workgroups", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("streams", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
     def as_dict(self) -> dict:

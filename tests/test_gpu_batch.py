@@ -83,15 +83,16 @@ def test_batch_solve_uneven_vs_oracle(hf, oracle_mod):
             p.close()
 
 
-@pytest.mark.parametrize("lanes,block", [(4, 1024), (8, 1024), (16, 1024), (4, 256),
-                                         (8, 256), (16, 256)])
-def test_batch_plan_configs_with_cut(hf, oracle_mod, lanes, block):
+@pytest.mark.parametrize("lanes,block,streams", [(4, 1024, 1), (8, 1024, 4), (16, 1024, 16),
+                                                 (4, 256, 2), (8, 256, 8), (16, 256, 3)])
+def test_batch_plan_configs_with_cut(hf, oracle_mod, lanes, block, streams):
     hgs = uneven_set(24, seed0=100)
     refs = _oracle_all(oracle_mod, hgs)
     probs = [hf.FlowProblem.from_hypergraph(h) for h in hgs]
     try:
-        _say(f"plan lanes={lanes} block={block}")
-        with hf.FlowBatch(probs, with_cut=True, group_lanes=lanes, block_threads=block) as b:
+        _say(f"plan lanes={lanes} block={block} streams={streams}")
+        with hf.FlowBatch(probs, with_cut=True, group_lanes=lanes, block_threads=block,
+                          streams=streams) as b:
             flows = b.run(with_cut=True)
             assert list(flows) == [r.flow for r in refs]
             _check_sides(b, hgs, refs, f"lanes={lanes} block={block}")
@@ -107,7 +108,7 @@ def test_batch_relabel_intervals(hf, oracle_mod, gr):
     probs = [hf.FlowProblem.from_hypergraph(h) for h in hgs]
     try:
         _say(f"gr_interval={gr}")
-        with hf.FlowBatch(probs, with_cut=True, gr_interval=gr, workgroups=5) as b:
+        with hf.FlowBatch(probs, with_cut=True, gr_interval=gr, workgroups=5, streams=5) as b:
             flows = b.run(with_cut=True)
             assert list(flows) == [r.flow for r in refs]
             _check_sides(b, hgs, refs, f"gr={gr}")
@@ -174,6 +175,7 @@ def test_batch_tune_and_cache(hf, oracle_mod):
                 cfg = b.tune(cache)
                 assert cfg["group_lanes"] in (4, 8, 16)
                 assert cfg["block_threads"] in (256, 1024)
+                assert 1 <= cfg["streams"] <= 64
                 assert b.config() == cfg
                 flows = b.run(with_cut=True)
                 assert list(flows) == [r.flow for r in refs]
@@ -204,6 +206,9 @@ def test_batch_errors(hf):
         assert ei.value.name == "FP_ERR_INVALID"
         with pytest.raises(hf.HyperflowError) as ei:
             hf.FlowBatch(probs, block_threads=512)
+        assert ei.value.name == "FP_ERR_INVALID"
+        with pytest.raises(hf.HyperflowError) as ei:
+            hf.FlowBatch(probs, streams=65)
         assert ei.value.name == "FP_ERR_INVALID"
         with hf.FlowBatch(probs) as b:
             with pytest.raises(hf.HyperflowError) as ei:
