@@ -8,11 +8,17 @@ Contents
 --------
 ``maxflow``            plain C FIFO push-relabel on the explicit Lawler
                        expansion (``lawler_pr.c``), excess-seeded source-side
-                       BFS; optional preflow-to-flow self check.
+                       BFS; optional preflow-to-flow self check; optional
+                       maximal sink side by reverse residual BFS.
+``flowcutter``         the FlowCutter loop (section "Flow-Based Refinement",
+                       algorithm "FlowCutter Core") with one piercing node
+                       per iteration, every max flow solved from scratch.
 ``brute_force``        enumerate every source side X with S <= X <= V \\ T
                        (<= 16 free vertices): F = min cut, minimal X =
                        intersection of all minimisers (min cuts form a
-                       lattice, so the intersection is itself a minimiser).
+                       lattice, so the intersection is itself a minimiser);
+                       ``brute_force_sides`` also gives the union (the
+                       maximal minimiser).
 ``edmonds_karp``       shortest augmenting paths on a separately built
                        explicit graph (pure Python; small inputs).
 ``scipy_maxflow``      the same network through
@@ -78,6 +84,11 @@ def _load():
                                        ctypes.c_int32, ctypes.c_int32, i64p, u8p,
                                        u8p, i64p]
         lib.oracle_maxflow.restype = ctypes.c_int
+        lib.oracle_maxflow_sides.argtypes = [ctypes.c_int32, ctypes.c_int32, i32p, i32p,
+                                             i32p, i32p, ctypes.c_int32, i32p,
+                                             ctypes.c_int32, ctypes.c_int32, i64p, u8p,
+                                             u8p, u8p, i64p]
+        lib.oracle_maxflow_sides.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -87,17 +98,20 @@ def _p(a, ct):
 
 
 class OracleResult:
-    def __init__(self, F, vside, nside, stats):
+    def __init__(self, F, vside, nside, stats, tside=None):
         self.flow = int(F)
         self.vertex_side = vside
         self.net_side = nside
+        self.sink_side = tside
         self.stats = dict(relabels=int(stats[0]), pushes=int(stats[1]),
                           global_relabels=int(stats[2]), nodes=int(stats[3]),
                           arcs=int(stats[4]), inf=int(stats[5]))
 
 
-def maxflow(hg, selfcheck: bool = False) -> OracleResult:
-    """Maximum flow value and minimal source side of ``hg`` (C oracle)."""
+def maxflow(hg, selfcheck: bool = False, sink_side: bool = False) -> OracleResult:
+    """Maximum flow value and minimal source side of ``hg`` (C oracle);
+    with ``sink_side`` also the maximal sink side (vertices that reach a sink
+    in the residual network), as ``result.sink_side``."""
     lib = _load()
     V, E = hg.num_vertices, hg.num_nets
     off = np.ascontiguousarray(hg.net_offsets, dtype=np.int32)
@@ -109,14 +123,25 @@ def maxflow(hg, selfcheck: bool = False) -> OracleResult:
     vside = np.zeros(max(V, 1), dtype=np.uint8)
     nside = np.zeros(max(E, 1), dtype=np.uint8)
     stats = np.zeros(8, dtype=np.int64)
-    rc = lib.oracle_maxflow(V, E, _p(off, ctypes.c_int32), _p(pins, ctypes.c_int32),
-                            _p(w, ctypes.c_int32), _p(S, ctypes.c_int32), len(S),
-                            _p(T, ctypes.c_int32), len(T), 1 if selfcheck else 0,
-                            _p(F, ctypes.c_int64), _p(vside, ctypes.c_uint8),
-                            _p(nside, ctypes.c_uint8), _p(stats, ctypes.c_int64))
+    if sink_side:
+        tside = np.zeros(max(V, 1), dtype=np.uint8)
+        rc = lib.oracle_maxflow_sides(V, E, _p(off, ctypes.c_int32), _p(pins, ctypes.c_int32),
+                                      _p(w, ctypes.c_int32), _p(S, ctypes.c_int32), len(S),
+                                      _p(T, ctypes.c_int32), len(T), 1 if selfcheck else 0,
+                                      _p(F, ctypes.c_int64), _p(vside, ctypes.c_uint8),
+                                      _p(nside, ctypes.c_uint8), _p(tside, ctypes.c_uint8),
+                                      _p(stats, ctypes.c_int64))
+    else:
+        tside = None
+        rc = lib.oracle_maxflow(V, E, _p(off, ctypes.c_int32), _p(pins, ctypes.c_int32),
+                                _p(w, ctypes.c_int32), _p(S, ctypes.c_int32), len(S),
+                                _p(T, ctypes.c_int32), len(T), 1 if selfcheck else 0,
+                                _p(F, ctypes.c_int64), _p(vside, ctypes.c_uint8),
+                                _p(nside, ctypes.c_uint8), _p(stats, ctypes.c_int64))
     if rc != 0:
         raise RuntimeError(f"oracle_maxflow failed: {ERRORS.get(rc, rc)}")
-    return OracleResult(F[0], vside[:V].copy(), nside[:E].copy(), stats)
+    return OracleResult(F[0], vside[:V].copy(), nside[:E].copy(), stats,
+                        None if tside is None else tside[:V].copy())
 
 
 # ---------------------------------------------------------------------------
@@ -188,6 +213,34 @@ def brute_force(hg):
     for v in x_min:
         x[v] = True
     return best, x, count
+
+
+def brute_force_sides(hg):
+    """(F, minimal minimiser, maximal minimiser) by enumeration (<= 16 free
+    vertices).  The maximal minimiser is the union of all minimisers; its
+    complement is the maximal sink side."""
+    V = hg.num_vertices
+    S = set(int(v) for v in hg.sources)
+    T = set(int(v) for v in hg.sinks)
+    free = [v for v in range(V) if v not in S and v not in T]
+    if len(free) > 16:
+        raise ValueError("brute force limited to 16 free vertices")
+    nets = [set(int(v) for v in n) for n in hg.nets()]
+    w = [int(c) for c in hg.net_weights]
+    best, lo, hi = None, None, None
+    for mask in range(1 << len(free)):
+        X = set(S) | {v for i, v in enumerate(free) if mask >> i & 1}
+        c = sum(we for n, we in zip(nets, w) if 0 < len(n & X) < len(n))
+        if best is None or c < best:
+            best, lo, hi = c, set(X), set(X)
+        elif c == best:
+            lo &= X
+            hi |= X
+    xl = np.zeros(V, dtype=bool)
+    xh = np.zeros(V, dtype=bool)
+    xl[list(lo)] = True
+    xh[list(hi)] = True
+    return best, xl, xh
 
 
 def _lawler_arcs(hg):
@@ -401,3 +454,108 @@ def residual_labels(hg, f_in, f_out, f_b):
                     dv[u] = lvl + 1
                     q.append(("v", int(u)))
     return dv, din, dout
+
+
+# ---------------------------------------------------------------------------
+# FlowCutter (section "Flow-Based Refinement", algorithm "FlowCutter Core",
+# paragraph "Piercing")
+# ---------------------------------------------------------------------------
+
+class _WithTerminals:
+    """The hypergraph of ``hg`` with the terminal sets S, T (bool masks)."""
+
+    def __init__(self, hg, S, T):
+        self.num_vertices = hg.num_vertices
+        self.num_nets = hg.num_nets
+        self.net_offsets = hg.net_offsets
+        self.pins = hg.pins
+        self.net_weights = hg.net_weights
+        self.sources = np.nonzero(S)[0].astype(np.int32)
+        self.sinks = np.nonzero(T)[0].astype(np.int32)
+
+
+class FlowCutterResult:
+    def __init__(self, status, flow, x, iterations, trace, S, T):
+        self.status = status          # "balanced", "infeasible" or "cap"
+        self.flow = int(flow)         # cut weight of the returned bipartition
+        self.vertex_side = x          # bool per vertex: the returned source side
+        self.iterations = iterations  # max-flow computations
+        self.trace = trace            # per iteration (side, node, F, c(S_r), c(T_r))
+        self.sources = S
+        self.sinks = T
+
+
+def _cut_nets(hg, side):
+    """Nets with a pin inside ``side`` and a pin outside (bool per net)."""
+    inside = _pins_inside(hg, side)
+    sizes = np.diff(hg.net_offsets)
+    return (inside > 0) & (inside < sizes)
+
+
+def _piercing_node(hg, cut, sr, tr, own_terminals_side):
+    """Smallest-id pin of a cut net outside S_r and T_r (avoids an augmenting
+    path); otherwise the smallest-id pin of a cut net on the opposite side
+    that is not yet a terminal; -1 if there is none."""
+    E = hg.num_nets
+    net_of = np.repeat(np.arange(E), np.diff(hg.net_offsets))
+    on_cut = cut[net_of]
+    pins = hg.pins[on_cut]
+    free = pins[~sr[pins] & ~tr[pins]]
+    if free.size:
+        return int(free.min()), False
+    aug = pins[own_terminals_side[pins]]
+    if aug.size:
+        return int(aug.min()), True
+    return -1, False
+
+
+def flowcutter(hg, vertex_weights, max_source_weight, max_sink_weight,
+               max_iterations=100000):
+    """FlowCutter with one piercing node per iteration.
+
+    Each iteration solves the max flow of the current (S, T) from scratch
+    (warm starting changes only the work, not F, S_r or T_r, which the
+    current terminal sets determine), derives the minimal source side S_r
+    and the maximal sink side T_r, and returns the first balanced
+    bipartition, trying (S_r, V \\ S_r) before (V \\ T_r, T_r).  Otherwise the
+    lighter of S_r and T_r (source side on ties) becomes the new terminal
+    set plus one piercing node: the smallest-id pin, outside S_r and T_r, of
+    a net cut by that side's bipartition; if there is none, the smallest-id
+    such pin on the other side that is not yet a terminal (it creates an
+    augmenting path).  Balanced: c(X) <= max_source_weight and
+    c(V \\ X) <= max_sink_weight.
+    """
+    V = hg.num_vertices
+    c = np.asarray(vertex_weights, dtype=np.int64)
+    total = int(c.sum())
+    S = np.zeros(V, dtype=bool)
+    T = np.zeros(V, dtype=bool)
+    S[hg.sources] = True
+    T[hg.sinks] = True
+    trace = []
+    for it in range(1, max_iterations + 1):
+        r = maxflow(_WithTerminals(hg, S, T), sink_side=True)
+        sr = r.vertex_side.astype(bool)
+        tr = r.sink_side.astype(bool)
+        cs, ct = int(c[sr].sum()), int(c[tr].sum())
+        if cs <= max_source_weight and total - cs <= max_sink_weight:
+            trace.append((-1, -1, r.flow, cs, ct))
+            return FlowCutterResult("balanced", r.flow, sr, it, trace, S, T)
+        if total - ct <= max_source_weight and ct <= max_sink_weight:
+            trace.append((-1, -1, r.flow, cs, ct))
+            return FlowCutterResult("balanced", r.flow, ~tr, it, trace, S, T)
+        if cs <= ct:
+            p, _ = _piercing_node(hg, _cut_nets(hg, sr), sr, tr, tr & ~T)
+            trace.append((0, p, r.flow, cs, ct))
+            if p < 0:
+                return FlowCutterResult("infeasible", r.flow, sr, it, trace, S, T)
+            S = sr.copy()
+            S[p] = True
+        else:
+            p, _ = _piercing_node(hg, _cut_nets(hg, tr), sr, tr, sr & ~S)
+            trace.append((1, p, r.flow, cs, ct))
+            if p < 0:
+                return FlowCutterResult("infeasible", r.flow, ~tr, it, trace, S, T)
+            T = tr.copy()
+            T[p] = True
+    return FlowCutterResult("cap", trace[-1][2], sr, max_iterations, trace, S, T)

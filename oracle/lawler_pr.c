@@ -32,6 +32,12 @@
  * non-terminal nodes that still hold excess.  The reached set is the unique
  * inclusion-minimal source side of a minimum cut.
  *
+ * Sink side (same section, algorithm "FlowCutter Core": the sink-side cut is
+ * the reverse residual BFS from T): every node that can still reach tau in
+ * the residual network.  Its vertices form the unique inclusion-maximal sink
+ * side of a minimum cut (the complement of the union of all minimum-cut
+ * source sides).
+ *
  * Optional self-check (flag bit 0): convert the preflow into a flow by
  * continuing push / relabel above label n until every excess has returned to
  * sig, then BFS from sig alone and require the identical reached set.
@@ -244,6 +250,31 @@ static void forward_bfs(pr_t *s, uint8_t *reached, int seed_excess) {
   }
 }
 
+/* Reverse residual BFS from tau: marks every node with a residual path to
+ * tau.  A node a joins when some arc (a, b) with b marked has residual
+ * capacity; that arc is the pair of an arc stored at b. */
+static void reverse_bfs(pr_t *s, uint8_t *reaches) {
+  graph_t *g = s->g;
+  int64_t h = 0, t = 0;
+  memset(reaches, 0, (size_t)s->n);
+  reaches[s->tau] = 1;
+  s->bfs[t++] = s->tau;
+  while (h < t) {
+    int32_t b = s->bfs[h++];
+    for (int64_t x = g->first[b]; x < g->first[b + 1]; ++x) {
+      int32_t a = g->head[x];
+      if (!reaches[a] && g->cap[g->rev[x]] > 0) {
+        reaches[a] = 1;
+        s->bfs[t++] = a;
+      }
+    }
+  }
+}
+
+static int solve(int32_t V, int32_t E, const int32_t *off, const int32_t *pins, const int32_t *w,
+                 const int32_t *S, int32_t nS, const int32_t *T, int32_t nT, int32_t flags,
+                 int64_t *F, uint8_t *vside, uint8_t *nside, uint8_t *tside, int64_t *stats);
+
 /*
  * oracle_maxflow: minimum S-T cut of a hypergraph via its Lawler expansion.
  *
@@ -259,6 +290,21 @@ int oracle_maxflow(int32_t V, int32_t E, const int32_t *off, const int32_t *pins
                    const int32_t *w, const int32_t *S, int32_t nS, const int32_t *T,
                    int32_t nT, int32_t flags, int64_t *F, uint8_t *vside,
                    uint8_t *nside, int64_t *stats) {
+  return solve(V, E, off, pins, w, S, nS, T, nT, flags, F, vside, nside, NULL, stats);
+}
+
+/* As oracle_maxflow, and tside[V] (may be NULL): 1 if the vertex is on the
+ * maximal sink side (reaches tau in the residual network). */
+int oracle_maxflow_sides(int32_t V, int32_t E, const int32_t *off, const int32_t *pins,
+                         const int32_t *w, const int32_t *S, int32_t nS, const int32_t *T,
+                         int32_t nT, int32_t flags, int64_t *F, uint8_t *vside,
+                         uint8_t *nside, uint8_t *tside, int64_t *stats) {
+  return solve(V, E, off, pins, w, S, nS, T, nT, flags, F, vside, nside, tside, stats);
+}
+
+static int solve(int32_t V, int32_t E, const int32_t *off, const int32_t *pins, const int32_t *w,
+                 const int32_t *S, int32_t nS, const int32_t *T, int32_t nT, int32_t flags,
+                 int64_t *F, uint8_t *vside, uint8_t *nside, uint8_t *tside, int64_t *stats) {
   if (V < 0 || E < 0 || nS < 1 || nT < 1 || off[0] != 0) return OR_ERR_INPUT;
   for (int32_t e = 0; e < E; ++e)
     if (off[e + 1] < off[e] || w[e] < 1) return OR_ERR_INPUT;
@@ -323,6 +369,24 @@ int oracle_maxflow(int32_t V, int32_t E, const int32_t *off, const int32_t *pins
   for (int32_t v = 0; v < V; ++v) vside[v] = reached[v];
   for (int32_t e = 0; e < E; ++e)
     nside[e] = (uint8_t)(reached[V + e] | (reached[V + E + e] << 1));
+  if (tside) {
+    uint8_t *reaches = (uint8_t *)malloc((size_t)s.n);
+    if (!reaches) {
+      rc = OR_ERR_ALLOC;
+      goto done;
+    }
+    reverse_bfs(&s, reaches);
+    int clash = reaches[s.sig];
+    for (int32_t v = 0; v < V; ++v) {
+      tside[v] = reaches[v];
+      clash |= reaches[v] & reached[v];
+    }
+    free(reaches);
+    if (clash) {
+      rc = OR_ERR_SINK_REACHED; /* a source-side node reaches the sink */
+      goto done;
+    }
+  }
 
   if (flags & 1) {
     /* Return every remaining excess to the source: labels may now exceed n;

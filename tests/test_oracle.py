@@ -220,6 +220,98 @@ def test_splitmix64_reference_values():
 # mutation check of the pins
 # ---------------------------------------------------------------------------
 
+def _cutter_cases():
+    with open(os.path.join(HERE, "golden", "flowcutter.json")) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("case", _cutter_cases(), ids=lambda c: c["name"])
+def test_flowcutter_fixture(oracle_mod, case):
+    hg = inputs.hypergraph_from_nets(case["V"], case["nets"], case["w"], case["S"], case["T"])
+    r = oracle_mod.flowcutter(hg, np.ones(case["V"]), case["max_source"], case["max_sink"])
+    assert r.status == case["status"]
+    assert r.flow == case["F"]
+    assert np.nonzero(r.vertex_side)[0].tolist() == case["x"]
+    assert r.iterations == case["iterations"]
+    assert [list(t) for t in r.trace] == case["trace"]
+
+
+@pytest.mark.parametrize("block", range(3))
+def test_sink_side_vs_brute_force(oracle_mod, block):
+    """Maximal sink side = complement of the union of all minimisers."""
+    for seed in range(block * 100, block * 100 + 100):
+        hg = inputs.tiny_hypergraph(seed)
+        F, xl, xh = oracle_mod.brute_force_sides(hg)
+        r = oracle_mod.maxflow(hg, sink_side=True)
+        assert r.flow == F, seed
+        assert (r.vertex_side.astype(bool) == xl).all(), seed
+        assert (r.sink_side.astype(bool) == ~xh).all(), seed
+
+
+def test_flowcutter_tiny_invariants(oracle_mod):
+    """On tiny inputs: every returned cut is a minimum cut of the final
+    terminal sets (brute force), respects them and the balance bounds when
+    balanced; flows never decrease; at most |V| iterations."""
+    rng = np.random.default_rng(7)
+    seen = set()
+    for seed in range(300):
+        hg = inputs.tiny_hypergraph(seed)
+        V = hg.num_vertices
+        c = rng.integers(1, 4, V)
+        total = int(c.sum())
+        L = (total + 1) // 2 + int(rng.integers(0, 3))
+        r = oracle_mod.flowcutter(hg, c, L, L)
+        seen.add(r.status)
+        assert r.iterations <= V
+        flows = [t[2] for t in r.trace]
+        assert flows == sorted(flows), seed
+        x = r.vertex_side.astype(bool)
+        assert r.flow == oracle_mod.cut_weight(hg, x), seed
+        assert x[r.sources].all() and not x[r.sinks].any(), seed
+        fin = inputs.hypergraph_from_nets(V, [list(n) for n in hg.nets()], hg.net_weights,
+                                          np.nonzero(r.sources)[0], np.nonzero(r.sinks)[0])
+        assert oracle_mod.brute_force(fin)[0] == r.flow, seed
+        if r.status == "balanced":
+            assert int(c[x].sum()) <= L and total - int(c[x].sum()) <= L, seed
+    assert seen >= {"balanced", "infeasible"}
+
+
+CUTTER_MUTANTS = {
+    "pierce heavier side": ("if cs <= ct:", "if cs > ct:"),
+    "largest id": ("return int(free.min()), False", "return int(free.max()), False"),
+    "skip sink-side balance": ("if total - ct <= max_source_weight and ct <= max_sink_weight:",
+                               "if False:"),
+    "sink side = complement": ("tr = r.sink_side.astype(bool)", "tr = ~sr"),
+    "no augmenting fallback": ("aug = pins[own_terminals_side[pins]]", "aug = pins[:0]"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CUTTER_MUTANTS))
+def test_flowcutter_pins_catch_planted_mistakes(oracle_mod, name):
+    """A copy of the oracle's FlowCutter with one planted mistake must fail
+    at least one hand-derived fixture."""
+    import inspect
+    old, new = CUTTER_MUTANTS[name]
+    src = inspect.getsource(oracle_mod._piercing_node) + "\n" + inspect.getsource(
+        oracle_mod.flowcutter)
+    assert old in src
+    ns = dict(vars(oracle_mod))
+    exec(compile(src.replace(old, new), "<mutant>", "exec"), ns)
+    failed = False
+    for case in _cutter_cases():
+        hg = inputs.hypergraph_from_nets(case["V"], case["nets"], case["w"], case["S"],
+                                         case["T"])
+        try:
+            r = ns["flowcutter"](hg, np.ones(case["V"]), case["max_source"], case["max_sink"])
+            ok = (r.status == case["status"] and r.flow == case["F"] and
+                  [list(t) for t in r.trace] == case["trace"] and
+                  np.nonzero(r.vertex_side)[0].tolist() == case["x"])
+        except Exception:
+            ok = False
+        failed |= not ok
+    assert failed, f"mutant '{name}' passes every FlowCutter fixture"
+
+
 MUTANTS = {
     "bridge capacity off by one": ("ADD_ARC(ein, eout, (int64_t)w[e]);",
                                    "ADD_ARC(ein, eout, (int64_t)w[e] + 1);"),
