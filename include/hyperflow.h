@@ -273,21 +273,98 @@ void flow_batch_destroy(fp_batch *batch);
 fp_status flow_problem_reset(fp_problem *problem);
 
 /*
+ * flow_problem_sink_side: maximal sink side of the minimum cut after a
+ * solve -- the vertices that can still reach a sink in the residual network
+ * (paper, algorithm "FlowCutter Core": backward residual BFS from T; the
+ * uncapped network, as for the source side).  It is the complement of the
+ * union of all minimum-cut source sides, so it does not depend on the
+ * schedule.
+ *
+ *   mem_kind     memory kind of vertex_side
+ *   vertex_side  |V| bytes: 1 if the vertex reaches a sink
+ *
+ * Errors: FP_ERR_STATE before a successful solve, FP_ERR_DEVICE (an
+ * internal check found a source that reaches a sink).
+ */
+fp_status flow_problem_sink_side(fp_problem *problem, void *hip_stream, int32_t mem_kind,
+                                 uint8_t *vertex_side);
+
+/*
  * flow_problem_pierce: turn vertices into terminals for the next solve of an
  * incremental sequence (paper, section "Flow-Based Refinement", algorithm
  * "FlowCutter Core"; paragraphs "Sink-Side Piercing" and "Maintain Distance
  * Labels").  side 0: every vertex of the current minimal source side plus
  * the given vertices becomes a source; side 1: every vertex of the current
- * maximal sink side (vertices that reach a sink in the residual network)
- * plus the given vertices becomes a sink, and excess held by new sinks is
- * added to the flow value.  Flows are kept.
+ * maximal sink side plus the given vertices becomes a sink, and excess held
+ * by new sinks is added to the flow value.  The flow is kept (flows on the
+ * pin arcs of new sources are cancelled and a net gaining its first source
+ * pin receives its contracted source arc's w(e)), so the next
+ * maxflow_solve continues from it.
  *
- *   vertices  n host vertex ids (none may lie on the opposite terminal side)
+ *   vertices  n host vertex ids (none may be a terminal of the other side;
+ *             terminals of the pierced side are ignored)
  *
- * Errors: FP_ERR_STATE before a solve, FP_ERR_INVALID.
+ * Errors: FP_ERR_STATE before a successful solve, FP_ERR_INVALID (nothing
+ * is changed then).
  */
 fp_status flow_problem_pierce(fp_problem *problem, int32_t side, const int32_t *vertices,
                               int32_t n, void *hip_stream);
+
+/* Result of flow_problem_flowcutter. */
+typedef struct {
+  int64_t flow;          /* cut weight of the returned bipartition            */
+  int64_t source_weight; /* c(X) of the returned source side X                */
+  int64_t sink_weight;   /* c(V \ X)                                         */
+  int32_t iterations;    /* maximum flows computed                            */
+  int32_t status;        /* 0 balanced, 1 no piercing vertex left (the last
+                            cut is returned), 2 iteration cap (the last
+                            source side is returned)                        */
+  int32_t side;          /* 0: X = S_r (minimal source side); 1: X = V \ T_r
+                            (complement of the maximal sink side)           */
+  int32_t augmenting;    /* piercing steps that could not avoid an augmenting
+                            path                                             */
+  int64_t reserved[4];
+} fp_cutter_result;
+
+/* One FlowCutter iteration. */
+typedef struct {
+  int32_t side;          /* side pierced (0 source, 1 sink); -1 when the
+                            iteration ended the run                          */
+  int32_t node;          /* piercing vertex, -1 if none                       */
+  int64_t flow;          /* maximum flow value of the iteration               */
+  int64_t source_weight; /* c(S_r)                                            */
+  int64_t sink_weight;   /* c(T_r)                                            */
+} fp_cutter_step;
+
+/*
+ * flow_problem_flowcutter: FlowCutter on the problem's current terminals
+ * (paper, section "Flow-Based Refinement": algorithm "FlowCutter Core" and
+ * paragraph "Piercing"), one piercing vertex per iteration, every flow warm
+ * started from the previous one.  Each iteration solves the maximum flow,
+ * derives S_r and T_r, and stops when (S_r, V \ S_r) or else
+ * (V \ T_r, T_r) is balanced: c(X) <= max_source_weight and
+ * c(V \ X) <= max_sink_weight.  Otherwise the lighter of S_r and T_r
+ * (source side on ties) becomes the terminal set plus one piercing vertex:
+ * the smallest-id pin, outside S_r and T_r, of a net cut by that side's
+ * bipartition; else the smallest-id vertex outside S_r and T_r; else the
+ * smallest-id such cut-net pin on the other side that is not a terminal yet
+ * (an augmenting path follows).
+ *
+ *   vertex_weights  host, |V| ints >= 0
+ *   max_iterations  >= 1
+ *   mem_kind        memory kind of vertex_side
+ *   vertex_side     |V| bytes: the returned source side X
+ *   result          host out
+ *   trace           host, max_iterations entries, or NULL
+ *
+ * The handle keeps the final terminals and flow.  Errors: FP_ERR_INVALID,
+ * FP_ERR_ABORTED (a solve ran out of its round budget), FP_ERR_DEVICE.
+ */
+fp_status flow_problem_flowcutter(fp_problem *problem, const int32_t *vertex_weights,
+                                  int64_t max_source_weight, int64_t max_sink_weight,
+                                  int32_t max_iterations, void *hip_stream, int32_t mem_kind,
+                                  uint8_t *vertex_side, fp_cutter_result *result,
+                                  fp_cutter_step *trace);
 
 /* Counters of the handle (host out). */
 fp_status flow_problem_stats(const fp_problem *problem, fp_stats *out);

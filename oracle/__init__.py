@@ -493,9 +493,12 @@ def _cut_nets(hg, side):
 
 
 def _piercing_node(hg, cut, sr, tr, own_terminals_side):
-    """Smallest-id pin of a cut net outside S_r and T_r (avoids an augmenting
-    path); otherwise the smallest-id pin of a cut net on the opposite side
-    that is not yet a terminal; -1 if there is none."""
+    """Piercing vertex, in order of preference: the smallest-id pin outside
+    S_r and T_r of a net cut by the pierced side's bipartition (a boundary
+    vertex that avoids an augmenting path); the smallest-id vertex outside
+    S_r and T_r anywhere (still no augmenting path); the smallest-id pin of
+    such a cut net on the opposite side that is not yet a terminal (creates
+    an augmenting path).  (-1, False) if there is none."""
     E = hg.num_nets
     net_of = np.repeat(np.arange(E), np.diff(hg.net_offsets))
     on_cut = cut[net_of]
@@ -503,6 +506,9 @@ def _piercing_node(hg, cut, sr, tr, own_terminals_side):
     free = pins[~sr[pins] & ~tr[pins]]
     if free.size:
         return int(free.min()), False
+    anywhere = np.nonzero(~sr & ~tr)[0]
+    if anywhere.size:
+        return int(anywhere[0]), False
     aug = pins[own_terminals_side[pins]]
     if aug.size:
         return int(aug.min()), True
@@ -521,8 +527,9 @@ def flowcutter(hg, vertex_weights, max_source_weight, max_sink_weight,
     lighter of S_r and T_r (source side on ties) becomes the new terminal
     set plus one piercing node: the smallest-id pin, outside S_r and T_r, of
     a net cut by that side's bipartition; if there is none, the smallest-id
-    such pin on the other side that is not yet a terminal (it creates an
-    augmenting path).  Balanced: c(X) <= max_source_weight and
+    vertex outside S_r and T_r anywhere; if there is none, the smallest-id
+    such cut-net pin on the other side that is not yet a terminal (it
+    creates an augmenting path).  Balanced: c(X) <= max_source_weight and
     c(V \\ X) <= max_sink_weight.
     """
     V = hg.num_vertices

@@ -256,6 +256,40 @@ fp_status flow_problem_pierce(fp_problem* problem, int32_t side, const int32_t* 
   return pierce_problem(problem, side, vertices, n, static_cast<hipStream_t>(hip_stream));
 }
 
+fp_status flow_problem_sink_side(fp_problem* problem, void* hip_stream, int32_t mem_kind,
+                                 uint8_t* vertex_side) {
+  g_last_error.clear();
+  if (!problem) {
+    set_error("NULL handle");
+    return FP_ERR_STATE;
+  }
+  if (!vertex_side || (mem_kind != 0 && mem_kind != 1)) {
+    set_error("vertex_side must be non-NULL and mem_kind 0 or 1");
+    return FP_ERR_INVALID;
+  }
+  return sink_side_problem(problem, static_cast<hipStream_t>(hip_stream), mem_kind, vertex_side);
+}
+
+fp_status flow_problem_flowcutter(fp_problem* problem, const int32_t* vertex_weights,
+                                  int64_t max_source_weight, int64_t max_sink_weight,
+                                  int32_t max_iterations, void* hip_stream, int32_t mem_kind,
+                                  uint8_t* vertex_side, fp_cutter_result* result,
+                                  fp_cutter_step* trace) {
+  g_last_error.clear();
+  if (!problem) {
+    set_error("NULL handle");
+    return FP_ERR_STATE;
+  }
+  if (!vertex_weights || !vertex_side || !result || max_iterations < 1 ||
+      (mem_kind != 0 && mem_kind != 1)) {
+    set_error("invalid FlowCutter arguments");
+    return FP_ERR_INVALID;
+  }
+  return flowcutter_problem(problem, vertex_weights, max_source_weight, max_sink_weight,
+                            max_iterations, static_cast<hipStream_t>(hip_stream), mem_kind,
+                            vertex_side, result, trace);
+}
+
 fp_status flow_problem_stats(const fp_problem* problem, fp_stats* out) {
   if (!problem || !out) {
     set_error("NULL argument");

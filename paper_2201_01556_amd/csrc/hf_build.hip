@@ -505,8 +505,10 @@ void release_problem(fp_problem* pb) {
   }
   for (auto e : pb->free_events) hipEventDestroy(e);
   if (pb->pool) hipFree(pb->pool);
+  if (pb->cw) hipFree(pb->cw);
   if (pb->ctl_h) hipHostFree(pb->ctl_h);
   pb->pool = nullptr;
+  pb->cw = nullptr;
   pb->ctl_h = nullptr;
 }
 

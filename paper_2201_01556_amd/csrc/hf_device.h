@@ -60,6 +60,8 @@ enum : int32_t {
   ERR_LABEL = 1,         // a relabel did not raise the label
   ERR_SINK_REACHED = 2,  // forward cut BFS reached a sink
   ERR_INVARIANT = 4,     // debug invariant check failed
+  ERR_SOURCE_REACHED = 8,  // sink-side BFS reached a source
+  ERR_PIERCE_TERMINAL = 1024,  // a piercing vertex is a terminal of the other side
   ERR_BUILD_PIN = 16,
   ERR_BUILD_OFFSETS = 32,
   ERR_BUILD_WEIGHT = 64,
@@ -98,6 +100,9 @@ struct Ctl {
   unsigned long long relabels;  // relabel operations
   unsigned long long bytes[KC_N];
   unsigned long long items[KC_N];
+  unsigned long long side_weight[2];  // FlowCutter: c(S_r), c(T_r)
+  int32_t pierce[3];  // FlowCutter: smallest free boundary / augmenting / free vertex
+  int32_t pad;
 };
 
 struct Dev {
@@ -1289,6 +1294,235 @@ __device__ void phase_cut_out(const Dev& g, int ep, uint8_t* vside, uint8_t* nsi
   }
 }
 
+// ---------------------------------------------------------------------------
+// maximal sink side: reverse residual BFS from the sinks over the uncapped
+// network (paper, algorithm "FlowCutter Core": T_r by backward residual
+// BFS).  Node a joins when it has a residual arc into the current level:
+//   into a vertex u   from e_out (infinite) and from e_in if flow(u, e_in) > 0
+//   into e_in         from every pin (u -> e_in uncapped) and from e_out if fb > 0
+//   into e_out        from e_in if fb < w and from pins u with flow(e_out, u) > 0
+// Sources never join (a maximum preflow leaves no residual path from the
+// source to a sink); reaching one is reported as ERR_SOURCE_REACHED.
+// ---------------------------------------------------------------------------
+
+// Seeds: the sinks.  The BFS counters must be clear (phase_reset_bfs).
+__device__ void phase_sink_seed(const Dev& g, int ep, int tile0, int tstride, lds_int* lds) {
+  const BlockQ q = bq_bind(lds, g.ctl->bcnt[0], g.list[0]);
+  const int ntiles = sweep_tiles(g);
+  for (int tile = tile0; tile < ntiles; tile += tstride) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int v = (2 * tile + j) * blockDim.x + threadIdx.x;
+      const bool seed = v < g.V && g.role[v] == 2;
+      if (seed) g.stamp[v] = ep;
+      qpush(g, q, v, seed);
+    }
+    bq_tile_end(q, 2 * blockDim.x);
+  }
+  bq_flush(q);
+}
+
+__device__ void phase_bfs_sink_lb(const Dev& g, int level, int ep, int tile0, int tstride, int kc,
+                                  lds_int* lds) {
+  const int c3 = level % 3, n3 = (level + 1) % 3, z3 = (level + 2) % 3;
+  if (tile0 == 0 && threadIdx.x < kNL) g.ctl->bcnt[z3][threadIdx.x] = 0;
+  const int cp = level & 1, np = (level + 1) & 1;
+  const BlockQ q = bq_bind(lds, g.ctl->bcnt[n3], g.list[np]);
+  const ArcTile t = arc_tile(lds + bq_words());
+  const Prefix4 pre(load_counts(g.ctl->bcnt[c3]));
+  const int ntiles = (pre.total + blockDim.x - 1) / blockDim.x;
+  uint32_t nbytes = 0, narcs = 0;
+  bool hit_source = false;
+  for (int tile = tile0; tile < ntiles; tile += tstride) {
+    int nt = 0;
+    const int A = load_arc_tile(g, t, cp, pre, tile, &nt);
+    for (int a0 = 0; a0 < A; a0 += blockDim.x) {
+      const int a = a0 + threadIdx.x;
+      int t1 = 0, t2 = 0;
+      bool v1 = false, v2 = false;
+      if (a < A) {
+        const int k = arc_owner(t, nt, a);
+        const int x = t.node[k];
+        const int j = a - t.off[k];
+        const int b = t.beg[k];
+        ++narcs;
+        if (x < g.V) {
+          const int2 ep2 = g.vinc[b + j];
+          t1 = g.NB + 2 * ep2.x;
+          t2 = t1 + 1;
+          nbytes += 12;
+          v2 = stamp_first(g, t2, ep);                                         // e_out -> x
+          if (g.w[ep2.x] - g.fpin[2 * ep2.y] > 0) v1 = stamp_first(g, t1, ep);  // e_in -> x
+        } else {
+          const int e = (x - g.NB) >> 1;
+          const bool in = ((x - g.NB) & 1) == 0;
+          if (j == 0) {  // bridge
+            const int fbv = g.fb[e];
+            nbytes += 8;
+            t1 = in ? x + 1 : x - 1;
+            if (in ? fbv > 0 : fbv < g.w[e]) v1 = stamp_first(g, t1, ep);
+          } else {
+            const int i = b + j - 1;
+            t1 = g.pin_v[i];
+            const int r = g.role[t1];
+            nbytes += 8;
+            const bool arc = in || g.fpin[2 * i + 1] > 0;  // u -> e_in always, u -> e_out by flow
+            if (arc) {
+              if (r == 1) hit_source = true;
+              else v1 = stamp_first(g, t1, ep);
+            }
+          }
+        }
+      }
+      qpush(g, q, t1, v1);
+      qpush(g, q, t2, v2);
+      bq_tile_end(q, 2 * blockDim.x);
+    }
+    __syncthreads();  // the tile area is rewritten by the next tile
+  }
+  bq_flush(q);
+  if (hit_source) atomicOr(&g.ctl->err, ERR_SOURCE_REACHED);
+  wave_add_u64(&g.ctl->bytes[kc], (unsigned long long)nbytes + 12ull * narcs);
+  wave_add_u64(&g.ctl->items[kc], narcs);
+}
+
+// Clear the BFS counters and the FlowCutter side weights (own launch: the
+// next phase appends to the counters).
+__device__ void phase_reset_bfs(const Dev& g) {
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < kNL; ++k) g.ctl->bcnt[i][k] = 0;
+    g.ctl->side_weight[0] = 0ull;
+    g.ctl->side_weight[1] = 0ull;
+    for (int i = 0; i < 3; ++i) g.ctl->pierce[i] = kInf;
+  }
+}
+
+// Vertex bitmap of a BFS: 1 where the vertex carries stamp ep (when
+// invert, 1 where it does not).
+__device__ void phase_side_out(const Dev& g, int ep, bool invert, uint8_t* vside, int t0,
+                               int tstride) {
+  if (t0 == 0) {
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < kNL; ++k) g.ctl->bcnt[i][k] = 0;
+  }
+  for (int v = t0; v < g.V; v += tstride) vside[v] = (uint8_t)((g.stamp[v] == ep) != invert);
+}
+
+// ---------------------------------------------------------------------------
+// FlowCutter steps (paper, section "Flow-Based Refinement": algorithm
+// "FlowCutter Core", paragraphs "Piercing", "Sink-Side Piercing" and
+// "Maintain Distance Labels").  S_r carries stamp ep_s (sources included),
+// T_r stamp ep_t (sinks included).
+// ---------------------------------------------------------------------------
+
+// Weights c(S_r) and c(T_r), and pierce[2] = the smallest vertex outside
+// both (the counters are cleared by phase_reset_bfs).
+__device__ void phase_fc_weights(const Dev& g, const int32_t* cw, int ep_s, int ep_t, int t0,
+                                 int tstride) {
+  unsigned long long ws = 0, wt = 0;
+  int first_free = kInf;
+  for (int v = t0; v < g.V; v += tstride) {
+    const int st = g.stamp[v];
+    if (st == ep_s) ws += (unsigned long long)cw[v];
+    else if (st == ep_t) wt += (unsigned long long)cw[v];
+    else first_free = min(first_free, v);
+  }
+  wave_add_u64(&g.ctl->side_weight[0], ws);
+  wave_add_u64(&g.ctl->side_weight[1], wt);
+  if (first_free != kInf) atomicMin(&g.ctl->pierce[2], first_free);
+}
+
+// Piercing candidates of one side, thread per net.  side 0: nets cut by
+// (S_r, V - S_r), i.e. with a pin in S_r (e_in reached) and not all pins in
+// it (e_out not reached); side 1: nets with pins in T_r and outside it.
+// pierce[0] = smallest such pin outside S_r and T_r, pierce[1] = smallest
+// such pin on the opposite side that is not a terminal yet.
+__device__ void phase_fc_candidates(const Dev& g, int side, int ep_s, int ep_t, int t0,
+                                    int tstride) {
+  int best_free = kInf, best_aug = kInf;
+  for (int e = t0; e < g.E; e += tstride) {
+    const int beg = g.net_off[e], end = g.net_off[e + 1];
+    bool cut;
+    if (side == 0) {
+      cut = g.stamp[g.NB + 2 * e] == ep_s && g.stamp[g.NB + 2 * e + 1] != ep_s;
+    } else {
+      bool any_in = false, any_out = false;
+      for (int p = beg; p < end; ++p) {
+        const bool in = g.stamp[g.pin_v[p]] == ep_t;
+        any_in |= in;
+        any_out |= !in;
+      }
+      cut = any_in && any_out;
+    }
+    if (!cut) continue;
+    const int other = side == 0 ? ep_t : ep_s;
+    const int other_role = side == 0 ? 2 : 1;
+    for (int p = beg; p < end; ++p) {
+      const int u = g.pin_v[p];
+      const int st = g.stamp[u];
+      if (st != ep_s && st != ep_t) best_free = min(best_free, u);
+      else if (st == other && g.role[u] != other_role) best_aug = min(best_aug, u);
+    }
+  }
+  if (best_free != kInf) atomicMin(&g.ctl->pierce[0], best_free);
+  if (best_aug != kInf) atomicMin(&g.ctl->pierce[1], best_aug);
+}
+
+// Every free vertex with stamp ep_s becomes a source.  The flows of its
+// pin arcs are cancelled (flow(u, e_in) back out of e_in's excess, flow
+// (e_out, u) back into e_out's excess), and a net that gains its first
+// source pin receives w(e) through its contracted source arc, so the state
+// stays a preflow of the new network with the same flow value.
+__device__ void phase_pierce_sources(const Dev& g, int ep_s, int t0, int tstride) {
+  for (int v = t0; v < g.V; v += tstride) {
+    if (g.role[v] != 0 || g.stamp[v] != ep_s) continue;
+    g.role[v] = 1;
+    for (int i = g.vtx_off[v]; i < g.vtx_off[v + 1]; ++i) {
+      const int2 ep = g.vinc[i];
+      const int e = ep.x;
+      const int we = g.w[e];
+      const int fin = we - g.fpin[2 * ep.y];
+      const int fout = g.fpin[2 * ep.y + 1];
+      int add_in = -fin;
+      const int old = atomicOr(&g.nflag[e], 1);
+      if (!(old & 1)) add_in += we;
+      if (add_in) atomicAdd(&g.x[g.NB + 2 * e], add_in);
+      if (fout) atomicAdd(&g.x[g.NB + 2 * e + 1], fout);
+      g.fpin[2 * ep.y] = we;
+      g.fpin[2 * ep.y + 1] = 0;
+    }
+  }
+}
+
+// Every free vertex with stamp ep_t becomes a sink; excess it holds joins
+// the flow value (paragraph "Sink-Side Piercing").
+__device__ void phase_pierce_sinks(const Dev& g, int ep_t, int t0, int tstride) {
+  unsigned long long gained = 0;
+  for (int v = t0; v < g.V; v += tstride) {
+    if (g.role[v] != 0 || g.stamp[v] != ep_t) continue;
+    g.role[v] = 2;
+    const int xv = g.x[v];
+    if (xv > 0) {
+      gained += (unsigned long long)xv;
+      g.x[v] = 0;
+    }
+    for (int i = g.vtx_off[v]; i < g.vtx_off[v + 1]; ++i) atomicOr(&g.nflag[g.vinc[i].x], 2);
+  }
+  wave_add_u64(&g.ctl->flow, gained);
+}
+
+// Stamp the given vertices with ep; a vertex that is a terminal of kind
+// `forbidden` is reported as ERR_PIERCE_TERMINAL.
+__device__ void phase_mark(const Dev& g, const int32_t* vs, int n, int ep, int forbidden, int t0,
+                           int tstride) {
+  for (int i = t0; i < n; i += tstride) {
+    const int v = vs[i];
+    if (g.role[v] == forbidden) atomicOr(&g.ctl->err, ERR_PIERCE_TERMINAL);
+    else if (g.role[v] == 0) g.stamp[v] = ep;
+  }
+}
+
 // Debug: preflow feasibility (excess = inflow - outflow >= 0, capacities) and
 // label validity on every residual arc of the capped network, after a
 // completed round.  Thread per vertex / net / pin.
@@ -1333,7 +1567,7 @@ __device__ void phase_check(const Dev& g, int t0, int tstride) {
       const int we = g.w[e];
       if (rin < 0 || rin > we || fout < 0) bad = true;
       const int r = g.role[u];
-      if (r != 0 && rin != we) bad = true;  // no flow leaves a terminal
+      if (r == 1 && rin != we) bad = true;  // no flow leaves a source
       if (r == 1 && fout != 0) bad = true;  // nothing enters a source
       const int du = g.d[u], din = g.d[g.NB + 2 * e], dout = g.d[g.NB + 2 * e + 1];
       if (r == 0) {

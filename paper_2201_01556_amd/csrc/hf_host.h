@@ -52,6 +52,7 @@ struct fp_problem {
   int32_t epoch = 1;         // stamp value of the next round / BFS
   bool inited = false;
   bool solved = false;
+  int32_t* cw = nullptr;     // vertex weights of the last FlowCutter run (device)
   fp_stats st{};
   // profiling
   std::vector<hf::Timer> pending;
@@ -89,6 +90,10 @@ fp_status batch_config(const fp_batch* b, fp_batch_config* out);
 void release_batch(fp_batch* b);
 fp_status pierce_problem(fp_problem* pb, int32_t side, const int32_t* vertices, int32_t n,
                          hipStream_t s);
+fp_status sink_side_problem(fp_problem* pb, hipStream_t s, int32_t mem_kind, uint8_t* vside);
+fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src, int64_t max_snk,
+                             int32_t max_iters, hipStream_t s, int32_t mem_kind, uint8_t* vside,
+                             fp_cutter_result* res, fp_cutter_step* trace);
 fp_status export_state(fp_problem* pb, hipStream_t s, int32_t* f_in, int32_t* f_out,
                        int32_t* f_b, int32_t* labels, int32_t* excess);
 void release_problem(fp_problem* pb);

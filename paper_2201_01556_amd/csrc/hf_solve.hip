@@ -82,6 +82,44 @@ __global__ void __launch_bounds__(kBlock) k_bfs_fwd(Dev g, int level, int ep) {
   phase_bfs_fwd<G>(g, level, ep, blockIdx.x, gridDim.x, KC_BFS_FWD, lds);
 }
 
+__global__ void __launch_bounds__(kBlock) k_bfs_sink(Dev g, int level, int ep) {
+  HF_QUEUE_LDS;
+  phase_bfs_sink_lb(g, level, ep, blockIdx.x, gridDim.x, KC_BFS_FWD, lds);
+}
+
+__global__ void __launch_bounds__(kBlock) k_sink_seed(Dev g, int ep) {
+  HF_QUEUE_LDS;
+  phase_sink_seed(g, ep, blockIdx.x, gridDim.x, lds);
+}
+
+__global__ void k_reset_bfs(Dev g) { phase_reset_bfs(g); }
+
+__global__ void __launch_bounds__(kThreads) k_side_out(Dev g, int ep, int invert, uint8_t* vs) {
+  phase_side_out(g, ep, invert != 0, vs, gthread(), gthreads());
+}
+
+__global__ void __launch_bounds__(kThreads) k_fc_weights(Dev g, const int32_t* cw, int ep_s,
+                                                         int ep_t) {
+  phase_fc_weights(g, cw, ep_s, ep_t, gthread(), gthreads());
+}
+
+__global__ void __launch_bounds__(kThreads) k_fc_candidates(Dev g, int side, int ep_s, int ep_t) {
+  phase_fc_candidates(g, side, ep_s, ep_t, gthread(), gthreads());
+}
+
+__global__ void __launch_bounds__(kThreads) k_pierce_sources(Dev g, int ep_s) {
+  phase_pierce_sources(g, ep_s, gthread(), gthreads());
+}
+
+__global__ void __launch_bounds__(kThreads) k_pierce_sinks(Dev g, int ep_t) {
+  phase_pierce_sinks(g, ep_t, gthread(), gthreads());
+}
+
+__global__ void __launch_bounds__(kThreads) k_mark(Dev g, const int32_t* vs, int n, int ep,
+                                                   int forbidden) {
+  phase_mark(g, vs, n, ep, forbidden, gthread(), gthreads());
+}
+
 __global__ void __launch_bounds__(kThreads) k_cut_out(Dev g, int ep, uint8_t* vs, uint8_t* ns) {
   phase_cut_out(g, ep, vs, ns, gthread(), gthreads());
 }
@@ -136,9 +174,12 @@ __global__ void __launch_bounds__(kBlock) k_round_loop(Dev g, int epoch0, int ma
   }
 }
 
-// BFS levels inside one workgroup (reverse when ep < 0, forward otherwise).
+// BFS levels inside one workgroup: mode 0 the global relabel (reverse,
+// capped), 1 the source side (forward, uncapped), 2 the sink side (reverse,
+// uncapped).
 template <int G>
-__global__ void __launch_bounds__(kBlock) k_bfs_loop(Dev g, int level0, int cap, int ep) {
+__global__ void __launch_bounds__(kBlock) k_bfs_loop(Dev g, int level0, int cap, int ep,
+                                                     int mode) {
   HF_QUEUE_LDS;
   int level = level0;
   for (;;) {
@@ -146,8 +187,9 @@ __global__ void __launch_bounds__(kBlock) k_bfs_loop(Dev g, int level0, int cap,
     const int nf = count_all_vol(g.ctl->bcnt[c3]);
     if (nf == 0 || nf > cap) break;
     __syncthreads();
-    if (ep < 0) phase_bfs_rev<G>(g, level, 0, 1, KC_LOOP_BFS, lds);
-    else phase_bfs_fwd<G>(g, level, ep, 0, 1, KC_LOOP_BFS, lds);
+    if (mode == 0) phase_bfs_rev<G>(g, level, 0, 1, KC_LOOP_BFS, lds);
+    else if (mode == 1) phase_bfs_fwd<G>(g, level, ep, 0, 1, KC_LOOP_BFS, lds);
+    else phase_bfs_sink_lb(g, level, ep, 0, 1, KC_LOOP_BFS, lds);
     __syncthreads();
     ++level;
   }
@@ -224,8 +266,9 @@ static fp_status sync_ctl(fp_problem* pb, hipStream_t s, const char* what = "") 
 }
 
 template <int G>
-static fp_status run_bfs(fp_problem* pb, hipStream_t s, int ep, int* levels_out) {
-  // level 0 is already in bcnt[0]; ep < 0 = reverse (global relabel)
+static fp_status run_bfs(fp_problem* pb, hipStream_t s, int ep, int mode, int* levels_out) {
+  // level 0 is already in bcnt[0]; mode 0 global relabel (ep unused),
+  // 1 source side, 2 sink side (stamps ep)
   Dev& g = pb->dev;
   const int cap = pb->opt.tail_threshold;
   int level = 0;
@@ -237,8 +280,8 @@ static fp_status run_bfs(fp_problem* pb, hipStream_t s, int ep, int* levels_out)
     if (nf == 0) break;
     if (nf <= cap && !pb->opt.debug_checks) {
       {
-        Launch L(pb, s, ep < 0 ? KK_BFS_REV_LOOP : KK_BFS_FWD_LOOP);
-        k_bfs_loop<G><<<1, kBlock, 0, s>>>(g, level, cap, ep);
+        Launch L(pb, s, mode == 0 ? KK_BFS_REV_LOOP : KK_BFS_FWD_LOOP);
+        k_bfs_loop<G><<<1, kBlock, 0, s>>>(g, level, cap, ep, mode);
       }
       st = sync_ctl(pb, s, "bfs-loop");
       if (st) return st;
@@ -247,16 +290,19 @@ static fp_status run_bfs(fp_problem* pb, hipStream_t s, int ep, int* levels_out)
       const int steps = 8;
       const int big_min = pb->opt.bottom_up_min > 0 ? pb->opt.bottom_up_min : (1 << 30);
       for (int i = 0; i < steps; ++i) {
-        if (ep < 0) {
+        if (mode == 0) {
           {
             Launch L(pb, s, KK_BFS_REV);
             k_bfs_rev<G><<<kMaxFrontierBlocks, kBlock, 0, s>>>(g, level + i, big_min);
           }
           Launch L(pb, s, KK_BFS_COLLECT);
           k_bfs_collect<<<sweep_blocks(g.N), kBlock, 0, s>>>(g, level + i, big_min);
-        } else {
+        } else if (mode == 1) {
           Launch L(pb, s, KK_BFS_FWD);
           k_bfs_fwd<G><<<kMaxFrontierBlocks, kBlock, 0, s>>>(g, level + i, ep);
+        } else {
+          Launch L(pb, s, KK_BFS_FWD);
+          k_bfs_sink<<<kMaxFrontierBlocks, kBlock, 0, s>>>(g, level + i, ep);
         }
       }
       level += steps;
@@ -276,7 +322,7 @@ static fp_status global_relabel(fp_problem* pb, hipStream_t s) {
     k_gr_reset<<<sweep_blocks(g.N), kBlock, 0, s>>>(g);
   }
   int levels = 0;
-  fp_status st = run_bfs<G>(pb, s, -1, &levels);
+  fp_status st = run_bfs<G>(pb, s, -1, 0, &levels);
   if (st) return st;
   {
     Launch L(pb, s, KK_GATHER);
@@ -457,7 +503,7 @@ static fp_status cut_impl(fp_problem* pb, hipStream_t s, uint8_t* vs, uint8_t* n
     k_cut_seed<<<sweep_blocks(g.N), kBlock, 0, s>>>(g, ep);
   }
   int levels = 0;
-  fp_status st = run_bfs<G>(pb, s, ep, &levels);
+  fp_status st = run_bfs<G>(pb, s, ep, 1, &levels);
   if (st) return st;
   pb->st.bfs_levels += levels;
   {
@@ -502,9 +548,277 @@ fp_status cut_problem(fp_problem* pb, hipStream_t s, int32_t mem_kind, uint8_t* 
   return FP_OK;
 }
 
-fp_status pierce_problem(fp_problem*, int32_t, const int32_t*, int32_t, hipStream_t) {
-  set_error("flow_problem_pierce is not available in this build");
-  return FP_ERR_STATE;
+// ---------------------------------------------------------------------------
+// source / sink sides, piercing and the FlowCutter loop (paper, section
+// "Flow-Based Refinement", algorithm "FlowCutter Core")
+// ---------------------------------------------------------------------------
+
+// Stamp S_r (sources, then the forward residual BFS of the uncapped network
+// seeded with the excess nodes); returns the stamp value.
+template <int G>
+static fp_status source_side_stamps(fp_problem* pb, hipStream_t s, int* ep_out) {
+  Dev& g = pb->dev;
+  const int ep = pb->epoch++;
+  {
+    Launch L(pb, s, KK_CUT_SEED);
+    k_cut_seed<<<sweep_blocks(g.N), kBlock, 0, s>>>(g, ep);
+  }
+  int levels = 0;
+  fp_status st = run_bfs<G>(pb, s, ep, 1, &levels);
+  if (st) return st;
+  pb->st.bfs_levels += levels;
+  k_reset_bfs<<<1, 64, 0, s>>>(g);
+  st = sync_ctl(pb, s);
+  if (st) return st;
+  if (pb->ctl_h->err & ERR_SINK_REACHED) {
+    set_error("internal check: a sink is reachable from the source side");
+    return FP_ERR_DEVICE;
+  }
+  *ep_out = ep;
+  return FP_OK;
+}
+
+// Stamp T_r (sinks, then the reverse residual BFS of the uncapped network).
+template <int G>
+static fp_status sink_side_stamps(fp_problem* pb, hipStream_t s, int* ep_out) {
+  Dev& g = pb->dev;
+  const int ep = pb->epoch++;
+  k_reset_bfs<<<1, 64, 0, s>>>(g);
+  {
+    Launch L(pb, s, KK_CUT_SEED);
+    k_sink_seed<<<sweep_blocks(g.N), kBlock, 0, s>>>(g, ep);
+  }
+  int levels = 0;
+  fp_status st = run_bfs<G>(pb, s, ep, 2, &levels);
+  if (st) return st;
+  pb->st.bfs_levels += levels;
+  k_reset_bfs<<<1, 64, 0, s>>>(g);
+  st = sync_ctl(pb, s);
+  if (st) return st;
+  if (pb->ctl_h->err & ERR_SOURCE_REACHED) {
+    set_error("internal check: a source reaches a sink in the residual network");
+    return FP_ERR_DEVICE;
+  }
+  *ep_out = ep;
+  return FP_OK;
+}
+
+template <int G>
+static fp_status sides_impl(fp_problem* pb, hipStream_t s, int want, int* ep_s, int* ep_t) {
+  fp_status st = FP_OK;
+  if (want & 1) st = source_side_stamps<G>(pb, s, ep_s);
+  if (st == FP_OK && (want & 2)) st = sink_side_stamps<G>(pb, s, ep_t);
+  return st;
+}
+
+static fp_status sides(fp_problem* pb, hipStream_t s, int want, int* ep_s, int* ep_t) {
+  switch (pb->opt.group_lanes) {
+    case 4: return sides_impl<4>(pb, s, want, ep_s, ep_t);
+    case 16: return sides_impl<16>(pb, s, want, ep_s, ep_t);
+    default: return sides_impl<8>(pb, s, want, ep_s, ep_t);
+  }
+}
+
+fp_status sink_side_problem(fp_problem* pb, hipStream_t s, int32_t mem_kind, uint8_t* vside) {
+  if (!pb->solved) {
+    set_error("flow_problem_sink_side called before a successful maxflow_solve");
+    return FP_ERR_STATE;
+  }
+  int ep_t = 0;
+  fp_status st = sides(pb, s, 2, nullptr, &ep_t);
+  if (st) return st;
+  uint8_t* vs = mem_kind == 0 ? reinterpret_cast<uint8_t*>(pb->dev.list[1][kBigList]) : vside;
+  k_side_out<<<sweep_grid(pb->V), kThreads, 0, s>>>(pb->dev, ep_t, 0, vs);
+  hipError_t he = hipGetLastError();
+  if (he == hipSuccess && mem_kind == 0)
+    he = hipMemcpyAsync(vside, vs, pb->V, hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  if (he != hipSuccess) return hip_fail(he, "writing the sink side");
+  return FP_OK;
+}
+
+// Turn S_r (side 0) or T_r (side 1), stamped ep, plus the stamped piercing
+// vertices into terminals.
+static fp_status apply_pierce(fp_problem* pb, hipStream_t s, int side, int ep) {
+  Dev& g = pb->dev;
+  if (side == 0) k_pierce_sources<<<sweep_grid(g.V), kThreads, 0, s>>>(g, ep);
+  else k_pierce_sinks<<<sweep_grid(g.V), kThreads, 0, s>>>(g, ep);
+  hipError_t he = hipGetLastError();
+  if (he != hipSuccess) return hip_fail(he, "piercing");
+  pb->solved = false;
+  return FP_OK;
+}
+
+fp_status pierce_problem(fp_problem* pb, int32_t side, const int32_t* vertices, int32_t n,
+                         hipStream_t s) {
+  if (!pb->solved) {
+    set_error("flow_problem_pierce called before a successful maxflow_solve");
+    return FP_ERR_STATE;
+  }
+  for (int32_t i = 0; i < n; ++i)
+    if (vertices[i] < 0 || vertices[i] >= pb->V) {
+      set_error("piercing vertex %d out of range", vertices[i]);
+      return FP_ERR_INVALID;
+    }
+  int ep_s = 0, ep_t = 0;
+  fp_status st = sides(pb, s, side == 0 ? 1 : 2, &ep_s, &ep_t);
+  if (st) return st;
+  const int ep = side == 0 ? ep_s : ep_t;
+  if (n > 0) {
+    int32_t* dv = nullptr;
+    hipError_t he = hipMallocAsync(reinterpret_cast<void**>(&dv), (size_t)n * sizeof(int32_t), s);
+    if (he == hipSuccess)
+      he = hipMemcpyAsync(dv, vertices, (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (he == hipSuccess) {
+      k_mark<<<sweep_grid(n), kThreads, 0, s>>>(pb->dev, dv, n, ep, side == 0 ? 2 : 1);
+      he = hipGetLastError();
+    }
+    if (dv) (void)hipFreeAsync(dv, s);
+    if (he != hipSuccess) return hip_fail(he, "marking piercing vertices");
+    st = sync_ctl(pb, s);
+    if (st) return st;
+    if (pb->ctl_h->err & ERR_PIERCE_TERMINAL) {
+      // clear the flag; nothing has been pierced
+      pb->ctl_h->err &= ~ERR_PIERCE_TERMINAL;
+      he = hipMemcpyAsync(&pb->dev.ctl->err, &pb->ctl_h->err, sizeof(int32_t),
+                          hipMemcpyHostToDevice, s);
+      if (he == hipSuccess) he = hipStreamSynchronize(s);
+      if (he != hipSuccess) return hip_fail(he, "clearing the pierce check");
+      set_error("a piercing vertex is a terminal of the other side");
+      return FP_ERR_INVALID;
+    }
+  }
+  return apply_pierce(pb, s, side, ep);
+}
+
+fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src, int64_t max_snk,
+                             int32_t max_iters, hipStream_t s, int32_t mem_kind, uint8_t* vside,
+                             fp_cutter_result* res, fp_cutter_step* trace) {
+  Dev& g = pb->dev;
+  long long total = 0;
+  for (int32_t v = 0; v < pb->V; ++v) {
+    if (vw[v] < 0) {
+      set_error("vertex weight of %d is negative", v);
+      return FP_ERR_INVALID;
+    }
+    total += vw[v];
+  }
+  hipError_t he = hipSuccess;
+  if (!pb->cw) {
+    he = hipMalloc(reinterpret_cast<void**>(&pb->cw), (size_t)pb->V * sizeof(int32_t));
+    if (he != hipSuccess) {
+      pb->cw = nullptr;
+      return hip_fail(he, "allocating vertex weights");
+    }
+  }
+  he = hipMemcpyAsync(pb->cw, vw, (size_t)pb->V * sizeof(int32_t), hipMemcpyHostToDevice, s);
+  if (he != hipSuccess) return hip_fail(he, "copying vertex weights");
+  fp_cutter_result r{};
+  uint8_t* vs = mem_kind == 0 ? reinterpret_cast<uint8_t*>(pb->dev.list[1][kBigList]) : vside;
+  int out_ep = -1, out_invert = 0;
+  long long last_cs = 0;
+  r.status = 2;  // iteration cap unless a branch below decides
+  for (int32_t it = 1; it <= max_iters; ++it) {
+    int64_t F = 0;
+    fp_status st = solve_problem(pb, s, &F);
+    if (st) return st;
+    int ep_s = 0, ep_t = 0;
+    st = sides(pb, s, 3, &ep_s, &ep_t);
+    if (st) return st;
+    k_fc_weights<<<sweep_grid(pb->V), kThreads, 0, s>>>(g, pb->cw, ep_s, ep_t);
+    st = sync_ctl(pb, s);
+    if (st) return st;
+    const long long cs = (long long)pb->ctl_h->side_weight[0];
+    const long long ct = (long long)pb->ctl_h->side_weight[1];
+    r.iterations = it;
+    r.flow = F;
+    out_ep = ep_s;  // the iteration cap reports this iteration's S_r
+    last_cs = cs;
+    fp_cutter_step step{};
+    step.flow = F;
+    step.source_weight = cs;
+    step.sink_weight = ct;
+    step.side = -1;
+    step.node = -1;
+    bool done = false;
+    if (cs <= max_src && total - cs <= max_snk) {
+      r.status = 0;
+      r.side = 0;
+      r.source_weight = cs;
+      r.sink_weight = total - cs;
+      out_ep = ep_s;
+      out_invert = 0;
+      done = true;
+    } else if (total - ct <= max_src && ct <= max_snk) {
+      r.status = 0;
+      r.side = 1;
+      r.source_weight = total - ct;
+      r.sink_weight = ct;
+      out_ep = ep_t;
+      out_invert = 1;
+      done = true;
+    }
+    if (!done) {
+      const int side = cs <= ct ? 0 : 1;
+      k_fc_candidates<<<sweep_grid(pb->E), kThreads, 0, s>>>(g, side, ep_s, ep_t);
+      st = sync_ctl(pb, s);
+      if (st) return st;
+      // a free boundary pin, else any free vertex, else an augmenting pin
+      int p = pb->ctl_h->pierce[0];
+      bool aug = false;
+      if (p == kInf) p = pb->ctl_h->pierce[2];
+      if (p == kInf) {
+        p = pb->ctl_h->pierce[1];
+        aug = true;
+      }
+      step.side = side;
+      step.node = p == kInf ? -1 : p;
+      if (p == kInf) {
+        r.status = 1;
+        r.side = side;
+        if (side == 0) {
+          r.source_weight = cs;
+          r.sink_weight = total - cs;
+          out_ep = ep_s;
+          out_invert = 0;
+        } else {
+          r.source_weight = total - ct;
+          r.sink_weight = ct;
+          out_ep = ep_t;
+          out_invert = 1;
+        }
+        done = true;
+      } else {
+        if (aug) r.augmenting++;
+        const int ep = side == 0 ? ep_s : ep_t;
+        he = hipMemcpyAsync(g.stamp + p, &ep, sizeof(int32_t), hipMemcpyHostToDevice, s);
+        if (he == hipSuccess) he = hipStreamSynchronize(s);  // ep lives on the host stack
+        if (he != hipSuccess) return hip_fail(he, "marking the piercing vertex");
+        st = apply_pierce(pb, s, side, ep);
+        if (st) return st;
+      }
+    }
+    if (trace) trace[it - 1] = step;
+    if (done) break;
+  }
+  if (r.status == 2) {  // iteration cap: the last iteration's S_r (its stamps survive piercing)
+    r.side = 0;
+    r.source_weight = last_cs;
+    r.sink_weight = total - last_cs;
+    out_invert = 0;
+  }
+  if (out_ep < 0) {
+    set_error("max_iterations must be at least 1");
+    return FP_ERR_INVALID;
+  }
+  k_side_out<<<sweep_grid(pb->V), kThreads, 0, s>>>(g, out_ep, out_invert, vs);
+  he = hipGetLastError();
+  if (he == hipSuccess && mem_kind == 0)
+    he = hipMemcpyAsync(vside, vs, pb->V, hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  if (he != hipSuccess) return hip_fail(he, "writing the FlowCutter side");
+  *res = r;
+  return FP_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -10,7 +10,8 @@ The C entry points are exposed under their own names
 (``flow_problem_create``, ``maxflow_solve``, ``mincut_source_side``,
 ``flow_batch_solve``, ``flow_batch_create``, ``flow_batch_run``,
 ``flow_batch_tune``, ``flow_batch_get_config``, ``flow_batch_destroy``,
-``flow_problem_reset``, ``flow_problem_pierce``, ``flow_problem_stats``,
+``flow_problem_reset``, ``flow_problem_sink_side``, ``flow_problem_pierce``,
+``flow_problem_flowcutter``, ``flow_problem_stats``,
 ``flow_problem_kernel_times``, ``flow_problem_destroy``, ``fp_last_error``)
 plus small owner classes :class:`FlowProblem` and :class:`FlowBatch`.
 """
@@ -88,6 +89,31 @@ class BatchConfig(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
 
 
+class CutterResult(ctypes.Structure):
+    _fields_ = [
+        ("flow", ctypes.c_int64),
+        ("source_weight", ctypes.c_int64),
+        ("sink_weight", ctypes.c_int64),
+        ("iterations", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("side", ctypes.c_int32),
+        ("augmenting", ctypes.c_int32),
+        ("reserved", ctypes.c_int64 * 4),
+    ]
+
+
+class CutterStep(ctypes.Structure):
+    _fields_ = [
+        ("side", ctypes.c_int32),
+        ("node", ctypes.c_int32),
+        ("flow", ctypes.c_int64),
+        ("source_weight", ctypes.c_int64),
+        ("sink_weight", ctypes.c_int64),
+    ]
+
+
+CUTTER_STATUS = {0: "balanced", 1: "infeasible", 2: "cap"}
+
 EXPORTED = [
     "flow_problem_create",
     "maxflow_solve",
@@ -99,7 +125,9 @@ EXPORTED = [
     "flow_batch_get_config",
     "flow_batch_destroy",
     "flow_problem_reset",
+    "flow_problem_sink_side",
     "flow_problem_pierce",
+    "flow_problem_flowcutter",
     "flow_problem_stats",
     "flow_problem_kernel_times",
     "flow_problem_export_state",
@@ -145,6 +173,11 @@ def load_library(path: str = LIB_PATH):
     lib.flow_problem_reset.restype = ctypes.c_int
     lib.flow_problem_pierce.argtypes = [vp, i32, vp, i32, vp]
     lib.flow_problem_pierce.restype = ctypes.c_int
+    lib.flow_problem_sink_side.argtypes = [vp, vp, i32, vp]
+    lib.flow_problem_sink_side.restype = ctypes.c_int
+    lib.flow_problem_flowcutter.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int64, i32, vp, i32,
+                                            vp, ctypes.POINTER(CutterResult), vp]
+    lib.flow_problem_flowcutter.restype = ctypes.c_int
     lib.flow_problem_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     lib.flow_problem_stats.restype = ctypes.c_int
     lib.flow_problem_kernel_times.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_char_p),
@@ -336,6 +369,48 @@ def flow_problem_reset(handle):
     _check(load_library().flow_problem_reset(handle))
 
 
+def flow_problem_sink_side(handle, num_vertices, vertex_side=None, stream=None):
+    """Maximal sink side (vertices that reach a sink in the residual
+    network).  Host numpy array unless a device tensor is given."""
+    if vertex_side is None:
+        vertex_side = np.zeros(max(num_vertices, 1), dtype=np.uint8)
+    vp, vk, _ = _ptr(vertex_side, np.uint8)
+    _check(load_library().flow_problem_sink_side(handle, _stream_ptr(stream), vk, vp))
+    if vk == 0:
+        return np.asarray(vertex_side)[:num_vertices]
+    return vertex_side
+
+
+def flow_problem_flowcutter(handle, num_vertices, vertex_weights, max_source_weight,
+                            max_sink_weight, max_iterations=100000, vertex_side=None,
+                            stream=None, want_trace=True):
+    """FlowCutter on the handle's current terminals.  Returns (result dict,
+    source side X, trace list of (side, node, flow, c(S_r), c(T_r)))."""
+    lib = load_library()
+    vw = np.ascontiguousarray(vertex_weights, dtype=np.int32)
+    if vw.shape[0] != num_vertices:
+        raise ValueError("one weight per vertex")
+    if vertex_side is None:
+        vertex_side = np.zeros(max(num_vertices, 1), dtype=np.uint8)
+    vp, vk, _ = _ptr(vertex_side, np.uint8)
+    res = CutterResult()
+    steps = (CutterStep * max(int(max_iterations), 1))() if want_trace else None
+    _check(lib.flow_problem_flowcutter(handle, vw.ctypes.data, int(max_source_weight),
+                                       int(max_sink_weight), int(max_iterations),
+                                       _stream_ptr(stream), vk, vp, ctypes.byref(res),
+                                       ctypes.cast(steps, ctypes.c_void_p) if steps else None))
+    out = dict(flow=int(res.flow), source_weight=int(res.source_weight),
+               sink_weight=int(res.sink_weight), iterations=int(res.iterations),
+               status=CUTTER_STATUS.get(res.status, str(res.status)), side=int(res.side),
+               augmenting=int(res.augmenting))
+    trace = []
+    if steps is not None:
+        trace = [(int(t.side), int(t.node), int(t.flow), int(t.source_weight),
+                  int(t.sink_weight)) for t in steps[:res.iterations]]
+    x = np.asarray(vertex_side)[:num_vertices] if vk == 0 else vertex_side
+    return out, x, trace
+
+
 def flow_problem_pierce(handle, side: int, vertices, stream=None):
     v = np.ascontiguousarray(vertices, dtype=np.int32)
     _check(load_library().flow_problem_pierce(handle, int(side), v.ctypes.data, len(v),
@@ -419,6 +494,15 @@ class FlowProblem:
 
     def pierce(self, side: int, vertices):
         flow_problem_pierce(self.handle, side, vertices, self.stream)
+
+    def sink_side(self, vertex_side=None):
+        return flow_problem_sink_side(self.handle, self.num_vertices, vertex_side, self.stream)
+
+    def flowcutter(self, vertex_weights, max_source_weight, max_sink_weight,
+                   max_iterations=100000, vertex_side=None, want_trace=True):
+        return flow_problem_flowcutter(self.handle, self.num_vertices, vertex_weights,
+                                       max_source_weight, max_sink_weight, max_iterations,
+                                       vertex_side, self.stream, want_trace)
 
     def stats(self) -> dict:
         return flow_problem_stats(self.handle)

@@ -1,0 +1,197 @@
+"""GPU parity of the incremental FlowCutter path (maximal sink side,
+piercing with warm-started flows, the FlowCutter loop) against the CPU
+oracle, through the C ABI.
+
+Every quantity compared is determined by the terminal sets alone (flow
+value, minimal source side, maximal sink side) or by the deterministic
+piercing rule on top of them (the FlowCutter trace), so the GPU must match
+the oracle exactly although it warm starts and the oracle solves every
+iteration from scratch.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2201_01556_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _say(msg):
+    print(f"[gpu-cutter] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def hf():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2201_01556_amd import hyperflow
+    hyperflow.load_library()
+    return hyperflow
+
+
+def _with_terminals(hg, S, T):
+    return inputs.Hypergraph(hg.num_vertices, hg.net_offsets, hg.pins, hg.net_weights,
+                             hg.vertex_weights, np.asarray(sorted(S), dtype=np.int32),
+                             np.asarray(sorted(T), dtype=np.int32))
+
+
+def balance_limit(total):
+    """floor(103 * ceil(c(V) / 2) / 100): eps = 0.03 on two blocks."""
+    return (103 * (-(-int(total) // 2))) // 100
+
+
+@pytest.mark.parametrize("block", range(2))
+def test_sink_side_tiny_vs_oracle(hf, oracle_mod, block):
+    for seed in range(block * 150, block * 150 + 150):
+        hg = inputs.tiny_hypergraph(seed)
+        _say(f"tiny seed {seed}")
+        r = oracle_mod.maxflow(hg, sink_side=True)
+        with hf.FlowProblem.from_hypergraph(hg) as p:
+            assert p.solve() == r.flow
+            t = p.sink_side()
+        assert (t.astype(bool) == r.sink_side.astype(bool)).all(), seed
+
+
+def test_sink_side_uniform_vs_oracle(hf, oracle_mod):
+    for seed in range(10):
+        hg = inputs.uniform_hypergraph(seed)
+        r = oracle_mod.maxflow(hg, sink_side=True)
+        with hf.FlowProblem.from_hypergraph(hg, group_lanes=[4, 8, 16][seed % 3]) as p:
+            assert p.solve() == r.flow
+            t = p.sink_side()
+        assert (t.astype(bool) == r.sink_side.astype(bool)).all(), seed
+
+
+@pytest.mark.parametrize("side", [0, 1])
+def test_pierce_warm_start_vs_oracle(hf, oracle_mod, side):
+    """Solve, pierce (S_r or T_r plus one vertex), solve again warm with the
+    invariant checker on: flow and both sides equal a fresh oracle solve of
+    the new terminal sets."""
+    for seed in range(12):
+        hg = inputs.uniform_hypergraph(seed, num_vertices=600, num_nets=900, num_sources=20,
+                                       num_sinks=20)
+        _say(f"pierce side {side} seed {seed}")
+        with hf.FlowProblem.from_hypergraph(hg, debug_checks=1) as p:
+            p.solve()
+            vs, _ = p.source_side()
+            ts = p.sink_side()
+            free = np.nonzero(~vs.astype(bool) & ~ts.astype(bool))[0]
+            pick = int(free[len(free) // 2]) if free.size else None
+            if side == 0:
+                S = set(np.nonzero(vs)[0].tolist()) | ({pick} if pick is not None else set())
+                T = set(hg.sinks.tolist())
+            else:
+                S = set(hg.sources.tolist())
+                T = set(np.nonzero(ts)[0].tolist()) | ({pick} if pick is not None else set())
+            p.pierce(side, [] if pick is None else [pick])
+            F = p.solve()
+            vs2, ns2 = p.source_side()
+            ts2 = p.sink_side()
+        r = oracle_mod.maxflow(_with_terminals(hg, S, T), sink_side=True)
+        assert F == r.flow, seed
+        assert (vs2.astype(bool) == r.vertex_side.astype(bool)).all(), seed
+        assert (ns2 == r.net_side).all(), seed
+        assert (ts2.astype(bool) == r.sink_side.astype(bool)).all(), seed
+
+
+def test_pierce_errors(hf):
+    hg = inputs.uniform_hypergraph(3, num_vertices=300, num_nets=450, num_sources=10,
+                                   num_sinks=10)
+    with hf.FlowProblem.from_hypergraph(hg) as p:
+        with pytest.raises(hf.HyperflowError) as ei:
+            p.pierce(0, [1])
+        assert ei.value.name == "FP_ERR_STATE"
+        F = p.solve()
+        with pytest.raises(hf.HyperflowError) as ei:
+            p.pierce(0, [int(hg.sinks[0])])
+        assert ei.value.name == "FP_ERR_INVALID"
+        with pytest.raises(hf.HyperflowError) as ei:
+            p.pierce(1, [hg.num_vertices])
+        assert ei.value.name == "FP_ERR_INVALID"
+        # nothing changed: the handle is still solved with the same flow
+        assert p.solve() == F
+
+
+def _cutter_cases():
+    with open(os.path.join(HERE, "golden", "flowcutter.json")) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("case", _cutter_cases(), ids=lambda c: c["name"])
+def test_flowcutter_fixtures(hf, case):
+    hg = inputs.hypergraph_from_nets(case["V"], case["nets"], case["w"], case["S"], case["T"])
+    with hf.FlowProblem.from_hypergraph(hg) as p:
+        res, x, trace = p.flowcutter(np.ones(case["V"]), case["max_source"], case["max_sink"])
+    assert res["status"] == case["status"]
+    assert res["flow"] == case["F"]
+    assert res["iterations"] == case["iterations"]
+    assert np.nonzero(x)[0].tolist() == case["x"]
+    assert [list(t) for t in trace] == case["trace"]
+
+
+def _compare_cutter(hf, oracle_mod, hg, c, Ls, Lt, max_iter, tag, **opts):
+    ref = oracle_mod.flowcutter(hg, c, Ls, Lt, max_iterations=max_iter)
+    with hf.FlowProblem.from_hypergraph(hg, **opts) as p:
+        res, x, trace = p.flowcutter(c, Ls, Lt, max_iterations=max_iter)
+    assert res["iterations"] == ref.iterations, tag
+    assert [tuple(t) for t in trace] == [tuple(t) for t in ref.trace], tag
+    assert res["status"] == ref.status, tag
+    assert res["flow"] == ref.flow, tag
+    assert (x.astype(bool) == ref.vertex_side.astype(bool)).all(), tag
+    return res
+
+
+def test_flowcutter_tiny_vs_oracle(hf, oracle_mod):
+    rng = np.random.default_rng(11)
+    for seed in range(200):
+        hg = inputs.tiny_hypergraph(seed)
+        c = rng.integers(1, 4, hg.num_vertices)
+        L = (int(c.sum()) + 1) // 2 + int(rng.integers(0, 3))
+        _compare_cutter(hf, oracle_mod, hg, c, L, L, 100, f"tiny {seed}",
+                        debug_checks=1 if seed % 5 == 0 else 0)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_flowcutter_uniform_vs_oracle(hf, oracle_mod, seed):
+    """2,000 vertices, 3,000 nets; vertex weights U{1..3}; eps = 0.03."""
+    hg = inputs.uniform_hypergraph(seed)
+    c = np.random.default_rng(seed).integers(1, 4, hg.num_vertices)
+    L = balance_limit(c.sum())
+    _say(f"uniform {seed}")
+    res = _compare_cutter(hf, oracle_mod, hg, c, L, L, 5000, f"uniform {seed}",
+                          group_lanes=[4, 8, 16][seed % 3])
+    assert res["status"] == "balanced"
+
+
+def test_flowcutter_block_pairs_vs_oracle(hf, oracle_mod):
+    """Region problems of a partitioned hypergraph, balance = the k-way
+    bound on both blocks (s and t carry the rest of their blocks)."""
+    bp = inputs.block_pair_problems(0, num_vertices=20000, target_pins=100000, k=8,
+                                    max_problems=6)
+    for i, h in enumerate(bp.problems):
+        _say(f"block pair {i}")
+        res = _compare_cutter(hf, oracle_mod, h, h.vertex_weights, bp.lmax, bp.lmax, 3000,
+                              f"pair {i}")
+        assert res["flow"] >= 0
+
+
+def test_flowcutter_zipf_prefix_vs_oracle(hf, oracle_mod):
+    """The 200k-vertex incremental instance (Zipf sizes clamped to 200,
+    vertex weights U{1..3}): the first 25 iterations match the oracle."""
+    hg = inputs.zipf_hypergraph(0, 200_000, 400_000, size_hi=200, vertex_weight_hi=3)
+    c = hg.vertex_weights
+    L = balance_limit(c.sum())
+    _say("zipf 200k prefix")
+    ref = oracle_mod.flowcutter(hg, c, L, L, max_iterations=25)
+    with hf.FlowProblem.from_hypergraph(hg) as p:
+        res, x, trace = p.flowcutter(c, L, L, max_iterations=25)
+    assert [tuple(t) for t in trace] == [tuple(t) for t in ref.trace]
+    assert res["status"] == ref.status
+    assert (x.astype(bool) == ref.vertex_side.astype(bool)).all()

@@ -283,6 +283,7 @@ CUTTER_MUTANTS = {
                                "if False:"),
     "sink side = complement": ("tr = r.sink_side.astype(bool)", "tr = ~sr"),
     "no augmenting fallback": ("aug = pins[own_terminals_side[pins]]", "aug = pins[:0]"),
+    "no free-vertex fallback": ("anywhere = np.nonzero(~sr & ~tr)[0]", "anywhere = pins[:0]"),
 }
 
 
