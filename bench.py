@@ -48,6 +48,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the block-pair batch workload")
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--batch-problems", type=int, default=500)
+    ap.add_argument("--no-cutter", action="store_true",
+                    help="skip the incremental FlowCutter workload")
+    ap.add_argument("--cutter-iterations", type=int, default=400)
     ap.add_argument("--profile", type=int, default=2,
                     help="HIP-event timing inside the timed steps: 0 off, 1 every kernel, "
                          "2 only the reverse-BFS level kernel (the dominant one)")
@@ -156,6 +159,10 @@ def main():
                       np.array_equal(vs.cpu().numpy(), ref.vertex_side) and
                       np.array_equal(ns.cpu().numpy(), ref.net_side))
 
+    cutter = None
+    if not args.no_cutter:
+        cutter = bench_cutter(args, hyperflow, inputs, torch, np)
+
     batch = None
     if not args.no_batch:
         del arrays, vs, ns
@@ -190,6 +197,7 @@ def main():
         "parity_vs_oracle": parity,
         "kernels": kernels,
         "batch": batch,
+        "cutter": cutter,
     }
     print(json.dumps(out), flush=True)
 
@@ -202,6 +210,47 @@ def _cut_weight(hg, side, np):
     cnt = np.bincount(net_of, weights=inside, minlength=hg.num_nets)
     cut = (cnt > 0) & (cnt < sizes)
     return int(hg.net_weights[cut].sum())
+
+
+def bench_cutter(args, hyperflow, inputs, torch, np):
+    """Incremental FlowCutter on one region: 200,000 vertices, 400,000 nets
+    with Zipf(2.2) sizes clamped to [2, 200], vertex weights U{1..3}, 1 %
+    hash-selected sources and sinks, eps = 0.03.  One piercing vertex per
+    iteration and warm-started flows; a bounded number of iterations is
+    timed (the instance needs far more to balance)."""
+    _log("generating the FlowCutter region")
+    hg = inputs.zipf_hypergraph(args.seed, 200_000, 400_000, size_hi=200, vertex_weight_hi=3)
+    c = hg.vertex_weights
+    L = (103 * (-(-int(c.sum()) // 2))) // 100
+    iters = args.cutter_iterations
+    out = dict(workload=f"flowcutter: {hg.num_vertices} vertices, {hg.num_nets} nets, "
+                        f"Zipf(2.2) sizes clamped to [2,200], vertex weights U{{1..3}}, "
+                        f"eps=0.03 (L={L}), one piercing vertex per iteration",
+               pins=hg.num_pins, unit="iterations/s")
+    with hyperflow.FlowProblem.from_hypergraph(hg, device=True) as p:
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res, x, trace = p.flowcutter(c, L, L, max_iterations=iters)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+    out.update(value=round(res["iterations"] / dt, 2), iterations=res["iterations"],
+               seconds=round(dt, 3), status=res["status"], flow=res["flow"],
+               source_weight=res["source_weight"], sink_weight=res["sink_weight"],
+               augmenting=res["augmenting"],
+               first_steps=[list(t) for t in trace[:3]], last_step=list(trace[-1]))
+    if not args.no_cpu_baseline:
+        import oracle
+        k = 3
+        t = time.perf_counter()
+        ref = oracle.flowcutter(hg, c, L, L, max_iterations=k)
+        dt = time.perf_counter() - t
+        out["parity_vs_oracle_prefix"] = [tuple(s) for s in ref.trace] == \
+            [tuple(s) for s in trace[:k]]
+        out["cpu_baseline"] = dict(value=round(k / dt, 3), unit="iterations/s", cores=1,
+                                   kind="oracle",
+                                   sample=f"the first {k} iterations, every max flow solved from "
+                                          "scratch, single thread")
+    return out
 
 
 def bench_batch(args, hyperflow, inputs, torch, np):

@@ -490,7 +490,7 @@ __device__ void push_vertex(const Dev& g, const RoundArgs& ra, const BlockQ& q, 
 
 template <int G>
 __device__ void push_ein(const Dev& g, const RoundArgs& ra, const BlockQ& q, int node, bool has,
-                         int gl, uint32_t& nbytes) {
+                         int gl, uint32_t& nbytes, unsigned long long& to_sink) {
   const int e = (node - g.NB) >> 1;
   int k = 0, X = 0;
   if (has) {
@@ -535,7 +535,10 @@ __device__ void push_ein(const Dev& g, const RoundArgs& ra, const BlockQ& q, int
         const uint32_t used = min(carry + excl, UX);
         const uint32_t give = min(want, UX - used);
         if (give) g.fpin[2 * i] = rin + (int)give;
-        deliver(g, ra, q, u, give);
+        // a pin labelled 0 is a sink: a vertex pierced into the sink side
+        // can still carry flow into e_in, and returning it reaches the sink
+        if (du == 0) to_sink += give;
+        deliver(g, ra, q, u, du != 0 ? give : 0u);
         if (valid && r > give) cand = min(cand, du + 1);
         carry = min(carry + __shfl(incl, G - 1, G), UX);
         if (carry >= UX) break;
@@ -611,7 +614,7 @@ __device__ __forceinline__ void push_node(const Dev& g, const RoundArgs& ra, con
                                           unsigned long long& to_sink) {
   // kind is wave-divergent only across groups; each branch is group-uniform
   if (!has || v < g.V) push_vertex<G>(g, ra, q, v, has, gl, nbytes);
-  else if (((v - g.NB) & 1) == 0) push_ein<G>(g, ra, q, v, has, gl, nbytes);
+  else if (((v - g.NB) & 1) == 0) push_ein<G>(g, ra, q, v, has, gl, nbytes, to_sink);
   else push_eout<G>(g, ra, q, v, has, gl, nbytes, to_sink);
 }
 
@@ -646,7 +649,7 @@ __device__ void phase_push(const Dev& g, int epoch, int tile0, int tstride, int 
         const int v = has ? g.list[ra.cur][k][idx] : 0;
         nitems += has && (lane % G) == 0;
         if (k == 0) push_vertex<G>(g, ra, q, v, has, lane % G, nbytes);
-        else if (k == 1) push_ein<G>(g, ra, q, v, has, lane % G, nbytes);
+        else if (k == 1) push_ein<G>(g, ra, q, v, has, lane % G, nbytes, to_sink);
         else push_eout<G>(g, ra, q, v, has, lane % G, nbytes, to_sink);
       } else {
         const int v = g.list[ra.cur][kBigList][it - its.start[kBigList]];
