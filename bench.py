@@ -51,6 +51,11 @@ def main():
     ap.add_argument("--no-cutter", action="store_true",
                     help="skip the incremental FlowCutter workload")
     ap.add_argument("--cutter-iterations", type=int, default=400)
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-pruning workload")
+    ap.add_argument("--learned-seeds", type=int, default=8,
+                    help="block-pair instances for the learned scorer (3/4 train, 1/4 eval)")
+    ap.add_argument("--learned-steps", type=int, default=2000)
     ap.add_argument("--profile", type=int, default=2,
                     help="HIP-event timing inside the timed steps: 0 off, 1 every kernel, "
                          "2 only the reverse-BFS level kernel (the dominant one)")
@@ -164,10 +169,14 @@ def main():
         cutter = bench_cutter(args, hyperflow, inputs, torch, np)
 
     batch = None
+    learned = None
+    del arrays, vs, ns
+    torch.cuda.empty_cache()
     if not args.no_batch:
-        del arrays, vs, ns
-        torch.cuda.empty_cache()
         batch = bench_batch(args, hyperflow, inputs, torch, np)
+    if not args.no_learned:
+        learned = bench_learned(args, hyperflow, inputs, torch, np,
+                                batch["config"] if batch else None)
 
     st = stats[-1]
     out = {
@@ -198,6 +207,7 @@ def main():
         "kernels": kernels,
         "batch": batch,
         "cutter": cutter,
+        "learned": learned,
     }
     print(json.dumps(out), flush=True)
 
@@ -250,6 +260,119 @@ def bench_cutter(args, hyperflow, inputs, torch, np):
                                    kind="oracle",
                                    sample=f"the first {k} iterations, every max flow solved from "
                                           "scratch, single thread")
+    return out
+
+
+def bench_learned(args, hyperflow, inputs, torch, np, config):
+    """Learned pruning: block-pair instances for seeds 0..K-1 (3/4 train,
+    1/4 eval).  Labels come from the plain schedule: a problem improves when
+    its minimum cut is lighter than the cut it had (cut_before - F > 0).
+    The scorer trains on the device (full-batch Adam); its threshold is the
+    largest one that skips no improving training problem.  On the eval
+    instances the plain batch (every problem), the learned schedule
+    (inference, then the batch of the kept problems) and the paper's
+    cut < 10 rule are timed, all with the source-side cut."""
+    K = max(2, args.learned_seeds)
+    n_train = max(1, (3 * K) // 4)
+    cfg = dict(config or {})
+    cfg = {k: v for k, v in cfg.items() if k in ("group_lanes", "gr_interval", "streams")}
+
+    def instance(seed):
+        bp = inputs.block_pair_problems(seed, max_problems=args.batch_problems)
+        hgs = bp.problems
+        feats = inputs.scorer_features(hgs)
+        cut_before = np.array([h.meta["cut_before"] for h in hgs], dtype=np.int64)
+        pair_cut = np.array([h.meta["cut"] for h in hgs], dtype=np.int64)
+        return hgs, feats, cut_before, pair_cut
+
+    def solve_all(hgs, skip=None):
+        probs = [hyperflow.FlowProblem.from_hypergraph(h, device=True) for h in hgs]
+        torch.cuda.synchronize()
+        try:
+            with hyperflow.FlowBatch(probs, with_cut=True, **cfg) as plan:
+                t = time.perf_counter()
+                flows = plan.run(skip=skip, with_cut=True)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t
+        finally:
+            for p in probs:
+                p.close()
+        return flows, dt
+
+    _log(f"learned pruning: {n_train} training instances")
+    Xtr, ytr, gtr = [], [], []
+    for seed in range(n_train):
+        hgs, feats, cb, _ = instance(seed)
+        flows, _ = solve_all(hgs)
+        gain = cb - flows
+        Xtr.append(feats)
+        ytr.append((gain > 0).astype(np.float32))
+        gtr.append(gain)
+        _log(f"  seed {seed}: {len(hgs)} problems, {int((gain > 0).sum())} improve")
+    Xtr = np.concatenate(Xtr)
+    ytr = np.concatenate(ytr)
+    out = dict(workload=f"block-pair instances, seeds 0..{K - 1}: train {n_train}, "
+                        f"eval {K - n_train}; labels = minimum cut lighter than the cut before",
+               unit="refinements/s", train_problems=int(len(ytr)),
+               train_positive_fraction=round(float(ytr.mean()), 4))
+    init = inputs.scorer_init_params(0)
+    with hyperflow.Scorer(init) as sc:
+        sc.fit_normalization(Xtr)
+        if not args.no_cpu_baseline:
+            from oracle import mlp as omlp
+            loss_gpu, g_gpu = sc.gradient(Xtr, ytr)
+            xn, _, _ = omlp.normalize(Xtr)
+            loss_ref, g_ref = omlp.grad(init.astype(np.float64), xn, ytr)
+            out["gradient_rel_err_vs_oracle"] = float(
+                np.linalg.norm(g_gpu - g_ref) / max(np.linalg.norm(g_ref), 1e-30))
+            out["loss_vs_oracle"] = [float(loss_gpu), float(loss_ref)]
+        t = time.perf_counter()
+        losses = sc.train(Xtr, ytr, args.learned_steps, lr=1e-3)
+        torch.cuda.synchronize()
+        out["train_s"] = round(time.perf_counter() - t, 3)
+        out["loss_first_last"] = [float(losses[0]), float(losses[-1])]
+        params, ms = sc.params()
+        usable = bool(np.all(np.isfinite(params)))
+        ptr = sc.predict(Xtr)
+        pos = ytr > 0
+        theta = float(ptr[pos].min()) if pos.any() else 1.0
+        out["threshold"] = theta
+        out["train_skip_rate"] = round(float((ptr < theta).mean()), 4)
+        out["fallback_to_plain"] = not usable
+        ev = dict(problems=0, positive=0, plain_s=0.0, learned_s=0.0, rule_s=0.0, skipped=0,
+                  missed_gain=0, total_gain=0, rule_skipped=0, rule_missed_gain=0)
+        for seed in range(n_train, K):
+            hgs, feats, cb, pair_cut = instance(seed)
+            flows, t_plain = solve_all(hgs)
+            gain = cb - flows
+            t0 = time.perf_counter()
+            p = sc.predict(feats) if usable else np.ones(len(hgs), dtype=np.float32)
+            skip = (p < theta).astype(np.uint8)
+            t_inf = time.perf_counter() - t0
+            _, t_kept = solve_all(hgs, skip)
+            rule = (pair_cut < 10).astype(np.uint8)
+            _, t_rule = solve_all(hgs, rule)
+            ev["problems"] += len(hgs)
+            ev["positive"] += int((gain > 0).sum())
+            ev["plain_s"] += t_plain
+            ev["learned_s"] += t_inf + t_kept
+            ev["rule_s"] += t_rule
+            ev["skipped"] += int(skip.sum())
+            ev["missed_gain"] += int(gain[(skip > 0) & (gain > 0)].sum())
+            ev["total_gain"] += int(gain[gain > 0].sum())
+            ev["rule_skipped"] += int(rule.sum())
+            ev["rule_missed_gain"] += int(gain[(rule > 0) & (gain > 0)].sum())
+            _log(f"  eval seed {seed}: skipped {int(skip.sum())} of {len(hgs)}")
+    n = ev["problems"]
+    out.update(eval_problems=n, eval_positive_fraction=round(ev["positive"] / max(n, 1), 4),
+               skip_rate=round(ev["skipped"] / max(n, 1), 4),
+               missed_gain=ev["missed_gain"],
+               missed_gain_pct=round(100.0 * ev["missed_gain"] / max(ev["total_gain"], 1), 3),
+               value=round(n / ev["learned_s"], 2) if ev["learned_s"] else None,
+               plain_value=round(n / ev["plain_s"], 2) if ev["plain_s"] else None,
+               rule_value=round(n / ev["rule_s"], 2) if ev["rule_s"] else None,
+               rule_skip_rate=round(ev["rule_skipped"] / max(n, 1), 4),
+               rule_missed_gain=ev["rule_missed_gain"])
     return out
 
 

@@ -366,6 +366,63 @@ fp_status flow_problem_flowcutter(fp_problem *problem, const int32_t *vertex_wei
                                   uint8_t *vertex_side, fp_cutter_result *result,
                                   fp_cutter_step *trace);
 
+/*
+ * Learned pruning scorer (pattern of the paper's pruning rules, section
+ * "Parallel Active Block Scheduling", paragraph "Implementation Details":
+ * unpromising block-pair flow problems are skipped).  A perceptron
+ * 12 -> 64 -> 64 -> 1 with ReLU hidden units maps a problem's features to
+ * the probability that refining it improves the cut; it is trained on the
+ * outcomes of the plain run-everything schedule with the mean binary
+ * cross-entropy on logits and full-batch Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8).  Everything runs in FP32 on the device; the feature
+ * normalization statistics are computed in FP64.
+ *
+ * Parameters (FP_SCORER_PARAMS floats, row-major): W1 [64 x 12], b1 [64],
+ * W2 [64 x 64], b2 [64], W3 [64], b3.  Features: n x 12 int64, row-major,
+ * non-negative; each is transformed by log1p and z-scored with the mean and
+ * population deviation of the data given to scorer_fit_normalization (a
+ * deviation below 1e-9 is replaced by 1).  mem_kind applies to features,
+ * labels and probabilities (0 host, 1 device).
+ */
+#define FP_SCORER_PARAMS 5057
+typedef struct fp_scorer fp_scorer; /* opaque, library-owned */
+
+/* init_params: host, FP_SCORER_PARAMS finite floats (the caller draws the
+ * initialization).  Errors: FP_ERR_INVALID, FP_ERR_OOM, FP_ERR_DEVICE. */
+fp_status scorer_create(const float *init_params, void *hip_stream, fp_scorer **out);
+
+/* Normalization statistics from n >= 1 samples. */
+fp_status scorer_fit_normalization(fp_scorer *scorer, const int64_t *features, int32_t n,
+                                   int32_t mem_kind, void *hip_stream);
+
+/* Gradient (host, FP_SCORER_PARAMS) and mean loss (host) of the current
+ * parameters on n labelled samples (labels 0 or 1).  FP_ERR_STATE before
+ * the normalization is fitted. */
+fp_status scorer_gradient(fp_scorer *scorer, const int64_t *features, const float *labels,
+                          int32_t n, int32_t mem_kind, void *hip_stream, float *gradient,
+                          float *loss);
+
+/* `steps` full-batch Adam steps with learning rate lr; losses (host, steps
+ * entries, or NULL) receives the loss before each step. */
+fp_status scorer_train(fp_scorer *scorer, const int64_t *features, const float *labels,
+                       int32_t n, int32_t mem_kind, int32_t steps, float lr, void *hip_stream,
+                       float *losses);
+
+/* Probabilities of n samples (memory kind mem_kind). */
+fp_status scorer_predict(fp_scorer *scorer, const int64_t *features, int32_t n,
+                         int32_t mem_kind, void *hip_stream, float *probabilities);
+
+/* Parameters (host) and normalization (host, 12 means then 12 deviations,
+ * may be NULL). */
+fp_status scorer_get_params(const fp_scorer *scorer, float *params, double *mean_std);
+
+/* Load parameters and, if mean_std is not NULL, the normalization.
+ * FP_ERR_INVALID for non-finite values or non-positive deviations (the
+ * caller then keeps the plain schedule). */
+fp_status scorer_set_params(fp_scorer *scorer, const float *params, const double *mean_std);
+
+void scorer_destroy(fp_scorer *scorer);
+
 /* Counters of the handle (host out). */
 fp_status flow_problem_stats(const fp_problem *problem, fp_stats *out);
 

@@ -290,6 +290,111 @@ fp_status flow_problem_flowcutter(fp_problem* problem, const int32_t* vertex_wei
                             vertex_side, result, trace);
 }
 
+static fp_status check_samples(const void* f, int32_t n, int32_t mem_kind) {
+  if (!f || n < 1 || (mem_kind != 0 && mem_kind != 1)) {
+    set_error("need features, n >= 1 and mem_kind 0 or 1");
+    return FP_ERR_INVALID;
+  }
+  return FP_OK;
+}
+
+fp_status scorer_create(const float* init_params, void* hip_stream, fp_scorer** out) {
+  g_last_error.clear();
+  if (!out || !init_params) {
+    set_error("NULL argument");
+    return FP_ERR_INVALID;
+  }
+  *out = nullptr;
+  return scorer_create_impl(init_params, static_cast<hipStream_t>(hip_stream), out);
+}
+
+fp_status scorer_fit_normalization(fp_scorer* scorer, const int64_t* features, int32_t n,
+                                   int32_t mem_kind, void* hip_stream) {
+  g_last_error.clear();
+  if (!scorer) {
+    set_error("NULL scorer");
+    return FP_ERR_STATE;
+  }
+  fp_status st = check_samples(features, n, mem_kind);
+  if (st) return st;
+  return scorer_fit_impl(scorer, features, n, mem_kind, static_cast<hipStream_t>(hip_stream));
+}
+
+fp_status scorer_gradient(fp_scorer* scorer, const int64_t* features, const float* labels,
+                          int32_t n, int32_t mem_kind, void* hip_stream, float* gradient,
+                          float* loss) {
+  g_last_error.clear();
+  if (!scorer) {
+    set_error("NULL scorer");
+    return FP_ERR_STATE;
+  }
+  fp_status st = check_samples(features, n, mem_kind);
+  if (st) return st;
+  if (!labels || !gradient || !loss) {
+    set_error("NULL argument");
+    return FP_ERR_INVALID;
+  }
+  return scorer_gradient_impl(scorer, features, labels, n, mem_kind,
+                              static_cast<hipStream_t>(hip_stream), gradient, loss);
+}
+
+fp_status scorer_train(fp_scorer* scorer, const int64_t* features, const float* labels,
+                       int32_t n, int32_t mem_kind, int32_t steps, float lr, void* hip_stream,
+                       float* losses) {
+  g_last_error.clear();
+  if (!scorer) {
+    set_error("NULL scorer");
+    return FP_ERR_STATE;
+  }
+  fp_status st = check_samples(features, n, mem_kind);
+  if (st) return st;
+  if (!labels || steps < 0 || !(lr > 0.f)) {
+    set_error("need labels, steps >= 0 and lr > 0");
+    return FP_ERR_INVALID;
+  }
+  return scorer_train_impl(scorer, features, labels, n, mem_kind, steps, lr,
+                           static_cast<hipStream_t>(hip_stream), losses);
+}
+
+fp_status scorer_predict(fp_scorer* scorer, const int64_t* features, int32_t n, int32_t mem_kind,
+                         void* hip_stream, float* probabilities) {
+  g_last_error.clear();
+  if (!scorer) {
+    set_error("NULL scorer");
+    return FP_ERR_STATE;
+  }
+  fp_status st = check_samples(features, n, mem_kind);
+  if (st) return st;
+  if (!probabilities) {
+    set_error("NULL probabilities");
+    return FP_ERR_INVALID;
+  }
+  return scorer_predict_impl(scorer, features, n, mem_kind, static_cast<hipStream_t>(hip_stream),
+                             probabilities);
+}
+
+fp_status scorer_get_params(const fp_scorer* scorer, float* params, double* mean_std) {
+  g_last_error.clear();
+  if (!scorer || !params) {
+    set_error("NULL argument");
+    return FP_ERR_INVALID;
+  }
+  return scorer_get_impl(scorer, params, mean_std);
+}
+
+fp_status scorer_set_params(fp_scorer* scorer, const float* params, const double* mean_std) {
+  g_last_error.clear();
+  if (!scorer || !params) {
+    set_error("NULL argument");
+    return FP_ERR_INVALID;
+  }
+  return scorer_set_impl(scorer, params, mean_std);
+}
+
+void scorer_destroy(fp_scorer* scorer) {
+  if (scorer) scorer_destroy_impl(scorer);
+}
+
 fp_status flow_problem_stats(const fp_problem* problem, fp_stats* out) {
   if (!problem || !out) {
     set_error("NULL argument");

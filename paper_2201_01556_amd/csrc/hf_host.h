@@ -88,6 +88,17 @@ fp_status run_batch(fp_batch* b, const uint8_t* skip, int32_t with_cut, hipStrea
 fp_status tune_batch(fp_batch* b, hipStream_t s, const char* cache_path, fp_batch_config* chosen);
 fp_status batch_config(const fp_batch* b, fp_batch_config* out);
 void release_batch(fp_batch* b);
+fp_status scorer_create_impl(const float* init, hipStream_t s, fp_scorer** out);
+void scorer_destroy_impl(fp_scorer* sc);
+fp_status scorer_fit_impl(fp_scorer* sc, const int64_t* f, int n, int mem_kind, hipStream_t s);
+fp_status scorer_gradient_impl(fp_scorer* sc, const int64_t* f, const float* y, int n,
+                               int mem_kind, hipStream_t s, float* grad, float* loss);
+fp_status scorer_train_impl(fp_scorer* sc, const int64_t* f, const float* y, int n, int mem_kind,
+                            int steps, float lr, hipStream_t s, float* losses);
+fp_status scorer_predict_impl(fp_scorer* sc, const int64_t* f, int n, int mem_kind,
+                              hipStream_t s, float* prob);
+fp_status scorer_get_impl(const fp_scorer* sc, float* params, double* mean_std);
+fp_status scorer_set_impl(fp_scorer* sc, const float* params, const double* mean_std);
 fp_status pierce_problem(fp_problem* pb, int32_t side, const int32_t* vertices, int32_t n,
                          hipStream_t s);
 fp_status sink_side_problem(fp_problem* pb, hipStream_t s, int32_t mem_kind, uint8_t* vside);

@@ -132,8 +132,18 @@ EXPORTED = [
     "flow_problem_kernel_times",
     "flow_problem_export_state",
     "flow_problem_destroy",
+    "scorer_create",
+    "scorer_fit_normalization",
+    "scorer_gradient",
+    "scorer_train",
+    "scorer_predict",
+    "scorer_get_params",
+    "scorer_set_params",
+    "scorer_destroy",
     "fp_last_error",
 ]
+
+SCORER_PARAMS = 5057
 
 _lib = None
 
@@ -187,6 +197,22 @@ def load_library(path: str = LIB_PATH):
     lib.flow_problem_export_state.restype = ctypes.c_int
     lib.flow_problem_destroy.argtypes = [vp]
     lib.flow_problem_destroy.restype = None
+    lib.scorer_create.argtypes = [vp, vp, ctypes.POINTER(vp)]
+    lib.scorer_create.restype = ctypes.c_int
+    lib.scorer_fit_normalization.argtypes = [vp, vp, i32, i32, vp]
+    lib.scorer_fit_normalization.restype = ctypes.c_int
+    lib.scorer_gradient.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp]
+    lib.scorer_gradient.restype = ctypes.c_int
+    lib.scorer_train.argtypes = [vp, vp, vp, i32, i32, i32, ctypes.c_float, vp, vp]
+    lib.scorer_train.restype = ctypes.c_int
+    lib.scorer_predict.argtypes = [vp, vp, i32, i32, vp, vp]
+    lib.scorer_predict.restype = ctypes.c_int
+    lib.scorer_get_params.argtypes = [vp, vp, vp]
+    lib.scorer_get_params.restype = ctypes.c_int
+    lib.scorer_set_params.argtypes = [vp, vp, vp]
+    lib.scorer_set_params.restype = ctypes.c_int
+    lib.scorer_destroy.argtypes = [vp]
+    lib.scorer_destroy.restype = None
     lib.fp_last_error.argtypes = []
     lib.fp_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -573,6 +599,87 @@ class FlowBatch:
     def close(self):
         if self.handle:
             flow_batch_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Scorer:
+    """Owner of a learned pruning scorer (MLP 12 -> 64 -> 64 -> 1 on the
+    device).  Features: int64 [n x 12] host arrays; labels float 0/1."""
+
+    def __init__(self, init_params, stream=None):
+        self.stream = stream
+        p = np.ascontiguousarray(init_params, dtype=np.float32)
+        if p.shape != (SCORER_PARAMS,):
+            raise ValueError(f"need {SCORER_PARAMS} parameters")
+        h = ctypes.c_void_p()
+        _check(load_library().scorer_create(p.ctypes.data, _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h
+
+    @staticmethod
+    def _feats(features):
+        f = np.ascontiguousarray(features, dtype=np.int64)
+        if f.ndim != 2 or f.shape[1] != 12:
+            raise ValueError("features must be n x 12")
+        return f
+
+    def fit_normalization(self, features):
+        f = self._feats(features)
+        _check(load_library().scorer_fit_normalization(self.handle, f.ctypes.data, f.shape[0], 0,
+                                                       _stream_ptr(self.stream)))
+
+    def gradient(self, features, labels):
+        f = self._feats(features)
+        y = np.ascontiguousarray(labels, dtype=np.float32)
+        g = np.zeros(SCORER_PARAMS, dtype=np.float32)
+        loss = np.zeros(1, dtype=np.float32)
+        _check(load_library().scorer_gradient(self.handle, f.ctypes.data, y.ctypes.data,
+                                              f.shape[0], 0, _stream_ptr(self.stream),
+                                              g.ctypes.data, loss.ctypes.data))
+        return float(loss[0]), g
+
+    def train(self, features, labels, steps, lr=1e-3):
+        f = self._feats(features)
+        y = np.ascontiguousarray(labels, dtype=np.float32)
+        losses = np.zeros(max(steps, 1), dtype=np.float32)
+        _check(load_library().scorer_train(self.handle, f.ctypes.data, y.ctypes.data, f.shape[0],
+                                           0, int(steps), float(lr), _stream_ptr(self.stream),
+                                           losses.ctypes.data))
+        return losses[:steps]
+
+    def predict(self, features):
+        f = self._feats(features)
+        p = np.zeros(f.shape[0], dtype=np.float32)
+        _check(load_library().scorer_predict(self.handle, f.ctypes.data, f.shape[0], 0,
+                                             _stream_ptr(self.stream), p.ctypes.data))
+        return p
+
+    def params(self):
+        p = np.zeros(SCORER_PARAMS, dtype=np.float32)
+        ms = np.zeros(24, dtype=np.float64)
+        _check(load_library().scorer_get_params(self.handle, p.ctypes.data, ms.ctypes.data))
+        return p, ms
+
+    def set_params(self, params, mean_std=None):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        ms = None if mean_std is None else np.ascontiguousarray(mean_std, dtype=np.float64)
+        _check(load_library().scorer_set_params(self.handle, p.ctypes.data,
+                                                None if ms is None else ms.ctypes.data))
+
+    def close(self):
+        if self.handle:
+            load_library().scorer_destroy(self.handle)
             self.handle = None
 
     def __enter__(self):

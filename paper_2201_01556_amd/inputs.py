@@ -46,6 +46,8 @@ __all__ = [
     "zipf_sizes_until",
     "BlockPairSet",
     "block_pair_problems",
+    "scorer_init_params",
+    "scorer_features",
 ]
 
 
@@ -429,3 +431,23 @@ def block_pair_problems(seed: int, num_vertices: int = 2_000_000,
     finally:
         L.hfr_free(ctx)
     return BlockPairSet(hg, block, bw, lmax, moves, obj0, obj1, problems)
+
+
+def scorer_init_params(seed: int) -> np.ndarray:
+    """Initial parameters of the 12 -> 64 -> 64 -> 1 scorer (5,057 float32,
+    layout W1, b1, W2, b2, W3, b3): every weight and bias of a layer with
+    fan-in f drawn uniformly from [-1/sqrt(f), 1/sqrt(f)] (PCG64(seed))."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for shape, fan_in in (((64, 12), 12), ((64,), 12), ((64, 64), 64), ((64,), 64),
+                          ((1, 64), 64), ((1,), 64)):
+        b = 1.0 / np.sqrt(fan_in)
+        parts.append(rng.uniform(-b, b, size=shape).ravel())
+    return np.concatenate(parts).astype(np.float32)
+
+
+def scorer_features(problems) -> np.ndarray:
+    """The 12 integer features of each block-pair problem (int64 [n x 12]):
+    pair cut weight, region pins, boundary vertices, 7 net-size bins, c(Vi),
+    c(Vj)."""
+    return np.stack([np.asarray(p.meta["features"], dtype=np.int64) for p in problems])
