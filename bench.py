@@ -53,9 +53,12 @@ def main():
     ap.add_argument("--cutter-iterations", type=int, default=400)
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-pruning workload")
-    ap.add_argument("--learned-seeds", type=int, default=8,
+    ap.add_argument("--learned-seeds", type=int, default=4,
                     help="block-pair instances for the learned scorer (3/4 train, 1/4 eval)")
     ap.add_argument("--learned-steps", type=int, default=2000)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run one plain elementwise copy of BYTES bytes (counter "
+                         "calibration for the traffic figure) and exit")
     ap.add_argument("--profile", type=int, default=2,
                     help="HIP-event timing inside the timed steps: 0 off, 1 every kernel, "
                          "2 only the reverse-BFS level kernel (the dominant one)")
@@ -69,6 +72,18 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_probe:
+        # one kernel that reads BYTES and writes BYTES: the HBM counters of
+        # this launch calibrate those of the solver kernels
+        n = args.copy_probe // 4
+        x = torch.ones(n, dtype=torch.int32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_probe_bytes=4 * n)), flush=True)
+        return
 
     from paper_2201_01556_amd import hyperflow, inputs
 
@@ -145,7 +160,8 @@ def main():
             achieved = bpl / avg_s / 1e9
             roofline = dict(kernel=dom, bound="hbm", achieved=round(achieved, 3),
                             peak=HBM_PEAK_GBS, unit="GB/s",
-                            frac=round(achieved / HBM_PEAK_GBS, 6), traffic=None,
+                            frac=round(achieved / HBM_PEAK_GBS, 6),
+                            traffic=measured_traffic(dom),
                             bytes_per_launch=bpl, avg_launch_us=round(avg_s * 1e6, 3),
                             share_of_step=round(d["ms"] / args.steps / ms_per_step, 4))
 
@@ -212,6 +228,40 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "zipf1M_bfs_rev_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2201_01556_amd", "csrc", f)
+                  for f in ("hf_device.h", "hf_solve.hip")]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated by a plain copy), or None when the
+    kernel sources changed since the counters were taken."""
+    if kernel != "bfs_rev" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and line.lstrip().startswith("- "):
+                k, v = line.strip()[2:].split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def _cut_weight(hg, side, np):
     off = hg.net_offsets.astype(np.int64)
     sizes = np.diff(off)
@@ -263,6 +313,18 @@ def bench_cutter(args, hyperflow, inputs, torch, np):
     return out
 
 
+_PAIRS = {}
+
+
+def _pairs(inputs, seed, max_problems):
+    """Block-pair instance of a seed, built once per run (the batch and the
+    learned legs share seed 0)."""
+    key = (seed, max_problems)
+    if key not in _PAIRS:
+        _PAIRS[key] = inputs.block_pair_problems(seed, max_problems=max_problems)
+    return _PAIRS[key]
+
+
 def bench_learned(args, hyperflow, inputs, torch, np, config):
     """Learned pruning: block-pair instances for seeds 0..K-1 (3/4 train,
     1/4 eval).  Labels come from the plain schedule: a problem improves when
@@ -278,7 +340,7 @@ def bench_learned(args, hyperflow, inputs, torch, np, config):
     cfg = {k: v for k, v in cfg.items() if k in ("group_lanes", "gr_interval", "streams")}
 
     def instance(seed):
-        bp = inputs.block_pair_problems(seed, max_problems=args.batch_problems)
+        bp = _pairs(inputs, seed, args.batch_problems)
         hgs = bp.problems
         feats = inputs.scorer_features(hgs)
         cut_before = np.array([h.meta["cut_before"] for h in hgs], dtype=np.int64)
@@ -381,7 +443,7 @@ def bench_batch(args, hyperflow, inputs, torch, np):
     block-pair problems; every run solves and extracts the source side."""
     t0 = time.perf_counter()
     _log("generating the block-pair workload")
-    bp = inputs.block_pair_problems(args.seed, max_problems=args.batch_problems)
+    bp = _pairs(inputs, args.seed, args.batch_problems)
     hgs = bp.problems
     gen_s = time.perf_counter() - t0
     n = len(hgs)
