@@ -77,6 +77,7 @@ constexpr int kStaleFrontier = 1500;  // "only few active nodes" (paper)
 template <int G>
 __device__ int wg_global_relabel(const Dev& g, int epoch, lds_int* lds, int* levels) {
   phase_gr_reset(g, 0, 1, lds);
+  phase_gr_bits(g, threadIdx.x, blockDim.x);
   __syncthreads();
   int level = 0;
   for (;;) {

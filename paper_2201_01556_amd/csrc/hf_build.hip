@@ -144,6 +144,7 @@ __global__ void k_scatter(Dev g, int32_t* cursor) {
       else hi = mid;
     }
     const int u = g.pin_v[p];
+    const_cast<int32_t*>(g.pin_net)[p] = lo;
     const int pos = atomicAdd(&cursor[u], 1);
     const_cast<int2*>(g.vinc)[pos] = make_int2(lo, p);
     const int r = g.role[u];
@@ -303,6 +304,7 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
   auto add = [&](size_t n) { bytes += align_up(n + 1); };
   add((E + 1) * 4ull);        // net_off
   add(P * 4ull);              // pin_v
+  add(P * 4ull);              // pin_net
   add(E * 4ull);              // w
   add((V + 1) * 4ull);        // vtx_off
   add(P * 8ull);              // vinc
@@ -320,6 +322,8 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
   add(N * 4ull);              // dx[1]
   add(((N + 31) / 32) * 4ull); // big-node bitmap
   add(((N + 31) / 32) * 4ull); // labelled hint bitmap
+  add(((P + 31) / 32) * 4ull); // residual bits of the pin arcs (global relabel)
+  add(((E + 7) / 8) * 4ull);   // residual bits of the nets (global relabel)
   add(sizeof(Ctl));           // ctl
   add(64);                    // scratch for the weight sum
   he = hipMalloc(&pb->pool, bytes);
@@ -365,11 +369,14 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
   uint32_t* bigbits = c.take<uint32_t>((N + 31) / 32);
   g.bigbits = bigbits;
   g.seen = c.take<uint32_t>((N + 31) / 32);
+  g.pinres = c.take<uint32_t>((P + 31) / 32);
+  g.netres = c.take<uint32_t>((E + 7) / 8);
   g.bfs_arc = pb->opt.bfs_arc_parallel;
   g.ctl = c.take<Ctl>(1);
   unsigned long long* wsum = c.take<unsigned long long>(1);
   g.net_off = net_off;
   g.pin_v = pin_v;
+  g.pin_net = c.take<int32_t>(P);
   g.w = w;
   g.vtx_off = vtx_off;
   g.vinc = vinc;

@@ -109,6 +109,7 @@ struct Dev {
   int32_t V, E, P, NB, N, nT, big_deg, bfs_arc;  // bfs_arc: arc-parallel BFS levels
   const int32_t* net_off;  // E+1
   const int32_t* pin_v;    // P
+  const int32_t* pin_net;  // P   net of each pin slot
   const int32_t* w;        // E
   const int32_t* vtx_off;  // V+1
   const int2* vinc;        // P   {net, pin slot}, per vertex sorted by slot
@@ -123,6 +124,10 @@ struct Dev {
   int32_t* stamp;          // N
   const uint32_t* bigbits; // ceil(N/32) words: bit v set when node v has more than big_deg arcs
   uint32_t* seen;          // ceil(N/32) words: reverse BFS hint "node has a label" (see label_rev)
+  uint32_t* pinres;        // ceil(P/32) words: bit of pin slot p = flow(u, e_in) > 0
+  uint32_t* netres;        // ceil(E/8) words, 4 bits per net: bit0 = e_in -> e_out
+                           // residual (fb < w), bit1 = pins carry flow out of
+                           // e_out, bit2 = e_out -> e_in residual (fb > 0)
   int32_t* list[2][kNL];   // [parity][list]: capacities V, E, E, N
   Ctl* ctl;
 };
@@ -710,6 +715,50 @@ __device__ void phase_apply(const Dev& g, int epoch, int tile0, int tstride, int
 // reverse residual BFS from the sinks (global relabel) over the capped network
 // ---------------------------------------------------------------------------
 
+// Global relabel, step 2: residual bits that the reverse BFS tests, so that
+// its checks of an arc hit two small bitmaps instead of scattered flows.
+// The flow state does not change during a global relabel.
+//   pinres: one bit per pin slot p of net e: flow(u, e_in) = w(e) - r_in > 0
+//           (the reverse arc e_in -> u is residual)
+//   netres: four bits per net: bit0 fb < w (e_in -> e_out residual), bit1
+//           some pin carries flow out of e_out (fb exceeds e_out's excess),
+//           bit2 fb > 0 (e_out -> e_in residual)
+// Thread per slot, then per net; t0 wave-aligned, tstride a multiple of 64.
+__device__ void phase_gr_bits(const Dev& g, int t0, int tstride) {
+  const int lane = lane_id();
+  // pin slots: a lane per slot, a wave per 64 slots (two words of the bitmap)
+  const int np = (g.P + 63) & ~63;
+  const int pwords = (g.P + 31) >> 5;
+  for (int p = t0; p < np; p += tstride) {
+    const bool f = p < g.P && g.fpin[2 * p] < g.w[g.pin_net[p]];
+    const unsigned long long m = __ballot(f);
+    const int word = ((p - lane) >> 5) + lane;
+    if (lane < 2 && word < pwords) g.pinres[word] = (uint32_t)(m >> (32 * lane));
+  }
+  // nets: a lane per net, eight nibbles per word
+  const int ne = (g.E + 63) & ~63;
+  for (int e = t0; e < ne; e += tstride) {
+    uint32_t b = 0;
+    if (e < g.E) {
+      const int fbv = g.fb[e], eo = g.NB + 2 * e + 1;
+      const int out = fbv - (g.x[eo] + g.dx[0][eo] + g.dx[1][eo]);
+      b = (fbv < g.w[e] ? 1u : 0u) | (out > 0 ? 2u : 0u) | (fbv > 0 ? 4u : 0u);
+    }
+    uint32_t v = b << (4 * (lane & 7));
+    v |= __shfl_xor(v, 1);
+    v |= __shfl_xor(v, 2);
+    v |= __shfl_xor(v, 4);
+    if ((lane & 7) == 0 && e < g.E) g.netres[e >> 3] = v;
+  }
+}
+
+__device__ __forceinline__ bool pin_flow_in(const Dev& g, int p) {
+  return (g.pinres[p >> 5] >> (p & 31)) & 1u;
+}
+__device__ __forceinline__ uint32_t net_bits(const Dev& g, int e) {
+  return (g.netres[e >> 3] >> (4 * (e & 7))) & 15u;
+}
+
 // The "labelled" hint of the reverse BFS is a bitmap small enough to stay in
 // the L2, so checking an arc whose tail is already labelled costs no access
 // to the large label array.  Bits are set with a plain read-modify-write; a
@@ -763,7 +812,7 @@ __device__ void bfs_rev_node(const Dev& g, const BlockQ& q, int x, bool has, int
         const uint32_t sw = g.seen[t1 >> 5] >> (t1 & 31);
         nbytes += 12;
         if (!(sw & 2u)) vout = label_rev<kClaim>(g, t1 + 1, lvl);  // e_out -> x infinite
-        if (!(sw & 1u) && g.w[ep.x] - g.fpin[2 * ep.y] > 0)        // e_in -> x reverse
+        if (!(sw & 1u) && pin_flow_in(g, ep.y))                    // e_in -> x reverse
           vin = label_rev<kClaim>(g, t1, lvl);
       }
       if (kClaim) {
@@ -774,17 +823,16 @@ __device__ void bfs_rev_node(const Dev& g, const BlockQ& q, int x, bool has, int
   } else if (isnet) {
     const int e = (x - g.NB) >> 1;
     const bool in = ((x - g.NB) & 1) == 0;
-    const int we = g.w[e];
-    const int fbv = g.fb[e];
+    const uint32_t nb = net_bits(g, e);
     int beg = g.net_off[e], end = g.net_off[e + 1];
     // in-arcs of e_out from pins carry flow(e_out, u) > 0; their sum is the
     // outflow fb - excess(e_out), so a net without outflow skips its pins
-    if (!in && fbv == g.x[x] + g.dx[0][x] + g.dx[1][x]) end = beg;
+    if (!in && !(nb & 2u)) end = beg;
     nbytes += 16;
     bool vb = false;
     if (gl == 0) {
-      if (in) vb = fbv > 0 && label_rev<kClaim>(g, x + 1, lvl);    // e_out -> e_in residual fb
-      else vb = we - fbv > 0 && label_rev<kClaim>(g, x - 1, lvl);  // e_in -> e_out residual w - fb
+      if (in) vb = (nb & 4u) && label_rev<kClaim>(g, x + 1, lvl);  // e_out -> e_in residual fb
+      else vb = (nb & 1u) && label_rev<kClaim>(g, x - 1, lvl);     // e_in -> e_out residual w - fb
     }
     if (kClaim) qpush(g, q, in ? x + 1 : x - 1, vb);
     for (int base = beg; base < end; base += G) {

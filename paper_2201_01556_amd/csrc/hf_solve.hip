@@ -30,6 +30,10 @@ __device__ __forceinline__ int gthreads() { return gridDim.x * blockDim.x; }
 
 __global__ void __launch_bounds__(kThreads) k_init(Dev g) { phase_init(g, gthread(), gthreads()); }
 
+__global__ void __launch_bounds__(kThreads) k_gr_bits(Dev g) {
+  phase_gr_bits(g, gthread(), gthreads());
+}
+
 __global__ void __launch_bounds__(kBlock) k_gr_reset(Dev g) {
   HF_QUEUE_LDS;
   phase_gr_reset(g, blockIdx.x, gridDim.x, lds);
@@ -320,6 +324,7 @@ static fp_status global_relabel(fp_problem* pb, hipStream_t s) {
   {
     Launch L(pb, s, KK_GR_RESET);
     k_gr_reset<<<sweep_blocks(g.N), kBlock, 0, s>>>(g);
+    k_gr_bits<<<sweep_grid(std::max(g.P, g.E)), kThreads, 0, s>>>(g);
   }
   int levels = 0;
   fp_status st = run_bfs<G>(pb, s, -1, 0, &levels);
