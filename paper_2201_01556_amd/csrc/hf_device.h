@@ -141,11 +141,60 @@ __device__ __forceinline__ unsigned long long lanemask_lt() {
   return (1ull << lane_id()) - 1ull;
 }
 
-// Sum over the wave, one atomic.  The whole wave must be active.
-__device__ __forceinline__ void wave_add_u64(unsigned long long* dst, unsigned long long v) {
+// Workgroup sums of up to three per-thread counters, added to the global
+// counters by thread 0: one atomic per workgroup and counter.  Same-address
+// atomics issued by every wave of a full grid serialise in the memory system
+// and cost more than the work they count.  Block-uniform (every thread of the
+// workgroup calls it); blockDim a multiple of 64, at most 1024.
+__device__ void block_add_u64(unsigned long long* d0, unsigned long long v0,
+                              unsigned long long* d1 = nullptr, unsigned long long v1 = 0ull,
+                              unsigned long long* d2 = nullptr, unsigned long long v2 = 0ull) {
+  __shared__ unsigned long long part[3][16];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  if (lane_id() == 0 && v != 0ull) atomicAdd(dst, v);
+  for (int o = 32; o > 0; o >>= 1) {
+    v0 += __shfl_xor(v0, o);
+    v1 += __shfl_xor(v1, o);
+    v2 += __shfl_xor(v2, o);
+  }
+  const int wid = threadIdx.x >> 6;
+  if (lane_id() == 0) {
+    part[0][wid] = v0;
+    part[1][wid] = v1;
+    part[2][wid] = v2;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int c = threadIdx.x;
+    unsigned long long s = 0ull;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += part[c][w];
+    unsigned long long* d = c == 0 ? d0 : (c == 1 ? d1 : d2);
+    if (d != nullptr && s != 0ull) atomicAdd(d, s);
+  }
+  __syncthreads();  // part may be written again by a later call
+}
+
+// Workgroup minima of two per-thread values, folded into the global values
+// by thread 0 (atomic min).  Block-uniform, as block_add_u64.
+__device__ void block_min_i32(int32_t* d0, int v0, int32_t* d1, int v1) {
+  __shared__ int part[2][16];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    v0 = min(v0, __shfl_xor(v0, o));
+    v1 = min(v1, __shfl_xor(v1, o));
+  }
+  const int wid = threadIdx.x >> 6;
+  if (lane_id() == 0) {
+    part[0][wid] = v0;
+    part[1][wid] = v1;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const int c = threadIdx.x;
+    int m = part[c][0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = min(m, part[c][w]);
+    if (m != kInf) atomicMin(c == 0 ? d0 : d1, m);
+  }
+  __syncthreads();
 }
 
 template <int G>
@@ -665,9 +714,8 @@ __device__ void phase_push(const Dev& g, int epoch, int tile0, int tstride, int 
     bq_tile_end(q, q.cap / 2);
   }
   bq_flush(q);
-  wave_add_u64(&g.ctl->flow, to_sink);
-  wave_add_u64(&g.ctl->bytes[kc], (unsigned long long)nbytes + 4ull * nitems);
-  wave_add_u64(&g.ctl->items[kc], nitems);
+  block_add_u64(&g.ctl->flow, to_sink, &g.ctl->bytes[kc],
+                (unsigned long long)nbytes + 4ull * nitems, &g.ctl->items[kc], nitems);
 }
 
 // Apply phase over the same frontier: relabel nodes left with excess; thread
@@ -706,9 +754,7 @@ __device__ void phase_apply(const Dev& g, int epoch, int tile0, int tstride, int
     bq_tile_end(q, (int)blockDim.x);
   }
   bq_flush(q);
-  wave_add_u64(&g.ctl->relabels, nrel);
-  wave_add_u64(&g.ctl->bytes[kc], nbytes);
-  wave_add_u64(&g.ctl->items[kc], nrel);
+  block_add_u64(&g.ctl->relabels, nrel, &g.ctl->bytes[kc], nbytes, &g.ctl->items[kc], nrel);
 }
 
 // ---------------------------------------------------------------------------
@@ -885,8 +931,8 @@ __device__ void phase_bfs_rev_node(const Dev& g, int level, int tile0, int tstri
     if (kClaim) bq_tile_end(q, q.cap / 2);
   }
   if (kClaim) bq_flush(q);
-  wave_add_u64(&g.ctl->bytes[kc], (unsigned long long)nbytes + 4ull * nitems);
-  wave_add_u64(&g.ctl->items[kc], nitems);
+  block_add_u64(&g.ctl->bytes[kc], (unsigned long long)nbytes + 4ull * nitems, &g.ctl->items[kc],
+                nitems);
 }
 
 // ---------------------------------------------------------------------------
@@ -1051,8 +1097,8 @@ __device__ void phase_bfs_rev_lb(const Dev& g, int level, int tile0, int tstride
     __syncthreads();  // the tile area is rewritten by the next tile
   }
   if (kClaim) bq_flush(q);
-  wave_add_u64(&g.ctl->bytes[kc], (unsigned long long)nbytes + 12ull * narcs);
-  wave_add_u64(&g.ctl->items[kc], narcs);
+  block_add_u64(&g.ctl->bytes[kc], (unsigned long long)nbytes + 12ull * narcs, &g.ctl->items[kc],
+                narcs);
 }
 
 // One level of the forward BFS of the uncapped network, arc-parallel.
@@ -1115,8 +1161,8 @@ __device__ void phase_bfs_fwd_lb(const Dev& g, int level, int ep, int tile0, int
     __syncthreads();  // the tile area is rewritten by the next tile
   }
   bq_flush(q);
-  wave_add_u64(&g.ctl->bytes[kc], (unsigned long long)nbytes + 12ull * narcs);
-  wave_add_u64(&g.ctl->items[kc], narcs);
+  block_add_u64(&g.ctl->bytes[kc], (unsigned long long)nbytes + 12ull * narcs, &g.ctl->items[kc],
+                narcs);
 }
 
 template <int G>
@@ -1433,8 +1479,8 @@ __device__ void phase_bfs_sink_lb(const Dev& g, int level, int ep, int tile0, in
   }
   bq_flush(q);
   if (hit_source) atomicOr(&g.ctl->err, ERR_SOURCE_REACHED);
-  wave_add_u64(&g.ctl->bytes[kc], (unsigned long long)nbytes + 12ull * narcs);
-  wave_add_u64(&g.ctl->items[kc], narcs);
+  block_add_u64(&g.ctl->bytes[kc], (unsigned long long)nbytes + 12ull * narcs, &g.ctl->items[kc],
+                narcs);
 }
 
 // Clear the BFS counters and the FlowCutter side weights (own launch: the
@@ -1479,9 +1525,8 @@ __device__ void phase_fc_weights(const Dev& g, const int32_t* cw, int ep_s, int 
     else if (st == ep_t) wt += (unsigned long long)cw[v];
     else first_free = min(first_free, v);
   }
-  wave_add_u64(&g.ctl->side_weight[0], ws);
-  wave_add_u64(&g.ctl->side_weight[1], wt);
-  if (first_free != kInf) atomicMin(&g.ctl->pierce[2], first_free);
+  block_add_u64(&g.ctl->side_weight[0], ws, &g.ctl->side_weight[1], wt);
+  block_min_i32(&g.ctl->pierce[2], first_free, &g.ctl->pierce[2], kInf);
 }
 
 // Piercing candidates of one side, thread per net.  side 0: nets cut by
@@ -1516,8 +1561,7 @@ __device__ void phase_fc_candidates(const Dev& g, int side, int ep_s, int ep_t, 
       else if (st == other && g.role[u] != other_role) best_aug = min(best_aug, u);
     }
   }
-  if (best_free != kInf) atomicMin(&g.ctl->pierce[0], best_free);
-  if (best_aug != kInf) atomicMin(&g.ctl->pierce[1], best_aug);
+  block_min_i32(&g.ctl->pierce[0], best_free, &g.ctl->pierce[1], best_aug);
 }
 
 // Every free vertex with stamp ep_s becomes a source.  The flows of its
@@ -1560,7 +1604,7 @@ __device__ void phase_pierce_sinks(const Dev& g, int ep_t, int t0, int tstride) 
     }
     for (int i = g.vtx_off[v]; i < g.vtx_off[v + 1]; ++i) atomicOr(&g.nflag[g.vinc[i].x], 2);
   }
-  wave_add_u64(&g.ctl->flow, gained);
+  block_add_u64(&g.ctl->flow, gained);
 }
 
 // Stamp the given vertices with ep; a vertex that is a terminal of kind
