@@ -17,7 +17,7 @@ namespace hf {
 constexpr int kThreads = 256;  // plain element-wise kernels
 constexpr int kBlock = 1024;   // frontier, sweep and single-workgroup kernels
 constexpr int kMaxFrontierBlocks = 512;
-constexpr int kMaxSweepBlocks = 256;
+constexpr int kMaxSweepBlocks = 512;
 constexpr long long kRoundGuard = 200000000ll;  // rounds per solve before giving up
 
 __device__ __forceinline__ int gwave() { return (blockIdx.x * blockDim.x + threadIdx.x) >> 6; }
