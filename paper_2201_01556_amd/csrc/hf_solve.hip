@@ -25,6 +25,12 @@ __device__ __forceinline__ int gwaves() { return (gridDim.x * blockDim.x) >> 6; 
 __device__ __forceinline__ int gthread() { return blockIdx.x * blockDim.x + threadIdx.x; }
 __device__ __forceinline__ int gthreads() { return gridDim.x * blockDim.x; }
 
+// BFS level kernels are latency bound: ask the compiler to fit eight waves per
+// SIMD (two 1024-thread workgroups per CU, which the LDS allows), spilling a
+// few scalar registers into vector lanes instead of leaving one workgroup per
+// CU.
+#define HF_TWO_WORKGROUPS_PER_CU __attribute__((amdgpu_waves_per_eu(8)))
+
 // LDS staging area of the workgroup's list appends
 #define HF_QUEUE_LDS __shared__ int32_t hf_bq[lds_words(kBlock)]; lds_int* const lds = (lds_int*)hf_bq
 
@@ -44,7 +50,8 @@ __global__ void __launch_bounds__(kBlock) k_gr_reset(Dev g) {
 // level; smaller levels claim and list new nodes directly.  Both kernels read
 // the same count, so they agree on the mode.
 template <int G>
-__global__ void __launch_bounds__(kBlock) k_bfs_rev(Dev g, int level, int big_min) {
+__global__ void __launch_bounds__(kBlock) HF_TWO_WORKGROUPS_PER_CU
+k_bfs_rev(Dev g, int level, int big_min) {
   HF_QUEUE_LDS;
   const int c3 = level % 3;
   const int nf = count_all(g.ctl->bcnt[c3]);
@@ -81,12 +88,14 @@ __global__ void __launch_bounds__(kBlock) k_cut_seed(Dev g, int ep) {
 }
 
 template <int G>
-__global__ void __launch_bounds__(kBlock) k_bfs_fwd(Dev g, int level, int ep) {
+__global__ void __launch_bounds__(kBlock) HF_TWO_WORKGROUPS_PER_CU
+k_bfs_fwd(Dev g, int level, int ep) {
   HF_QUEUE_LDS;
   phase_bfs_fwd<G>(g, level, ep, blockIdx.x, gridDim.x, KC_BFS_FWD, lds);
 }
 
-__global__ void __launch_bounds__(kBlock) k_bfs_sink(Dev g, int level, int ep) {
+__global__ void __launch_bounds__(kBlock) HF_TWO_WORKGROUPS_PER_CU
+k_bfs_sink(Dev g, int level, int ep) {
   HF_QUEUE_LDS;
   phase_bfs_sink_lb(g, level, ep, blockIdx.x, gridDim.x, KC_BFS_FWD, lds);
 }
