@@ -73,9 +73,9 @@ typedef struct {
   int32_t debug_checks;       /* 1 = verify preflow and labelling invariants
                                  after every round (slow; test use)          */
   int32_t tail_threshold;     /* frontier size at or below which a single
-                                 workgroup runs the rounds; default 1024     */
+                                 workgroup runs the rounds; default 256      */
   int32_t group_lanes;        /* lanes per small frontier node: 4, 8 or 16;
-                                 default 4                                   */
+                                 default 8                                   */
   int32_t big_degree;         /* nodes with more arcs go wave-per-node;
                                  default 32                                  */
   int32_t profile;            /* 1 = time every kernel launch with HIP events,
@@ -91,7 +91,8 @@ typedef struct {
   int32_t bottom_up_min;      /* reverse-BFS levels with at least this many
                                  nodes are expanded without atomics and the
                                  next level is collected by a sweep over the
-                                 labels; default N/128, -1 = never          */
+                                 labels; default N/50 (at least 1024),
+                                 -1 = never                                  */
   int32_t bfs_arc_parallel;   /* 1 = BFS levels split work per arc (prefix sum
                                  over the level's arc counts) instead of per
                                  node; default 0                             */

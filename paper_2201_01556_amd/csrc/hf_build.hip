@@ -252,8 +252,8 @@ fp_options resolve_options(const fp_options* o) {
   fp_options r{};
   if (o) r = *o;
   if (r.relabel_factor_x16 <= 0) r.relabel_factor_x16 = 16;
-  if (r.tail_threshold <= 0) r.tail_threshold = 1024;
-  if (r.group_lanes != 4 && r.group_lanes != 8 && r.group_lanes != 16) r.group_lanes = 4;
+  if (r.tail_threshold <= 0) r.tail_threshold = 256;
+  if (r.group_lanes != 4 && r.group_lanes != 8 && r.group_lanes != 16) r.group_lanes = 8;
   if (r.big_degree <= 0) r.big_degree = 32;
   if (r.gr_interval == 0) r.gr_interval = 16;
   if (r.gr_interval < 0) r.gr_interval = 0;
@@ -291,7 +291,7 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
     set_error("network too large for 31-bit ids (V=%d E=%d P=%d)", V, E, P);
     return FP_ERR_OVERFLOW;
   }
-  if (pb->opt.bottom_up_min == 0) pb->opt.bottom_up_min = (int32_t)std::max<long long>(N / 128, 1024);
+  if (pb->opt.bottom_up_min == 0) pb->opt.bottom_up_min = (int32_t)std::max<long long>(N / 50, 1024);
   if (pb->opt.bottom_up_min < 0) pb->opt.bottom_up_min = 0;
   pb->P = P;
   pb->NB = (int32_t)NB;

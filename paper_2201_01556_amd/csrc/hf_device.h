@@ -485,6 +485,8 @@ __device__ __forceinline__ void finish_push(const Dev& g, int u, uint32_t X, uin
 
 // ---------------------------------------------------------------------------
 // push phase, per node kind (G lanes per node, group-uniform control flow)
+// nbytes accumulates algorithmic bytes: a node's own fields once per node
+// (lane 0 of its group), each arc's fields by the lane that scans the arc.
 // ---------------------------------------------------------------------------
 
 template <int G>
@@ -496,7 +498,7 @@ __device__ void push_vertex(const Dev& g, const RoundArgs& ra, const BlockQ& q, 
     X = take_excess(g, ra, u, gl);
     beg = g.vtx_off[u];
     end = g.vtx_off[u + 1];
-    nbytes += 20;
+    if (gl == 0) nbytes += 20;
   }
   const bool active = has && k < g.N && X > 0;
   const uint32_t UX = active ? (uint32_t)X : 0u;
@@ -550,7 +552,7 @@ __device__ void push_ein(const Dev& g, const RoundArgs& ra, const BlockQ& q, int
   if (has) {
     k = g.d[node];
     X = take_excess(g, ra, node, gl);
-    nbytes += 12;
+    if (gl == 0) nbytes += 12;
   }
   const bool active = has && k < g.N && X > 0;
   const uint32_t UX = active ? (uint32_t)X : 0u;
@@ -560,7 +562,7 @@ __device__ void push_ein(const Dev& g, const RoundArgs& ra, const BlockQ& q, int
     const int we = g.w[e];
     const int fbv = g.fb[e];
     const int dout = g.d[node + 1];
-    nbytes += 20;
+    if (gl == 0) nbytes += 20;
     const uint32_t rb = (uint32_t)(we - fbv);
     const bool ab = rb > 0u && dout == k - 1;
     const uint32_t gb = ab ? min(rb, UX) : 0u;
@@ -610,7 +612,7 @@ __device__ void push_eout(const Dev& g, const RoundArgs& ra, const BlockQ& q, in
   if (has) {
     k = g.d[node];
     X = take_excess(g, ra, node, gl);
-    nbytes += 12;
+    if (gl == 0) nbytes += 12;
   }
   const bool active = has && k < g.N && X > 0;
   const uint32_t UX = active ? (uint32_t)X : 0u;
@@ -618,7 +620,7 @@ __device__ void push_eout(const Dev& g, const RoundArgs& ra, const BlockQ& q, in
   int cand = kInf;
   if (active) {
     const int beg = g.net_off[e], end = g.net_off[e + 1];
-    nbytes += 8;
+    if (gl == 0) nbytes += 8;
     // pins first: the arcs e_out -> u are infinite, so the first admissible
     // pin takes all remaining excess
     for (int base = beg; base < end; base += G) {
@@ -650,7 +652,7 @@ __device__ void push_eout(const Dev& g, const RoundArgs& ra, const BlockQ& q, in
     if (carry < UX) {  // reverse bridge e_out -> e_in
       const int rb = g.fb[e];
       const int din = g.d[node - 1];
-      nbytes += 8;
+      if (gl == 0) nbytes += 8;
       const bool ab = rb > 0 && din == k - 1;
       const uint32_t gb = ab ? min((uint32_t)rb, UX - carry) : 0u;
       if (gb && gl == 0) g.fb[e] = rb - (int)gb;
@@ -820,9 +822,10 @@ __device__ __forceinline__ void set_seen(const Dev& g, int v) {
 // Label v with lvl if it is unlabelled.  With kClaim the first writer wins
 // by compare-and-swap on the label and reports it; otherwise a plain store
 // (all writers of a level store the same value).
-template <bool kClaim>
+// kChecked: the caller has just read v's hint bit and found it clear.
+template <bool kClaim, bool kChecked = false>
 __device__ __forceinline__ bool label_rev(const Dev& g, int v, int lvl) {
-  if (seen_bit(g, v)) return false;
+  if (!kChecked && seen_bit(g, v)) return false;
   if (!kClaim) {
     if (g.d[v] != g.N) return false;
     g.d[v] = lvl;
@@ -857,9 +860,9 @@ __device__ void bfs_rev_node(const Dev& g, const BlockQ& q, int x, bool has, int
         // bits of e_in and e_out share a word (NB and 2e are even)
         const uint32_t sw = g.seen[t1 >> 5] >> (t1 & 31);
         nbytes += 12;
-        if (!(sw & 2u)) vout = label_rev<kClaim>(g, t1 + 1, lvl);  // e_out -> x infinite
+        if (!(sw & 2u)) vout = label_rev<kClaim, true>(g, t1 + 1, lvl);  // e_out -> x infinite
         if (!(sw & 1u) && pin_flow_in(g, ep.y))                    // e_in -> x reverse
-          vin = label_rev<kClaim>(g, t1, lvl);
+          vin = label_rev<kClaim, true>(g, t1, lvl);
       }
       if (kClaim) {
         qpush(g, q, t1, vin);
@@ -874,7 +877,7 @@ __device__ void bfs_rev_node(const Dev& g, const BlockQ& q, int x, bool has, int
     // in-arcs of e_out from pins carry flow(e_out, u) > 0; their sum is the
     // outflow fb - excess(e_out), so a net without outflow skips its pins
     if (!in && !(nb & 2u)) end = beg;
-    nbytes += 16;
+    if (gl == 0) nbytes += 16;
     bool vb = false;
     if (gl == 0) {
       if (in) vb = (nb & 4u) && label_rev<kClaim>(g, x + 1, lvl);  // e_out -> e_in residual fb
@@ -1068,9 +1071,9 @@ __device__ void phase_bfs_rev_lb(const Dev& g, int level, int tile0, int tstride
           t2 = t1 + 1;
           const uint32_t sw = g.seen[t1 >> 5] >> (t1 & 31);
           nbytes += 12;
-          if (!(sw & 2u)) v2 = label_rev<kClaim>(g, t2, lvl);  // e_out -> x infinite
+          if (!(sw & 2u)) v2 = label_rev<kClaim, true>(g, t2, lvl);  // e_out -> x infinite
           if (!(sw & 1u) && g.w[e] - g.fpin[2 * ep.y] > 0)     // e_in -> x reverse
-            v1 = label_rev<kClaim>(g, t1, lvl);
+            v1 = label_rev<kClaim, true>(g, t1, lvl);
         } else {
           const int e = (x - g.NB) >> 1;
           const bool in = ((x - g.NB) & 1) == 0;
