@@ -174,9 +174,9 @@ fp_status mincut_source_side(fp_problem *problem, void *hip_stream, int32_t mem_
                              uint8_t *vertex_side, uint8_t *net_side);
 
 /*
- * flow_batch_solve: solve many independent problems in one persistent
- * launch (one workgroup per problem, largest first), with the same device
- * phases as maxflow_solve.  Problems may differ in size.  Equivalent to
+ * flow_batch_solve: solve many independent problems with the same device
+ * phases as maxflow_solve, concurrently (default batch plan below, largest
+ * problems first).  Problems may differ in size.  Equivalent to
  * flow_batch_create (no cut outputs, default configuration),
  * flow_batch_run and flow_batch_destroy.
  *
@@ -198,10 +198,22 @@ fp_status flow_batch_solve(fp_problem *const *problems, int32_t count,
 /*
  * Batch plans: many independent problems solved concurrently, the pattern of
  * the paper's refinement scheduler (section "Parallel Active Block
- * Scheduling").  Problems are taken from a shared queue, largest (pins +
- * network nodes) first, by `streams` host workers, each driving the
- * single-problem path on a HIP stream of its own, so the kernels and host
- * round trips of different problems overlap.  (A persistent kernel that
+ * Scheduling").  Two schedules:
+ *   0 (workers)  problems are taken from a shared queue, largest (pins +
+ *                network nodes) first, by `streams` host workers, each
+ *                driving the single-problem path on a HIP stream of its own,
+ *                so the kernels and host round trips of different problems
+ *                overlap;
+ *   1 (union)    the kept problems are copied into one network, their
+ *                disjoint union, and solved once with the device-wide
+ *                kernels: the union's minimal minimum cut is the union of
+ *                the problems' minimal minimum cuts, and a problem's flow
+ *                value is the weight of its nets that cut cuts (checked
+ *                against the union's flow value).  Each run starts from the
+ *                zero flow of every problem's current terminals (same
+ *                results as a warm start) and leaves the problems' own
+ *                handles untouched.
+ * (A persistent kernel that
  * runs each problem inside one workgroup, replayed from a captured HIP
  * graph, is built but switched off: its first GPU run ended in a memory
  * access fault whose cause has not been found; block_threads and workgroups
@@ -218,7 +230,9 @@ typedef struct {
   int32_t workgroups;    /* persistent workgroups; 0 = as many as fit on
                             the device at once (at most one per problem)   */
   int32_t streams;       /* concurrent workers (streams), 1..64; 0 = 4      */
-  int32_t reserved[3];
+  int32_t schedule;      /* 0 = concurrent workers; 1 = union: the kept
+                            problems solved as one network (see below)     */
+  int32_t reserved[2];
 } fp_batch_config;
 
 /*
@@ -239,23 +253,26 @@ fp_status flow_batch_create(fp_problem *const *problems, int32_t count,
                             fp_batch **out);
 
 /*
- * flow_batch_run: solve every problem not skipped (warm: a problem that was
- * solved or pierced before continues from its flow; a fresh or reset one
- * starts from zero), and with with_cut = 1 also write its minimal source
- * side.  flow_values as in flow_batch_solve.  Skipped problems are not
- * touched.  Errors as flow_batch_solve; FP_ERR_INVALID when with_cut = 1
- * but the plan has no vertex_sides.
+ * flow_batch_run: solve every problem not skipped (workers schedule: warm, a
+ * problem that was solved or pierced before continues from its flow, a
+ * fresh or reset one starts from zero, and every solved handle behaves as
+ * after maxflow_solve; union schedule: see above), and with with_cut = 1
+ * also write its minimal source side.  flow_values as in flow_batch_solve.
+ * Skipped problems are not touched.  Errors as flow_batch_solve
+ * (FP_ERR_OVERFLOW when the union exceeds 31-bit ids); FP_ERR_INVALID when
+ * with_cut = 1 but the plan has no vertex_sides.
  */
 fp_status flow_batch_run(fp_batch *batch, const uint8_t *skip, int32_t with_cut,
                          void *hip_stream, int64_t *flow_values);
 
 /*
- * flow_batch_tune: time candidate configurations (number of streams, lanes
- * per node, global relabel interval) on this batch, each run from the zero
- * flow, and keep the fastest.  With a cache_path (or NULL), a configuration stored
- * under the batch's signature (device, problem count, total pins, total
- * network nodes) is reused without timing, and a newly timed one is
- * appended.  Leaves every problem solved.  chosen may be NULL.
+ * flow_batch_tune: time candidate configurations (schedule and number of
+ * streams, lanes per node, global relabel interval) on this batch, each run
+ * from the zero flow, and keep the fastest.  With a cache_path (or NULL), a
+ * configuration stored under the batch's signature (device, problem count,
+ * total pins, total network nodes) is reused without timing, and a newly
+ * timed one is appended.  Ends with a run of the chosen configuration (with
+ * the workers schedule every problem is then solved).  chosen may be NULL.
  */
 fp_status flow_batch_tune(fp_batch *batch, void *hip_stream, const char *cache_path,
                           fp_batch_config *chosen);

@@ -177,17 +177,9 @@ fp_status flow_batch_create(fp_problem* const* problems, int32_t count,
         set_error("vertex_sides[%d] is NULL", i);
         return FP_ERR_INVALID;
       }
-  if (config) {
-    fp_batch_config c = *config;
-    if (c.group_lanes == 0) c.group_lanes = 4;
-    if (c.block_threads == 0) c.block_threads = 1024;
-    if (c.streams == 0) c.streams = 4;
-    if (!((c.group_lanes == 4 || c.group_lanes == 8 || c.group_lanes == 16) &&
-          (c.block_threads == 256 || c.block_threads == 1024) && c.gr_interval >= -1 &&
-          c.workgroups >= 0 && c.streams >= 1 && c.streams <= 64)) {
-      set_error("invalid batch configuration");
-      return FP_ERR_INVALID;
-    }
+  if (config && !batch_config_ok(config)) {
+    set_error("invalid batch configuration");
+    return FP_ERR_INVALID;
   }
   return create_batch(problems, count, vertex_sides, net_sides, config,
                       static_cast<hipStream_t>(hip_stream), out);

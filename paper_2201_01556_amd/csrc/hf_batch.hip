@@ -302,6 +302,8 @@ struct fp_batch {
   fp_batch_config exec_cfg[2]{};
   int cus = 0;
   std::vector<hipStream_t> workers;  // streams of the concurrent schedule
+  void* umem = nullptr;              // scratch of the union schedule
+  size_t umem_bytes = 0;
 };
 
 namespace hf {
@@ -320,7 +322,12 @@ static fp_batch_config resolve_batch_config(const fp_batch_config* c) {
 static bool batch_config_valid(const fp_batch_config& c) {
   return (c.group_lanes == 4 || c.group_lanes == 8 || c.group_lanes == 16) &&
          (c.block_threads == 256 || c.block_threads == 1024) && c.gr_interval >= -1 &&
-         c.workgroups >= 0 && c.streams >= 1 && c.streams <= 64;
+         c.workgroups >= 0 && c.streams >= 1 && c.streams <= 64 &&
+         (c.schedule == 0 || c.schedule == 1);
+}
+
+bool batch_config_ok(const fp_batch_config* c) {
+  return batch_config_valid(resolve_batch_config(c));
 }
 
 static void drop_graphs(fp_batch* b) {
@@ -338,8 +345,10 @@ void release_batch(fp_batch* b) {
   if (b->cap) (void)hipStreamDestroy(b->cap);
   if (b->dmem) (void)hipFree(b->dmem);
   if (b->hmem) (void)hipHostFree(b->hmem);
+  if (b->umem) (void)hipFree(b->umem);
   b->cap = nullptr;
-  b->dmem = b->hmem = nullptr;
+  b->dmem = b->hmem = b->umem = nullptr;
+  b->umem_bytes = 0;
 }
 
 fp_status create_batch(fp_problem* const* pbs, int32_t count, uint8_t* const* vsides,
@@ -590,8 +599,274 @@ static fp_status batch_concurrent(fp_batch* b, const uint8_t* skip, int32_t with
   return first;
 }
 
+
+// ---------------------------------------------------------------------------
+// union schedule: the kept problems as one network
+//
+// The problems are independent, so their disjoint union is one flow network
+// (the sources and sinks of all problems together).  A maximum preflow of the
+// union restricted to a problem is a maximum preflow of that problem, and the
+// minimal minimum cut of the union is the union of the problems' minimal
+// minimum cuts, since the cut weight is a sum over the components.  One solve
+// of the union therefore runs every problem in the same device-wide kernels:
+// a global relabel is one reverse BFS over all problems and a round
+// discharges all their frontiers.  A problem's flow value is the weight of
+// its nets cut by the minimal source side (maximum flow equals minimum cut);
+// their sum must equal the union's flow value.
+// ---------------------------------------------------------------------------
+
+struct UnionMap {
+  const int32_t* ids;   // [n] problem index of each kept problem
+  const int32_t* voff;  // [n+1] first union vertex of each kept problem
+  const int32_t* eoff;  // [n+1] first union net
+  const int32_t* poff;  // [n+1] first union pin slot
+  int32_t n;
+};
+
+// kept problem owning union element x: the largest i < n with off[i] <= x
+// (off[n] is the total, above x)
+__device__ __forceinline__ int union_part(const int32_t* off, int n, int x) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= x) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(256) k_union_nets(const Dev* devs, UnionMap m, int32_t E,
+                                                    int32_t* net_off, int32_t* w) {
+  const int t0 = blockIdx.x * blockDim.x + threadIdx.x, ts = gridDim.x * blockDim.x;
+  for (int e = t0; e < E; e += ts) {
+    const int i = union_part(m.eoff, m.n, e);
+    const Dev& d = devs[m.ids[i]];
+    const int le = e - m.eoff[i];
+    net_off[e] = m.poff[i] + d.net_off[le];
+    w[e] = d.w[le];
+  }
+  if (t0 == 0) net_off[E] = m.poff[m.n];
+}
+
+__global__ void __launch_bounds__(256) k_union_pins(const Dev* devs, UnionMap m, int32_t P,
+                                                    int32_t* pins) {
+  const int t0 = blockIdx.x * blockDim.x + threadIdx.x, ts = gridDim.x * blockDim.x;
+  for (int p = t0; p < P; p += ts) {
+    const int i = union_part(m.poff, m.n, p);
+    pins[p] = m.voff[i] + devs[m.ids[i]].pin_v[p - m.poff[i]];
+  }
+}
+
+// Terminal lists of the union from the problems' current roles (piercing
+// included); list order does not matter.
+__global__ void __launch_bounds__(256) k_union_terminals(const Dev* devs, UnionMap m, int32_t V,
+                                                         int32_t* src, int32_t* snk,
+                                                         int32_t* counts) {
+  const int t0 = blockIdx.x * blockDim.x + threadIdx.x, ts = gridDim.x * blockDim.x;
+  for (int v = t0; v < V; v += ts) {
+    const int i = union_part(m.voff, m.n, v);
+    const int r = devs[m.ids[i]].role[v - m.voff[i]];
+    if (r == 1) src[atomicAdd(&counts[0], 1)] = v;
+    else if (r == 2) snk[atomicAdd(&counts[1], 1)] = v;
+  }
+}
+
+// Flow value of kept problem blockIdx.x: weight of its nets with e_in on the
+// source side and e_out not (bit0 set, bit1 clear).
+__global__ void __launch_bounds__(256) k_union_flows(UnionMap m, const int32_t* w,
+                                                     const uint8_t* nside,
+                                                     unsigned long long* flows) {
+  const int i = blockIdx.x;
+  unsigned long long sum = 0ull;
+  for (int e = m.eoff[i] + threadIdx.x; e < m.eoff[i + 1]; e += blockDim.x)
+    if ((nside[e] & 3u) == 1u) sum += (unsigned long long)w[e];
+  block_add_u64(&flows[i], sum);
+}
+
+// Scatter the union's sides into the problems' side buffers.
+__global__ void __launch_bounds__(256) k_union_sides(UnionMap m, int32_t V, int32_t E,
+                                                     const uint8_t* vside, const uint8_t* nside,
+                                                     uint8_t* const* vs, uint8_t* const* ns) {
+  const int t0 = blockIdx.x * blockDim.x + threadIdx.x, ts = gridDim.x * blockDim.x;
+  for (int v = t0; v < V; v += ts) {
+    const int i = union_part(m.voff, m.n, v);
+    vs[m.ids[i]][v - m.voff[i]] = vside[v];
+  }
+  if (ns == nullptr) return;
+  for (int e = t0; e < E; e += ts) {
+    const int i = union_part(m.eoff, m.n, e);
+    uint8_t* dst = ns[m.ids[i]];
+    if (dst) dst[e - m.eoff[i]] = nside[e];
+  }
+}
+
+static int union_grid(long long n) {
+  const long long b = (n + 255) / 256;
+  return (int)std::max<long long>(1, std::min<long long>(b, 8192));
+}
+
+// Solve the kept problems as one network.  The problems' own handles are not
+// touched: every run starts from the zero flow of each problem's current
+// terminals, which gives the same flow values and minimal source sides as a
+// warm start would.
+static fp_status batch_union(fp_batch* b, const uint8_t* skip, int32_t with_cut, hipStream_t s,
+                             int64_t* flows, float* ms) {
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<int32_t> ids;
+  std::vector<int32_t> voff(1, 0), eoff(1, 0), poff(1, 0);
+  long long V = 0, E = 0, P = 0;
+  for (int32_t i = 0; i < b->count; ++i) {
+    if (skip && skip[i]) {
+      if (flows) flows[i] = -1;
+      continue;
+    }
+    const fp_problem* pb = b->pbs[i];
+    ids.push_back(i);
+    V += pb->V;
+    E += pb->E;
+    P += pb->P;
+    if (V >= (1ll << 30) || E >= (1ll << 30) || P >= (1ll << 31) - 1) {
+      set_error("the union of the batch is too large for 31-bit ids (V=%lld E=%lld P=%lld)", V,
+                E, P);
+      return FP_ERR_OVERFLOW;
+    }
+    voff.push_back((int32_t)V);
+    eoff.push_back((int32_t)E);
+    poff.push_back((int32_t)P);
+  }
+  const int32_t n = (int32_t)ids.size();
+  if (n == 0) {
+    if (ms) *ms = 0.f;
+    return FP_OK;
+  }
+  // scratch: map, union inputs, terminal lists, sides, flows
+  size_t off = 0;
+  auto carve = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  const size_t o_ids = carve((size_t)n * 4);
+  const size_t o_voff = carve((size_t)(n + 1) * 4);
+  const size_t o_eoff = carve((size_t)(n + 1) * 4);
+  const size_t o_poff = carve((size_t)(n + 1) * 4);
+  const size_t o_noff = carve((size_t)(E + 1) * 4);
+  const size_t o_w = carve((size_t)E * 4 + 4);
+  const size_t o_pins = carve((size_t)P * 4 + 4);
+  const size_t o_src = carve((size_t)V * 4);
+  const size_t o_snk = carve((size_t)V * 4);
+  const size_t o_cnt = carve(8);
+  const size_t o_flows = carve((size_t)n * 8);
+  const size_t o_vs = carve((size_t)V);
+  const size_t o_ns = carve((size_t)E + 1);
+  hipError_t he = hipSuccess;
+  if (off > b->umem_bytes) {
+    if (b->umem) (void)hipFree(b->umem);
+    b->umem = nullptr;
+    b->umem_bytes = 0;
+    he = hipMalloc(&b->umem, off);
+    if (he != hipSuccess) {
+      b->umem = nullptr;
+      return hip_fail(he, "allocating the union scratch");
+    }
+    b->umem_bytes = off;
+  }
+  char* d = static_cast<char*>(b->umem);
+  UnionMap m;
+  m.ids = reinterpret_cast<const int32_t*>(d + o_ids);
+  m.voff = reinterpret_cast<const int32_t*>(d + o_voff);
+  m.eoff = reinterpret_cast<const int32_t*>(d + o_eoff);
+  m.poff = reinterpret_cast<const int32_t*>(d + o_poff);
+  m.n = n;
+  int32_t* noff_u = reinterpret_cast<int32_t*>(d + o_noff);
+  int32_t* w_u = reinterpret_cast<int32_t*>(d + o_w);
+  int32_t* pins_u = reinterpret_cast<int32_t*>(d + o_pins);
+  int32_t* src = reinterpret_cast<int32_t*>(d + o_src);
+  int32_t* snk = reinterpret_cast<int32_t*>(d + o_snk);
+  int32_t* cnt = reinterpret_cast<int32_t*>(d + o_cnt);
+  unsigned long long* flows_d = reinterpret_cast<unsigned long long*>(d + o_flows);
+  uint8_t* vs_u = reinterpret_cast<uint8_t*>(d + o_vs);
+  uint8_t* ns_u = reinterpret_cast<uint8_t*>(d + o_ns);
+  for (int32_t i = 0; i < b->count; ++i) b->devs_h[i] = b->pbs[i]->dev;
+  he = hipMemcpyAsync(b->devs_d, b->devs_h, (size_t)b->count * sizeof(Dev), hipMemcpyHostToDevice,
+                      s);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(d + o_ids, ids.data(), (size_t)n * 4, hipMemcpyHostToDevice, s);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(d + o_voff, voff.data(), (size_t)(n + 1) * 4, hipMemcpyHostToDevice, s);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(d + o_eoff, eoff.data(), (size_t)(n + 1) * 4, hipMemcpyHostToDevice, s);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(d + o_poff, poff.data(), (size_t)(n + 1) * 4, hipMemcpyHostToDevice, s);
+  if (he == hipSuccess) he = hipMemsetAsync(cnt, 0, 8, s);
+  if (he == hipSuccess) he = hipMemsetAsync(flows_d, 0, (size_t)n * 8, s);
+  if (he != hipSuccess) return hip_fail(he, "staging the union map");
+  k_union_nets<<<union_grid(E + 1), 256, 0, s>>>(b->devs_d, m, (int32_t)E, noff_u, w_u);
+  if (P) k_union_pins<<<union_grid(P), 256, 0, s>>>(b->devs_d, m, (int32_t)P, pins_u);
+  k_union_terminals<<<union_grid(V), 256, 0, s>>>(b->devs_d, m, (int32_t)V, src, snk, cnt);
+  int32_t counts[2] = {0, 0};
+  he = hipGetLastError();
+  if (he == hipSuccess) he = hipMemcpyAsync(counts, cnt, 8, hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess) he = hipStreamSynchronize(s);  // the host vectors are read until here
+  if (he != hipSuccess) return hip_fail(he, "building the union network");
+  fp_problem* u = new (std::nothrow) fp_problem();
+  if (!u) {
+    set_error("host allocation failed");
+    return FP_ERR_OOM;
+  }
+  u->device = b->device;
+  u->V = (int32_t)V;
+  u->E = (int32_t)E;
+  fp_options o{};
+  o.group_lanes = b->cfg.group_lanes;
+  o.gr_interval = b->cfg.gr_interval;
+  u->opt = resolve_options(&o);
+  fp_status st = FP_OK;
+  if (counts[0] < 1 || counts[1] < 1) {
+    set_error("the kept problems hold %d sources and %d sinks", counts[0], counts[1]);
+    st = FP_ERR_INVALID;
+  }
+  if (st == FP_OK) st = build_problem(u, noff_u, pins_u, w_u, src, counts[0], snk, counts[1], 1, s);
+  int64_t F = 0;
+  if (st == FP_OK) st = solve_problem(u, s, &F);
+  if (st == FP_OK) st = cut_problem(u, s, 1, vs_u, ns_u);
+  std::vector<unsigned long long> fh(n, 0ull);
+  if (st == FP_OK) {
+    k_union_flows<<<n, 256, 0, s>>>(m, u->dev.w, ns_u, flows_d);
+    if (with_cut)
+      k_union_sides<<<union_grid(std::max(V, E)), 256, 0, s>>>(
+          m, (int32_t)V, (int32_t)E, vs_u, ns_u, b->vs_d, b->has_ns ? b->ns_d : nullptr);
+    he = hipGetLastError();
+    if (he == hipSuccess)
+      he = hipMemcpyAsync(fh.data(), flows_d, (size_t)n * 8, hipMemcpyDeviceToHost, s);
+    if (he == hipSuccess) he = hipStreamSynchronize(s);
+    if (he != hipSuccess) st = hip_fail(he, "splitting the union's flow");
+  }
+  if (st != FP_OK) {
+    (void)hipStreamSynchronize(s);
+    release_problem(u);
+    delete u;
+    return st;
+  }
+  release_problem(u);
+  delete u;
+  unsigned long long total = 0ull;
+  for (int32_t k = 0; k < n; ++k) total += fh[k];
+  if ((int64_t)total != F) {
+    set_error("internal check: the problems' cut weights sum to %llu, the union's flow is %lld",
+              total, (long long)F);
+    return FP_ERR_DEVICE;
+  }
+  if (flows)
+    for (int32_t k = 0; k < n; ++k) flows[ids[k]] = (int64_t)fh[k];
+  if (ms)
+    *ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return FP_OK;
+}
+
 static fp_status batch_replay(fp_batch* b, const uint8_t* skip, int32_t with_cut, bool force_init,
                               hipStream_t s, int64_t* flows, float* ms) {
+  if (b->cfg.schedule == 1) return batch_union(b, skip, with_cut, s, flows, ms);
   if (!kPersistentBatch) return batch_concurrent(b, skip, with_cut, force_init, s, flows, ms);
   hipGraphExec_t exec = nullptr;
   fp_status st = batch_graph(b, with_cut ? 1 : 0, &exec);
@@ -707,10 +982,12 @@ static bool cache_lookup(const char* path, const std::string& sig, fp_batch_conf
   if (!path) return false;
   FILE* f = fopen(path, "r");
   if (!f) return false;
-  char key[256];
-  int g = 0, bs = 0, gr = 0, wg = 0, ns = 0;
+  char line[512], key[256];
+  int g = 0, bs = 0, gr = 0, wg = 0, ns = 0, sc = 0;
   bool found = false;
-  while (fscanf(f, "%255s %d %d %d %d %d", key, &g, &bs, &gr, &wg, &ns) == 6) {
+  while (fgets(line, sizeof(line), f)) {
+    // lines of another layout are skipped
+    if (sscanf(line, "%255s %d %d %d %d %d %d", key, &g, &bs, &gr, &wg, &ns, &sc) != 7) continue;
     if (sig == key) {  // the last entry for a signature wins
       *c = fp_batch_config{};
       c->group_lanes = g;
@@ -718,6 +995,7 @@ static bool cache_lookup(const char* path, const std::string& sig, fp_batch_conf
       c->gr_interval = gr;
       c->workgroups = wg;
       c->streams = ns;
+      c->schedule = sc;
       found = batch_config_valid(*c);
     }
   }
@@ -729,8 +1007,8 @@ static void cache_store(const char* path, const std::string& sig, const fp_batch
   if (!path) return;
   FILE* f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "%s %d %d %d %d %d\n", sig.c_str(), c.group_lanes, c.block_threads, c.gr_interval,
-          c.workgroups, c.streams);
+  fprintf(f, "%s %d %d %d %d %d %d\n", sig.c_str(), c.group_lanes, c.block_threads,
+          c.gr_interval, c.workgroups, c.streams, c.schedule);
   fclose(f);
 }
 
@@ -762,8 +1040,9 @@ fp_status tune_batch(fp_batch* b, hipStream_t s, const char* cache_path, fp_batc
     }
     return FP_OK;
   };
-  // one knob at a time, each from the best so far: concurrency (streams;
-  // block size for the persistent kernel), lanes per node, relabel interval
+  // one knob at a time, each from the best so far: schedule and concurrency
+  // (worker streams or the union; block size for the persistent kernel),
+  // lanes per node, relabel interval
   if (kPersistentBatch) {
     const int blocks[2] = {1024, 256};
     for (int bs : blocks) {
@@ -776,10 +1055,15 @@ fp_status tune_batch(fp_batch* b, hipStream_t s, const char* cache_path, fp_batc
     const int streams[5] = {1, 2, 4, 8, 16};
     for (int ns : streams) {
       fp_batch_config c = base;
+      c.schedule = 0;
       c.streams = ns;
       fp_status st = trial(c);
       if (st) return st;
     }
+    fp_batch_config c = base;
+    c.schedule = 1;
+    fp_status st = trial(c);
+    if (st) return st;
   }
   const int lanes[3] = {4, 8, 16};
   const fp_batch_config conc = best;

@@ -80,6 +80,8 @@ fp_status cut_problem(fp_problem* pb, hipStream_t s, int32_t mem_kind, uint8_t* 
                       uint8_t* nside);
 fp_status batch_solve(fp_problem* const* pbs, int32_t count, const uint8_t* skip,
                       hipStream_t s, int64_t* flows);
+// a configuration (zero fields = defaults) that create_batch accepts
+bool batch_config_ok(const fp_batch_config* c);
 fp_status create_batch(fp_problem* const* pbs, int32_t count, uint8_t* const* vsides,
                        uint8_t* const* nsides, const fp_batch_config* config, hipStream_t s,
                        fp_batch** out);

@@ -82,7 +82,8 @@ class BatchConfig(ctypes.Structure):
         ("gr_interval", ctypes.c_int32),
         ("workgroups", ctypes.c_int32),
         ("streams", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("schedule", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
     def as_dict(self) -> dict:

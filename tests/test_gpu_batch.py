@@ -3,10 +3,11 @@ the CPU oracle, through the C ABI.
 
 A batch runs the same device phases as the single-problem path under a
 different schedule, so flow values and minimal source sides must match the
-oracle bit-exactly for every configuration.  The persistent one-workgroup-
-per-problem kernel is switched off in the library (its first GPU run ended
-in a memory fault whose cause is not found yet); the plans then run their
-problems one after another, and these tests check that schedule.
+oracle bit-exactly for every configuration: concurrent workers (each
+problem on its own stream) and the union schedule (the kept problems as one
+network).  The persistent one-workgroup-per-problem kernel is switched off
+in the library (its first GPU run ended in a memory fault whose cause is
+not found yet).
 """
 import os
 import sys
@@ -191,6 +192,65 @@ def test_batch_tune_and_cache(hf, oracle_mod):
             p.close()
 
 
+@pytest.mark.parametrize("lanes,gr", [(4, 0), (8, -1), (16, 8), (8, 1)])
+def test_batch_union_vs_oracle(hf, oracle_mod, lanes, gr):
+    """Union schedule: the kept problems solved as one network; flows and
+    minimal source sides per problem equal the oracle's."""
+    hgs = uneven_set(24, seed0=600)
+    refs = _oracle_all(oracle_mod, hgs)
+    probs = [hf.FlowProblem.from_hypergraph(h) for h in hgs]
+    try:
+        _say(f"union schedule lanes={lanes} gr={gr}")
+        with hf.FlowBatch(probs, with_cut=True, schedule=1, group_lanes=lanes,
+                          gr_interval=gr) as b:
+            flows = b.run(with_cut=True)
+            assert list(flows) == [r.flow for r in refs]
+            _check_sides(b, hgs, refs, f"union lanes={lanes} gr={gr}")
+            skip = np.zeros(24, dtype=np.uint8)
+            skip[[0, 5, 23]] = 1
+            flows = b.run(skip=skip)
+            for i in range(24):
+                assert flows[i] == (-1 if skip[i] else refs[i].flow)
+            assert list(b.run(skip=np.ones(24, dtype=np.uint8))) == [-1] * 24
+    finally:
+        for p in probs:
+            p.close()
+
+
+def test_batch_union_block_pairs_and_pierced(hf, oracle_mod, small_pairs):
+    """Union schedule on block-pair regions, then with one problem pierced:
+    the union takes each problem's current terminals."""
+    hgs = small_pairs.problems
+    refs = _oracle_all(oracle_mod, hgs)
+    probs = [hf.FlowProblem.from_hypergraph(h) for h in hgs]
+    twin = hf.FlowProblem.from_hypergraph(hgs[0])
+    try:
+        _say(f"union schedule, {len(hgs)} block-pair problems")
+        with hf.FlowBatch(probs, with_cut=True, schedule=1) as b:
+            flows = b.run(with_cut=True)
+            assert list(flows) == [r.flow for r in refs]
+            _check_sides(b, hgs, refs, "union block pairs")
+            # pierce problem 0 (and its twin) on the source side
+            probs[0].solve()
+            twin.solve()
+            vs, _ = probs[0].source_side()
+            outside = np.nonzero(vs == 0)[0]
+            v = int(outside[outside != hgs[0].sinks[0]][0])
+            probs[0].pierce(0, [v])
+            twin.pierce(0, [v])
+            f_twin = twin.solve()
+            twin_vs, twin_ns = twin.source_side()
+            flows = b.run(with_cut=True)
+            assert flows[0] == f_twin
+            vs0, ns0 = b.sides(0)
+            assert (vs0 == twin_vs).all() and (ns0 == twin_ns).all()
+            assert list(flows[1:]) == [r.flow for r in refs[1:]]
+    finally:
+        twin.close()
+        for p in probs:
+            p.close()
+
+
 @pytest.mark.skip(reason="persistent batch kernel switched off: its first GPU run ended in a "
                          "memory access fault whose cause has not been found")
 def test_persistent_batch_kernel():
@@ -209,6 +269,9 @@ def test_batch_errors(hf):
         assert ei.value.name == "FP_ERR_INVALID"
         with pytest.raises(hf.HyperflowError) as ei:
             hf.FlowBatch(probs, streams=65)
+        assert ei.value.name == "FP_ERR_INVALID"
+        with pytest.raises(hf.HyperflowError) as ei:
+            hf.FlowBatch(probs, schedule=2)
         assert ei.value.name == "FP_ERR_INVALID"
         with hf.FlowBatch(probs) as b:
             with pytest.raises(hf.HyperflowError) as ei:
