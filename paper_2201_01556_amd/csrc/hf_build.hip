@@ -1,11 +1,14 @@
 // Problem creation: copy the inputs to the device, validate them and build
-// the device layout (net CSR as given, vertex incidence CSR by a counting
-// sort with per-vertex ordering by pin slot, terminal roles, per-net terminal
-// flags).  Every step runs on the device.
+// the device layout (net CSR as given, vertex incidence CSR by a stable radix
+// sort of the pins by vertex, so each vertex lists its pins in slot order;
+// terminal roles, per-net terminal flags).  Every step runs on the device.
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/iterator/counting_iterator.hpp>
 
 #include "hf_host.h"
 
@@ -27,15 +30,14 @@ __global__ void k_check_nets(Dev g, unsigned long long* wsum) {
     else s += (unsigned long long)we;
   }
   if (err) atomicOr(&g.ctl->err, err);
-  if (s) atomicAdd(wsum, s);
+  block_add_u64(wsum, s);
 }
 
-__global__ void k_count_pins(Dev g, int32_t* cnt) {
+__global__ void k_check_pins(Dev g) {
   int err = 0;
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < g.P; p += gridDim.x * blockDim.x) {
     const int u = g.pin_v[p];
     if (u < 0 || u >= g.V) err |= ERR_BUILD_PIN;
-    else atomicAdd(&cnt[u + 1], 1);
   }
   if (err) atomicOr(&g.ctl->err, err);
 }
@@ -59,152 +61,45 @@ __global__ void k_role_check(Dev g) {
   if (err) atomicOr(&g.ctl->err, err);
 }
 
-// inclusive scan, three passes over tiles of 2048 ints
-constexpr int kScanThreads = 256;
-constexpr int kScanPer = 8;
-constexpr int kScanTile = kScanThreads * kScanPer;
-
-__device__ int block_excl_scan(int v, int* sh_wave, int* total) {
-  // inclusive within the wave
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  int incl = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int t = __shfl_up(incl, o);
-    if (lane >= o) incl += t;
-  }
-  if (lane == 63) sh_wave[wid] = incl;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int run = 0;
-    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
-      const int t = sh_wave[i];
-      sh_wave[i] = run;
-      run += t;
-    }
-    *total = run;
-  }
-  __syncthreads();
-  return sh_wave[wid] + incl - v;
-}
-
-__global__ void k_scan_tiles(int32_t* a, int n, int32_t* bsum) {
-  __shared__ int sh_wave[kScanThreads / 64];
-  __shared__ int total;
-  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
-  int loc[kScanPer];
-  int run = 0;
-#pragma unroll
-  for (int j = 0; j < kScanPer; ++j) {
-    const int i = base + j;
-    run += (i < n) ? a[i] : 0;
-    loc[j] = run;
-  }
-  const int off = block_excl_scan(run, sh_wave, &total);
-#pragma unroll
-  for (int j = 0; j < kScanPer; ++j) {
-    const int i = base + j;
-    if (i < n) a[i] = loc[j] + off;
-  }
-  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
-}
-
-// exclusive scan of the tile sums, one block
-__global__ void k_scan_sums(int32_t* bsum, int nb) {
-  __shared__ int sh_wave[kScanThreads / 64];
-  __shared__ int total;
-  int carry = 0;
-  for (int base = 0; base < nb; base += blockDim.x) {
-    const int i = base + threadIdx.x;
-    const int v = i < nb ? bsum[i] : 0;
-    const int ex = block_excl_scan(v, sh_wave, &total);
-    __syncthreads();
-    if (i < nb) bsum[i] = carry + ex;
-    carry += total;
-    __syncthreads();
-  }
-}
-
-__global__ void k_scan_add(int32_t* a, int n, const int32_t* bsum) {
-  const int add = bsum[blockIdx.x];
-  const int base = blockIdx.x * kScanTile;
-  for (int j = threadIdx.x; j < kScanTile; j += blockDim.x) {
-    const int i = base + j;
-    if (i < n) a[i] += add;
-  }
-}
-
-__global__ void k_scatter(Dev g, int32_t* cursor) {
+// Net of every pin slot: the last e with net_off[e] <= p.
+__global__ void k_pin_nets(Dev g) {
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < g.P; p += gridDim.x * blockDim.x) {
-    // net of pin slot p: last e with net_off[e] <= p
     int lo = 0, hi = g.E;  // answer in [0, E)
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
       if (g.net_off[mid] <= p) lo = mid;
       else hi = mid;
     }
-    const int u = g.pin_v[p];
     const_cast<int32_t*>(g.pin_net)[p] = lo;
-    const int pos = atomicAdd(&cursor[u], 1);
-    const_cast<int2*>(g.vinc)[pos] = make_int2(lo, p);
-    const int r = g.role[u];
-    if (r) atomicOr(&g.nflag[lo], r);
   }
 }
 
-// sort each vertex's incidences by pin slot (deterministic layout), then a
-// repeated net in one list means a vertex appears twice in that net
-__global__ void k_sort_incidences(Dev g) {
+// Vertex offsets from the pins sorted by vertex: vtx_off[u] = first sorted
+// position holding a vertex >= u (position P past the last); each position
+// fills the offsets of the vertices between its predecessor's vertex and its
+// own, so vertices without pins get empty ranges.
+__global__ void k_vtx_offsets(const int32_t* keys, int P, int V, int32_t* vtx_off) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= P; i += gridDim.x * blockDim.x) {
+    const int prev = i == 0 ? -1 : keys[i - 1];
+    const int cur = i == P ? V : keys[i];
+    for (int u = prev + 1; u <= cur; ++u) vtx_off[u] = i;
+  }
+}
+
+// Incidences in sorted order: vinc[i] = {net, slot} of the i-th sorted pin;
+// a vertex's pins are in slot order, hence grouped by net, so a vertex twice
+// in one net shows as two neighbours with the same net.  Nets learn whether
+// they hold a source or a sink pin.
+__global__ void k_incidences(Dev g, const int32_t* keys, const int32_t* slots) {
   int err = 0;
-  int2* inc = const_cast<int2*>(g.vinc);
-  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.V; v += gridDim.x * blockDim.x) {
-    const int lo = g.vtx_off[v], hi = g.vtx_off[v + 1];
-    const int n = hi - lo;
-    int2* a = inc + lo;
-    if (n <= 16) {
-      for (int i = 1; i < n; ++i) {
-        const int2 t = a[i];
-        int j = i - 1;
-        while (j >= 0 && a[j].y > t.y) {
-          a[j + 1] = a[j];
-          --j;
-        }
-        a[j + 1] = t;
-      }
-    } else {
-      // heapsort by .y
-      for (int start = n / 2 - 1; start >= 0; --start) {
-        int r = start;
-        for (;;) {
-          int c = 2 * r + 1;
-          if (c >= n) break;
-          if (c + 1 < n && a[c + 1].y > a[c].y) ++c;
-          if (a[r].y >= a[c].y) break;
-          const int2 t = a[r];
-          a[r] = a[c];
-          a[c] = t;
-          r = c;
-        }
-      }
-      for (int end = n - 1; end > 0; --end) {
-        const int2 t = a[0];
-        a[0] = a[end];
-        a[end] = t;
-        int r = 0;
-        for (;;) {
-          int c = 2 * r + 1;
-          if (c >= end) break;
-          if (c + 1 < end && a[c + 1].y > a[c].y) ++c;
-          if (a[r].y >= a[c].y) break;
-          const int2 t2 = a[r];
-          a[r] = a[c];
-          a[c] = t2;
-          r = c;
-        }
-      }
-    }
-    for (int i = 1; i < n; ++i)
-      if (a[i].x == a[i - 1].x) err |= ERR_BUILD_DUP;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g.P; i += gridDim.x * blockDim.x) {
+    const int p = slots[i];
+    const int e = g.pin_net[p];
+    const int u = keys[i];
+    const_cast<int2*>(g.vinc)[i] = make_int2(e, p);
+    if (i > 0 && keys[i - 1] == u && g.pin_net[slots[i - 1]] == e) err |= ERR_BUILD_DUP;
+    const int r = g.role[u];
+    if (r) atomicOr(&g.nflag[e], r);
   }
   if (err) atomicOr(&g.ctl->err, err);
 }
@@ -389,14 +284,13 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
   if (he == hipSuccess) he = hipMemcpyAsync(terms + nS, sinks, nT * 4ull, kind, s);
   if (he == hipSuccess) he = hipMemsetAsync(g.ctl, 0, sizeof(Ctl), s);
   if (he == hipSuccess) he = hipMemsetAsync(wsum, 0, 8, s);
-  if (he == hipSuccess) he = hipMemsetAsync(vtx_off, 0, (V + 1) * 4ull, s);
   if (he == hipSuccess) he = hipMemsetAsync(g.role, 0, V * 4ull, s);
   if (he == hipSuccess && E) he = hipMemsetAsync(g.nflag, 0, E * 4ull, s);
   if (he != hipSuccess) return hip_fail(he, "copying inputs");
 
   // validation
   if (E) k_check_nets<<<grid_for(E), 256, 0, s>>>(g, wsum);
-  if (P) k_count_pins<<<grid_for(P), 256, 0, s>>>(g, vtx_off);
+  if (P) k_check_pins<<<grid_for(P), 256, 0, s>>>(g);
   k_roles<<<grid_for(nS + nT), 256, 0, s>>>(g, terms, nS, terms + nS, nT);
   k_role_check<<<grid_for(V), 256, 0, s>>>(g);
   int32_t err = 0;
@@ -430,19 +324,26 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
     return FP_ERR_OVERFLOW;
   }
 
-  // vertex incidence CSR: counts -> offsets
-  const int ntiles = (V + kScanTile - 1) / kScanTile;
-  int32_t* bsum = g.x;  // scratch
-  if (V) {
-    k_scan_tiles<<<ntiles, kScanThreads, 0, s>>>(vtx_off + 1, V, bsum);
-    k_scan_sums<<<1, kScanThreads, 0, s>>>(bsum, ntiles);
-    k_scan_add<<<ntiles, kScanThreads, 0, s>>>(vtx_off + 1, V, bsum);
+  // vertex incidence CSR: stable radix sort of (vertex, slot) pairs by
+  // vertex; the pin-flow array is scratch until the first solve initialises it
+  int32_t* keys = g.fpin;
+  int32_t* slots = g.fpin + P;
+  if (P) {
+    unsigned bits = 1;
+    while (bits < 31 && (1ll << bits) < (long long)V) ++bits;
+    const rocprim::counting_iterator<int32_t> slot0(0);
+    size_t tb = 0;
+    he = rocprim::radix_sort_pairs(nullptr, tb, pin_v, keys, slot0, slots, (size_t)P, 0u, bits, s);
+    void* tmp = nullptr;
+    if (he == hipSuccess) he = hipMallocAsync(&tmp, std::max<size_t>(tb, 1), s);
+    if (he == hipSuccess)
+      he = rocprim::radix_sort_pairs(tmp, tb, pin_v, keys, slot0, slots, (size_t)P, 0u, bits, s);
+    if (tmp) (void)hipFreeAsync(tmp, s);
+    if (he != hipSuccess) return hip_fail(he, "sorting the pins by vertex");
+    k_pin_nets<<<grid_for(P), 256, 0, s>>>(g);
   }
-  int32_t* cursor = g.stamp;  // scratch
-  he = hipMemcpyAsync(cursor, vtx_off, V * 4ull, hipMemcpyDeviceToDevice, s);
-  if (he != hipSuccess) return hip_fail(he, "building incidences");
-  if (P) k_scatter<<<grid_for(P), 256, 0, s>>>(g, cursor);
-  k_sort_incidences<<<grid_for(V), 256, 0, s>>>(g);
+  k_vtx_offsets<<<grid_for((long long)P + 1), 256, 0, s>>>(keys, P, V, vtx_off);
+  if (P) k_incidences<<<grid_for(P), 256, 0, s>>>(g, keys, slots);
   k_bigbits<<<grid_for((N + 31) / 32), 256, 0, s>>>(g, bigbits);
   he = hipMemcpyAsync(&err, &g.ctl->err, 4, hipMemcpyDeviceToHost, s);
   if (he == hipSuccess) he = hipStreamSynchronize(s);
