@@ -50,7 +50,7 @@ def main():
     ap.add_argument("--batch-problems", type=int, default=500)
     ap.add_argument("--no-cutter", action="store_true",
                     help="skip the incremental FlowCutter workload")
-    ap.add_argument("--cutter-iterations", type=int, default=400)
+    ap.add_argument("--cutter-iterations", type=int, default=2000)
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-pruning workload")
     ap.add_argument("--learned-seeds", type=int, default=4,
@@ -337,7 +337,7 @@ def bench_learned(args, hyperflow, inputs, torch, np, config):
     K = max(2, args.learned_seeds)
     n_train = max(1, (3 * K) // 4)
     cfg = dict(config or {})
-    cfg = {k: v for k, v in cfg.items() if k in ("group_lanes", "gr_interval", "streams")}
+    cfg = {k: v for k, v in cfg.items() if k in ("group_lanes", "gr_interval", "streams", "schedule")}
 
     def instance(seed):
         bp = _pairs(inputs, seed, args.batch_problems)

@@ -189,7 +189,7 @@ __device__ void wg_solve(const Dev& g, const BatchParam& p, BatchResult& r, int*
 template <int G>
 __device__ bool wg_cut(const Dev& g, int ep, uint8_t* vs, uint8_t* ns, lds_int* lds,
                        int* levels) {
-  phase_cut_seed(g, ep, 0, 1, lds);
+  phase_cut_seed(g, ep, false, 0, 1, lds);
   __syncthreads();
   int level = 0;
   for (;;) {

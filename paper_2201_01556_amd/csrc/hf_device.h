@@ -101,7 +101,8 @@ struct Ctl {
   unsigned long long bytes[KC_N];
   unsigned long long items[KC_N];
   unsigned long long side_weight[2];  // FlowCutter: c(S_r), c(T_r)
-  int32_t pierce[3];  // FlowCutter: smallest free boundary / augmenting / free vertex
+  int32_t pierce[5];  // FlowCutter: per side s, [3s] smallest free boundary pin and
+                      // [3s + 1] smallest augmenting pin; [2] smallest free vertex
   int32_t pad;
 };
 
@@ -1345,8 +1346,10 @@ __device__ void phase_gather(const Dev& g, int epoch, int tile0, int tstride, ld
 
 // Cut BFS seeds: sources (marked, nothing to expand: their only arcs are the
 // contracted source arcs into e_in), e_in of nets with a source pin, and
-// every non-terminal node holding excess.
-__device__ void phase_cut_seed(const Dev& g, int ep, int tile0, int tstride, lds_int* lds) {
+// every non-terminal node holding excess.  With only_new, nodes that already
+// carry ep are left out (growing an existing source side).
+__device__ void phase_cut_seed(const Dev& g, int ep, bool only_new, int tile0, int tstride,
+                               lds_int* lds) {
   const BlockQ q = bq_bind(lds, g.ctl->bcnt[0], g.list[0]);
   const int ntiles = sweep_tiles(g);
   for (int tile = tile0; tile < ntiles; tile += tstride) {
@@ -1364,6 +1367,7 @@ __device__ void phase_cut_seed(const Dev& g, int ep, int tile0, int tstride, lds
           const bool in = ((v - g.NB) & 1) == 0;
           seed = g.x[v] > 0 || (in && (g.nflag[e] & 1));
         }
+        if (seed && only_new && g.stamp[v] == ep) seed = false;
         if (seed) g.stamp[v] = ep;
       }
       qpush(g, q, v, seed);
@@ -1494,7 +1498,17 @@ __device__ void phase_reset_bfs(const Dev& g) {
       for (int k = 0; k < kNL; ++k) g.ctl->bcnt[i][k] = 0;
     g.ctl->side_weight[0] = 0ull;
     g.ctl->side_weight[1] = 0ull;
-    for (int i = 0; i < 3; ++i) g.ctl->pierce[i] = kInf;
+    for (int i = 0; i < 5; ++i) g.ctl->pierce[i] = kInf;
+  }
+}
+
+// One seed vertex p (already stamped by the caller) as BFS level 0.  The
+// BFS counters must be clear (phase_reset_bfs).
+__device__ void phase_seed_vertex(const Dev& g, int p) {
+  if (threadIdx.x == 0) {
+    const int k = list_of(g, p);
+    g.list[0][k][0] = p;
+    g.ctl->bcnt[0][k] = 1;
   }
 }
 
@@ -1532,39 +1546,39 @@ __device__ void phase_fc_weights(const Dev& g, const int32_t* cw, int ep_s, int 
   block_min_i32(&g.ctl->pierce[2], first_free, &g.ctl->pierce[2], kInf);
 }
 
-// Piercing candidates of one side, thread per net.  side 0: nets cut by
+// Piercing candidates of both sides, thread per net.  Side 0: nets cut by
 // (S_r, V - S_r), i.e. with a pin in S_r (e_in reached) and not all pins in
-// it (e_out not reached); side 1: nets with pins in T_r and outside it.
-// pierce[0] = smallest such pin outside S_r and T_r, pierce[1] = smallest
-// such pin on the opposite side that is not a terminal yet.
-__device__ void phase_fc_candidates(const Dev& g, int side, int ep_s, int ep_t, int t0,
-                                    int tstride) {
-  int best_free = kInf, best_aug = kInf;
+// it (e_out not reached); side 1: nets with pins in T_r and outside it.  For
+// side s, pierce[3s] = smallest such pin outside S_r and T_r, pierce[3s+1] =
+// smallest such pin on the opposite side that is not a terminal yet.
+__device__ void phase_fc_candidates(const Dev& g, int ep_s, int ep_t, int t0, int tstride) {
+  int free0 = kInf, aug0 = kInf, free1 = kInf, aug1 = kInf;
   for (int e = t0; e < g.E; e += tstride) {
     const int beg = g.net_off[e], end = g.net_off[e + 1];
-    bool cut;
-    if (side == 0) {
-      cut = g.stamp[g.NB + 2 * e] == ep_s && g.stamp[g.NB + 2 * e + 1] != ep_s;
-    } else {
-      bool any_in = false, any_out = false;
-      for (int p = beg; p < end; ++p) {
-        const bool in = g.stamp[g.pin_v[p]] == ep_t;
-        any_in |= in;
-        any_out |= !in;
-      }
-      cut = any_in && any_out;
+    const bool cut0 = g.stamp[g.NB + 2 * e] == ep_s && g.stamp[g.NB + 2 * e + 1] != ep_s;
+    bool any_in = false, any_out = false;
+    for (int p = beg; p < end; ++p) {
+      const bool in = g.stamp[g.pin_v[p]] == ep_t;
+      any_in |= in;
+      any_out |= !in;
     }
-    if (!cut) continue;
-    const int other = side == 0 ? ep_t : ep_s;
-    const int other_role = side == 0 ? 2 : 1;
+    const bool cut1 = any_in && any_out;
+    if (!cut0 && !cut1) continue;
     for (int p = beg; p < end; ++p) {
       const int u = g.pin_v[p];
       const int st = g.stamp[u];
-      if (st != ep_s && st != ep_t) best_free = min(best_free, u);
-      else if (st == other && g.role[u] != other_role) best_aug = min(best_aug, u);
+      if (st != ep_s && st != ep_t) {
+        if (cut0) free0 = min(free0, u);
+        if (cut1) free1 = min(free1, u);
+      } else if (st == ep_t) {
+        if (cut0 && g.role[u] != 2) aug0 = min(aug0, u);
+      } else if (cut1 && g.role[u] != 1) {
+        aug1 = min(aug1, u);
+      }
     }
   }
-  block_min_i32(&g.ctl->pierce[0], best_free, &g.ctl->pierce[1], best_aug);
+  block_min_i32(&g.ctl->pierce[0], free0, &g.ctl->pierce[1], aug0);
+  block_min_i32(&g.ctl->pierce[3], free1, &g.ctl->pierce[4], aug1);
 }
 
 // Every free vertex with stamp ep_s becomes a source.  The flows of its

@@ -82,9 +82,9 @@ __global__ void __launch_bounds__(kBlock) k_apply(Dev g, int epoch) {
   phase_apply(g, epoch, blockIdx.x, gridDim.x, KC_APPLY, lds);
 }
 
-__global__ void __launch_bounds__(kBlock) k_cut_seed(Dev g, int ep) {
+__global__ void __launch_bounds__(kBlock) k_cut_seed(Dev g, int ep, int only_new) {
   HF_QUEUE_LDS;
-  phase_cut_seed(g, ep, blockIdx.x, gridDim.x, lds);
+  phase_cut_seed(g, ep, only_new != 0, blockIdx.x, gridDim.x, lds);
 }
 
 template <int G>
@@ -107,6 +107,8 @@ __global__ void __launch_bounds__(kBlock) k_sink_seed(Dev g, int ep) {
 
 __global__ void k_reset_bfs(Dev g) { phase_reset_bfs(g); }
 
+__global__ void k_seed_vertex(Dev g, int p) { phase_seed_vertex(g, p); }
+
 __global__ void __launch_bounds__(kThreads) k_side_out(Dev g, int ep, int invert, uint8_t* vs) {
   phase_side_out(g, ep, invert != 0, vs, gthread(), gthreads());
 }
@@ -116,8 +118,12 @@ __global__ void __launch_bounds__(kThreads) k_fc_weights(Dev g, const int32_t* c
   phase_fc_weights(g, cw, ep_s, ep_t, gthread(), gthreads());
 }
 
-__global__ void __launch_bounds__(kThreads) k_fc_candidates(Dev g, int side, int ep_s, int ep_t) {
-  phase_fc_candidates(g, side, ep_s, ep_t, gthread(), gthreads());
+__global__ void __launch_bounds__(kThreads) k_fc_candidates(Dev g, int ep_s, int ep_t) {
+  phase_fc_candidates(g, ep_s, ep_t, gthread(), gthreads());
+}
+
+__global__ void k_stamp_vertex(Dev g, int p, int ep) {
+  if (threadIdx.x == 0) g.stamp[p] = ep;
 }
 
 __global__ void __launch_bounds__(kThreads) k_pierce_sources(Dev g, int ep_s) {
@@ -514,7 +520,7 @@ static fp_status cut_impl(fp_problem* pb, hipStream_t s, uint8_t* vs, uint8_t* n
   const int ep = pb->epoch++;
   {
     Launch L(pb, s, KK_CUT_SEED);
-    k_cut_seed<<<sweep_blocks(g.N), kBlock, 0, s>>>(g, ep);
+    k_cut_seed<<<sweep_blocks(g.N), kBlock, 0, s>>>(g, ep, 0);
   }
   int levels = 0;
   fp_status st = run_bfs<G>(pb, s, ep, 1, &levels);
@@ -575,7 +581,7 @@ static fp_status source_side_stamps(fp_problem* pb, hipStream_t s, int* ep_out) 
   const int ep = pb->epoch++;
   {
     Launch L(pb, s, KK_CUT_SEED);
-    k_cut_seed<<<sweep_blocks(g.N), kBlock, 0, s>>>(g, ep);
+    k_cut_seed<<<sweep_blocks(g.N), kBlock, 0, s>>>(g, ep, 0);
   }
   int levels = 0;
   fp_status st = run_bfs<G>(pb, s, ep, 1, &levels);
@@ -623,6 +629,38 @@ static fp_status sides_impl(fp_problem* pb, hipStream_t s, int want, int* ep_s, 
   if (want & 1) st = source_side_stamps<G>(pb, s, ep_s);
   if (st == FP_OK && (want & 2)) st = sink_side_stamps<G>(pb, s, ep_t);
   return st;
+}
+
+// Grow the reachable set stamped ep -- S_r (side 0, forward BFS) or T_r
+// (side 1, reverse BFS) -- after vertex p, which already carries ep, was
+// pierced into that side without an augmenting path.  The flow is then
+// unchanged, and so is the other side's reachable set.  Piercing adds no residual arc: a sink pierce changes
+// no arc, so T_r grows by what reaches p; a source pierce removes the arcs
+// that carried flow between new sources and their nets and leaves the
+// returned flow as excess at the arc heads, so the old S_r stays reachable
+// and S_r grows by what the new seeds reach (every seed of the full source
+// side that does not carry ep yet: e_in of p's nets, heads that received
+// returned flow).
+template <int G>
+static fp_status grow_side_impl(fp_problem* pb, hipStream_t s, int side, int ep, int p) {
+  Dev& g = pb->dev;
+  k_reset_bfs<<<1, 64, 0, s>>>(g);
+  if (side == 0) k_cut_seed<<<sweep_blocks(g.N), kBlock, 0, s>>>(g, ep, 1);
+  else k_seed_vertex<<<1, 64, 0, s>>>(g, p);
+  int levels = 0;
+  fp_status st = run_bfs<G>(pb, s, ep, side == 0 ? 1 : 2, &levels);
+  if (st) return st;
+  pb->st.bfs_levels += levels;
+  k_reset_bfs<<<1, 64, 0, s>>>(g);  // the caller's next sync checks the error flags
+  return FP_OK;
+}
+
+static fp_status grow_side(fp_problem* pb, hipStream_t s, int side, int ep, int p) {
+  switch (pb->opt.group_lanes) {
+    case 4: return grow_side_impl<4>(pb, s, side, ep, p);
+    case 16: return grow_side_impl<16>(pb, s, side, ep, p);
+    default: return grow_side_impl<8>(pb, s, side, ep, p);
+  }
 }
 
 static fp_status sides(fp_problem* pb, hipStream_t s, int want, int* ep_s, int* ep_t) {
@@ -732,16 +770,48 @@ fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src,
   int out_ep = -1, out_invert = 0;
   long long last_cs = 0;
   r.status = 2;  // iteration cap unless a branch below decides
+  // reachable sets kept across a pierce without augmenting path (grow_side)
+  int prev_ep_s = -1, prev_ep_t = -1, grow = -1, grow_vertex = -1;
+  int64_t last_F = 0;
   for (int32_t it = 1; it <= max_iters; ++it) {
     int64_t F = 0;
-    fp_status st = solve_problem(pb, s, &F);
-    if (st) return st;
+    fp_status st = FP_OK;
+    if (grow >= 0 && !pb->opt.debug_checks) {
+      // the last pierce took a vertex outside S_r and T_r: no residual path
+      // joins it to the other side (paragraph "Piercing"), so the preflow
+      // stays maximum and the flow value unchanged; no solve is needed
+      F = last_F;
+      pb->solved = true;
+    } else {
+      const int64_t rounds0 = pb->st.rounds;
+      st = solve_problem(pb, s, &F);
+      if (st) return st;
+      if (grow >= 0 && (pb->st.rounds != rounds0 || F != last_F)) {
+        set_error("internal check: a pierce without augmenting path changed the flow");
+        return FP_ERR_DEVICE;
+      }
+    }
+    last_F = F;
     int ep_s = 0, ep_t = 0;
-    st = sides(pb, s, 3, &ep_s, &ep_t);
+    if (grow >= 0) {
+      ep_s = prev_ep_s;
+      ep_t = prev_ep_t;
+      st = grow_side(pb, s, grow, grow == 0 ? ep_s : ep_t, grow_vertex);
+    } else {
+      st = sides(pb, s, 3, &ep_s, &ep_t);
+    }
     if (st) return st;
+    grow = -1;
+    prev_ep_s = ep_s;
+    prev_ep_t = ep_t;
     k_fc_weights<<<sweep_grid(pb->V), kThreads, 0, s>>>(g, pb->cw, ep_s, ep_t);
+    k_fc_candidates<<<sweep_grid(pb->E), kThreads, 0, s>>>(g, ep_s, ep_t);
     st = sync_ctl(pb, s);
     if (st) return st;
+    if (pb->ctl_h->err & (ERR_SINK_REACHED | ERR_SOURCE_REACHED)) {
+      set_error("internal check: a pierce without augmenting path connected a source and a sink");
+      return FP_ERR_DEVICE;
+    }
     const long long cs = (long long)pb->ctl_h->side_weight[0];
     const long long ct = (long long)pb->ctl_h->side_weight[1];
     r.iterations = it;
@@ -774,15 +844,12 @@ fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src,
     }
     if (!done) {
       const int side = cs <= ct ? 0 : 1;
-      k_fc_candidates<<<sweep_grid(pb->E), kThreads, 0, s>>>(g, side, ep_s, ep_t);
-      st = sync_ctl(pb, s);
-      if (st) return st;
       // a free boundary pin, else any free vertex, else an augmenting pin
-      int p = pb->ctl_h->pierce[0];
+      int p = pb->ctl_h->pierce[3 * side];
       bool aug = false;
       if (p == kInf) p = pb->ctl_h->pierce[2];
       if (p == kInf) {
-        p = pb->ctl_h->pierce[1];
+        p = pb->ctl_h->pierce[3 * side + 1];
         aug = true;
       }
       step.side = side;
@@ -804,9 +871,13 @@ fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src,
         done = true;
       } else {
         if (aug) r.augmenting++;
+        else {
+          grow = side;
+          grow_vertex = p;
+        }
         const int ep = side == 0 ? ep_s : ep_t;
-        he = hipMemcpyAsync(g.stamp + p, &ep, sizeof(int32_t), hipMemcpyHostToDevice, s);
-        if (he == hipSuccess) he = hipStreamSynchronize(s);  // ep lives on the host stack
+        k_stamp_vertex<<<1, 64, 0, s>>>(g, p, ep);
+        he = hipGetLastError();
         if (he != hipSuccess) return hip_fail(he, "marking the piercing vertex");
         st = apply_pierce(pb, s, side, ep);
         if (st) return st;
