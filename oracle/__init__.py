@@ -475,12 +475,13 @@ class _WithTerminals:
 
 
 class FlowCutterResult:
-    def __init__(self, status, flow, x, iterations, trace, S, T):
+    def __init__(self, status, flow, x, iterations, trace, S, T, counts=None):
         self.status = status          # "balanced", "infeasible" or "cap"
         self.flow = int(flow)         # cut weight of the returned bipartition
         self.vertex_side = x          # bool per vertex: the returned source side
         self.iterations = iterations  # max-flow computations
         self.trace = trace            # per iteration (side, node, F, c(S_r), c(T_r))
+        self.counts = counts          # per iteration: vertices pierced (0 at the end)
         self.sources = S
         self.sinks = T
 
@@ -515,9 +516,24 @@ def _piercing_node(hg, cut, sr, tr, own_terminals_side):
     return -1, False
 
 
+# Pierces of a side made one vertex at a time before bulk piercing starts
+# measuring (paragraph "Bulk Piercing": one node for the first few rounds).
+BULK_WARMUP = 3
+
+
+def _augmenting_candidates(hg, cut, own_terminals_side):
+    """Sorted distinct pins of cut nets that lie on the other side and are
+    not terminals yet (each creates an augmenting path)."""
+    net_of = np.repeat(np.arange(hg.num_nets), np.diff(hg.net_offsets))
+    pins = hg.pins[cut[net_of]]
+    return np.unique(pins[own_terminals_side[pins]])
+
+
 def flowcutter(hg, vertex_weights, max_source_weight, max_sink_weight,
-               max_iterations=100000):
-    """FlowCutter with one piercing node per iteration.
+               max_iterations=100000, bulk_percent=0):
+    """FlowCutter, one piercing node per iteration or, with bulk_percent > 0,
+    bulk piercing (paragraph "Bulk Piercing" of the section "Flow-Based
+    Refinement").
 
     Each iteration solves the max flow of the current (S, T) from scratch
     (warm starting changes only the work, not F, S_r or T_r, which the
@@ -531,6 +547,17 @@ def flowcutter(hg, vertex_weights, max_source_weight, max_sink_weight,
     such cut-net pin on the other side that is not yet a terminal (it
     creates an augmenting path).  Balanced: c(X) <= max_source_weight and
     c(V \\ X) <= max_sink_weight.
+
+    Bulk piercing, in integer arithmetic (beta = bulk_percent / 100): only
+    when the pierced side has no candidate that avoids an augmenting path,
+    and after that side's first BULK_WARMUP pierces.  Each side keeps its
+    own measurement -- weight its reachable set gained per pierced vertex,
+    the gain taken at the next iteration -- and its own goal: the term
+    starts at c(V) // 2 - c(side) when the side first bulk-pierces and is
+    multiplied by beta every bulk iteration; the goal is the term plus what
+    the previous goal missed.  The side then takes the
+    max(1, goal * pierced // gained) smallest-id augmenting candidates (all
+    of them if fewer).  The trace names the smallest one.
     """
     V = hg.num_vertices
     c = np.asarray(vertex_weights, dtype=np.int64)
@@ -539,30 +566,61 @@ def flowcutter(hg, vertex_weights, max_source_weight, max_sink_weight,
     T = np.zeros(V, dtype=bool)
     S[hg.sources] = True
     T[hg.sinks] = True
-    trace = []
+    trace, counts = [], []
+    pierces = [0, 0]   # pierces made per side
+    gained = [0, 0]    # measured weight gained per side ...
+    pierced = [0, 0]   # ... by this many pierced vertices
+    term = [None, None]
+    missed = [0, 0]
+    pending = None     # (side, c(side) before its pierce, vertices, goal)
     for it in range(1, max_iterations + 1):
         r = maxflow(_WithTerminals(hg, S, T), sink_side=True)
         sr = r.vertex_side.astype(bool)
         tr = r.sink_side.astype(bool)
         cs, ct = int(c[sr].sum()), int(c[tr].sum())
+        if pending is not None:
+            s, before, k, goal = pending
+            gain = max(0, (cs if s == 0 else ct) - before)
+            gained[s] += gain
+            pierced[s] += k
+            if goal is not None:
+                missed[s] = max(0, goal - gain)
+            pending = None
         if cs <= max_source_weight and total - cs <= max_sink_weight:
             trace.append((-1, -1, r.flow, cs, ct))
-            return FlowCutterResult("balanced", r.flow, sr, it, trace, S, T)
+            counts.append(0)
+            return FlowCutterResult("balanced", r.flow, sr, it, trace, S, T, counts)
         if total - ct <= max_source_weight and ct <= max_sink_weight:
             trace.append((-1, -1, r.flow, cs, ct))
-            return FlowCutterResult("balanced", r.flow, ~tr, it, trace, S, T)
-        if cs <= ct:
-            p, _ = _piercing_node(hg, _cut_nets(hg, sr), sr, tr, tr & ~T)
-            trace.append((0, p, r.flow, cs, ct))
-            if p < 0:
-                return FlowCutterResult("infeasible", r.flow, sr, it, trace, S, T)
+            counts.append(0)
+            return FlowCutterResult("balanced", r.flow, ~tr, it, trace, S, T, counts)
+        side = 0 if cs <= ct else 1
+        own, mine = (sr, tr & ~T) if side == 0 else (tr, sr & ~S)
+        cut = _cut_nets(hg, own)
+        p, aug = _piercing_node(hg, cut, sr, tr, mine)
+        trace.append((side, p, r.flow, cs, ct))
+        if p < 0:
+            counts.append(0)
+            x = sr if side == 0 else ~tr
+            return FlowCutterResult("infeasible", r.flow, x, it, trace, S, T, counts)
+        nodes = np.array([p])
+        goal = None
+        weight = cs if side == 0 else ct
+        if (aug and bulk_percent > 0 and pierces[side] >= BULK_WARMUP
+                and gained[side] > 0):
+            if term[side] is None:
+                term[side] = max(0, total // 2 - weight)
+            term[side] = term[side] * bulk_percent // 100
+            goal = term[side] + missed[side]
+            k = max(1, goal * pierced[side] // gained[side])
+            nodes = _augmenting_candidates(hg, cut, mine)[:k]
+        counts.append(int(nodes.size))
+        pierces[side] += 1
+        pending = (side, weight, int(nodes.size), goal)
+        if side == 0:
             S = sr.copy()
-            S[p] = True
+            S[nodes] = True
         else:
-            p, _ = _piercing_node(hg, _cut_nets(hg, tr), sr, tr, sr & ~S)
-            trace.append((1, p, r.flow, cs, ct))
-            if p < 0:
-                return FlowCutterResult("infeasible", r.flow, ~tr, it, trace, S, T)
             T = tr.copy()
-            T[p] = True
-    return FlowCutterResult("cap", trace[-1][2], sr, max_iterations, trace, S, T)
+            T[nodes] = True
+    return FlowCutterResult("cap", trace[-1][2], sr, max_iterations, trace, S, T, counts)

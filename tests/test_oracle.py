@@ -225,15 +225,29 @@ def _cutter_cases():
         return json.load(f)["cases"]
 
 
+def _run_cutter_case(fn, case):
+    hg = inputs.hypergraph_from_nets(case["V"], case["nets"], case["w"], case["S"], case["T"])
+    c = np.asarray(case.get("c", np.ones(case["V"])))
+    return fn(hg, c, case["max_source"], case["max_sink"],
+              bulk_percent=case.get("bulk_percent", 0))
+
+
+def _counts_of(case):
+    """Vertices pierced per iteration: as listed, else one per iteration."""
+    if "counts" in case:
+        return case["counts"]
+    return [1] * (case["iterations"] - 1) + [0]
+
+
 @pytest.mark.parametrize("case", _cutter_cases(), ids=lambda c: c["name"])
 def test_flowcutter_fixture(oracle_mod, case):
-    hg = inputs.hypergraph_from_nets(case["V"], case["nets"], case["w"], case["S"], case["T"])
-    r = oracle_mod.flowcutter(hg, np.ones(case["V"]), case["max_source"], case["max_sink"])
+    r = _run_cutter_case(oracle_mod.flowcutter, case)
     assert r.status == case["status"]
     assert r.flow == case["F"]
     assert np.nonzero(r.vertex_side)[0].tolist() == case["x"]
     assert r.iterations == case["iterations"]
     assert [list(t) for t in r.trace] == case["trace"]
+    assert r.counts == _counts_of(case)
 
 
 @pytest.mark.parametrize("block", range(3))
@@ -277,13 +291,20 @@ def test_flowcutter_tiny_invariants(oracle_mod):
 
 
 CUTTER_MUTANTS = {
-    "pierce heavier side": ("if cs <= ct:", "if cs > ct:"),
+    "pierce heavier side": ("side = 0 if cs <= ct else 1", "side = 0 if cs > ct else 1"),
     "largest id": ("return int(free.min()), False", "return int(free.max()), False"),
     "skip sink-side balance": ("if total - ct <= max_source_weight and ct <= max_sink_weight:",
                                "if False:"),
     "sink side = complement": ("tr = r.sink_side.astype(bool)", "tr = ~sr"),
     "no augmenting fallback": ("aug = pins[own_terminals_side[pins]]", "aug = pins[:0]"),
     "no free-vertex fallback": ("anywhere = np.nonzero(~sr & ~tr)[0]", "anywhere = pins[:0]"),
+    "bulk without warm-up": ("pierces[side] >= BULK_WARMUP", "pierces[side] >= 0"),
+    "bulk on free vertices": ("if (aug and bulk_percent > 0", "if (bulk_percent > 0"),
+    "bulk ratio inverted": ("k = max(1, goal * pierced[side] // gained[side])",
+                            "k = max(1, goal * gained[side] // pierced[side])"),
+    "bulk term from c(V)": ("term[side] = max(0, total // 2 - weight)",
+                            "term[side] = max(0, total - weight)"),
+    "bulk forgets the missed goal": ("goal = term[side] + missed[side]", "goal = term[side]"),
 }
 
 
@@ -300,12 +321,11 @@ def test_flowcutter_pins_catch_planted_mistakes(oracle_mod, name):
     exec(compile(src.replace(old, new), "<mutant>", "exec"), ns)
     failed = False
     for case in _cutter_cases():
-        hg = inputs.hypergraph_from_nets(case["V"], case["nets"], case["w"], case["S"],
-                                         case["T"])
         try:
-            r = ns["flowcutter"](hg, np.ones(case["V"]), case["max_source"], case["max_sink"])
+            r = _run_cutter_case(ns["flowcutter"], case)
             ok = (r.status == case["status"] and r.flow == case["F"] and
                   [list(t) for t in r.trace] == case["trace"] and
+                  r.counts == _counts_of(case) and
                   np.nonzero(r.vertex_side)[0].tolist() == case["x"])
         except Exception:
             ok = False
