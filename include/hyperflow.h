@@ -352,13 +352,16 @@ typedef struct {
   int64_t flow;          /* maximum flow value of the iteration               */
   int64_t source_weight; /* c(S_r)                                            */
   int64_t sink_weight;   /* c(T_r)                                            */
+  int32_t count;         /* vertices pierced (node is the smallest); 0 when
+                            the iteration ended the run                      */
+  int32_t reserved;
 } fp_cutter_step;
 
 /*
  * flow_problem_flowcutter: FlowCutter on the problem's current terminals
  * (paper, section "Flow-Based Refinement": algorithm "FlowCutter Core" and
- * paragraph "Piercing"), one piercing vertex per iteration, every flow warm
- * started from the previous one.  Each iteration solves the maximum flow,
+ * paragraphs "Piercing" and "Bulk Piercing"), every flow warm started from
+ * the previous one.  Each iteration solves the maximum flow,
  * derives S_r and T_r, and stops when (S_r, V \ S_r) or else
  * (V \ T_r, T_r) is balanced: c(X) <= max_source_weight and
  * c(V \ X) <= max_sink_weight.  Otherwise the lighter of S_r and T_r
@@ -366,10 +369,24 @@ typedef struct {
  * the smallest-id pin, outside S_r and T_r, of a net cut by that side's
  * bipartition; else the smallest-id vertex outside S_r and T_r; else the
  * smallest-id such cut-net pin on the other side that is not a terminal yet
- * (an augmenting path follows).
+ * (an augmenting path follows).  A pierce of a vertex outside S_r and T_r
+ * keeps the flow maximum: the next iteration skips the solve and only grows
+ * the pierced side's reachable set.
+ *
+ * Bulk piercing (bulk_percent = beta in percent, 1..99; 0 = one vertex per
+ * iteration), in integer arithmetic: only when the pierced side has no
+ * candidate avoiding an augmenting path and after that side's first three
+ * pierces.  Each side measures the weight its reachable set gained per
+ * pierced vertex (the gain taken at the next iteration) and keeps a goal:
+ * the term starts at c(V) / 2 - c(side) at the side's first bulk iteration
+ * and is multiplied by beta every bulk iteration; goal = term + what the
+ * previous goal missed.  The side then takes the
+ * max(1, goal * pierced / gained) smallest-id augmenting candidates (all of
+ * them if fewer).
  *
  *   vertex_weights  host, |V| ints >= 0
  *   max_iterations  >= 1
+ *   bulk_percent    0..99
  *   mem_kind        memory kind of vertex_side
  *   vertex_side     |V| bytes: the returned source side X
  *   result          host out
@@ -380,9 +397,9 @@ typedef struct {
  */
 fp_status flow_problem_flowcutter(fp_problem *problem, const int32_t *vertex_weights,
                                   int64_t max_source_weight, int64_t max_sink_weight,
-                                  int32_t max_iterations, void *hip_stream, int32_t mem_kind,
-                                  uint8_t *vertex_side, fp_cutter_result *result,
-                                  fp_cutter_step *trace);
+                                  int32_t max_iterations, int32_t bulk_percent,
+                                  void *hip_stream, int32_t mem_kind, uint8_t *vertex_side,
+                                  fp_cutter_result *result, fp_cutter_step *trace);
 
 /*
  * Learned pruning scorer (pattern of the paper's pruning rules, section

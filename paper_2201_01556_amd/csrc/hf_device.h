@@ -1512,6 +1512,80 @@ __device__ void phase_seed_vertex(const Dev& g, int p) {
   }
 }
 
+// Bulk piercing (paragraph "Bulk Piercing"): flag[u] = 1 for every augmenting
+// candidate of side `side` -- a pin of a net cut by that side's bipartition
+// that lies on the opposite side's reachable set and is not a terminal yet.
+// Thread per net; flags are cleared by the caller.
+__device__ void phase_fc_mark_augmenting(const Dev& g, int side, int ep_s, int ep_t,
+                                         uint8_t* flag, int t0, int tstride) {
+  for (int e = t0; e < g.E; e += tstride) {
+    const int beg = g.net_off[e], end = g.net_off[e + 1];
+    bool cut;
+    if (side == 0) {
+      cut = g.stamp[g.NB + 2 * e] == ep_s && g.stamp[g.NB + 2 * e + 1] != ep_s;
+    } else {
+      bool any_in = false, any_out = false;
+      for (int p = beg; p < end; ++p) {
+        const bool in = g.stamp[g.pin_v[p]] == ep_t;
+        any_in |= in;
+        any_out |= !in;
+      }
+      cut = any_in && any_out;
+    }
+    if (!cut) continue;
+    const int other = side == 0 ? ep_t : ep_s;
+    const int other_role = side == 0 ? 2 : 1;
+    for (int p = beg; p < end; ++p) {
+      const int u = g.pin_v[p];
+      if (g.stamp[u] == other && g.role[u] != other_role) flag[u] = 1;
+    }
+  }
+}
+
+// Exclusive prefix of per-thread 0/1 values over a workgroup (blockDim a
+// multiple of 64, at most 1024); *total gets the workgroup's sum.
+__device__ int block_rank(int f, int* total) {
+  __shared__ int wsum[17];
+  const int lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const unsigned long long m = __ballot(f != 0);
+  const int below = __popcll(m & lanemask_lt());
+  if (lane == 0) wsum[wid] = __popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int i = 0; i < nw; ++i) {
+      const int t = wsum[i];
+      wsum[i] = run;
+      run += t;
+    }
+    wsum[nw] = run;
+  }
+  __syncthreads();
+  const int r = wsum[wid] + below;
+  *total = wsum[nw];
+  __syncthreads();
+  return r;
+}
+
+// Flag counts per workgroup tile of blockDim vertices.
+__device__ void phase_count_flags(const uint8_t* flag, int V, int32_t* counts) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  int total = 0;
+  block_rank(v < V && flag[v] != 0, &total);
+  if (threadIdx.x == 0) counts[blockIdx.x] = total;
+}
+
+// Stamp with ep the k flagged vertices of smallest id; offsets[b] = flags
+// before tile b.
+__device__ void phase_select_flags(Dev g, const uint8_t* flag, int V, const int32_t* offsets,
+                                   int k, int ep) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool f = v < V && flag[v] != 0;
+  int total = 0;
+  const int r = offsets[blockIdx.x] + block_rank(f, &total);
+  if (f && r < k) g.stamp[v] = ep;
+}
+
 // Vertex bitmap of a BFS: 1 where the vertex carries stamp ep (when
 // invert, 1 where it does not).
 __device__ void phase_side_out(const Dev& g, int ep, bool invert, uint8_t* vside, int t0,

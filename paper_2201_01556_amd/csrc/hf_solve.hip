@@ -122,6 +122,47 @@ __global__ void __launch_bounds__(kThreads) k_fc_candidates(Dev g, int ep_s, int
   phase_fc_candidates(g, ep_s, ep_t, gthread(), gthreads());
 }
 
+__global__ void __launch_bounds__(kThreads) k_fc_mark_augmenting(Dev g, int side, int ep_s,
+                                                                 int ep_t, uint8_t* flag) {
+  phase_fc_mark_augmenting(g, side, ep_s, ep_t, flag, gthread(), gthreads());
+}
+
+__global__ void __launch_bounds__(kBlock) k_count_flags(const uint8_t* flag, int V,
+                                                        int32_t* counts) {
+  phase_count_flags(flag, V, counts);
+}
+
+// exclusive scan of n tile counts in place, total to counts[n]; one workgroup
+__global__ void __launch_bounds__(kBlock) k_scan_counts(int32_t* counts, int n) {
+  __shared__ int carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < n; base += blockDim.x) {
+    const int i = base + threadIdx.x;
+    const int c = i < n ? counts[i] : 0;
+    // inclusive scan over the workgroup in LDS (Hillis-Steele)
+    __shared__ int buf[kBlock];
+    buf[threadIdx.x] = c;
+    __syncthreads();
+    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+      const int t = threadIdx.x >= (unsigned)o ? buf[threadIdx.x - o] : 0;
+      __syncthreads();
+      buf[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < n) counts[i] = carry + buf[threadIdx.x] - c;
+    __syncthreads();
+    if (threadIdx.x == 0) carry += buf[blockDim.x - 1];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) counts[n] = carry;
+}
+
+__global__ void __launch_bounds__(kBlock) k_select_flags(Dev g, const uint8_t* flag, int V,
+                                                         const int32_t* offsets, int k, int ep) {
+  phase_select_flags(g, flag, V, offsets, k, ep);
+}
+
 __global__ void k_stamp_vertex(Dev g, int p, int ep) {
   if (threadIdx.x == 0) g.stamp[p] = ep;
 }
@@ -743,9 +784,23 @@ fp_status pierce_problem(fp_problem* pb, int32_t side, const int32_t* vertices, 
   return apply_pierce(pb, s, side, ep);
 }
 
+// Pierces of a side made one vertex at a time before bulk piercing measures
+// (paragraph "Bulk Piercing": one node for the first few rounds).
+constexpr int kBulkWarmup = 3;
+
+// Scratch of the bulk selection: candidate flags, then tile counts.
+struct BulkScratch {
+  void* mem = nullptr;
+  hipStream_t s = nullptr;
+  ~BulkScratch() {
+    if (mem) (void)hipFreeAsync(mem, s);
+  }
+};
+
 fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src, int64_t max_snk,
-                             int32_t max_iters, hipStream_t s, int32_t mem_kind, uint8_t* vside,
-                             fp_cutter_result* res, fp_cutter_step* trace) {
+                             int32_t max_iters, int32_t bulk_percent, hipStream_t s,
+                             int32_t mem_kind, uint8_t* vside, fp_cutter_result* res,
+                             fp_cutter_step* trace) {
   Dev& g = pb->dev;
   long long total = 0;
   for (int32_t v = 0; v < pb->V; ++v) {
@@ -765,6 +820,24 @@ fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src,
   }
   he = hipMemcpyAsync(pb->cw, vw, (size_t)pb->V * sizeof(int32_t), hipMemcpyHostToDevice, s);
   if (he != hipSuccess) return hip_fail(he, "copying vertex weights");
+  const int ntiles = (pb->V + kBlock - 1) / kBlock;
+  const size_t flag_bytes = ((size_t)pb->V + 3) & ~(size_t)3;
+  BulkScratch bulk;
+  bulk.s = s;
+  if (bulk_percent > 0) {
+    he = hipMallocAsync(&bulk.mem, flag_bytes + 4 * ((size_t)ntiles + 1), s);
+    if (he != hipSuccess) {
+      bulk.mem = nullptr;
+      return hip_fail(he, "allocating the bulk piercing scratch");
+    }
+  }
+  uint8_t* flags = static_cast<uint8_t*>(bulk.mem);
+  int32_t* tile_counts = bulk.mem ? reinterpret_cast<int32_t*>(flags + flag_bytes) : nullptr;
+  // bulk piercing bookkeeping per side, integer arithmetic (see the header)
+  long long pierces[2] = {0, 0}, gained[2] = {0, 0}, pierced[2] = {0, 0};
+  long long term[2] = {-1, -1}, missed[2] = {0, 0};
+  int pend_side = -1;
+  long long pend_before = 0, pend_count = 0, pend_goal = -1;
   fp_cutter_result r{};
   uint8_t* vs = mem_kind == 0 ? reinterpret_cast<uint8_t*>(pb->dev.list[1][kBigList]) : vside;
   int out_ep = -1, out_invert = 0;
@@ -814,6 +887,13 @@ fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src,
     }
     const long long cs = (long long)pb->ctl_h->side_weight[0];
     const long long ct = (long long)pb->ctl_h->side_weight[1];
+    if (pend_side >= 0) {  // gain of the side pierced last iteration
+      const long long gain = std::max(0ll, (pend_side == 0 ? cs : ct) - pend_before);
+      gained[pend_side] += gain;
+      pierced[pend_side] += pend_count;
+      if (pend_goal >= 0) missed[pend_side] = std::max(0ll, pend_goal - gain);
+      pend_side = -1;
+    }
     r.iterations = it;
     r.flow = F;
     out_ep = ep_s;  // the iteration cap reports this iteration's S_r
@@ -824,6 +904,7 @@ fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src,
     step.sink_weight = ct;
     step.side = -1;
     step.node = -1;
+    step.count = 0;
     bool done = false;
     if (cs <= max_src && total - cs <= max_snk) {
       r.status = 0;
@@ -876,9 +957,42 @@ fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src,
           grow_vertex = p;
         }
         const int ep = side == 0 ? ep_s : ep_t;
-        k_stamp_vertex<<<1, 64, 0, s>>>(g, p, ep);
-        he = hipGetLastError();
-        if (he != hipSuccess) return hip_fail(he, "marking the piercing vertex");
+        const long long weight = side == 0 ? cs : ct;
+        long long k = 1, goal = -1;
+        if (aug && bulk_percent > 0 && pierces[side] >= kBulkWarmup && gained[side] > 0) {
+          if (term[side] < 0) term[side] = std::max(0ll, total / 2 - weight);
+          term[side] = term[side] * bulk_percent / 100;
+          goal = term[side] + missed[side];
+          k = std::max(1ll, goal * pierced[side] / gained[side]);
+        }
+        long long count = 1;
+        if (k > 1) {
+          // the k smallest-id augmenting candidates of this side
+          he = hipMemsetAsync(flags, 0, flag_bytes, s);
+          if (he != hipSuccess) return hip_fail(he, "clearing the candidate flags");
+          k_fc_mark_augmenting<<<sweep_grid(pb->E), kThreads, 0, s>>>(g, side, ep_s, ep_t, flags);
+          k_count_flags<<<ntiles, kBlock, 0, s>>>(flags, pb->V, tile_counts);
+          k_scan_counts<<<1, kBlock, 0, s>>>(tile_counts, ntiles);
+          const int kk = (int)std::min<long long>(k, pb->V);
+          k_select_flags<<<ntiles, kBlock, 0, s>>>(g, flags, pb->V, tile_counts, kk, ep);
+          int32_t found = 0;
+          he = hipGetLastError();
+          if (he == hipSuccess)
+            he = hipMemcpyAsync(&found, tile_counts + ntiles, 4, hipMemcpyDeviceToHost, s);
+          if (he == hipSuccess) he = hipStreamSynchronize(s);
+          if (he != hipSuccess) return hip_fail(he, "selecting the piercing vertices");
+          count = std::min<long long>(k, found);
+        } else {
+          k_stamp_vertex<<<1, 64, 0, s>>>(g, p, ep);
+          he = hipGetLastError();
+          if (he != hipSuccess) return hip_fail(he, "marking the piercing vertex");
+        }
+        step.count = (int32_t)count;
+        pierces[side] += 1;
+        pend_side = side;
+        pend_before = weight;
+        pend_count = count;
+        pend_goal = goal;
         st = apply_pierce(pb, s, side, ep);
         if (st) return st;
       }

@@ -110,6 +110,8 @@ class CutterStep(ctypes.Structure):
         ("flow", ctypes.c_int64),
         ("source_weight", ctypes.c_int64),
         ("sink_weight", ctypes.c_int64),
+        ("count", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -186,8 +188,8 @@ def load_library(path: str = LIB_PATH):
     lib.flow_problem_pierce.restype = ctypes.c_int
     lib.flow_problem_sink_side.argtypes = [vp, vp, i32, vp]
     lib.flow_problem_sink_side.restype = ctypes.c_int
-    lib.flow_problem_flowcutter.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int64, i32, vp, i32,
-                                            vp, ctypes.POINTER(CutterResult), vp]
+    lib.flow_problem_flowcutter.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int64, i32, i32, vp,
+                                            i32, vp, ctypes.POINTER(CutterResult), vp]
     lib.flow_problem_flowcutter.restype = ctypes.c_int
     lib.flow_problem_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     lib.flow_problem_stats.restype = ctypes.c_int
@@ -410,9 +412,10 @@ def flow_problem_sink_side(handle, num_vertices, vertex_side=None, stream=None):
 
 def flow_problem_flowcutter(handle, num_vertices, vertex_weights, max_source_weight,
                             max_sink_weight, max_iterations=100000, vertex_side=None,
-                            stream=None, want_trace=True):
+                            stream=None, want_trace=True, bulk_percent=0):
     """FlowCutter on the handle's current terminals.  Returns (result dict,
-    source side X, trace list of (side, node, flow, c(S_r), c(T_r)))."""
+    source side X, trace list of (side, node, flow, c(S_r), c(T_r))); the
+    dict's "counts" lists the vertices pierced per iteration."""
     lib = load_library()
     vw = np.ascontiguousarray(vertex_weights, dtype=np.int32)
     if vw.shape[0] != num_vertices:
@@ -424,7 +427,8 @@ def flow_problem_flowcutter(handle, num_vertices, vertex_weights, max_source_wei
     steps = (CutterStep * max(int(max_iterations), 1))() if want_trace else None
     _check(lib.flow_problem_flowcutter(handle, vw.ctypes.data, int(max_source_weight),
                                        int(max_sink_weight), int(max_iterations),
-                                       _stream_ptr(stream), vk, vp, ctypes.byref(res),
+                                       int(bulk_percent), _stream_ptr(stream), vk, vp,
+                                       ctypes.byref(res),
                                        ctypes.cast(steps, ctypes.c_void_p) if steps else None))
     out = dict(flow=int(res.flow), source_weight=int(res.source_weight),
                sink_weight=int(res.sink_weight), iterations=int(res.iterations),
@@ -434,6 +438,7 @@ def flow_problem_flowcutter(handle, num_vertices, vertex_weights, max_source_wei
     if steps is not None:
         trace = [(int(t.side), int(t.node), int(t.flow), int(t.source_weight),
                   int(t.sink_weight)) for t in steps[:res.iterations]]
+        out["counts"] = [int(t.count) for t in steps[:res.iterations]]
     x = np.asarray(vertex_side)[:num_vertices] if vk == 0 else vertex_side
     return out, x, trace
 
@@ -526,10 +531,10 @@ class FlowProblem:
         return flow_problem_sink_side(self.handle, self.num_vertices, vertex_side, self.stream)
 
     def flowcutter(self, vertex_weights, max_source_weight, max_sink_weight,
-                   max_iterations=100000, vertex_side=None, want_trace=True):
+                   max_iterations=100000, vertex_side=None, want_trace=True, bulk_percent=0):
         return flow_problem_flowcutter(self.handle, self.num_vertices, vertex_weights,
                                        max_source_weight, max_sink_weight, max_iterations,
-                                       vertex_side, self.stream, want_trace)
+                                       vertex_side, self.stream, want_trace, bulk_percent)
 
     def stats(self) -> dict:
         return flow_problem_stats(self.handle)

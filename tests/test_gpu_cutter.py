@@ -127,25 +127,85 @@ def _cutter_cases():
 @pytest.mark.parametrize("case", _cutter_cases(), ids=lambda c: c["name"])
 def test_flowcutter_fixtures(hf, case):
     hg = inputs.hypergraph_from_nets(case["V"], case["nets"], case["w"], case["S"], case["T"])
+    c = np.asarray(case.get("c", np.ones(case["V"])))
     with hf.FlowProblem.from_hypergraph(hg) as p:
-        res, x, trace = p.flowcutter(np.ones(case["V"]), case["max_source"], case["max_sink"])
+        res, x, trace = p.flowcutter(c, case["max_source"], case["max_sink"],
+                                     bulk_percent=case.get("bulk_percent", 0))
     assert res["status"] == case["status"]
     assert res["flow"] == case["F"]
     assert res["iterations"] == case["iterations"]
     assert np.nonzero(x)[0].tolist() == case["x"]
     assert [list(t) for t in trace] == case["trace"]
+    counts = case.get("counts", [1] * (case["iterations"] - 1) + [0])
+    assert res["counts"] == counts
 
 
-def _compare_cutter(hf, oracle_mod, hg, c, Ls, Lt, max_iter, tag, **opts):
-    ref = oracle_mod.flowcutter(hg, c, Ls, Lt, max_iterations=max_iter)
+def _compare_cutter(hf, oracle_mod, hg, c, Ls, Lt, max_iter, tag, bulk_percent=0, **opts):
+    ref = oracle_mod.flowcutter(hg, c, Ls, Lt, max_iterations=max_iter,
+                                bulk_percent=bulk_percent)
     with hf.FlowProblem.from_hypergraph(hg, **opts) as p:
-        res, x, trace = p.flowcutter(c, Ls, Lt, max_iterations=max_iter)
+        res, x, trace = p.flowcutter(c, Ls, Lt, max_iterations=max_iter,
+                                     bulk_percent=bulk_percent)
     assert res["iterations"] == ref.iterations, tag
     assert [tuple(t) for t in trace] == [tuple(t) for t in ref.trace], tag
+    assert res["counts"] == ref.counts, tag
     assert res["status"] == ref.status, tag
     assert res["flow"] == ref.flow, tag
     assert (x.astype(bool) == ref.vertex_side.astype(bool)).all(), tag
     return res
+
+
+def _random_region(seed):
+    """14..23 vertices, 1..3 nets per vertex of 2..3 pins, unit weights;
+    source 0, sink V-1 (shapes on which bulk piercing triggers)."""
+    rng = np.random.default_rng(seed)
+    V = int(rng.integers(14, 24))
+    E = int(rng.integers(V, 3 * V))
+    nets = [sorted(rng.choice(V, int(rng.integers(2, 4)), replace=False).tolist())
+            for _ in range(E)]
+    return inputs.hypergraph_from_nets(V, nets, [1] * E, [0], [V - 1])
+
+
+def test_flowcutter_bulk_small_vs_oracle(hf, oracle_mod):
+    """Bulk piercing (beta 55 %) on 120 small regions against the oracle,
+    trace, pierced counts and result; some of them bulk-pierce."""
+    bulked = 0
+    for seed in range(120):
+        hg = _random_region(seed)
+        c = np.ones(hg.num_vertices)
+        L = (hg.num_vertices + 1) // 2
+        res = _compare_cutter(hf, oracle_mod, hg, c, L, L, 100, f"bulk small {seed}",
+                              bulk_percent=55, debug_checks=1 if seed % 7 == 0 else 0)
+        bulked += max(res["counts"]) > 1
+    assert bulked >= 3
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_flowcutter_bulk_uniform_vs_oracle(hf, oracle_mod, seed):
+    hg = inputs.uniform_hypergraph(seed)
+    c = np.random.default_rng(seed).integers(1, 4, hg.num_vertices)
+    L = balance_limit(c.sum())
+    _say(f"bulk uniform {seed}")
+    _compare_cutter(hf, oracle_mod, hg, c, L, L, 5000, f"bulk uniform {seed}",
+                    bulk_percent=[55, 30, 80][seed])
+
+
+def test_flowcutter_bulk_zipf_balanced(hf, oracle_mod):
+    """The 200k-vertex instance with bulk piercing runs to a balanced cut;
+    the returned side is a certificate: its cut weight is the flow value and
+    both sides respect the bound."""
+    hg = inputs.zipf_hypergraph(0, 200_000, 400_000, size_hi=200, vertex_weight_hi=3)
+    c = hg.vertex_weights.astype(np.int64)
+    L = balance_limit(c.sum())
+    _say("zipf 200k with bulk piercing")
+    with hf.FlowProblem.from_hypergraph(hg) as p:
+        res, x, trace = p.flowcutter(c, L, L, max_iterations=100000, bulk_percent=55)
+    x = x.astype(bool)
+    _say(f"status {res['status']} after {res['iterations']} iterations, F {res['flow']}")
+    assert res["status"] == "balanced"
+    assert oracle_mod.cut_weight(hg, x) == res["flow"]
+    assert int(c[x].sum()) <= L and int(c[~x].sum()) <= L
+    assert max(res["counts"]) > 1
 
 
 def test_flowcutter_tiny_vs_oracle(hf, oracle_mod):
