@@ -96,7 +96,11 @@ typedef struct {
   int32_t bfs_arc_parallel;   /* 1 = BFS levels split work per arc (prefix sum
                                  over the level's arc counts) instead of per
                                  node; default 0                             */
-  int32_t reserved[5];
+  int32_t pull_min;           /* reverse-BFS levels with at least this many
+                                 nodes run bottom-up: every unlabelled node
+                                 looks for a residual arc into the level
+                                 (stops at the first); 0 = never            */
+  int32_t reserved[4];
 } fp_options;
 
 /* Counters of the last solve (cumulative over warm-started solves). */

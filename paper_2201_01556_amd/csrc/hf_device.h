@@ -1169,6 +1169,56 @@ __device__ void phase_bfs_fwd_lb(const Dev& g, int level, int ep, int tile0, int
                 narcs);
 }
 
+// Bottom-up (pull) level, thread per node in id order: every unlabelled
+// node scans its residual out-arcs of the capped network and takes label
+// level+1 at the first arc into the level (only its own thread writes it):
+//   vertex u:  u -> e_in if r_in > 0, u -> e_out if flow(e_out, u) > 0
+//   e_in:      e_in -> e_out if fb < w, e_in -> u if flow(u, e_in) > 0
+//   e_out:     e_out -> e_in if fb > 0, e_out -> u always
+// The labels of the next level are then collected by the sweep.
+__device__ void phase_bfs_rev_pull(const Dev& g, int level, int t0, int tstride, int kc) {
+  // ring slot that nobody reads this level: the count of level+2
+  if (t0 < kNL) g.ctl->bcnt[(level + 2) % 3][t0] = 0;
+  const int lvl = level + 1;
+  uint32_t nbytes = 0, narcs = 0;
+  for (int v = t0; v < g.N; v += tstride) {
+    if (seen_bit(g, v) || (v >= g.V && v < g.NB)) continue;
+    if (g.d[v] != g.N) continue;
+    bool hit = false;
+    if (v < g.V) {
+      const int beg = g.vtx_off[v], end = g.vtx_off[v + 1];
+      nbytes += 12;
+      for (int i = beg; i < end && !hit; ++i) {
+        const int2 ep = g.vinc[i];
+        const int2 dl = *reinterpret_cast<const int2*>(g.d + g.NB + 2 * ep.x);
+        const int2 fp = *reinterpret_cast<const int2*>(g.fpin + 2 * ep.y);
+        hit = (fp.x > 0 && dl.x == level) || (fp.y > 0 && dl.y == level);
+        nbytes += 24;
+        ++narcs;
+      }
+    } else {
+      const int e = (v - g.NB) >> 1;
+      const bool in = ((v - g.NB) & 1) == 0;
+      const uint32_t nb = net_bits(g, e);
+      nbytes += 16;
+      ++narcs;
+      hit = in ? ((nb & 1u) && g.d[v + 1] == level) : ((nb & 4u) && g.d[v - 1] == level);
+      const int beg = g.net_off[e], end = g.net_off[e + 1];
+      for (int p = beg; p < end && !hit; ++p) {
+        if (in && !pin_flow_in(g, p)) continue;
+        hit = g.d[g.pin_v[p]] == level;
+        nbytes += 8;
+        ++narcs;
+      }
+    }
+    if (hit) {
+      g.d[v] = lvl;
+      set_seen(g, v);
+    }
+  }
+  block_add_u64(&g.ctl->bytes[kc], nbytes, &g.ctl->items[kc], narcs);
+}
+
 template <int G>
 __device__ void phase_bfs_rev(const Dev& g, int level, int tile0, int tstride, int kc,
                               lds_int* lds) {

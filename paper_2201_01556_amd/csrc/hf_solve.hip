@@ -51,19 +51,25 @@ __global__ void __launch_bounds__(kBlock) k_gr_reset(Dev g) {
 // the same count, so they agree on the mode.
 template <int G>
 __global__ void __launch_bounds__(kBlock) HF_TWO_WORKGROUPS_PER_CU
-k_bfs_rev(Dev g, int level, int big_min) {
+k_bfs_rev(Dev g, int level, int big_min, int pull_min) {
   HF_QUEUE_LDS;
   const int c3 = level % 3;
   const int nf = count_all(g.ctl->bcnt[c3]);
-  if (nf >= big_min) phase_bfs_rev_expand<G>(g, level, blockIdx.x, gridDim.x, KC_BFS_REV, lds);
+  if (nf >= pull_min)
+    phase_bfs_rev_pull(g, level, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x,
+                       KC_BFS_REV);
+  else if (nf >= big_min)
+    phase_bfs_rev_expand<G>(g, level, blockIdx.x, gridDim.x, KC_BFS_REV, lds);
   else phase_bfs_rev<G>(g, level, blockIdx.x, gridDim.x, KC_BFS_REV, lds);
 }
 
-__global__ void __launch_bounds__(kBlock) k_bfs_collect(Dev g, int level, int big_min) {
+// Expanded and pulled levels list their new nodes by a sweep over the labels.
+__global__ void __launch_bounds__(kBlock) k_bfs_collect(Dev g, int level, int big_min,
+                                                        int pull_min) {
   HF_QUEUE_LDS;
   const int c3 = level % 3;
   const int nf = count_all(g.ctl->bcnt[c3]);
-  if (nf >= big_min) phase_bfs_collect(g, level, blockIdx.x, gridDim.x, lds);
+  if (nf >= min(big_min, pull_min)) phase_bfs_collect(g, level, blockIdx.x, gridDim.x, lds);
 }
 
 __global__ void __launch_bounds__(kBlock) k_gather(Dev g, int epoch) {
@@ -338,6 +344,11 @@ static fp_status run_bfs(fp_problem* pb, hipStream_t s, int ep, int mode, int* l
     const int c3 = level % 3;
     const long long nf = host_count(pb->ctl_h->bcnt[c3]);
     if (nf == 0) break;
+    // a level holds distinct nodes and a BFS has at most N levels
+    if (nf > g.N || level > g.N + 16) {
+      set_error("internal check: BFS level %d holds %lld nodes (N = %d)", level, nf, g.N);
+      return FP_ERR_DEVICE;
+    }
     if (nf <= cap && !pb->opt.debug_checks) {
       {
         Launch L(pb, s, mode == 0 ? KK_BFS_REV_LOOP : KK_BFS_FWD_LOOP);
@@ -349,14 +360,15 @@ static fp_status run_bfs(fp_problem* pb, hipStream_t s, int ep, int mode, int* l
     } else {
       const int steps = 8;
       const int big_min = pb->opt.bottom_up_min > 0 ? pb->opt.bottom_up_min : (1 << 30);
+      const int pull_min = pb->opt.pull_min > 0 ? pb->opt.pull_min : (1 << 30);
       for (int i = 0; i < steps; ++i) {
         if (mode == 0) {
           {
             Launch L(pb, s, KK_BFS_REV);
-            k_bfs_rev<G><<<kMaxFrontierBlocks, kBlock, 0, s>>>(g, level + i, big_min);
+            k_bfs_rev<G><<<kMaxFrontierBlocks, kBlock, 0, s>>>(g, level + i, big_min, pull_min);
           }
           Launch L(pb, s, KK_BFS_COLLECT);
-          k_bfs_collect<<<sweep_blocks(g.N), kBlock, 0, s>>>(g, level + i, big_min);
+          k_bfs_collect<<<sweep_blocks(g.N), kBlock, 0, s>>>(g, level + i, big_min, pull_min);
         } else if (mode == 1) {
           Launch L(pb, s, KK_BFS_FWD);
           k_bfs_fwd<G><<<kMaxFrontierBlocks, kBlock, 0, s>>>(g, level + i, ep);

@@ -57,7 +57,8 @@ class Options(ctypes.Structure):
         ("stale_rounds", ctypes.c_int32),
         ("bottom_up_min", ctypes.c_int32),
         ("bfs_arc_parallel", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("pull_min", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 

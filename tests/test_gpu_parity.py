@@ -108,7 +108,8 @@ def test_debug_invariants_every_round(hf, oracle_mod):
     dict(tail_threshold=1 << 30), dict(relabel_factor_x16=1), dict(relabel_factor_x16=256),
     dict(big_degree=2), dict(big_degree=100000), dict(bfs_arc_parallel=1),
     dict(bottom_up_min=-1), dict(bottom_up_min=1), dict(gr_interval=-1, stale_rounds=-1),
-    dict(gr_interval=1),
+    dict(gr_interval=1), dict(pull_min=1), dict(pull_min=1, tail_threshold=1),
+    dict(pull_min=5000),
 ], ids=str)
 def test_schedule_invariance(hf, oracle_mod, opts):
     """Every tuning knob changes only the schedule, never the result."""
@@ -120,13 +121,16 @@ def test_schedule_invariance(hf, oracle_mod, opts):
         assert_same(hg, r, F, vs, ns, str(opts))
 
 
-def test_labels_and_preflow_certificate(hf, oracle_mod):
+@pytest.mark.parametrize("opts", [dict(), dict(pull_min=1, tail_threshold=1),
+                                  dict(bottom_up_min=1, tail_threshold=1)], ids=str)
+def test_labels_and_preflow_certificate(hf, oracle_mod, opts):
     """After the solve the labels are exact residual distances of the final
     state (the terminating global relabel), the state is a feasible preflow
-    of the capped network, and the cut weight equals the flow value."""
+    of the capped network, and the cut weight equals the flow value; with
+    every multi-kernel BFS level pulled bottom-up or expanded as well."""
     hg = inputs.zipf_hypergraph(6, num_vertices=20000, num_nets=40000, size_hi=200)
-    _say("labels / certificate")
-    with hf.FlowProblem.from_hypergraph(hg) as p:
+    _say(f"labels / certificate {opts}")
+    with hf.FlowProblem.from_hypergraph(hg, **opts) as p:
         F = p.solve()
         vs, ns = p.source_side()
         s = p.export_state(hg.num_pins)
