@@ -104,18 +104,22 @@ __global__ void k_incidences(Dev g, const int32_t* keys, const int32_t* slots) {
   if (err) atomicOr(&g.ctl->err, err);
 }
 
-// bit v of the bitmap: node v has more than big_deg arcs (vertex: incident
-// nets; net node: pins plus the bridge); padding nodes are never big
-__global__ void k_bigbits(Dev g, uint32_t* bits) {
+// bit v of the bitmaps: node v has more than big_deg (kHugeDeg) arcs
+// (vertex: incident nets; net node: pins plus the bridge); padding nodes are
+// never big
+__global__ void k_bigbits(Dev g, uint32_t* bits, uint32_t* huge) {
   const int words = (g.N + 31) >> 5;
   for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < words; w += gridDim.x * blockDim.x) {
-    uint32_t m = 0;
+    uint32_t m = 0, h = 0;
     for (int b = 0; b < 32; ++b) {
       const int v = (w << 5) + b;
       if (v >= g.N || (v >= g.V && v < g.NB)) continue;
-      if (deg_of(g, v) > g.big_deg) m |= 1u << b;
+      const int d = deg_of(g, v);
+      if (d > g.big_deg) m |= 1u << b;
+      if (d > kHugeDeg) h |= 1u << b;
     }
     bits[w] = m;
+    huge[w] = h;
   }
 }
 
@@ -216,6 +220,7 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
   add(N * 4ull);              // dx[0]
   add(N * 4ull);              // dx[1]
   add(((N + 31) / 32) * 4ull); // big-node bitmap
+  add(((N + 31) / 32) * 4ull); // huge-node bitmap
   add(((N + 31) / 32) * 4ull); // labelled hint bitmap
   add(((P + 31) / 32) * 4ull); // residual bits of the pin arcs (global relabel)
   add(((E + 7) / 8) * 4ull);   // residual bits of the nets (global relabel)
@@ -263,6 +268,8 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
   g.dx[1] = c.take<int32_t>(N);
   uint32_t* bigbits = c.take<uint32_t>((N + 31) / 32);
   g.bigbits = bigbits;
+  uint32_t* hugebits = c.take<uint32_t>((N + 31) / 32);
+  g.hugebits = hugebits;
   g.seen = c.take<uint32_t>((N + 31) / 32);
   g.pinres = c.take<uint32_t>((P + 31) / 32);
   g.netres = c.take<uint32_t>((E + 7) / 8);
@@ -344,7 +351,7 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
   }
   k_vtx_offsets<<<grid_for((long long)P + 1), 256, 0, s>>>(keys, P, V, vtx_off);
   if (P) k_incidences<<<grid_for(P), 256, 0, s>>>(g, keys, slots);
-  k_bigbits<<<grid_for((N + 31) / 32), 256, 0, s>>>(g, bigbits);
+  k_bigbits<<<grid_for((N + 31) / 32), 256, 0, s>>>(g, bigbits, hugebits);
   he = hipMemcpyAsync(&err, &g.ctl->err, 4, hipMemcpyDeviceToHost, s);
   if (he == hipSuccess) he = hipStreamSynchronize(s);
   if (he == hipSuccess) he = hipGetLastError();

@@ -54,6 +54,9 @@ namespace hf {
 
 constexpr int kWave = 64;
 constexpr int kInf = 0x7fffffff;
+// Nodes with more arcs than this are scanned by a whole workgroup in the
+// reverse BFS (a wave alone would take thousands of steps).
+constexpr int kHugeDeg = 2048;
 
 // error bits reported through Ctl::err
 enum : int32_t {
@@ -124,6 +127,7 @@ struct Dev {
   int32_t* cand;           // N   relabel candidate of a node left with excess, -1 = none
   int32_t* stamp;          // N
   const uint32_t* bigbits; // ceil(N/32) words: bit v set when node v has more than big_deg arcs
+  const uint32_t* hugebits;  // ceil(N/32) words: bit v set when node v has more than kHugeDeg arcs
   uint32_t* seen;          // ceil(N/32) words: reverse BFS hint "node has a label" (see label_rev)
   uint32_t* pinres;        // ceil(P/32) words: bit of pin slot p = flow(u, e_in) > 0
   uint32_t* netres;        // ceil(E/8) words, 4 bits per net: bit0 = e_in -> e_out
@@ -320,6 +324,9 @@ __device__ __forceinline__ void bq_push1(const BlockQ& q, int k, int v, bool pre
 
 __device__ __forceinline__ bool is_big(const Dev& g, int v) {
   return (g.bigbits[v >> 5] >> (v & 31)) & 1u;
+}
+__device__ __forceinline__ bool is_huge(const Dev& g, int v) {
+  return (g.hugebits[v >> 5] >> (v & 31)) & 1u;
 }
 
 // list of a node: big nodes together, small ones by kind
@@ -838,10 +845,12 @@ __device__ __forceinline__ bool label_rev(const Dev& g, int v, int lvl) {
   return true;
 }
 
-// Node-grouped reverse BFS: G lanes per small node, a wave per big node.
-template <int G, bool kClaim>
-__device__ void bfs_rev_node(const Dev& g, const BlockQ& q, int x, bool has, int gl, int lvl,
-                             uint32_t& nbytes) {
+// Node-grouped reverse BFS: a group of `stride` lanes scans node x (G lanes
+// per small node, a wave per big node, the workgroup per huge node); gl is
+// the lane's index in the group.
+template <bool kClaim>
+__device__ __forceinline__ void bfs_rev_node(const Dev& g, const BlockQ& q, int x, bool has,
+                                             int gl, int stride, int lvl, uint32_t& nbytes) {
   const bool isv = has && x < g.V;
   const bool isnet = has && x >= g.NB;
   if (!has || isv) {
@@ -850,7 +859,7 @@ __device__ void bfs_rev_node(const Dev& g, const BlockQ& q, int x, bool has, int
       beg = g.vtx_off[x];
       end = g.vtx_off[x + 1];
     }
-    for (int base = beg; base < end; base += G) {
+    for (int base = beg; base < end; base += stride) {
       const int i = base + gl;
       const bool valid = i < end;
       bool vin = false, vout = false;
@@ -885,7 +894,7 @@ __device__ void bfs_rev_node(const Dev& g, const BlockQ& q, int x, bool has, int
       else vb = (nb & 1u) && label_rev<kClaim>(g, x - 1, lvl);     // e_in -> e_out residual w - fb
     }
     if (kClaim) qpush(g, q, in ? x + 1 : x - 1, vb);
-    for (int base = beg; base < end; base += G) {
+    for (int base = beg; base < end; base += stride) {
       const int i = base + gl;
       const bool valid = i < end;
       bool vu = false;
@@ -916,22 +925,37 @@ __device__ void phase_bfs_rev_node(const Dev& g, int level, int tile0, int tstri
   const int ntiles = (total + wpb - 1) / wpb;
   const int lane = lane_id();
   uint32_t nbytes = 0, nitems = 0;
-  for (int tile = tile0; tile < ntiles; tile += tstride) {
-    const int it = tile * wpb + wid;
-    if (it < total) {
-      const int k = its.list_of_item(it);
-      if (k < kBigList) {
-        const int idx = (it - its.start[k]) * NPW + lane / G;
-        const bool has = idx < its.n[k];
-        const int v = has ? g.list[cp][k][idx] : 0;
-        nitems += has && (lane % G) == 0;
-        bfs_rev_node<G, kClaim>(g, q, v, has, lane % G, level + 1, nbytes);
-      } else {
-        const int v = g.list[cp][kBigList][it - its.start[kBigList]];
-        nitems += lane == 0;
-        bfs_rev_node<kWave, kClaim>(g, q, v, true, lane, level + 1, nbytes);
+  // tiles of wave items, then one tile per big-list node in which only a huge
+  // node (more arcs than a wave should scan alone, such as a contracted
+  // terminal) is scanned, by the whole workgroup; a wave item skips it
+  const int nbig = its.n[kBigList];
+  for (int tile = tile0; tile < ntiles + nbig; tile += tstride) {
+    int v = 0, gl = 0, stride = G;
+    bool has = false;
+    if (tile < ntiles) {
+      const int it = tile * wpb + wid;
+      if (it < total) {
+        const int k = its.list_of_item(it);
+        if (k < kBigList) {
+          const int idx = (it - its.start[k]) * NPW + lane / G;
+          has = idx < its.n[k];
+          v = has ? g.list[cp][k][idx] : 0;
+          gl = lane % G;
+        } else {
+          v = g.list[cp][kBigList][it - its.start[kBigList]];
+          has = !is_huge(g, v);
+          gl = lane;
+          stride = kWave;
+        }
       }
+    } else {
+      v = g.list[cp][kBigList][tile - ntiles];
+      has = is_huge(g, v);  // block-uniform
+      gl = threadIdx.x;
+      stride = blockDim.x;
     }
+    nitems += has && gl == 0;
+    bfs_rev_node<kClaim>(g, q, v, has, gl, stride, level + 1, nbytes);
     if (kClaim) bq_tile_end(q, q.cap / 2);
   }
   if (kClaim) bq_flush(q);
