@@ -217,6 +217,9 @@ def main():
             "global_relabels": st["global_relabels"], "host_syncs": st["host_syncs"],
             "profiled_steps": profile,
         },
+        # whole step: algorithmic bytes of all counted kernels over the step time
+        "step_alg_bytes": st["alg_bytes"],
+        "step_alg_GBps": round(st["alg_bytes"] / (ms_per_step / 1e3) / 1e9, 3),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity_vs_oracle": parity,

@@ -113,7 +113,11 @@ typedef struct {
   int64_t restarts;         /* termination checks that found active nodes    */
   int64_t host_syncs;       /* host round trips                              */
   int64_t flow_value;       /* current flow value                            */
-  int64_t reserved[8];
+  int64_t alg_bytes;        /* algorithmic bytes moved by the discharge,
+                               relabel and BFS kernels since the handle was
+                               created (device counters: a node's own fields
+                               once, an arc's fields per scanned arc)        */
+  int64_t reserved[7];
 } fp_stats;
 
 /*

@@ -393,6 +393,9 @@ fp_status flow_problem_stats(const fp_problem* problem, fp_stats* out) {
     return FP_ERR_INVALID;
   }
   *out = problem->st;
+  out->alg_bytes = 0;
+  if (problem->ctl_h)
+    for (int c = 0; c < KC_N; ++c) out->alg_bytes += (int64_t)problem->ctl_h->bytes[c];
   return FP_OK;
 }
 

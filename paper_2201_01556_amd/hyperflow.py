@@ -72,7 +72,8 @@ class Stats(ctypes.Structure):
         ("restarts", ctypes.c_int64),
         ("host_syncs", ctypes.c_int64),
         ("flow_value", ctypes.c_int64),
-        ("reserved", ctypes.c_int64 * 8),
+        ("alg_bytes", ctypes.c_int64),
+        ("reserved", ctypes.c_int64 * 7),
     ]
 
 
