@@ -9,6 +9,7 @@
 
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/iterator/counting_iterator.hpp>
+#include <rocprim/iterator/transform_iterator.hpp>
 
 #include "hf_host.h"
 
@@ -86,18 +87,25 @@ __global__ void k_vtx_offsets(const int32_t* keys, int P, int V, int32_t* vtx_of
   }
 }
 
-// Incidences in sorted order: vinc[i] = {net, slot} of the i-th sorted pin;
-// a vertex's pins are in slot order, hence grouped by net, so a vertex twice
-// in one net shows as two neighbours with the same net.  Nets learn whether
-// they hold a source or a sink pin.
-__global__ void k_incidences(Dev g, const int32_t* keys, const int32_t* slots) {
+// Sort value of pin slot p: the incidence {net, slot} as one 64-bit word
+// (little-endian int2), read in slot order.
+struct IncidenceOfSlot {
+  const int32_t* pin_net;
+  __host__ __device__ unsigned long long operator()(int32_t p) const {
+    return ((unsigned long long)(uint32_t)p << 32) | (uint32_t)pin_net[p];
+  }
+};
+
+// Checks over the incidences in sorted order (vinc[i] = {net, slot} of the
+// i-th pin sorted by vertex): a vertex's pins are in slot order, hence
+// grouped by net, so a vertex twice in one net shows as two neighbours with
+// the same net.  Nets learn whether they hold a source or a sink pin.
+__global__ void k_incidences(Dev g, const int32_t* keys) {
   int err = 0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g.P; i += gridDim.x * blockDim.x) {
-    const int p = slots[i];
-    const int e = g.pin_net[p];
+    const int e = g.vinc[i].x;
     const int u = keys[i];
-    const_cast<int2*>(g.vinc)[i] = make_int2(e, p);
-    if (i > 0 && keys[i - 1] == u && g.pin_net[slots[i - 1]] == e) err |= ERR_BUILD_DUP;
+    if (i > 0 && keys[i - 1] == u && g.vinc[i - 1].x == e) err |= ERR_BUILD_DUP;
     const int r = g.role[u];
     if (r) atomicOr(&g.nflag[e], r);
   }
@@ -331,26 +339,29 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
     return FP_ERR_OVERFLOW;
   }
 
-  // vertex incidence CSR: stable radix sort of (vertex, slot) pairs by
-  // vertex; the pin-flow array is scratch until the first solve initialises it
+  // vertex incidence CSR: stable radix sort of the pins by vertex carrying
+  // their {net, slot} incidence straight into vinc; the pin-flow array is
+  // scratch for the sorted vertices until the first solve initialises it
   int32_t* keys = g.fpin;
-  int32_t* slots = g.fpin + P;
   if (P) {
+    k_pin_nets<<<grid_for(P), 256, 0, s>>>(g);
     unsigned bits = 1;
     while (bits < 31 && (1ll << bits) < (long long)V) ++bits;
-    const rocprim::counting_iterator<int32_t> slot0(0);
+    const auto inc = rocprim::make_transform_iterator(rocprim::counting_iterator<int32_t>(0),
+                                                      IncidenceOfSlot{g.pin_net});
+    unsigned long long* vinc_out = reinterpret_cast<unsigned long long*>(vinc);
     size_t tb = 0;
-    he = rocprim::radix_sort_pairs(nullptr, tb, pin_v, keys, slot0, slots, (size_t)P, 0u, bits, s);
+    he = rocprim::radix_sort_pairs(nullptr, tb, pin_v, keys, inc, vinc_out, (size_t)P, 0u, bits,
+                                   s);
     void* tmp = nullptr;
     if (he == hipSuccess) he = hipMallocAsync(&tmp, std::max<size_t>(tb, 1), s);
     if (he == hipSuccess)
-      he = rocprim::radix_sort_pairs(tmp, tb, pin_v, keys, slot0, slots, (size_t)P, 0u, bits, s);
+      he = rocprim::radix_sort_pairs(tmp, tb, pin_v, keys, inc, vinc_out, (size_t)P, 0u, bits, s);
     if (tmp) (void)hipFreeAsync(tmp, s);
     if (he != hipSuccess) return hip_fail(he, "sorting the pins by vertex");
-    k_pin_nets<<<grid_for(P), 256, 0, s>>>(g);
   }
   k_vtx_offsets<<<grid_for((long long)P + 1), 256, 0, s>>>(keys, P, V, vtx_off);
-  if (P) k_incidences<<<grid_for(P), 256, 0, s>>>(g, keys, slots);
+  if (P) k_incidences<<<grid_for(P), 256, 0, s>>>(g, keys);
   k_bigbits<<<grid_for((N + 31) / 32), 256, 0, s>>>(g, bigbits, hugebits);
   he = hipMemcpyAsync(&err, &g.ctl->err, 4, hipMemcpyDeviceToHost, s);
   if (he == hipSuccess) he = hipStreamSynchronize(s);

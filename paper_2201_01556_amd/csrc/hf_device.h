@@ -1313,10 +1313,8 @@ __device__ void phase_init(const Dev& g, int t0, int tstride) {
   }
   const int n = max(g.P, g.N);
   for (int i = t0; i < n; i += tstride) {
-    if (i < g.P) {
-      const int2 ep = g.vinc[i];
-      g.fpin[2 * ep.y] = g.w[ep.x];
-      g.fpin[2 * ep.y + 1] = 0;
+    if (i < g.P) {  // slot i: r_in = w(e), no flow (slots of a net are contiguous)
+      *reinterpret_cast<int2*>(g.fpin + 2 * i) = make_int2(g.w[g.pin_net[i]], 0);
     }
     if (i < g.N) {
       g.stamp[i] = -1;
