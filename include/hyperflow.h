@@ -292,6 +292,15 @@ fp_status flow_batch_get_config(const fp_batch *batch, fp_batch_config *out);
 void flow_batch_destroy(fp_batch *batch);
 
 /*
+ * flow_release_cached_memory: free the device pools and pinned control
+ * blocks that destroyed handles left for reuse.  Handles keep working; the
+ * library keeps at most 4 GiB of released pools per process and reuses a
+ * block for a new handle it covers without wasting more than half of it.
+ * Waits for the current device to be idle.
+ */
+void flow_release_cached_memory(void);
+
+/*
  * flow_problem_reset: forget the flow; the next solve starts from the zero
  * flow with the handle's current terminals.  Used to time or re-tune solves
  * of the same problem.

@@ -435,5 +435,13 @@ void flow_problem_destroy(fp_problem* problem) {
   delete problem;
 }
 
+void flow_release_cached_memory(void) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceSynchronize();
+  release_cached_memory();
+  (void)hipSetDevice(dev);
+}
+
 }  // extern "C"
 #pragma GCC visibility pop

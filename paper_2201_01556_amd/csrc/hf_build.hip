@@ -11,9 +11,112 @@
 #include <rocprim/iterator/counting_iterator.hpp>
 #include <rocprim/iterator/transform_iterator.hpp>
 
+#include <mutex>
+#include <vector>
+
 #include "hf_host.h"
 
 namespace hf {
+
+// ---------------------------------------------------------------------------
+// Reuse of released device pools and pinned control blocks.  A handle's pool
+// is one hipMalloc (hundreds of MB for large problems) and its control block
+// one pinned host allocation; creating and destroying handles in a loop
+// would otherwise pay both every time.  Released blocks are kept per device
+// (at most kCachedPoolBytes of pools and kCachedCtl control blocks) and
+// reused for a request they cover without wasting more than half of them.
+// Handles are destroyed only after their device work has finished, so a
+// cached block is idle.
+// ---------------------------------------------------------------------------
+
+constexpr size_t kCachedPoolBytes = 4ull << 30;
+constexpr size_t kCachedCtl = 256;
+
+struct CachedPool {
+  int device;
+  void* ptr;
+  size_t bytes;
+};
+
+static std::mutex g_cache_mu;
+static std::vector<CachedPool> g_pools;
+static std::vector<void*> g_ctls;
+
+static hipError_t pool_acquire(int device, size_t bytes, void** out, size_t* got) {
+  {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    int best = -1;
+    for (int i = 0; i < (int)g_pools.size(); ++i) {
+      const CachedPool& c = g_pools[i];
+      if (c.device != device || c.bytes < bytes || c.bytes > 2 * bytes) continue;
+      if (best < 0 || c.bytes < g_pools[best].bytes) best = i;
+    }
+    if (best >= 0) {
+      *out = g_pools[best].ptr;
+      *got = g_pools[best].bytes;
+      g_pools.erase(g_pools.begin() + best);
+      return hipSuccess;
+    }
+  }
+  *got = bytes;
+  return hipMalloc(out, bytes);
+}
+
+static void pool_release(int device, void* ptr, size_t bytes) {
+  if (!ptr) return;
+  std::vector<void*> drop;
+  {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    g_pools.push_back(CachedPool{device, ptr, bytes});
+    size_t total = 0;
+    for (const CachedPool& c : g_pools) total += c.bytes;
+    while (total > kCachedPoolBytes && !g_pools.empty()) {  // oldest first
+      total -= g_pools.front().bytes;
+      drop.push_back(g_pools.front().ptr);
+      g_pools.erase(g_pools.begin());
+    }
+  }
+  for (void* p : drop) (void)hipFree(p);
+}
+
+static hipError_t ctl_acquire(Ctl** out) {
+  {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    if (!g_ctls.empty()) {
+      *out = static_cast<Ctl*>(g_ctls.back());
+      g_ctls.pop_back();
+      return hipSuccess;
+    }
+  }
+  return hipHostMalloc((void**)out, sizeof(Ctl), hipHostMallocDefault);
+}
+
+static void ctl_release(Ctl* c) {
+  if (!c) return;
+  {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    if (g_ctls.size() < kCachedCtl) {
+      g_ctls.push_back(c);
+      return;
+    }
+  }
+  (void)hipHostFree(c);
+}
+
+void release_cached_memory() {
+  std::vector<CachedPool> pools;
+  std::vector<void*> ctls;
+  {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    pools.swap(g_pools);
+    ctls.swap(g_ctls);
+  }
+  for (const CachedPool& c : pools) {
+    (void)hipSetDevice(c.device);
+    (void)hipFree(c.ptr);
+  }
+  for (void* c : ctls) (void)hipHostFree(c);
+}
 
 // ---------------------------------------------------------------------------
 // validation / layout kernels (thread per element, grid-stride)
@@ -234,7 +337,7 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
   add(((E + 7) / 8) * 4ull);   // residual bits of the nets (global relabel)
   add(sizeof(Ctl));           // ctl
   add(64);                    // scratch for the weight sum
-  he = hipMalloc(&pb->pool, bytes);
+  he = pool_acquire(pb->device, bytes, &pb->pool, &pb->pool_bytes);
   if (he != hipSuccess) {
     pb->pool = nullptr;
     set_error("hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(he));
@@ -371,7 +474,7 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
     set_error("a vertex appears twice in one net");
     return FP_ERR_INVALID;
   }
-  he = hipHostMalloc((void**)&pb->ctl_h, sizeof(Ctl), hipHostMallocDefault);
+  he = ctl_acquire(&pb->ctl_h);
   if (he != hipSuccess) {
     pb->ctl_h = nullptr;
     return hip_fail(he, "allocating the pinned control block");
@@ -430,9 +533,9 @@ void release_problem(fp_problem* pb) {
     hipEventDestroy(t.b);
   }
   for (auto e : pb->free_events) hipEventDestroy(e);
-  if (pb->pool) hipFree(pb->pool);
+  pool_release(pb->device, pb->pool, pb->pool_bytes);
   if (pb->cw) hipFree(pb->cw);
-  if (pb->ctl_h) hipHostFree(pb->ctl_h);
+  ctl_release(pb->ctl_h);
   pb->pool = nullptr;
   pb->cw = nullptr;
   pb->ctl_h = nullptr;

@@ -48,6 +48,7 @@ struct fp_problem {
   fp_options opt{};
   hf::Dev dev{};
   void* pool = nullptr;
+  size_t pool_bytes = 0;     // capacity of the pool (a reused block may be larger)
   hf::Ctl* ctl_h = nullptr;  // pinned host mirror of the control block
   int32_t epoch = 1;         // stamp value of the next round / BFS
   bool inited = false;
@@ -111,6 +112,8 @@ fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src,
 fp_status export_state(fp_problem* pb, hipStream_t s, int32_t* f_in, int32_t* f_out,
                        int32_t* f_b, int32_t* labels, int32_t* excess);
 void release_problem(fp_problem* pb);
+// free the device pools and pinned control blocks kept for reuse
+void release_cached_memory();
 
 // profiling helpers
 void prof_begin(fp_problem* pb, int kind, hipStream_t s, Timer* t);

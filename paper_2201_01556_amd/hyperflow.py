@@ -145,6 +145,7 @@ EXPORTED = [
     "scorer_get_params",
     "scorer_set_params",
     "scorer_destroy",
+    "flow_release_cached_memory",
     "fp_last_error",
 ]
 
