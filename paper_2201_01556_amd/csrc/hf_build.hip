@@ -165,16 +165,12 @@ __global__ void k_role_check(Dev g) {
   if (err) atomicOr(&g.ctl->err, err);
 }
 
-// Net of every pin slot: the last e with net_off[e] <= p.
+// Net of every pin slot: thread per net over its slot range (offsets were
+// validated first).
 __global__ void k_pin_nets(Dev g) {
-  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < g.P; p += gridDim.x * blockDim.x) {
-    int lo = 0, hi = g.E;  // answer in [0, E)
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (g.net_off[mid] <= p) lo = mid;
-      else hi = mid;
-    }
-    const_cast<int32_t*>(g.pin_net)[p] = lo;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < g.E; e += gridDim.x * blockDim.x) {
+    const int end = g.net_off[e + 1];
+    for (int p = g.net_off[e]; p < end; ++p) const_cast<int32_t*>(g.pin_net)[p] = e;
   }
 }
 
@@ -447,7 +443,7 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
   // scratch for the sorted vertices until the first solve initialises it
   int32_t* keys = g.fpin;
   if (P) {
-    k_pin_nets<<<grid_for(P), 256, 0, s>>>(g);
+    k_pin_nets<<<grid_for(E), 256, 0, s>>>(g);
     unsigned bits = 1;
     while (bits < 31 && (1ll << bits) < (long long)V) ++bits;
     const auto inc = rocprim::make_transform_iterator(rocprim::counting_iterator<int32_t>(0),
