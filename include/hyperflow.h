@@ -217,7 +217,9 @@ fp_status flow_batch_solve(fp_problem *const *problems, int32_t count,
  *                kernels: the union's minimal minimum cut is the union of
  *                the problems' minimal minimum cuts, and a problem's flow
  *                value is the weight of its nets that cut cuts (checked
- *                against the union's flow value).  Each run starts from the
+ *                against the union's flow value).  Kept problems that do
+ *                not fit one union (union_pins, 31-bit ids) go to several,
+ *                in index order.  Each run starts from the
  *                zero flow of every problem's current terminals (same
  *                results as a warm start) and leaves the problems' own
  *                handles untouched.
@@ -240,7 +242,10 @@ typedef struct {
   int32_t streams;       /* concurrent workers (streams), 1..64; 0 = 4      */
   int32_t schedule;      /* 0 = concurrent workers; 1 = union: the kept
                             problems solved as one network (see below)     */
-  int32_t reserved[2];
+  int32_t union_pins;    /* union schedule: at most this many pins per
+                            union (bounds its device memory); 0 = as many
+                            as 31-bit ids allow                            */
+  int32_t reserved[1];
 } fp_batch_config;
 
 /*
@@ -266,9 +271,8 @@ fp_status flow_batch_create(fp_problem *const *problems, int32_t count,
  * fresh or reset one starts from zero, and every solved handle behaves as
  * after maxflow_solve; union schedule: see above), and with with_cut = 1
  * also write its minimal source side.  flow_values as in flow_batch_solve.
- * Skipped problems are not touched.  Errors as flow_batch_solve
- * (FP_ERR_OVERFLOW when the union exceeds 31-bit ids); FP_ERR_INVALID when
- * with_cut = 1 but the plan has no vertex_sides.
+ * Skipped problems are not touched.  Errors as flow_batch_solve;
+ * FP_ERR_INVALID when with_cut = 1 but the plan has no vertex_sides.
  */
 fp_status flow_batch_run(fp_batch *batch, const uint8_t *skip, int32_t with_cut,
                          void *hip_stream, int64_t *flow_values);

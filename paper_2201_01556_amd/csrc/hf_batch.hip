@@ -323,7 +323,7 @@ static bool batch_config_valid(const fp_batch_config& c) {
   return (c.group_lanes == 4 || c.group_lanes == 8 || c.group_lanes == 16) &&
          (c.block_threads == 256 || c.block_threads == 1024) && c.gr_interval >= -1 &&
          c.workgroups >= 0 && c.streams >= 1 && c.streams <= 64 &&
-         (c.schedule == 0 || c.schedule == 1);
+         (c.schedule == 0 || c.schedule == 1) && c.union_pins >= 0;
 }
 
 bool batch_config_ok(const fp_batch_config* c) {
@@ -709,36 +709,21 @@ static int union_grid(long long n) {
 // touched: every run starts from the zero flow of each problem's current
 // terminals, which gives the same flow values and minimal source sides as a
 // warm start would.
-static fp_status batch_union(fp_batch* b, const uint8_t* skip, int32_t with_cut, hipStream_t s,
-                             int64_t* flows, float* ms) {
-  const auto t0 = std::chrono::steady_clock::now();
-  std::vector<int32_t> ids;
+// One union of the problems `ids` (index order).
+static fp_status union_chunk(fp_batch* b, const std::vector<int32_t>& ids, int32_t with_cut,
+                             hipStream_t s, int64_t* flows) {
   std::vector<int32_t> voff(1, 0), eoff(1, 0), poff(1, 0);
   long long V = 0, E = 0, P = 0;
-  for (int32_t i = 0; i < b->count; ++i) {
-    if (skip && skip[i]) {
-      if (flows) flows[i] = -1;
-      continue;
-    }
+  for (int32_t i : ids) {
     const fp_problem* pb = b->pbs[i];
-    ids.push_back(i);
     V += pb->V;
     E += pb->E;
     P += pb->P;
-    if (V >= (1ll << 30) || E >= (1ll << 30) || P >= (1ll << 31) - 1) {
-      set_error("the union of the batch is too large for 31-bit ids (V=%lld E=%lld P=%lld)", V,
-                E, P);
-      return FP_ERR_OVERFLOW;
-    }
     voff.push_back((int32_t)V);
     eoff.push_back((int32_t)E);
     poff.push_back((int32_t)P);
   }
   const int32_t n = (int32_t)ids.size();
-  if (n == 0) {
-    if (ms) *ms = 0.f;
-    return FP_OK;
-  }
   // scratch: map, union inputs, terminal lists, sides, flows
   size_t off = 0;
   auto carve = [&](size_t bytes) {
@@ -859,6 +844,39 @@ static fp_status batch_union(fp_batch* b, const uint8_t* skip, int32_t with_cut,
   }
   if (flows)
     for (int32_t k = 0; k < n; ++k) flows[ids[k]] = (int64_t)fh[k];
+  return FP_OK;
+}
+
+// The kept problems in unions that fit 31-bit ids (a handle holds fewer than
+// 2^30 pins and 2^31 network nodes) and union_pins, in index order.
+static fp_status batch_union(fp_batch* b, const uint8_t* skip, int32_t with_cut, hipStream_t s,
+                             int64_t* flows, float* ms) {
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<int32_t> chunk;
+  long long V = 0, E = 0, P = 0;
+  const long long max_pins = b->cfg.union_pins > 0 ? b->cfg.union_pins : (1ll << 30) - 1;
+  for (int32_t i = 0; i <= b->count; ++i) {
+    const bool last = i == b->count;
+    if (!last && skip && skip[i]) {
+      if (flows) flows[i] = -1;
+      continue;
+    }
+    const fp_problem* pb = last ? nullptr : b->pbs[i];
+    const bool full = !last && !chunk.empty() &&
+                      (P + pb->P > max_pins ||
+                       V + pb->V + 2 + 2 * (E + pb->E) >= (1ll << 31) - 16);
+    if ((last || full) && !chunk.empty()) {
+      fp_status st = union_chunk(b, chunk, with_cut, s, flows);
+      if (st) return st;
+      chunk.clear();
+      V = E = P = 0;
+    }
+    if (last) break;
+    chunk.push_back(i);
+    V += pb->V;
+    E += pb->E;
+    P += pb->P;
+  }
   if (ms)
     *ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return FP_OK;
@@ -1020,6 +1038,7 @@ fp_status tune_batch(fp_batch* b, hipStream_t s, const char* cache_path, fp_batc
   const std::string sig = batch_signature(b);
   fp_batch_config cached{};
   if (cache_lookup(cache_path, sig, &cached)) {
+    cached.union_pins = b->cfg.union_pins;  // the caller's memory bound is not tuned
     b->cfg = cached;
     fp_status st = batch_replay(b, nullptr, 0, true, s, nullptr, nullptr);
     if (st) return st;

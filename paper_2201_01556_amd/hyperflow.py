@@ -85,7 +85,8 @@ class BatchConfig(ctypes.Structure):
         ("workgroups", ctypes.c_int32),
         ("streams", ctypes.c_int32),
         ("schedule", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("union_pins", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 1),
     ]
 
     def as_dict(self) -> dict:

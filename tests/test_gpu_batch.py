@@ -217,6 +217,24 @@ def test_batch_union_vs_oracle(hf, oracle_mod, lanes, gr):
             p.close()
 
 
+def test_batch_union_chunks(hf, oracle_mod):
+    """A bound on the pins per union splits the kept problems over several
+    unions (in index order); flows and sides are unchanged."""
+    hgs = uneven_set(16, seed0=700)
+    refs = _oracle_all(oracle_mod, hgs)
+    probs = [hf.FlowProblem.from_hypergraph(h) for h in hgs]
+    try:
+        for bound in (1, 3000, 20000):
+            _say(f"union chunks of at most {bound} pins")
+            with hf.FlowBatch(probs, with_cut=True, schedule=1, union_pins=bound) as b:
+                flows = b.run(with_cut=True)
+                assert list(flows) == [r.flow for r in refs]
+                _check_sides(b, hgs, refs, f"union_pins={bound}")
+    finally:
+        for p in probs:
+            p.close()
+
+
 def test_batch_union_block_pairs_and_pierced(hf, oracle_mod, small_pairs):
     """Union schedule on block-pair regions, then with one problem pierced:
     the union takes each problem's current terminals."""
@@ -272,6 +290,9 @@ def test_batch_errors(hf):
         assert ei.value.name == "FP_ERR_INVALID"
         with pytest.raises(hf.HyperflowError) as ei:
             hf.FlowBatch(probs, schedule=2)
+        assert ei.value.name == "FP_ERR_INVALID"
+        with pytest.raises(hf.HyperflowError) as ei:
+            hf.FlowBatch(probs, schedule=1, union_pins=-1)
         assert ei.value.name == "FP_ERR_INVALID"
         with hf.FlowBatch(probs) as b:
             with pytest.raises(hf.HyperflowError) as ei:
