@@ -332,17 +332,23 @@ static fp_status sync_ctl(fp_problem* pb, hipStream_t s, const char* what = "") 
 }
 
 template <int G>
-static fp_status run_bfs(fp_problem* pb, hipStream_t s, int ep, int mode, int* levels_out) {
-  // level 0 is already in bcnt[0]; mode 0 global relabel (ep unused),
+static fp_status run_bfs(fp_problem* pb, hipStream_t s, int ep, int mode, int* levels_out,
+                         long long level0_count = -1) {
+  // level 0 is already in bcnt[0] (level0_count nodes when the caller knows,
+  // which saves a host round trip); mode 0 global relabel (ep unused),
   // 1 source side, 2 sink side (stamps ep)
   Dev& g = pb->dev;
   const int cap = pb->opt.tail_threshold;
   int level = 0;
-  fp_status st = sync_ctl(pb, s);
-  if (st) return st;
-  for (;;) {
+  fp_status st = FP_OK;
+  if (level0_count < 0) {
+    st = sync_ctl(pb, s);
+    if (st) return st;
+  }
+  for (bool first = true;; first = false) {
     const int c3 = level % 3;
-    const long long nf = host_count(pb->ctl_h->bcnt[c3]);
+    const long long nf = first && level0_count >= 0 ? level0_count
+                                                    : host_count(pb->ctl_h->bcnt[c3]);
     if (nf == 0) break;
     // a level holds distinct nodes and a BFS has at most N levels
     if (nf > g.N || level > g.N + 16) {
@@ -701,7 +707,7 @@ static fp_status grow_side_impl(fp_problem* pb, hipStream_t s, int side, int ep,
   if (side == 0) k_cut_seed<<<sweep_blocks(g.N), kBlock, 0, s>>>(g, ep, 1);
   else k_seed_vertex<<<1, 64, 0, s>>>(g, p);
   int levels = 0;
-  fp_status st = run_bfs<G>(pb, s, ep, side == 0 ? 1 : 2, &levels);
+  fp_status st = run_bfs<G>(pb, s, ep, side == 0 ? 1 : 2, &levels, side == 0 ? -1 : 1);
   if (st) return st;
   pb->st.bfs_levels += levels;
   k_reset_bfs<<<1, 64, 0, s>>>(g);  // the caller's next sync checks the error flags
