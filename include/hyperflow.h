@@ -74,8 +74,9 @@ typedef struct {
                                  after every round (slow; test use)          */
   int32_t tail_threshold;     /* frontier size at or below which a single
                                  workgroup runs the rounds; default 256      */
-  int32_t group_lanes;        /* lanes per small frontier node: 4, 8 or 16;
-                                 default 8                                   */
+  int32_t group_lanes;        /* lanes per small frontier vertex: 4, 8 or
+                                 16 (small net nodes get half, at least 4);
+                                 default 16                                  */
   int32_t big_degree;         /* nodes with more arcs go wave-per-node;
                                  default 32                                  */
   int32_t profile;            /* 1 = time every kernel launch with HIP events,

@@ -259,7 +259,7 @@ fp_options resolve_options(const fp_options* o) {
   if (o) r = *o;
   if (r.relabel_factor_x16 <= 0) r.relabel_factor_x16 = 16;
   if (r.tail_threshold <= 0) r.tail_threshold = 256;
-  if (r.group_lanes != 4 && r.group_lanes != 8 && r.group_lanes != 16) r.group_lanes = 8;
+  if (r.group_lanes != 4 && r.group_lanes != 8 && r.group_lanes != 16) r.group_lanes = 16;
   if (r.big_degree <= 0) r.big_degree = 32;
   if (r.gr_interval == 0) r.gr_interval = 16;
   if (r.gr_interval < 0) r.gr_interval = 0;

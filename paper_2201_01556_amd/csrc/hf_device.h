@@ -400,19 +400,26 @@ struct Prefix4 {
   }
 };
 
-// Item layout of a frontier or BFS level: for each small list, groups of G
-// lanes take one node each (64/G nodes per wave item); then one big node per
-// wave item.
+// Lanes per small node: G for a vertex, half of it (at least 4) for a net
+// node, which has half as many arcs on average (nets of 3.7 pins against
+// vertices in 7.4 nets on the Zipf workloads); 16 and 8 measured best.
+template <int G>
+__host__ __device__ constexpr int lanes_of(int k) {
+  return k == 0 ? G : (G >= 8 ? G / 2 : G);
+}
+
+// Item layout of a frontier or BFS level: for each small list k, groups of
+// lanes_of<G>(k) lanes take one node each; then one big node per wave item.
 template <int G>
 struct Items {
   Quad n;
   Quad start;  // first item of each list
   int end;
   __device__ __forceinline__ explicit Items(const int32_t* cnt) {
-    constexpr int NPW = kWave / G;
+    constexpr int NV = kWave / lanes_of<G>(0), NN = kWave / lanes_of<G>(1);
     n = load_counts(cnt);
-    const int i0 = (n.v0 + NPW - 1) / NPW, i1 = (n.v1 + NPW - 1) / NPW,
-              i2 = (n.v2 + NPW - 1) / NPW;
+    const int i0 = (n.v0 + NV - 1) / NV, i1 = (n.v1 + NN - 1) / NN,
+              i2 = (n.v2 + NN - 1) / NN;
     start = Quad{0, i0, i0 + i1, i0 + i1 + i2};
     end = start.v3 + n.v3;
   }
@@ -695,7 +702,7 @@ __device__ void phase_push(const Dev& g, int epoch, int tile0, int tstride, int 
   }
   const BlockQ q = round_queue(g, ra, lds);
   const Items<G> its(g.ctl->fcnt[ra.cur3]);
-  constexpr int NPW = kWave / G;
+  constexpr int GN = lanes_of<G>(1);
   const int total = its.total();
   const int wpb = blockDim.x >> 6, wid = threadIdx.x >> 6;
   const int ntiles = (total + wpb - 1) / wpb;
@@ -708,13 +715,14 @@ __device__ void phase_push(const Dev& g, int epoch, int tile0, int tstride, int 
     if (it < total) {
       const int k = its.list_of_item(it);
       if (k < kBigList) {
-        const int idx = (it - its.start[k]) * NPW + lane / G;
+        const int gk = k == 0 ? G : GN;
+        const int idx = (it - its.start[k]) * (kWave / gk) + lane / gk;
         const bool has = idx < its.n[k];
         const int v = has ? g.list[ra.cur][k][idx] : 0;
-        nitems += has && (lane % G) == 0;
+        nitems += has && (lane % gk) == 0;
         if (k == 0) push_vertex<G>(g, ra, q, v, has, lane % G, nbytes);
-        else if (k == 1) push_ein<G>(g, ra, q, v, has, lane % G, nbytes, to_sink);
-        else push_eout<G>(g, ra, q, v, has, lane % G, nbytes, to_sink);
+        else if (k == 1) push_ein<GN>(g, ra, q, v, has, lane % GN, nbytes, to_sink);
+        else push_eout<GN>(g, ra, q, v, has, lane % GN, nbytes, to_sink);
       } else {
         const int v = g.list[ra.cur][kBigList][it - its.start[kBigList]];
         nitems += lane == 0;
@@ -919,7 +927,7 @@ __device__ void phase_bfs_rev_node(const Dev& g, int level, int tile0, int tstri
   const int cp = level & 1, np = (level + 1) & 1;
   const BlockQ q = bq_bind(lds, g.ctl->bcnt[n3], g.list[np]);
   const Items<G> its(g.ctl->bcnt[c3]);
-  constexpr int NPW = kWave / G;
+  constexpr int GN = lanes_of<G>(1);
   const int total = its.total();
   const int wpb = blockDim.x >> 6, wid = threadIdx.x >> 6;
   const int ntiles = (total + wpb - 1) / wpb;
@@ -937,10 +945,11 @@ __device__ void phase_bfs_rev_node(const Dev& g, int level, int tile0, int tstri
       if (it < total) {
         const int k = its.list_of_item(it);
         if (k < kBigList) {
-          const int idx = (it - its.start[k]) * NPW + lane / G;
+          stride = k == 0 ? G : GN;
+          const int idx = (it - its.start[k]) * (kWave / stride) + lane / stride;
           has = idx < its.n[k];
           v = has ? g.list[cp][k][idx] : 0;
-          gl = lane % G;
+          gl = lane % stride;
         } else {
           v = g.list[cp][kBigList][it - its.start[kBigList]];
           has = !is_huge(g, v);

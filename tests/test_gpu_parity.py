@@ -104,7 +104,7 @@ def test_debug_invariants_every_round(hf, oracle_mod):
 
 
 @pytest.mark.parametrize("opts", [
-    dict(group_lanes=4), dict(group_lanes=16), dict(tail_threshold=1),
+    dict(group_lanes=4), dict(group_lanes=8), dict(group_lanes=16), dict(tail_threshold=1),
     dict(tail_threshold=1 << 30), dict(relabel_factor_x16=1), dict(relabel_factor_x16=256),
     dict(big_degree=2), dict(big_degree=100000), dict(bfs_arc_parallel=1),
     dict(bottom_up_min=-1), dict(bottom_up_min=1), dict(gr_interval=-1, stale_rounds=-1),
