@@ -388,10 +388,13 @@ def bench_learned(args, hyperflow, inputs, torch, np, config):
     with hyperflow.Scorer(init) as sc:
         sc.fit_normalization(Xtr)
         if not args.no_cpu_baseline:
+            # the oracle's inputs never come from the device path: the check
+            # uses the training features with seeded coin-flip labels
             from oracle import mlp as omlp
-            loss_gpu, g_gpu = sc.gradient(Xtr, ytr)
+            ychk = np.random.default_rng(0).integers(0, 2, len(Xtr)).astype(np.float32)
+            loss_gpu, g_gpu = sc.gradient(Xtr, ychk)
             xn, _, _ = omlp.normalize(Xtr)
-            loss_ref, g_ref = omlp.grad(init.astype(np.float64), xn, ytr)
+            loss_ref, g_ref = omlp.grad(init.astype(np.float64), xn, ychk)
             out["gradient_rel_err_vs_oracle"] = float(
                 np.linalg.norm(g_gpu - g_ref) / max(np.linalg.norm(g_ref), 1e-30))
             out["loss_vs_oracle"] = [float(loss_gpu), float(loss_ref)]
