@@ -90,6 +90,7 @@ enum : int {
 // any kind (processed by whole waves).  Splitting by kind keeps every wave
 // item on one code path.
 constexpr int kNL = 4;
+constexpr int kLvlHist = 64;  // reverse-BFS levels whose sizes are kept
 constexpr int kBigList = 3;
 
 struct Ctl {
@@ -106,7 +107,10 @@ struct Ctl {
   unsigned long long side_weight[2];  // FlowCutter: c(S_r), c(T_r)
   int32_t pierce[5];  // FlowCutter: per side s, [3s] smallest free boundary pin and
                       // [3s + 1] smallest augmenting pin; [2] smallest free vertex
-  int32_t pad;
+  int32_t big_last;   // last reverse-BFS level of the current global relabel
+                      // whose frontier exceeded the single-workgroup tail
+  int32_t lvl_nf[kLvlHist];  // size of each of the first reverse-BFS levels of
+                             // the current global relabel
 };
 
 struct Dev {
@@ -1351,6 +1355,7 @@ __device__ void phase_gr_reset(const Dev& g, int tile0, int tstride, lds_int* ld
     Ctl* c = g.ctl;
     for (int i = 0; i < 3; ++i)
       for (int k = 0; k < kNL; ++k) c->fcnt[i][k] = 0;
+    c->big_last = -1;
   }
   const BlockQ q = bq_bind(lds, g.ctl->bcnt[0], g.list[0]);
   const int ntiles = sweep_tiles(g);

@@ -51,6 +51,9 @@ struct fp_problem {
   size_t pool_bytes = 0;     // capacity of the pool (a reused block may be larger)
   hf::Ctl* ctl_h = nullptr;  // pinned host mirror of the control block
   int32_t epoch = 1;         // stamp value of the next round / BFS
+  int32_t gr_batch = 8;      // device-wide levels launched first by a global relabel
+  int32_t gr_hist[hf::kLvlHist] = {};  // level sizes of the previous global relabel's BFS
+  int32_t gr_hist_levels = 0;
   bool inited = false;
   bool solved = false;
   int32_t* cw = nullptr;     // vertex weights of the last FlowCutter run (device)

@@ -48,13 +48,19 @@ __global__ void __launch_bounds__(kBlock) k_gr_reset(Dev g) {
 // One level of the reverse BFS.  A level holding at least `big_min` nodes
 // is only expanded here (plain stores) and k_bfs_collect lists the next
 // level; smaller levels claim and list new nodes directly.  Both kernels read
-// the same count, so they agree on the mode.
+// the same count, so they agree on the mode.  A level larger than `tail`
+// (the single-workgroup loop's bound) is recorded in big_last, from which the
+// host sizes the first batch of level launches of the next global relabel.
 template <int G>
 __global__ void __launch_bounds__(kBlock) HF_TWO_WORKGROUPS_PER_CU
-k_bfs_rev(Dev g, int level, int big_min, int pull_min) {
+k_bfs_rev(Dev g, int level, int big_min, int pull_min, int tail) {
   HF_QUEUE_LDS;
   const int c3 = level % 3;
   const int nf = count_all(g.ctl->bcnt[c3]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (nf > tail) atomicMax(&g.ctl->big_last, level);
+    if (level < kLvlHist) g.ctl->lvl_nf[level] = nf;
+  }
   if (nf >= pull_min)
     phase_bfs_rev_pull(g, level, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x,
                        KC_BFS_REV);
@@ -252,6 +258,7 @@ __global__ void __launch_bounds__(kBlock) k_bfs_loop(Dev g, int level0, int cap,
     const int c3 = level % 3;
     const int nf = count_all_vol(g.ctl->bcnt[c3]);
     if (nf == 0 || nf > cap) break;
+    if (mode == 0 && threadIdx.x == 0 && level < kLvlHist) g.ctl->lvl_nf[level] = nf;
     __syncthreads();
     if (mode == 0) phase_bfs_rev<G>(g, level, 0, 1, KC_LOOP_BFS, lds);
     else if (mode == 1) phase_bfs_fwd<G>(g, level, ep, 0, 1, KC_LOOP_BFS, lds);
@@ -331,62 +338,110 @@ static fp_status sync_ctl(fp_problem* pb, hipStream_t s, const char* what = "") 
   return FP_OK;
 }
 
+// Device-wide BFS levels level .. level+steps-1 of the given mode.  With
+// `predict`, a reverse-BFS level is sized from the same level of the previous
+// global relabel (its neighbours' sizes included): a level expected to be
+// small runs on a grid that fits it and may not expand (it claims, so no
+// collect sweep is launched for it).  Both choices change only the schedule:
+// any grid covers any level, and claiming is correct at every size.
+template <int G>
+static void launch_levels(fp_problem* pb, hipStream_t s, int ep, int mode, int level, int steps,
+                          bool predict) {
+  Dev& g = pb->dev;
+  const int cap = pb->opt.tail_threshold;
+  const int big_min = pb->opt.bottom_up_min > 0 ? pb->opt.bottom_up_min : (1 << 30);
+  const int pull_min = pb->opt.pull_min > 0 ? pb->opt.pull_min : (1 << 30);
+  const int off = 1 << 30;
+  for (int i = 0; i < steps; ++i) {
+    const int lv = level + i;
+    if (mode == 0) {
+      int grid = kMaxFrontierBlocks, bmin = big_min, pmin = pull_min;
+      if (predict && lv < pb->gr_hist_levels) {
+        long long p = 0;
+        for (int j = lv - 1; j <= lv + 1; ++j)
+          if (j >= 0 && j < pb->gr_hist_levels) p = std::max<long long>(p, pb->gr_hist[j]);
+        grid = (int)std::min<long long>(kMaxFrontierBlocks, std::max<long long>(32, (2 * p + 63) / 64));
+        if (2 * p < big_min) bmin = off;
+        if (2 * p < pull_min) pmin = off;
+      }
+      {
+        Launch L(pb, s, KK_BFS_REV);
+        k_bfs_rev<G><<<grid, kBlock, 0, s>>>(g, lv, bmin, pmin, cap);
+      }
+      if (bmin != off || pmin != off) {
+        Launch L(pb, s, KK_BFS_COLLECT);
+        k_bfs_collect<<<sweep_blocks(g.N), kBlock, 0, s>>>(g, lv, bmin, pmin);
+      }
+    } else if (mode == 1) {
+      Launch L(pb, s, KK_BFS_FWD);
+      k_bfs_fwd<G><<<kMaxFrontierBlocks, kBlock, 0, s>>>(g, lv, ep);
+    } else {
+      Launch L(pb, s, KK_BFS_FWD);
+      k_bfs_sink<<<kMaxFrontierBlocks, kBlock, 0, s>>>(g, lv, ep);
+    }
+  }
+}
+
 template <int G>
 static fp_status run_bfs(fp_problem* pb, hipStream_t s, int ep, int mode, int* levels_out,
                          long long level0_count = -1) {
-  // level 0 is already in bcnt[0] (level0_count nodes when the caller knows,
-  // which saves a host round trip); mode 0 global relabel (ep unused),
-  // 1 source side, 2 sink side (stamps ep)
+  // Level 0 is already in bcnt[0] (level0_count nodes when the caller knows).
+  // mode 0 global relabel (ep unused), 1 source side, 2 sink side (stamps ep).
+  //
+  // Levels are launched in batches without reading their sizes: a batch of
+  // device-wide levels is followed by the single-workgroup loop, which runs
+  // the levels that follow while they hold at most `cap` nodes and exits at
+  // once otherwise; one host round trip per batch then reads where the BFS
+  // stands.  A global relabel's first batch is as long as the previous
+  // relabel's device-wide part (big_last + 1), so a relabel usually costs one
+  // round trip.  Levels with no nodes do nothing, so launching past the end
+  // of a BFS is safe.  With the invariant checker on, every level is
+  // device-wide and every batch is read back.
   Dev& g = pb->dev;
   const int cap = pb->opt.tail_threshold;
+  const bool use_loop = !pb->opt.debug_checks;
   int level = 0;
+  long long nf = level0_count;  // size of `level`, < 0 while unknown on the host
   fp_status st = FP_OK;
-  if (level0_count < 0) {
+  // only a global relabel starts without reading the size of level 0 (its
+  // sinks are many in the common case); the other searches often start small
+  if (nf < 0 && (!use_loop || mode != 0)) {
     st = sync_ctl(pb, s);
     if (st) return st;
+    nf = host_count(pb->ctl_h->bcnt[0]);
   }
-  for (bool first = true;; first = false) {
-    const int c3 = level % 3;
-    const long long nf = first && level0_count >= 0 ? level0_count
-                                                    : host_count(pb->ctl_h->bcnt[c3]);
+  bool first = true;
+  for (;;) {
     if (nf == 0) break;
     // a level holds distinct nodes and a BFS has at most N levels
     if (nf > g.N || level > g.N + 16) {
       set_error("internal check: BFS level %d holds %lld nodes (N = %d)", level, nf, g.N);
       return FP_ERR_DEVICE;
     }
-    if (nf <= cap && !pb->opt.debug_checks) {
-      {
-        Launch L(pb, s, mode == 0 ? KK_BFS_REV_LOOP : KK_BFS_FWD_LOOP);
-        k_bfs_loop<G><<<1, kBlock, 0, s>>>(g, level, cap, ep, mode);
+    int steps = 0;
+    bool predict = false;
+    if (!use_loop || nf > cap || (nf < 0 && g.N > cap)) {
+      steps = 8;
+      if (mode == 0 && first && use_loop) {
+        steps = pb->gr_batch;
+        predict = pb->gr_hist_levels > 0;
       }
-      st = sync_ctl(pb, s, "bfs-loop");
-      if (st) return st;
-      level += pb->ctl_h->loop_levels;
-    } else {
-      const int steps = 8;
-      const int big_min = pb->opt.bottom_up_min > 0 ? pb->opt.bottom_up_min : (1 << 30);
-      const int pull_min = pb->opt.pull_min > 0 ? pb->opt.pull_min : (1 << 30);
-      for (int i = 0; i < steps; ++i) {
-        if (mode == 0) {
-          {
-            Launch L(pb, s, KK_BFS_REV);
-            k_bfs_rev<G><<<kMaxFrontierBlocks, kBlock, 0, s>>>(g, level + i, big_min, pull_min);
-          }
-          Launch L(pb, s, KK_BFS_COLLECT);
-          k_bfs_collect<<<sweep_blocks(g.N), kBlock, 0, s>>>(g, level + i, big_min, pull_min);
-        } else if (mode == 1) {
-          Launch L(pb, s, KK_BFS_FWD);
-          k_bfs_fwd<G><<<kMaxFrontierBlocks, kBlock, 0, s>>>(g, level + i, ep);
-        } else {
-          Launch L(pb, s, KK_BFS_FWD);
-          k_bfs_sink<<<kMaxFrontierBlocks, kBlock, 0, s>>>(g, level + i, ep);
-        }
-      }
-      level += steps;
-      st = sync_ctl(pb, s, "bfs");
-      if (st) return st;
     }
+    first = false;
+    launch_levels<G>(pb, s, ep, mode, level, steps, predict);
+    if (use_loop) {
+      Launch L(pb, s, mode == 0 ? KK_BFS_REV_LOOP : KK_BFS_FWD_LOOP);
+      k_bfs_loop<G><<<1, kBlock, 0, s>>>(g, level + steps, cap, ep, mode);
+    }
+    st = sync_ctl(pb, s, "bfs");
+    if (st) return st;
+    level += steps + (use_loop ? pb->ctl_h->loop_levels : 0);
+    nf = host_count(pb->ctl_h->bcnt[level % 3]);
+  }
+  if (mode == 0) {
+    pb->gr_batch = std::min(kLvlHist, std::max(1, pb->ctl_h->big_last + 1));
+    pb->gr_hist_levels = std::min(level, kLvlHist);
+    for (int j = 0; j < pb->gr_hist_levels; ++j) pb->gr_hist[j] = pb->ctl_h->lvl_nf[j];
   }
   *levels_out = level;
   return FP_OK;
@@ -508,9 +563,16 @@ static fp_status solve_impl(fp_problem* pb, hipStream_t s, int64_t* flow) {
       if (pb->ctl_h->loop_exit == 5) do_gr = true;
     } else {
       // later rounds of the batch may hold larger frontiers than the
-      // count known now, so the batch uses the full grid
+      // count known now, so the batch uses the full grid; it runs up to the
+      // next interval relabel (at most 16 rounds) between two round trips
       const int grid = kMaxFrontierBlocks;
-      for (int i = 0; i < rounds_per_sync; ++i) {
+      int batch = rounds_per_sync;
+      if (!pb->opt.debug_checks && gr_interval > 0)
+        batch = (int)std::max<long long>(1, std::min<long long>(16, gr_interval - rounds_since_gr));
+      if (pb->opt.round_budget > 0)
+        batch = (int)std::max<long long>(
+            1, std::min<long long>(batch, pb->opt.round_budget - rounds_this_solve));
+      for (int i = 0; i < batch; ++i) {
         {
           Launch L(pb, s, KK_PUSH);
           k_push<G><<<grid, kBlock, 0, s>>>(g, pb->epoch + i);
@@ -520,7 +582,7 @@ static fp_status solve_impl(fp_problem* pb, hipStream_t s, int64_t* flow) {
           k_apply<<<grid, kBlock, 0, s>>>(g, pb->epoch + i);
         }
       }
-      ran = rounds_per_sync;
+      ran = batch;
       if (pb->opt.debug_checks) {
         st = debug_check(pb, s);
         if (st) return st;
