@@ -475,7 +475,7 @@ class _WithTerminals:
 
 
 class FlowCutterResult:
-    def __init__(self, status, flow, x, iterations, trace, S, T, counts=None):
+    def __init__(self, status, flow, x, iterations, trace, S, T, counts=None, first_balanced=0):
         self.status = status          # "balanced", "infeasible" or "cap"
         self.flow = int(flow)         # cut weight of the returned bipartition
         self.vertex_side = x          # bool per vertex: the returned source side
@@ -484,6 +484,7 @@ class FlowCutterResult:
         self.counts = counts          # per iteration: vertices pierced (0 at the end)
         self.sources = S
         self.sinks = T
+        self.first_balanced = first_balanced  # iteration of the first balanced cut (0: none)
 
 
 def _cut_nets(hg, side):
@@ -530,7 +531,7 @@ def _augmenting_candidates(hg, cut, own_terminals_side):
 
 
 def flowcutter(hg, vertex_weights, max_source_weight, max_sink_weight,
-               max_iterations=100000, bulk_percent=0):
+               max_iterations=100000, bulk_percent=0, most_balanced=False):
     """FlowCutter, one piercing node per iteration or, with bulk_percent > 0,
     bulk piercing (paragraph "Bulk Piercing" of the section "Flow-Based
     Refinement").
@@ -558,6 +559,18 @@ def flowcutter(hg, vertex_weights, max_source_weight, max_sink_weight,
     the previous goal missed.  The side then takes the
     max(1, goal * pierced // gained) smallest-id augmenting candidates (all
     of them if fewer).  The trace names the smallest one.
+
+    Most balanced cut (paragraph "Most Balanced Cut"), with most_balanced:
+    from the first balanced iteration on, the run keeps piercing while no
+    augmenting path is created -- the lighter side takes its free boundary
+    pin, else any free vertex, by the rule above -- and stops when neither
+    side has a vertex outside S_r and T_r left (or at the iteration cap).
+    Every iteration offers (S_r, V \\ S_r) and (V \\ T_r, T_r); among the
+    balanced ones seen, the one with the lightest heavier side max(c(X),
+    c(V \\ X)) is returned (the first one found on ties).  The cut weight
+    stays the flow value of the first balanced iteration.  The paper repeats
+    this with randomized choices; here one pass follows the deterministic
+    smallest-id rule.
     """
     V = hg.num_vertices
     c = np.asarray(vertex_weights, dtype=np.int64)
@@ -573,6 +586,8 @@ def flowcutter(hg, vertex_weights, max_source_weight, max_sink_weight,
     term = [None, None]
     missed = [0, 0]
     pending = None     # (side, c(side) before its pierce, vertices, goal)
+    best = None        # most balanced cut so far: (heavier side, X, F)
+    first_balanced = 0
     for it in range(1, max_iterations + 1):
         r = maxflow(_WithTerminals(hg, S, T), sink_side=True)
         sr = r.vertex_side.astype(bool)
@@ -586,18 +601,42 @@ def flowcutter(hg, vertex_weights, max_source_weight, max_sink_weight,
             if goal is not None:
                 missed[s] = max(0, goal - gain)
             pending = None
+        balanced = []
         if cs <= max_source_weight and total - cs <= max_sink_weight:
-            trace.append((-1, -1, r.flow, cs, ct))
-            counts.append(0)
-            return FlowCutterResult("balanced", r.flow, sr, it, trace, S, T, counts)
+            balanced.append(sr)
         if total - ct <= max_source_weight and ct <= max_sink_weight:
+            balanced.append(~tr)
+        if balanced and not most_balanced:
             trace.append((-1, -1, r.flow, cs, ct))
             counts.append(0)
-            return FlowCutterResult("balanced", r.flow, ~tr, it, trace, S, T, counts)
+            return FlowCutterResult("balanced", r.flow, balanced[0], it, trace, S, T, counts,
+                                    it)
         side = 0 if cs <= ct else 1
         own, mine = (sr, tr & ~T) if side == 0 else (tr, sr & ~S)
         cut = _cut_nets(hg, own)
         p, aug = _piercing_node(hg, cut, sr, tr, mine)
+        if balanced or best is not None:
+            if best is None:
+                first_balanced = it
+            for x in balanced:
+                cx = int(c[x].sum())
+                heavier = max(cx, total - cx)
+                if best is None or heavier < best[0]:
+                    best = (heavier, x.copy(), r.flow)
+            if p < 0 or aug:
+                trace.append((-1, -1, r.flow, cs, ct))
+                counts.append(0)
+                return FlowCutterResult("balanced", best[2], best[1], it, trace, S, T, counts,
+                                        first_balanced)
+            trace.append((side, p, r.flow, cs, ct))
+            counts.append(1)
+            if side == 0:
+                S = sr.copy()
+                S[p] = True
+            else:
+                T = tr.copy()
+                T[p] = True
+            continue
         trace.append((side, p, r.flow, cs, ct))
         if p < 0:
             counts.append(0)
@@ -623,4 +662,7 @@ def flowcutter(hg, vertex_weights, max_source_weight, max_sink_weight,
         else:
             T = tr.copy()
             T[nodes] = True
+    if best is not None:
+        return FlowCutterResult("balanced", best[2], best[1], max_iterations, trace, S, T,
+                                counts, first_balanced)
     return FlowCutterResult("cap", trace[-1][2], sr, max_iterations, trace, S, T, counts)

@@ -442,6 +442,11 @@ static fp_status run_bfs(fp_problem* pb, hipStream_t s, int ep, int mode, int* l
     pb->gr_batch = std::min(kLvlHist, std::max(1, pb->ctl_h->big_last + 1));
     pb->gr_hist_levels = std::min(level, kLvlHist);
     for (int j = 0; j < pb->gr_hist_levels; ++j) pb->gr_hist[j] = pb->ctl_h->lvl_nf[j];
+    if (trace_on()) {
+      fprintf(stderr, "[hyperflow] relabel levels:");
+      for (int j = 0; j < pb->gr_hist_levels; ++j) fprintf(stderr, " %d", pb->gr_hist[j]);
+      fprintf(stderr, "\n");
+    }
   }
   *levels_out = level;
   return FP_OK;

@@ -228,8 +228,10 @@ def _cutter_cases():
 def _run_cutter_case(fn, case):
     hg = inputs.hypergraph_from_nets(case["V"], case["nets"], case["w"], case["S"], case["T"])
     c = np.asarray(case.get("c", np.ones(case["V"])))
-    return fn(hg, c, case["max_source"], case["max_sink"],
-              bulk_percent=case.get("bulk_percent", 0))
+    kw = dict(bulk_percent=case.get("bulk_percent", 0))
+    if case.get("most_balanced"):
+        kw["most_balanced"] = True
+    return fn(hg, c, case["max_source"], case["max_sink"], **kw)
 
 
 def _counts_of(case):
@@ -248,6 +250,8 @@ def test_flowcutter_fixture(oracle_mod, case):
     assert r.iterations == case["iterations"]
     assert [list(t) for t in r.trace] == case["trace"]
     assert r.counts == _counts_of(case)
+    if "first_balanced" in case:
+        assert r.first_balanced == case["first_balanced"]
 
 
 @pytest.mark.parametrize("block", range(3))
@@ -290,6 +294,44 @@ def test_flowcutter_tiny_invariants(oracle_mod):
     assert seen >= {"balanced", "infeasible"}
 
 
+def test_most_balanced_tiny_invariants(oracle_mod):
+    """On tiny inputs the balance phase only adds pierces after the first
+    balanced iteration: the run agrees with the plain run up to it, keeps
+    its flow value (the plain run's, itself pinned by brute force), returns
+    a cut of that weight that respects the original terminals and the
+    bounds, and whose heavier side is no heavier than the plain run's."""
+    rng = np.random.default_rng(17)
+    improved = 0
+    for seed in range(300):
+        hg = inputs.tiny_hypergraph(seed)
+        V = hg.num_vertices
+        c = rng.integers(1, 4, V)
+        total = int(c.sum())
+        L = (total + 1) // 2 + int(rng.integers(0, 4))
+        r0 = oracle_mod.flowcutter(hg, c, L, L)
+        r = oracle_mod.flowcutter(hg, c, L, L, most_balanced=True)
+        assert r.status == r0.status, seed
+        if r0.status != "balanced":
+            assert r.trace == r0.trace and r.first_balanced == 0, seed
+            continue
+        k = r0.iterations
+        assert r.first_balanced == r0.first_balanced == k, seed
+        assert r.trace[:k - 1] == r0.trace[:k - 1], seed
+        assert r.iterations <= k + V, seed
+        assert all(t[2] == r0.flow for t in r.trace[k - 1:]), seed
+        assert all(n <= 1 for n in r.counts[k - 1:]), seed
+        x = r.vertex_side.astype(bool)
+        assert r.flow == r0.flow == oracle_mod.cut_weight(hg, x), seed
+        assert x[hg.sources].all() and not x[hg.sinks].any(), seed
+        cx = int(c[x].sum())
+        assert cx <= L and total - cx <= L, seed
+        x0 = r0.vertex_side.astype(bool)
+        h0 = max(int(c[x0].sum()), total - int(c[x0].sum()))
+        assert max(cx, total - cx) <= h0, seed
+        improved += max(cx, total - cx) < h0
+    assert improved >= 5
+
+
 CUTTER_MUTANTS = {
     "pierce heavier side": ("side = 0 if cs <= ct else 1", "side = 0 if cs > ct else 1"),
     "largest id": ("return int(free.min()), False", "return int(free.max()), False"),
@@ -305,6 +347,14 @@ CUTTER_MUTANTS = {
     "bulk term from c(V)": ("term[side] = max(0, total // 2 - weight)",
                             "term[side] = max(0, total - weight)"),
     "bulk forgets the missed goal": ("goal = term[side] + missed[side]", "goal = term[side]"),
+    "balance ties take the later cut": ("if best is None or heavier < best[0]:",
+                                        "if best is None or heavier <= best[0]:"),
+    "balance phase pierces augmenting": ("if p < 0 or aug:", "if p < 0:"),
+    "balance phase ignores the sink side": ("            for x in balanced:\n",
+                                            "            for x in balanced[:1]:\n"),
+    "balance phase keeps the first cut": ("                    best = (heavier, x.copy(), r.flow)",
+                                          "                    best = best or (heavier, x.copy(), r.flow)"),
+    "balance phase starts late": ("                first_balanced = it", "                first_balanced = it + 1"),
 }
 
 
@@ -326,7 +376,8 @@ def test_flowcutter_pins_catch_planted_mistakes(oracle_mod, name):
             ok = (r.status == case["status"] and r.flow == case["F"] and
                   [list(t) for t in r.trace] == case["trace"] and
                   r.counts == _counts_of(case) and
-                  np.nonzero(r.vertex_side)[0].tolist() == case["x"])
+                  np.nonzero(r.vertex_side)[0].tolist() == case["x"] and
+                  r.first_balanced == case.get("first_balanced", r.first_balanced))
         except Exception:
             ok = False
         failed |= not ok
