@@ -305,6 +305,23 @@ def bench_cutter(args, hyperflow, inputs, torch, np):
                bulk_iterations=int(sum(1 for k in counts if k > 1)),
                cut_certificate=_cut_weight(hg, xb, np) == res["flow"],
                first_steps=[list(t) for t in trace[:3]], last_step=list(trace[-1]))
+    # the same run continued to the most balanced cut (paragraph "Most
+    # Balanced Cut"): pierces that avoid augmenting paths, no solves
+    with hyperflow.FlowProblem.from_hypergraph(hg, device=True) as p:
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        mb, xm, _ = p.flowcutter(c, L, L, max_iterations=iters, bulk_percent=55,
+                                 most_balanced=True)
+        torch.cuda.synchronize()
+        dtm = time.perf_counter() - t
+    xmb = np.asarray(xm).astype(bool)
+    out["most_balanced"] = dict(
+        iterations=mb["iterations"], first_balanced=mb["first_balanced"],
+        seconds=round(dtm, 3), status=mb["status"], flow=mb["flow"],
+        source_weight=mb["source_weight"], sink_weight=mb["sink_weight"],
+        heavier_side=max(mb["source_weight"], mb["sink_weight"]),
+        heavier_side_first_balanced=max(res["source_weight"], res["sink_weight"]),
+        cut_certificate=_cut_weight(hg, xmb, np) == mb["flow"])
     if not args.no_cpu_baseline:
         import oracle
         k = 3

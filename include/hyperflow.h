@@ -363,7 +363,9 @@ typedef struct {
                             (complement of the maximal sink side)           */
   int32_t augmenting;    /* piercing steps that could not avoid an augmenting
                             path                                             */
-  int64_t reserved[4];
+  int32_t first_balanced; /* iteration of the first balanced cut, 0 if none  */
+  int32_t reserved32;
+  int64_t reserved[3];
 } fp_cutter_result;
 
 /* One FlowCutter iteration. */
@@ -406,9 +408,21 @@ typedef struct {
  * max(1, goal * pierced / gained) smallest-id augmenting candidates (all of
  * them if fewer).
  *
+ * Most balanced cut (most_balanced = 1; paragraph "Most Balanced Cut"): from
+ * the first balanced iteration on, the run keeps piercing as long as no
+ * augmenting path is created -- the lighter side takes its free boundary
+ * pin, else any free vertex, by the rule above; no solve is needed -- and
+ * stops when no vertex outside S_r and T_r is left (or at the iteration
+ * cap).  Every iteration offers (S_r, V \ S_r) and then (V \ T_r, T_r);
+ * among the balanced ones the run returns the one whose heavier side
+ * max(c(X), c(V \ X)) is lightest, the first one found on ties.  The cut
+ * weight is the flow value of the first balanced iteration.  (The paper
+ * repeats this with randomized choices; this is one deterministic pass.)
+ *
  *   vertex_weights  host, |V| ints >= 0
  *   max_iterations  >= 1
  *   bulk_percent    0..99
+ *   most_balanced   0 or 1
  *   mem_kind        memory kind of vertex_side
  *   vertex_side     |V| bytes: the returned source side X
  *   result          host out
@@ -420,8 +434,9 @@ typedef struct {
 fp_status flow_problem_flowcutter(fp_problem *problem, const int32_t *vertex_weights,
                                   int64_t max_source_weight, int64_t max_sink_weight,
                                   int32_t max_iterations, int32_t bulk_percent,
-                                  void *hip_stream, int32_t mem_kind, uint8_t *vertex_side,
-                                  fp_cutter_result *result, fp_cutter_step *trace);
+                                  int32_t most_balanced, void *hip_stream, int32_t mem_kind,
+                                  uint8_t *vertex_side, fp_cutter_result *result,
+                                  fp_cutter_step *trace);
 
 /*
  * Learned pruning scorer (pattern of the paper's pruning rules, section

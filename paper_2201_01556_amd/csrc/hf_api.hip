@@ -264,8 +264,9 @@ fp_status flow_problem_sink_side(fp_problem* problem, void* hip_stream, int32_t 
 
 fp_status flow_problem_flowcutter(fp_problem* problem, const int32_t* vertex_weights,
                                   int64_t max_source_weight, int64_t max_sink_weight,
-                                  int32_t max_iterations, int32_t bulk_percent, void* hip_stream,
-                                  int32_t mem_kind, uint8_t* vertex_side, fp_cutter_result* result,
+                                  int32_t max_iterations, int32_t bulk_percent,
+                                  int32_t most_balanced, void* hip_stream, int32_t mem_kind,
+                                  uint8_t* vertex_side, fp_cutter_result* result,
                                   fp_cutter_step* trace) {
   g_last_error.clear();
   if (!problem) {
@@ -273,13 +274,15 @@ fp_status flow_problem_flowcutter(fp_problem* problem, const int32_t* vertex_wei
     return FP_ERR_STATE;
   }
   if (!vertex_weights || !vertex_side || !result || max_iterations < 1 ||
-      (mem_kind != 0 && mem_kind != 1) || bulk_percent < 0 || bulk_percent > 99) {
+      (mem_kind != 0 && mem_kind != 1) || bulk_percent < 0 || bulk_percent > 99 ||
+      (most_balanced != 0 && most_balanced != 1)) {
     set_error("invalid FlowCutter arguments");
     return FP_ERR_INVALID;
   }
   return flowcutter_problem(problem, vertex_weights, max_source_weight, max_sink_weight,
-                            max_iterations, bulk_percent, static_cast<hipStream_t>(hip_stream),
-                            mem_kind, vertex_side, result, trace);
+                            max_iterations, bulk_percent, most_balanced,
+                            static_cast<hipStream_t>(hip_stream), mem_kind, vertex_side, result,
+                            trace);
 }
 
 static fp_status check_samples(const void* f, int32_t n, int32_t mem_kind) {

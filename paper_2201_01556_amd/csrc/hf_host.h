@@ -109,9 +109,9 @@ fp_status pierce_problem(fp_problem* pb, int32_t side, const int32_t* vertices, 
                          hipStream_t s);
 fp_status sink_side_problem(fp_problem* pb, hipStream_t s, int32_t mem_kind, uint8_t* vside);
 fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src, int64_t max_snk,
-                             int32_t max_iters, int32_t bulk_percent, hipStream_t s,
-                             int32_t mem_kind, uint8_t* vside, fp_cutter_result* res,
-                             fp_cutter_step* trace);
+                             int32_t max_iters, int32_t bulk_percent, int32_t most_balanced,
+                             hipStream_t s, int32_t mem_kind, uint8_t* vside,
+                             fp_cutter_result* res, fp_cutter_step* trace);
 fp_status export_state(fp_problem* pb, hipStream_t s, int32_t* f_in, int32_t* f_out,
                        int32_t* f_b, int32_t* labels, int32_t* excess);
 void release_problem(fp_problem* pb);

@@ -883,9 +883,9 @@ struct BulkScratch {
 };
 
 fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src, int64_t max_snk,
-                             int32_t max_iters, int32_t bulk_percent, hipStream_t s,
-                             int32_t mem_kind, uint8_t* vside, fp_cutter_result* res,
-                             fp_cutter_step* trace) {
+                             int32_t max_iters, int32_t bulk_percent, int32_t most_balanced,
+                             hipStream_t s, int32_t mem_kind, uint8_t* vside,
+                             fp_cutter_result* res, fp_cutter_step* trace) {
   Dev& g = pb->dev;
   long long total = 0;
   for (int32_t v = 0; v < pb->V; ++v) {
@@ -907,17 +907,25 @@ fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src,
   if (he != hipSuccess) return hip_fail(he, "copying vertex weights");
   const int ntiles = (pb->V + kBlock - 1) / kBlock;
   const size_t flag_bytes = ((size_t)pb->V + 3) & ~(size_t)3;
+  const size_t count_bytes = 4 * ((size_t)ntiles + 1);
   BulkScratch bulk;
   bulk.s = s;
-  if (bulk_percent > 0) {
-    he = hipMallocAsync(&bulk.mem, flag_bytes + 4 * ((size_t)ntiles + 1), s);
+  if (bulk_percent > 0 || most_balanced) {
+    he = hipMallocAsync(&bulk.mem, 2 * flag_bytes + count_bytes, s);
     if (he != hipSuccess) {
       bulk.mem = nullptr;
-      return hip_fail(he, "allocating the bulk piercing scratch");
+      return hip_fail(he, "allocating the FlowCutter scratch");
     }
   }
+  // [flags: V bytes][tile counts][most balanced side so far: V bytes]
   uint8_t* flags = static_cast<uint8_t*>(bulk.mem);
   int32_t* tile_counts = bulk.mem ? reinterpret_cast<int32_t*>(flags + flag_bytes) : nullptr;
+  uint8_t* best_side = bulk.mem ? flags + flag_bytes + count_bytes : nullptr;
+  // most balanced cut: heavier side, kind and weights of the best cut so far
+  long long best_heavier = -1, best_src = 0, best_snk = 0;
+  int best_kind = 0;
+  int64_t best_F = 0;
+  int32_t first_balanced = 0;
   // bulk piercing bookkeeping per side, integer arithmetic (see the header)
   long long pierces[2] = {0, 0}, gained[2] = {0, 0}, pierced[2] = {0, 0};
   long long term[2] = {-1, -1}, missed[2] = {0, 0};
@@ -991,24 +999,64 @@ fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src,
     step.node = -1;
     step.count = 0;
     bool done = false;
-    if (cs <= max_src && total - cs <= max_snk) {
+    const bool bal0 = cs <= max_src && total - cs <= max_snk;  // (S_r, V \ S_r)
+    const bool bal1 = total - ct <= max_src && ct <= max_snk;  // (V \ T_r, T_r)
+    if (!most_balanced && bal0) {
       r.status = 0;
       r.side = 0;
       r.source_weight = cs;
       r.sink_weight = total - cs;
       out_ep = ep_s;
       out_invert = 0;
+      first_balanced = it;
       done = true;
-    } else if (total - ct <= max_src && ct <= max_snk) {
+    } else if (!most_balanced && bal1) {
       r.status = 0;
       r.side = 1;
       r.source_weight = total - ct;
       r.sink_weight = ct;
       out_ep = ep_t;
       out_invert = 1;
+      first_balanced = it;
       done = true;
-    }
-    if (!done) {
+    } else if (most_balanced && (bal0 || bal1 || best_heavier >= 0)) {
+      // most balanced cut: keep the best balanced cut offered so far (its
+      // side is copied now: later pierces grow the stamped sets) and pierce
+      // on while a vertex outside S_r and T_r is left
+      if (first_balanced == 0) first_balanced = it;
+      for (int kind = 0; kind < 2; ++kind) {
+        if (!(kind == 0 ? bal0 : bal1)) continue;
+        const long long src = kind == 0 ? cs : total - ct;
+        const long long heavier = std::max(src, total - src);
+        if (best_heavier >= 0 && heavier >= best_heavier) continue;
+        best_heavier = heavier;
+        best_kind = kind;
+        best_src = src;
+        best_snk = total - src;
+        best_F = F;
+        k_side_out<<<sweep_grid(pb->V), kThreads, 0, s>>>(g, kind == 0 ? ep_s : ep_t, kind,
+                                                          best_side);
+        he = hipGetLastError();
+        if (he != hipSuccess) return hip_fail(he, "keeping the most balanced cut");
+      }
+      const int side = cs <= ct ? 0 : 1;
+      int p = pb->ctl_h->pierce[3 * side];  // a free boundary pin, else any free vertex
+      if (p == kInf) p = pb->ctl_h->pierce[2];
+      if (p == kInf) {
+        done = true;
+      } else {
+        step.side = side;
+        step.node = p;
+        step.count = 1;
+        grow = side;
+        grow_vertex = p;
+        k_stamp_vertex<<<1, 64, 0, s>>>(g, p, side == 0 ? ep_s : ep_t);
+        he = hipGetLastError();
+        if (he != hipSuccess) return hip_fail(he, "marking the piercing vertex");
+        st = apply_pierce(pb, s, side, side == 0 ? ep_s : ep_t);
+        if (st) return st;
+      }
+    } else {
       const int side = cs <= ct ? 0 : 1;
       // a free boundary pin, else any free vertex, else an augmenting pin
       int p = pb->ctl_h->pierce[3 * side];
@@ -1085,20 +1133,31 @@ fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src,
     if (trace) trace[it - 1] = step;
     if (done) break;
   }
-  if (r.status == 2) {  // iteration cap: the last iteration's S_r (its stamps survive piercing)
-    r.side = 0;
-    r.source_weight = last_cs;
-    r.sink_weight = total - last_cs;
-    out_invert = 0;
-  }
   if (out_ep < 0) {
     set_error("max_iterations must be at least 1");
     return FP_ERR_INVALID;
   }
-  k_side_out<<<sweep_grid(pb->V), kThreads, 0, s>>>(g, out_ep, out_invert, vs);
-  he = hipGetLastError();
-  if (he == hipSuccess && mem_kind == 0)
-    he = hipMemcpyAsync(vside, vs, pb->V, hipMemcpyDeviceToHost, s);
+  r.first_balanced = first_balanced;
+  if (best_heavier >= 0) {  // most balanced cut (also when the cap ended the run)
+    r.status = 0;
+    r.side = best_kind;
+    r.flow = best_F;
+    r.source_weight = best_src;
+    r.sink_weight = best_snk;
+    he = hipMemcpyAsync(vside, best_side, pb->V,
+                        mem_kind == 0 ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s);
+  } else {
+    if (r.status == 2) {  // iteration cap: the last iteration's S_r (its stamps survive piercing)
+      r.side = 0;
+      r.source_weight = last_cs;
+      r.sink_weight = total - last_cs;
+      out_invert = 0;
+    }
+    k_side_out<<<sweep_grid(pb->V), kThreads, 0, s>>>(g, out_ep, out_invert, vs);
+    he = hipGetLastError();
+    if (he == hipSuccess && mem_kind == 0)
+      he = hipMemcpyAsync(vside, vs, pb->V, hipMemcpyDeviceToHost, s);
+  }
   if (he == hipSuccess) he = hipStreamSynchronize(s);
   if (he != hipSuccess) return hip_fail(he, "writing the FlowCutter side");
   *res = r;

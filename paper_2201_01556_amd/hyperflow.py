@@ -102,7 +102,9 @@ class CutterResult(ctypes.Structure):
         ("status", ctypes.c_int32),
         ("side", ctypes.c_int32),
         ("augmenting", ctypes.c_int32),
-        ("reserved", ctypes.c_int64 * 4),
+        ("first_balanced", ctypes.c_int32),
+        ("reserved32", ctypes.c_int32),
+        ("reserved", ctypes.c_int64 * 3),
     ]
 
 
@@ -192,8 +194,8 @@ def load_library(path: str = LIB_PATH):
     lib.flow_problem_pierce.restype = ctypes.c_int
     lib.flow_problem_sink_side.argtypes = [vp, vp, i32, vp]
     lib.flow_problem_sink_side.restype = ctypes.c_int
-    lib.flow_problem_flowcutter.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int64, i32, i32, vp,
-                                            i32, vp, ctypes.POINTER(CutterResult), vp]
+    lib.flow_problem_flowcutter.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int64, i32, i32, i32,
+                                            vp, i32, vp, ctypes.POINTER(CutterResult), vp]
     lib.flow_problem_flowcutter.restype = ctypes.c_int
     lib.flow_problem_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     lib.flow_problem_stats.restype = ctypes.c_int
@@ -416,7 +418,8 @@ def flow_problem_sink_side(handle, num_vertices, vertex_side=None, stream=None):
 
 def flow_problem_flowcutter(handle, num_vertices, vertex_weights, max_source_weight,
                             max_sink_weight, max_iterations=100000, vertex_side=None,
-                            stream=None, want_trace=True, bulk_percent=0):
+                            stream=None, want_trace=True, bulk_percent=0,
+                            most_balanced=False):
     """FlowCutter on the handle's current terminals.  Returns (result dict,
     source side X, trace list of (side, node, flow, c(S_r), c(T_r))); the
     dict's "counts" lists the vertices pierced per iteration."""
@@ -431,13 +434,14 @@ def flow_problem_flowcutter(handle, num_vertices, vertex_weights, max_source_wei
     steps = (CutterStep * max(int(max_iterations), 1))() if want_trace else None
     _check(lib.flow_problem_flowcutter(handle, vw.ctypes.data, int(max_source_weight),
                                        int(max_sink_weight), int(max_iterations),
-                                       int(bulk_percent), _stream_ptr(stream), vk, vp,
+                                       int(bulk_percent), int(bool(most_balanced)),
+                                       _stream_ptr(stream), vk, vp,
                                        ctypes.byref(res),
                                        ctypes.cast(steps, ctypes.c_void_p) if steps else None))
     out = dict(flow=int(res.flow), source_weight=int(res.source_weight),
                sink_weight=int(res.sink_weight), iterations=int(res.iterations),
                status=CUTTER_STATUS.get(res.status, str(res.status)), side=int(res.side),
-               augmenting=int(res.augmenting))
+               augmenting=int(res.augmenting), first_balanced=int(res.first_balanced))
     trace = []
     if steps is not None:
         trace = [(int(t.side), int(t.node), int(t.flow), int(t.source_weight),
@@ -535,10 +539,12 @@ class FlowProblem:
         return flow_problem_sink_side(self.handle, self.num_vertices, vertex_side, self.stream)
 
     def flowcutter(self, vertex_weights, max_source_weight, max_sink_weight,
-                   max_iterations=100000, vertex_side=None, want_trace=True, bulk_percent=0):
+                   max_iterations=100000, vertex_side=None, want_trace=True, bulk_percent=0,
+                   most_balanced=False):
         return flow_problem_flowcutter(self.handle, self.num_vertices, vertex_weights,
                                        max_source_weight, max_sink_weight, max_iterations,
-                                       vertex_side, self.stream, want_trace, bulk_percent)
+                                       vertex_side, self.stream, want_trace, bulk_percent,
+                                       most_balanced)
 
     def stats(self) -> dict:
         return flow_problem_stats(self.handle)

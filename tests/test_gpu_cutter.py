@@ -130,7 +130,10 @@ def test_flowcutter_fixtures(hf, case):
     c = np.asarray(case.get("c", np.ones(case["V"])))
     with hf.FlowProblem.from_hypergraph(hg) as p:
         res, x, trace = p.flowcutter(c, case["max_source"], case["max_sink"],
-                                     bulk_percent=case.get("bulk_percent", 0))
+                                     bulk_percent=case.get("bulk_percent", 0),
+                                     most_balanced=case.get("most_balanced", False))
+    if "first_balanced" in case:
+        assert res["first_balanced"] == case["first_balanced"]
     assert res["status"] == case["status"]
     assert res["flow"] == case["F"]
     assert res["iterations"] == case["iterations"]
@@ -140,13 +143,15 @@ def test_flowcutter_fixtures(hf, case):
     assert res["counts"] == counts
 
 
-def _compare_cutter(hf, oracle_mod, hg, c, Ls, Lt, max_iter, tag, bulk_percent=0, **opts):
+def _compare_cutter(hf, oracle_mod, hg, c, Ls, Lt, max_iter, tag, bulk_percent=0,
+                    most_balanced=False, **opts):
     ref = oracle_mod.flowcutter(hg, c, Ls, Lt, max_iterations=max_iter,
-                                bulk_percent=bulk_percent)
+                                bulk_percent=bulk_percent, most_balanced=most_balanced)
     with hf.FlowProblem.from_hypergraph(hg, **opts) as p:
         res, x, trace = p.flowcutter(c, Ls, Lt, max_iterations=max_iter,
-                                     bulk_percent=bulk_percent)
+                                     bulk_percent=bulk_percent, most_balanced=most_balanced)
     assert res["iterations"] == ref.iterations, tag
+    assert res["first_balanced"] == ref.first_balanced, tag
     assert [tuple(t) for t in trace] == [tuple(t) for t in ref.trace], tag
     assert res["counts"] == ref.counts, tag
     assert res["status"] == ref.status, tag
@@ -255,3 +260,72 @@ def test_flowcutter_zipf_prefix_vs_oracle(hf, oracle_mod):
     assert [tuple(t) for t in trace] == [tuple(t) for t in ref.trace]
     assert res["status"] == ref.status
     assert (x.astype(bool) == ref.vertex_side.astype(bool)).all()
+
+
+def test_most_balanced_tiny_vs_oracle(hf, oracle_mod):
+    """Most balanced cut on 200 tiny hypergraphs (loose bounds, so the
+    balance phase has room): trace, first balanced iteration and result."""
+    rng = np.random.default_rng(23)
+    longer = 0
+    for seed in range(200):
+        hg = inputs.tiny_hypergraph(seed)
+        c = rng.integers(1, 4, hg.num_vertices)
+        L = (int(c.sum()) + 1) // 2 + int(rng.integers(0, 5))
+        res = _compare_cutter(hf, oracle_mod, hg, c, L, L, 100, f"most balanced tiny {seed}",
+                              most_balanced=True, debug_checks=1 if seed % 5 == 0 else 0)
+        longer += res["iterations"] > res["first_balanced"] > 0
+    assert longer >= 20
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_most_balanced_uniform_vs_oracle(hf, oracle_mod, seed):
+    """2,000 vertices, 3,000 nets, vertex weights U{1..3}, eps = 0.03, with
+    bulk piercing for the first seed (which then ends without a balanced
+    cut: bulk pierces overshoot on this instance, in the oracle as well)."""
+    hg = inputs.uniform_hypergraph(seed)
+    c = np.random.default_rng(seed).integers(1, 4, hg.num_vertices)
+    L = balance_limit(c.sum())
+    _say(f"most balanced uniform {seed}")
+    res = _compare_cutter(hf, oracle_mod, hg, c, L, L, 5000, f"most balanced uniform {seed}",
+                          bulk_percent=55 if seed == 0 else 0, most_balanced=True,
+                          group_lanes=[4, 8, 16][seed % 3])
+    assert res["status"] == ("infeasible" if seed == 0 else "balanced")
+
+
+def test_most_balanced_block_pairs_vs_oracle(hf, oracle_mod):
+    bp = inputs.block_pair_problems(0, num_vertices=20000, target_pins=100000, k=8,
+                                    max_problems=4)
+    for i, h in enumerate(bp.problems):
+        _say(f"most balanced block pair {i}")
+        _compare_cutter(hf, oracle_mod, h, h.vertex_weights, bp.lmax, bp.lmax, 3000,
+                        f"most balanced pair {i}", bulk_percent=55, most_balanced=True)
+
+
+def test_most_balanced_zipf_improves_balance(hf, oracle_mod):
+    """The 200k-vertex instance with bulk piercing: the most balanced cut
+    keeps the first balanced cut's weight, is a certificate of it, respects
+    the bound and has a heavier side no heavier than the first balanced
+    cut's."""
+    hg = inputs.zipf_hypergraph(0, 200_000, 400_000, size_hi=200, vertex_weight_hi=3)
+    c = hg.vertex_weights.astype(np.int64)
+    total = int(c.sum())
+    L = balance_limit(total)
+    _say("zipf 200k, first balanced cut")
+    with hf.FlowProblem.from_hypergraph(hg) as p:
+        r0, x0, _ = p.flowcutter(c, L, L, max_iterations=100000, bulk_percent=55)
+    _say("zipf 200k, most balanced cut")
+    with hf.FlowProblem.from_hypergraph(hg) as p:
+        r1, x1, t1 = p.flowcutter(c, L, L, max_iterations=100000, bulk_percent=55,
+                                  most_balanced=True)
+    _say(f"first balanced at {r0['iterations']}: {r0['source_weight']}/{r0['sink_weight']}; "
+         f"most balanced after {r1['iterations']}: {r1['source_weight']}/{r1['sink_weight']}")
+    assert r0["status"] == r1["status"] == "balanced"
+    assert r1["first_balanced"] == r0["iterations"]
+    assert r1["flow"] == r0["flow"]
+    x1 = x1.astype(bool)
+    assert oracle_mod.cut_weight(hg, x1) == r1["flow"]
+    cx = int(c[x1].sum())
+    assert cx == r1["source_weight"] and total - cx == r1["sink_weight"]
+    assert cx <= L and total - cx <= L
+    assert max(cx, total - cx) <= max(r0["source_weight"], r0["sink_weight"])
+    assert all(t[2] == r0["flow"] for t in t1[r0["iterations"] - 1:])
