@@ -1142,9 +1142,22 @@ __device__ void phase_bfs_rev_lb(const Dev& g, int level, int tile0, int tstride
                 narcs);
 }
 
+// Visit v in the forward BFS stamped ep.  With kClaim the first visitor wins
+// (exchange on the stamp) and lists v; otherwise an unvisited v gets the
+// level's provisional stamp ep_tmp by a plain store (every writer stores the
+// same value) and the collect sweep lists it and stamps it ep.
+template <bool kClaim>
+__device__ __forceinline__ bool fwd_visit(const Dev& g, int v, int ep, int ep_tmp) {
+  if (kClaim) return stamp_first(g, v, ep);
+  const int sv = g.stamp[v];
+  if (sv != ep && sv != ep_tmp) g.stamp[v] = ep_tmp;
+  return false;
+}
+
 // One level of the forward BFS of the uncapped network, arc-parallel.
-__device__ void phase_bfs_fwd_lb(const Dev& g, int level, int ep, int tile0, int tstride, int kc,
-                                 lds_int* lds) {
+template <bool kClaim>
+__device__ void phase_bfs_fwd_lb(const Dev& g, int level, int ep, int ep_tmp, int tile0,
+                                 int tstride, int kc, lds_int* lds) {
   const int c3 = level % 3, n3 = (level + 1) % 3, z3 = (level + 2) % 3;
   if (tile0 == 0 && threadIdx.x < kNL) g.ctl->bcnt[z3][threadIdx.x] = 0;
   const int cp = level & 1, np = (level + 1) & 1;
@@ -1171,8 +1184,8 @@ __device__ void phase_bfs_fwd_lb(const Dev& g, int level, int ep, int tile0, int
           t1 = g.NB + 2 * ep2.x;
           t2 = t1 + 1;
           nbytes += 12;
-          v1 = stamp_first(g, t1, ep);                                 // x -> e_in (uncapped)
-          if (g.fpin[2 * ep2.y + 1] > 0) v2 = stamp_first(g, t2, ep);  // x -> e_out reverse
+          v1 = fwd_visit<kClaim>(g, t1, ep, ep_tmp);                    // x -> e_in (uncapped)
+          if (g.fpin[2 * ep2.y + 1] > 0) v2 = fwd_visit<kClaim>(g, t2, ep, ep_tmp);  // x -> e_out reverse
         } else {
           const int e = (x - g.NB) >> 1;
           const bool in = ((x - g.NB) & 1) == 0;
@@ -1180,28 +1193,30 @@ __device__ void phase_bfs_fwd_lb(const Dev& g, int level, int ep, int tile0, int
             const int fbv = g.fb[e];
             nbytes += 8;
             t1 = in ? x + 1 : x - 1;
-            if (in ? fbv < g.w[e] : fbv > 0) v1 = stamp_first(g, t1, ep);
+            if (in ? fbv < g.w[e] : fbv > 0) v1 = fwd_visit<kClaim>(g, t1, ep, ep_tmp);
           } else {
             const int i = b + j - 1;
             t1 = g.pin_v[i];
             nbytes += 8;
             if (in) {
-              if (g.w[e] - g.fpin[2 * i] > 0) v1 = stamp_first(g, t1, ep);  // e_in -> u reverse
+              if (g.w[e] - g.fpin[2 * i] > 0) v1 = fwd_visit<kClaim>(g, t1, ep, ep_tmp);  // e_in -> u reverse
             } else {
               const int r = g.role[t1];
               if (r == 2) atomicOr(&g.ctl->err, ERR_SINK_REACHED);
-              else if (r == 0) v1 = stamp_first(g, t1, ep);  // e_out -> u infinite
+              else if (r == 0) v1 = fwd_visit<kClaim>(g, t1, ep, ep_tmp);  // e_out -> u infinite
             }
           }
         }
       }
-      qpush(g, q, t1, v1);
-      qpush(g, q, t2, v2);
-      bq_tile_end(q, 2 * blockDim.x);
+      if (kClaim) {
+        qpush(g, q, t1, v1);
+        qpush(g, q, t2, v2);
+        bq_tile_end(q, 2 * blockDim.x);
+      }
     }
     __syncthreads();  // the tile area is rewritten by the next tile
   }
-  bq_flush(q);
+  if (kClaim) bq_flush(q);
   block_add_u64(&g.ctl->bytes[kc], (unsigned long long)nbytes + 12ull * narcs, &g.ctl->items[kc],
                 narcs);
 }
@@ -1305,7 +1320,32 @@ __device__ void phase_bfs_collect(const Dev& g, int level, int tile0, int tstrid
 template <int G>
 __device__ void phase_bfs_fwd(const Dev& g, int level, int ep, int tile0, int tstride, int kc,
                               lds_int* lds) {
-  phase_bfs_fwd_lb(g, level, ep, tile0, tstride, kc, lds);
+  phase_bfs_fwd_lb<true>(g, level, ep, 0, tile0, tstride, kc, lds);
+}
+
+// Large forward levels: expand with provisional stamps, then list the next
+// level by one sweep that turns them into the BFS stamp.
+__device__ void phase_bfs_fwd_expand(const Dev& g, int level, int ep, int ep_tmp, int tile0,
+                                     int tstride, int kc, lds_int* lds) {
+  phase_bfs_fwd_lb<false>(g, level, ep, ep_tmp, tile0, tstride, kc, lds);
+}
+
+__device__ void phase_bfs_fwd_collect(const Dev& g, int level, int ep, int ep_tmp, int tile0,
+                                      int tstride, lds_int* lds) {
+  const int n3 = (level + 1) % 3, np = (level + 1) & 1;
+  const BlockQ q = bq_bind(lds, g.ctl->bcnt[n3], g.list[np]);
+  const int ntiles = sweep_tiles(g);
+  for (int tile = tile0; tile < ntiles; tile += tstride) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int v = (2 * tile + j) * blockDim.x + threadIdx.x;
+      const bool fresh = v < g.N && g.stamp[v] == ep_tmp;
+      if (fresh) g.stamp[v] = ep;
+      qpush(g, q, v, fresh);
+    }
+    bq_tile_end(q, 2 * blockDim.x);
+  }
+  bq_flush(q);
 }
 
 // ---------------------------------------------------------------------------

@@ -99,11 +99,24 @@ __global__ void __launch_bounds__(kBlock) k_cut_seed(Dev g, int ep, int only_new
   phase_cut_seed(g, ep, only_new != 0, blockIdx.x, gridDim.x, lds);
 }
 
+// One level of the forward BFS (source side).  A level holding at least
+// `big_min` nodes gives its new nodes a provisional stamp (plain stores) and
+// k_bfs_fwd_collect lists them; smaller levels claim and list directly.
 template <int G>
 __global__ void __launch_bounds__(kBlock) HF_TWO_WORKGROUPS_PER_CU
-k_bfs_fwd(Dev g, int level, int ep) {
+k_bfs_fwd(Dev g, int level, int ep, int big_min, int ep_tmp) {
   HF_QUEUE_LDS;
-  phase_bfs_fwd<G>(g, level, ep, blockIdx.x, gridDim.x, KC_BFS_FWD, lds);
+  const int nf = count_all(g.ctl->bcnt[level % 3]);
+  if (nf >= big_min)
+    phase_bfs_fwd_expand(g, level, ep, ep_tmp, blockIdx.x, gridDim.x, KC_BFS_FWD, lds);
+  else phase_bfs_fwd<G>(g, level, ep, blockIdx.x, gridDim.x, KC_BFS_FWD, lds);
+}
+
+__global__ void __launch_bounds__(kBlock) k_bfs_fwd_collect(Dev g, int level, int ep, int ep_tmp,
+                                                            int big_min) {
+  HF_QUEUE_LDS;
+  const int nf = count_all(g.ctl->bcnt[level % 3]);
+  if (nf >= big_min) phase_bfs_fwd_collect(g, level, ep, ep_tmp, blockIdx.x, gridDim.x, lds);
 }
 
 __global__ void __launch_bounds__(kBlock) HF_TWO_WORKGROUPS_PER_CU
@@ -345,8 +358,8 @@ static fp_status sync_ctl(fp_problem* pb, hipStream_t s, const char* what = "") 
 // collect sweep is launched for it).  Both choices change only the schedule:
 // any grid covers any level, and claiming is correct at every size.
 template <int G>
-static void launch_levels(fp_problem* pb, hipStream_t s, int ep, int mode, int level, int steps,
-                          bool predict) {
+static void launch_levels(fp_problem* pb, hipStream_t s, int ep, int ep_tmp, int mode, int level,
+                          int steps, bool predict) {
   Dev& g = pb->dev;
   const int cap = pb->opt.tail_threshold;
   const int big_min = pb->opt.bottom_up_min > 0 ? pb->opt.bottom_up_min : (1 << 30);
@@ -373,8 +386,14 @@ static void launch_levels(fp_problem* pb, hipStream_t s, int ep, int mode, int l
         k_bfs_collect<<<sweep_blocks(g.N), kBlock, 0, s>>>(g, lv, bmin, pmin);
       }
     } else if (mode == 1) {
-      Launch L(pb, s, KK_BFS_FWD);
-      k_bfs_fwd<G><<<kMaxFrontierBlocks, kBlock, 0, s>>>(g, lv, ep);
+      {
+        Launch L(pb, s, KK_BFS_FWD);
+        k_bfs_fwd<G><<<kMaxFrontierBlocks, kBlock, 0, s>>>(g, lv, ep, big_min, ep_tmp);
+      }
+      if (big_min != off) {
+        Launch L(pb, s, KK_BFS_COLLECT);
+        k_bfs_fwd_collect<<<sweep_blocks(g.N), kBlock, 0, s>>>(g, lv, ep, ep_tmp, big_min);
+      }
     } else {
       Launch L(pb, s, KK_BFS_FWD);
       k_bfs_sink<<<kMaxFrontierBlocks, kBlock, 0, s>>>(g, lv, ep);
@@ -400,6 +419,9 @@ static fp_status run_bfs(fp_problem* pb, hipStream_t s, int ep, int mode, int* l
   Dev& g = pb->dev;
   const int cap = pb->opt.tail_threshold;
   const bool use_loop = !pb->opt.debug_checks;
+  // provisional stamp of the forward BFS's expanded levels (never a stamp
+  // value of anything else)
+  const int ep_tmp = mode == 1 ? pb->epoch++ : 0;
   int level = 0;
   long long nf = level0_count;  // size of `level`, < 0 while unknown on the host
   fp_status st = FP_OK;
@@ -428,7 +450,7 @@ static fp_status run_bfs(fp_problem* pb, hipStream_t s, int ep, int mode, int* l
       }
     }
     first = false;
-    launch_levels<G>(pb, s, ep, mode, level, steps, predict);
+    launch_levels<G>(pb, s, ep, ep_tmp, mode, level, steps, predict);
     if (use_loop) {
       Launch L(pb, s, mode == 0 ? KK_BFS_REV_LOOP : KK_BFS_FWD_LOOP);
       k_bfs_loop<G><<<1, kBlock, 0, s>>>(g, level + steps, cap, ep, mode);

@@ -329,3 +329,17 @@ def test_most_balanced_zipf_improves_balance(hf, oracle_mod):
     assert cx <= L and total - cx <= L
     assert max(cx, total - cx) <= max(r0["source_weight"], r0["sink_weight"])
     assert all(t[2] == r0["flow"] for t in t1[r0["iterations"] - 1:])
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_flowcutter_expanded_levels_vs_oracle(hf, oracle_mod, seed):
+    """Every BFS level device-wide and expanded (provisional stamps plus the
+    collect sweep on the source side, plain label stores on the relabel):
+    the same traces, with bulk piercing and the most balanced cut."""
+    hg = inputs.uniform_hypergraph(seed + 20)
+    c = np.random.default_rng(seed).integers(1, 4, hg.num_vertices)
+    L = balance_limit(c.sum())
+    _say(f"expanded levels {seed}")
+    _compare_cutter(hf, oracle_mod, hg, c, L, L, 5000, f"expanded levels {seed}",
+                    bulk_percent=55 * seed, most_balanced=True, bottom_up_min=1,
+                    tail_threshold=1)
