@@ -922,10 +922,90 @@ __device__ __forceinline__ void bfs_rev_node(const Dev& g, const BlockQ& q, int 
   }
 }
 
-template <int G, bool kClaim>
-__device__ void phase_bfs_rev_node(const Dev& g, int level, int tile0, int tstride, int kc,
-                                   lds_int* lds) {
-  // frontier of level `level` -> label level+1
+// Visit v in the forward BFS stamped ep.  With kClaim the first visitor wins
+// (exchange on the stamp) and lists v; otherwise an unvisited v gets the
+// level's provisional stamp ep_tmp by a plain store (every writer stores the
+// same value) and the collect sweep lists it and stamps it ep.
+template <bool kClaim>
+__device__ __forceinline__ bool fwd_visit(const Dev& g, int v, int ep, int ep_tmp) {
+  if (kClaim) return stamp_first(g, v, ep);
+  const int sv = g.stamp[v];
+  if (sv != ep && sv != ep_tmp) g.stamp[v] = ep_tmp;
+  return false;
+}
+
+// Node-grouped forward BFS of the uncapped residual network (source side): a
+// group of `stride` lanes scans node x's residual out-arcs.
+//   vertex u:  u -> e_in always (uncapped), u -> e_out when flow(e_out, u) > 0
+//   e_in:      e_in -> e_out when fb < w, e_in -> u when flow(u, e_in) > 0
+//   e_out:     e_out -> e_in when fb > 0, e_out -> u always (a sink reached
+//              is an internal error: the flow would not be maximum)
+template <bool kClaim>
+__device__ __forceinline__ void bfs_fwd_node(const Dev& g, const BlockQ& q, int x, bool has,
+                                             int gl, int stride, int ep, int ep_tmp,
+                                             uint32_t& nbytes) {
+  const bool isv = has && x < g.V;
+  const bool isnet = has && x >= g.NB;
+  if (!has || isv) {
+    int beg = 0, end = 0;
+    if (isv) {
+      beg = g.vtx_off[x];
+      end = g.vtx_off[x + 1];
+    }
+    for (int base = beg; base < end; base += stride) {
+      const int i = base + gl;
+      bool vin = false, vout = false;
+      int t1 = 0;
+      if (i < end) {
+        const int2 ep2 = g.vinc[i];
+        t1 = g.NB + 2 * ep2.x;
+        nbytes += 12;
+        vin = fwd_visit<kClaim>(g, t1, ep, ep_tmp);
+        if (g.fpin[2 * ep2.y + 1] > 0) vout = fwd_visit<kClaim>(g, t1 + 1, ep, ep_tmp);
+      }
+      if (kClaim) {
+        qpush(g, q, t1, vin);
+        qpush(g, q, t1 + 1, vout);
+      }
+    }
+  } else if (isnet) {
+    const int e = (x - g.NB) >> 1;
+    const bool in = ((x - g.NB) & 1) == 0;
+    const int beg = g.net_off[e], end = g.net_off[e + 1];
+    const int we = g.w[e];
+    bool vb = false;
+    if (gl == 0) {
+      const int fbv = g.fb[e];
+      nbytes += 16;
+      if (in ? fbv < we : fbv > 0) vb = fwd_visit<kClaim>(g, in ? x + 1 : x - 1, ep, ep_tmp);
+    }
+    if (kClaim) qpush(g, q, in ? x + 1 : x - 1, vb);
+    for (int base = beg; base < end; base += stride) {
+      const int i = base + gl;
+      bool vu = false;
+      int u = 0;
+      if (i < end) {
+        u = g.pin_v[i];
+        nbytes += 8;
+        if (in) {
+          if (we - g.fpin[2 * i] > 0) vu = fwd_visit<kClaim>(g, u, ep, ep_tmp);
+        } else {
+          const int r = g.role[u];
+          if (r == 2) atomicOr(&g.ctl->err, ERR_SINK_REACHED);
+          else if (r == 0) vu = fwd_visit<kClaim>(g, u, ep, ep_tmp);
+        }
+      }
+      if (kClaim) qpush(g, q, u, vu);
+    }
+  }
+}
+
+// One BFS level, node-grouped: the reverse BFS of a global relabel (labels
+// level+1) or, with kFwd, the forward BFS of the source side (stamp ep,
+// provisional stamp ep_tmp when expanding).
+template <int G, bool kClaim, bool kFwd>
+__device__ void phase_bfs_node(const Dev& g, int level, int ep, int ep_tmp, int tile0,
+                               int tstride, int kc, lds_int* lds) {
   const int c3 = level % 3, n3 = (level + 1) % 3, z3 = (level + 2) % 3;
   if (tile0 == 0 && threadIdx.x < kNL) g.ctl->bcnt[z3][threadIdx.x] = 0;
   const int cp = level & 1, np = (level + 1) & 1;
@@ -968,12 +1048,20 @@ __device__ void phase_bfs_rev_node(const Dev& g, int level, int tile0, int tstri
       stride = blockDim.x;
     }
     nitems += has && gl == 0;
-    bfs_rev_node<kClaim>(g, q, v, has, gl, stride, level + 1, nbytes);
+    if constexpr (kFwd) bfs_fwd_node<kClaim>(g, q, v, has, gl, stride, ep, ep_tmp, nbytes);
+    else bfs_rev_node<kClaim>(g, q, v, has, gl, stride, level + 1, nbytes);
     if (kClaim) bq_tile_end(q, q.cap / 2);
   }
   if (kClaim) bq_flush(q);
   block_add_u64(&g.ctl->bytes[kc], (unsigned long long)nbytes + 4ull * nitems, &g.ctl->items[kc],
                 nitems);
+}
+
+// frontier of level `level` -> label level+1
+template <int G, bool kClaim>
+__device__ void phase_bfs_rev_node(const Dev& g, int level, int tile0, int tstride, int kc,
+                                   lds_int* lds) {
+  phase_bfs_node<G, kClaim, false>(g, level, 0, 0, tile0, tstride, kc, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1142,18 +1230,6 @@ __device__ void phase_bfs_rev_lb(const Dev& g, int level, int tile0, int tstride
                 narcs);
 }
 
-// Visit v in the forward BFS stamped ep.  With kClaim the first visitor wins
-// (exchange on the stamp) and lists v; otherwise an unvisited v gets the
-// level's provisional stamp ep_tmp by a plain store (every writer stores the
-// same value) and the collect sweep lists it and stamps it ep.
-template <bool kClaim>
-__device__ __forceinline__ bool fwd_visit(const Dev& g, int v, int ep, int ep_tmp) {
-  if (kClaim) return stamp_first(g, v, ep);
-  const int sv = g.stamp[v];
-  if (sv != ep && sv != ep_tmp) g.stamp[v] = ep_tmp;
-  return false;
-}
-
 // One level of the forward BFS of the uncapped network, arc-parallel.
 template <bool kClaim>
 __device__ void phase_bfs_fwd_lb(const Dev& g, int level, int ep, int ep_tmp, int tile0,
@@ -1320,14 +1396,17 @@ __device__ void phase_bfs_collect(const Dev& g, int level, int tile0, int tstrid
 template <int G>
 __device__ void phase_bfs_fwd(const Dev& g, int level, int ep, int tile0, int tstride, int kc,
                               lds_int* lds) {
-  phase_bfs_fwd_lb<true>(g, level, ep, 0, tile0, tstride, kc, lds);
+  if (g.bfs_arc) phase_bfs_fwd_lb<true>(g, level, ep, 0, tile0, tstride, kc, lds);
+  else phase_bfs_node<G, true, true>(g, level, ep, 0, tile0, tstride, kc, lds);
 }
 
 // Large forward levels: expand with provisional stamps, then list the next
 // level by one sweep that turns them into the BFS stamp.
+template <int G>
 __device__ void phase_bfs_fwd_expand(const Dev& g, int level, int ep, int ep_tmp, int tile0,
                                      int tstride, int kc, lds_int* lds) {
-  phase_bfs_fwd_lb<false>(g, level, ep, ep_tmp, tile0, tstride, kc, lds);
+  if (g.bfs_arc) phase_bfs_fwd_lb<false>(g, level, ep, ep_tmp, tile0, tstride, kc, lds);
+  else phase_bfs_node<G, false, true>(g, level, ep, ep_tmp, tile0, tstride, kc, lds);
 }
 
 __device__ void phase_bfs_fwd_collect(const Dev& g, int level, int ep, int ep_tmp, int tile0,

@@ -108,7 +108,7 @@ k_bfs_fwd(Dev g, int level, int ep, int big_min, int ep_tmp) {
   HF_QUEUE_LDS;
   const int nf = count_all(g.ctl->bcnt[level % 3]);
   if (nf >= big_min)
-    phase_bfs_fwd_expand(g, level, ep, ep_tmp, blockIdx.x, gridDim.x, KC_BFS_FWD, lds);
+    phase_bfs_fwd_expand<G>(g, level, ep, ep_tmp, blockIdx.x, gridDim.x, KC_BFS_FWD, lds);
   else phase_bfs_fwd<G>(g, level, ep, blockIdx.x, gridDim.x, KC_BFS_FWD, lds);
 }
 
