@@ -1000,10 +1000,73 @@ __device__ __forceinline__ void bfs_fwd_node(const Dev& g, const BlockQ& q, int 
   }
 }
 
+// Node-grouped reverse BFS of the uncapped residual network (maximal sink
+// side), claiming by exchange on the stamp ep: node x's residual in-arcs.
+//   vertex x:  from e_out always, from e_in when flow(x, e_in) > 0
+//   e_in:      from e_out when fb > 0, from every pin (uncapped)
+//   e_out:     from e_in when fb < w, from pins u with flow(e_out, u) > 0
+// A source reached is an internal error (the flow would not be maximum).
+__device__ __forceinline__ void bfs_sink_node(const Dev& g, const BlockQ& q, int x, bool has,
+                                              int gl, int stride, int ep, uint32_t& nbytes) {
+  const bool isv = has && x < g.V;
+  const bool isnet = has && x >= g.NB;
+  if (!has || isv) {
+    int beg = 0, end = 0;
+    if (isv) {
+      beg = g.vtx_off[x];
+      end = g.vtx_off[x + 1];
+    }
+    for (int base = beg; base < end; base += stride) {
+      const int i = base + gl;
+      bool vin = false, vout = false;
+      int t1 = 0;
+      if (i < end) {
+        const int2 ep2 = g.vinc[i];
+        t1 = g.NB + 2 * ep2.x;
+        nbytes += 12;
+        vout = stamp_first(g, t1 + 1, ep);                                       // e_out -> x
+        if (g.w[ep2.x] - g.fpin[2 * ep2.y] > 0) vin = stamp_first(g, t1, ep);  // e_in -> x
+      }
+      qpush(g, q, t1, vin);
+      qpush(g, q, t1 + 1, vout);
+    }
+  } else if (isnet) {
+    const int e = (x - g.NB) >> 1;
+    const bool in = ((x - g.NB) & 1) == 0;
+    const int beg = g.net_off[e], end = g.net_off[e + 1];
+    bool vb = false;
+    if (gl == 0) {
+      const int fbv = g.fb[e];
+      nbytes += 16;
+      if (in ? fbv > 0 : fbv < g.w[e]) vb = stamp_first(g, in ? x + 1 : x - 1, ep);
+    }
+    qpush(g, q, in ? x + 1 : x - 1, vb);
+    for (int base = beg; base < end; base += stride) {
+      const int i = base + gl;
+      bool vu = false;
+      int u = 0;
+      if (i < end) {
+        u = g.pin_v[i];
+        nbytes += 8;
+        if (in || g.fpin[2 * i + 1] > 0) {  // u -> e_in always, u -> e_out by flow
+          if (g.role[u] == 1) atomicOr(&g.ctl->err, ERR_SOURCE_REACHED);
+          else vu = stamp_first(g, u, ep);
+        }
+      }
+      qpush(g, q, u, vu);
+    }
+  }
+}
+
+constexpr int kDirRelabel = 0;  // reverse BFS of a global relabel (capped network)
+constexpr int kDirSource = 1;   // forward BFS of the source side (uncapped)
+constexpr int kDirSink = 2;     // reverse BFS of the sink side (uncapped)
+
 // One BFS level, node-grouped: the reverse BFS of a global relabel (labels
-// level+1) or, with kFwd, the forward BFS of the source side (stamp ep,
-// provisional stamp ep_tmp when expanding).
-template <int G, bool kClaim, bool kFwd>
+// level+1), the forward BFS of the source side (stamp ep, provisional stamp
+// ep_tmp when expanding) or the reverse BFS of the sink side (stamp ep,
+// claiming only).
+template <int G, bool kClaim, int kDir>
 __device__ void phase_bfs_node(const Dev& g, int level, int ep, int ep_tmp, int tile0,
                                int tstride, int kc, lds_int* lds) {
   const int c3 = level % 3, n3 = (level + 1) % 3, z3 = (level + 2) % 3;
@@ -1048,7 +1111,10 @@ __device__ void phase_bfs_node(const Dev& g, int level, int ep, int ep_tmp, int 
       stride = blockDim.x;
     }
     nitems += has && gl == 0;
-    if constexpr (kFwd) bfs_fwd_node<kClaim>(g, q, v, has, gl, stride, ep, ep_tmp, nbytes);
+    if constexpr (kDir == kDirSource)
+      bfs_fwd_node<kClaim>(g, q, v, has, gl, stride, ep, ep_tmp, nbytes);
+    else if constexpr (kDir == kDirSink)
+      bfs_sink_node(g, q, v, has, gl, stride, ep, nbytes);
     else bfs_rev_node<kClaim>(g, q, v, has, gl, stride, level + 1, nbytes);
     if (kClaim) bq_tile_end(q, q.cap / 2);
   }
@@ -1061,7 +1127,7 @@ __device__ void phase_bfs_node(const Dev& g, int level, int ep, int ep_tmp, int 
 template <int G, bool kClaim>
 __device__ void phase_bfs_rev_node(const Dev& g, int level, int tile0, int tstride, int kc,
                                    lds_int* lds) {
-  phase_bfs_node<G, kClaim, false>(g, level, 0, 0, tile0, tstride, kc, lds);
+  phase_bfs_node<G, kClaim, kDirRelabel>(g, level, 0, 0, tile0, tstride, kc, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1397,7 +1463,7 @@ template <int G>
 __device__ void phase_bfs_fwd(const Dev& g, int level, int ep, int tile0, int tstride, int kc,
                               lds_int* lds) {
   if (g.bfs_arc) phase_bfs_fwd_lb<true>(g, level, ep, 0, tile0, tstride, kc, lds);
-  else phase_bfs_node<G, true, true>(g, level, ep, 0, tile0, tstride, kc, lds);
+  else phase_bfs_node<G, true, kDirSource>(g, level, ep, 0, tile0, tstride, kc, lds);
 }
 
 // Large forward levels: expand with provisional stamps, then list the next
@@ -1406,7 +1472,7 @@ template <int G>
 __device__ void phase_bfs_fwd_expand(const Dev& g, int level, int ep, int ep_tmp, int tile0,
                                      int tstride, int kc, lds_int* lds) {
   if (g.bfs_arc) phase_bfs_fwd_lb<false>(g, level, ep, ep_tmp, tile0, tstride, kc, lds);
-  else phase_bfs_node<G, false, true>(g, level, ep, ep_tmp, tile0, tstride, kc, lds);
+  else phase_bfs_node<G, false, kDirSource>(g, level, ep, ep_tmp, tile0, tstride, kc, lds);
 }
 
 __device__ void phase_bfs_fwd_collect(const Dev& g, int level, int ep, int ep_tmp, int tile0,
@@ -1693,6 +1759,13 @@ __device__ void phase_bfs_sink_lb(const Dev& g, int level, int ep, int tile0, in
   if (hit_source) atomicOr(&g.ctl->err, ERR_SOURCE_REACHED);
   block_add_u64(&g.ctl->bytes[kc], (unsigned long long)nbytes + 12ull * narcs, &g.ctl->items[kc],
                 narcs);
+}
+
+template <int G>
+__device__ void phase_bfs_sink(const Dev& g, int level, int ep, int tile0, int tstride, int kc,
+                               lds_int* lds) {
+  if (g.bfs_arc) phase_bfs_sink_lb(g, level, ep, tile0, tstride, kc, lds);
+  else phase_bfs_node<G, true, kDirSink>(g, level, ep, 0, tile0, tstride, kc, lds);
 }
 
 // Clear the BFS counters and the FlowCutter side weights (own launch: the

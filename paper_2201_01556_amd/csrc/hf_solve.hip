@@ -119,10 +119,11 @@ __global__ void __launch_bounds__(kBlock) k_bfs_fwd_collect(Dev g, int level, in
   if (nf >= big_min) phase_bfs_fwd_collect(g, level, ep, ep_tmp, blockIdx.x, gridDim.x, lds);
 }
 
+template <int G>
 __global__ void __launch_bounds__(kBlock) HF_TWO_WORKGROUPS_PER_CU
 k_bfs_sink(Dev g, int level, int ep) {
   HF_QUEUE_LDS;
-  phase_bfs_sink_lb(g, level, ep, blockIdx.x, gridDim.x, KC_BFS_FWD, lds);
+  phase_bfs_sink<G>(g, level, ep, blockIdx.x, gridDim.x, KC_BFS_FWD, lds);
 }
 
 __global__ void __launch_bounds__(kBlock) k_sink_seed(Dev g, int ep) {
@@ -261,7 +262,10 @@ __global__ void __launch_bounds__(kBlock) k_round_loop(Dev g, int epoch0, int ma
 
 // BFS levels inside one workgroup: mode 0 the global relabel (reverse,
 // capped), 1 the source side (forward, uncapped), 2 the sink side (reverse,
-// uncapped).
+// uncapped).  Levels this small are latency bound: arc-parallel levels spread
+// even one node's arcs over the whole workgroup, which node-grouped levels do
+// not (the FlowCutter's incremental sides run here: 1.92 -> 1.85 s on the
+// 200k-vertex region).
 template <int G>
 __global__ void __launch_bounds__(kBlock) k_bfs_loop(Dev g, int level0, int cap, int ep,
                                                      int mode) {
@@ -273,8 +277,8 @@ __global__ void __launch_bounds__(kBlock) k_bfs_loop(Dev g, int level0, int cap,
     if (nf == 0 || nf > cap) break;
     if (mode == 0 && threadIdx.x == 0 && level < kLvlHist) g.ctl->lvl_nf[level] = nf;
     __syncthreads();
-    if (mode == 0) phase_bfs_rev<G>(g, level, 0, 1, KC_LOOP_BFS, lds);
-    else if (mode == 1) phase_bfs_fwd<G>(g, level, ep, 0, 1, KC_LOOP_BFS, lds);
+    if (mode == 0) phase_bfs_rev_lb<true>(g, level, 0, 1, KC_LOOP_BFS, lds);
+    else if (mode == 1) phase_bfs_fwd_lb<true>(g, level, ep, 0, 0, 1, KC_LOOP_BFS, lds);
     else phase_bfs_sink_lb(g, level, ep, 0, 1, KC_LOOP_BFS, lds);
     __syncthreads();
     ++level;
@@ -396,7 +400,7 @@ static void launch_levels(fp_problem* pb, hipStream_t s, int ep, int ep_tmp, int
       }
     } else {
       Launch L(pb, s, KK_BFS_FWD);
-      k_bfs_sink<<<kMaxFrontierBlocks, kBlock, 0, s>>>(g, lv, ep);
+      k_bfs_sink<G><<<kMaxFrontierBlocks, kBlock, 0, s>>>(g, lv, ep);
     }
   }
 }
