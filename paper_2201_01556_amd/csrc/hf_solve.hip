@@ -356,11 +356,12 @@ static fp_status sync_ctl(fp_problem* pb, hipStream_t s, const char* what = "") 
 }
 
 // Device-wide BFS levels level .. level+steps-1 of the given mode.  With
-// `predict`, a reverse-BFS level is sized from the same level of the previous
-// global relabel (its neighbours' sizes included): a level expected to be
-// small runs on a grid that fits it and may not expand (it claims, so no
-// collect sweep is launched for it).  Both choices change only the schedule:
-// any grid covers any level, and claiming is correct at every size.
+// `predict`, a reverse-BFS level that the previous global relabel also
+// reached is sized from that relabel's level and its two neighbours: a level
+// expected to be small runs on a smaller grid (128 workgroups at least) and
+// may not expand (it claims, so no collect sweep is launched for it).  Both
+// choices change only the schedule: any grid covers any level, and claiming
+// is correct at every size.
 template <int G>
 static void launch_levels(fp_problem* pb, hipStream_t s, int ep, int ep_tmp, int mode, int level,
                           int steps, bool predict) {
@@ -377,7 +378,7 @@ static void launch_levels(fp_problem* pb, hipStream_t s, int ep, int ep_tmp, int
         long long p = 0;
         for (int j = lv - 1; j <= lv + 1; ++j)
           if (j >= 0 && j < pb->gr_hist_levels) p = std::max<long long>(p, pb->gr_hist[j]);
-        grid = (int)std::min<long long>(kMaxFrontierBlocks, std::max<long long>(32, (2 * p + 63) / 64));
+        grid = (int)std::min<long long>(kMaxFrontierBlocks, std::max<long long>(128, (2 * p + 63) / 64));
         if (2 * p < big_min) bmin = off;
         if (2 * p < pull_min) pmin = off;
       }
@@ -445,13 +446,10 @@ static fp_status run_bfs(fp_problem* pb, hipStream_t s, int ep, int mode, int* l
       return FP_ERR_DEVICE;
     }
     int steps = 0;
-    bool predict = false;
+    const bool predict = mode == 0 && use_loop && pb->gr_hist_levels > 0;
     if (!use_loop || nf > cap || (nf < 0 && g.N > cap)) {
       steps = 8;
-      if (mode == 0 && first && use_loop) {
-        steps = pb->gr_batch;
-        predict = pb->gr_hist_levels > 0;
-      }
+      if (mode == 0 && first && use_loop) steps = pb->gr_batch;
     }
     first = false;
     launch_levels<G>(pb, s, ep, ep_tmp, mode, level, steps, predict);
