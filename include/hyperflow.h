@@ -101,7 +101,11 @@ typedef struct {
                                  nodes run bottom-up: every unlabelled node
                                  looks for a residual arc into the level
                                  (stops at the first); 0 = never            */
-  int32_t reserved[4];
+  int32_t tail_gr_interval;   /* rounds between global relabels while the
+                                 frontier fits the single-workgroup loop
+                                 (tail_threshold); default 4 * gr_interval,
+                                 -1 = gr_interval                            */
+  int32_t reserved[3];
 } fp_options;
 
 /* Counters of the last solve (cumulative over warm-started solves). */

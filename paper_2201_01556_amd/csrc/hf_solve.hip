@@ -530,6 +530,13 @@ static fp_status solve_impl(fp_problem* pb, hipStream_t s, int64_t* flow) {
   const unsigned long long budget =
       (unsigned long long)((double)g.N * pb->opt.relabel_factor_x16 / 16.0) + 1ull;
   const int gr_interval = pb->opt.gr_interval;
+  // Once the frontier fits one workgroup, rounds cost a few microseconds and
+  // a global relabel (a BFS over every node) as much as two hundred of them,
+  // so the tail relabels less often (7.4M-pin flows, three seeds: every 64
+  // tail rounds is at most as slow as every 16 on each seed).
+  const int tail_interval = pb->opt.tail_gr_interval > 0 ? pb->opt.tail_gr_interval
+                            : pb->opt.tail_gr_interval < 0 ? gr_interval
+                                                           : 4 * gr_interval;
   const int stale_limit = pb->opt.stale_rounds;
   constexpr long long kStaleFrontier = 1500;  // "only few active nodes" (paper)
   unsigned long long rel_at_gr = pb->ctl_h->relabels;
@@ -548,6 +555,7 @@ static fp_status solve_impl(fp_problem* pb, hipStream_t s, int64_t* flow) {
     const int c3 = pb->epoch % 3;
     const long long nf = host_count(pb->ctl_h->fcnt[c3]);
     bool do_gr = false;
+    bool in_tail = false;  // these rounds ran in the single-workgroup loop
     if (nf == 0) {
       if (fresh_gr) break;
       // apparent termination: confirm with exact labels and restart if
@@ -575,7 +583,8 @@ static fp_status solve_impl(fp_problem* pb, hipStream_t s, int64_t* flow) {
     int ran = 0;
     if (nf <= cap && !pb->opt.debug_checks) {
       long long max_rounds = 1 << 16;  // per launch; the host loop continues
-      if (gr_interval > 0) max_rounds = std::min<long long>(max_rounds, gr_interval - rounds_since_gr);
+      if (tail_interval > 0)
+        max_rounds = std::min<long long>(max_rounds, tail_interval - rounds_since_gr);
       if (pb->opt.round_budget > 0)
         max_rounds = std::min<long long>(max_rounds, pb->opt.round_budget - rounds_this_solve);
       max_rounds = std::max<long long>(max_rounds, 1);
@@ -588,6 +597,7 @@ static fp_status solve_impl(fp_problem* pb, hipStream_t s, int64_t* flow) {
       st = sync_ctl(pb, s, "loop");
       if (st) return st;
       ran = pb->ctl_h->loop_rounds;
+      in_tail = true;
       pb->st.tail_rounds += ran;
       if (pb->ctl_h->loop_exit == 5) do_gr = true;
     } else {
@@ -634,7 +644,8 @@ static fp_status solve_impl(fp_problem* pb, hipStream_t s, int64_t* flow) {
     }
     if (stale_limit > 0 && stale >= stale_limit) do_gr = true;
     if (pb->ctl_h->relabels - rel_at_gr >= budget) do_gr = true;
-    if (gr_interval > 0 && rounds_since_gr >= gr_interval) do_gr = true;
+    const int interval = in_tail ? tail_interval : gr_interval;
+    if (interval > 0 && rounds_since_gr >= interval) do_gr = true;
     if (do_gr) {
       st = global_relabel<G>(pb, s);
       if (st) return st;

@@ -58,7 +58,8 @@ class Options(ctypes.Structure):
         ("bottom_up_min", ctypes.c_int32),
         ("bfs_arc_parallel", ctypes.c_int32),
         ("pull_min", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("tail_gr_interval", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 

@@ -109,7 +109,8 @@ def test_debug_invariants_every_round(hf, oracle_mod):
     dict(big_degree=2), dict(big_degree=100000), dict(bfs_arc_parallel=1),
     dict(bottom_up_min=-1), dict(bottom_up_min=1), dict(gr_interval=-1, stale_rounds=-1),
     dict(gr_interval=1), dict(pull_min=1), dict(pull_min=1, tail_threshold=1),
-    dict(pull_min=5000),
+    dict(pull_min=5000), dict(tail_gr_interval=-1), dict(tail_gr_interval=1),
+    dict(tail_gr_interval=1000, tail_threshold=1 << 30),
 ], ids=str)
 def test_schedule_invariance(hf, oracle_mod, opts):
     """Every tuning knob changes only the schedule, never the result."""
