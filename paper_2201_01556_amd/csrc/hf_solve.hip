@@ -408,9 +408,10 @@ static void launch_levels(fp_problem* pb, hipStream_t s, int ep, int ep_tmp, int
 
 template <int G>
 static fp_status run_bfs(fp_problem* pb, hipStream_t s, int ep, int mode, int* levels_out,
-                         long long level0_count = -1) {
-  // Level 0 is already in bcnt[0] (level0_count nodes when the caller knows).
-  // mode 0 global relabel (ep unused), 1 source side, 2 sink side (stamps ep).
+                         long long level0_count = -1, int level_start = 0) {
+  // Level `level_start` (0 unless the caller continues a search) is already
+  // in its ring slot (level0_count nodes when the caller knows).  mode 0
+  // global relabel (ep unused), 1 source side, 2 sink side (stamps ep).
   //
   // Levels are launched in batches without reading their sizes: a batch of
   // device-wide levels is followed by the single-workgroup loop, which runs
@@ -427,7 +428,7 @@ static fp_status run_bfs(fp_problem* pb, hipStream_t s, int ep, int mode, int* l
   // provisional stamp of the forward BFS's expanded levels (never a stamp
   // value of anything else)
   const int ep_tmp = mode == 1 ? pb->epoch++ : 0;
-  int level = 0;
+  int level = level_start;
   long long nf = level0_count;  // size of `level`, < 0 while unknown on the host
   fp_status st = FP_OK;
   // only a global relabel starts without reading the size of level 0 (its
@@ -435,7 +436,7 @@ static fp_status run_bfs(fp_problem* pb, hipStream_t s, int ep, int mode, int* l
   if (nf < 0 && (!use_loop || mode != 0)) {
     st = sync_ctl(pb, s);
     if (st) return st;
-    nf = host_count(pb->ctl_h->bcnt[0]);
+    nf = host_count(pb->ctl_h->bcnt[level % 3]);
   }
   bool first = true;
   for (;;) {
@@ -824,6 +825,56 @@ static fp_status grow_side(fp_problem* pb, hipStream_t s, int side, int ep, int 
   }
 }
 
+// The same growth without host round trips, for the common case of a small
+// one: seeds, then the single-workgroup loop from level 0, nothing read back.
+// The caller launches its side-weight and candidate kernels behind it, reads
+// everything in one round trip, and calls grow_side_finish when the loop
+// stopped at a level too large for it (its count is then nonzero).
+template <int G>
+static fp_status grow_side_start_impl(fp_problem* pb, hipStream_t s, int side, int ep, int p) {
+  Dev& g = pb->dev;
+  k_reset_bfs<<<1, 64, 0, s>>>(g);
+  if (side == 0) k_cut_seed<<<sweep_blocks(g.N), kBlock, 0, s>>>(g, ep, 1);
+  else k_seed_vertex<<<1, 64, 0, s>>>(g, p);
+  {
+    Launch L(pb, s, KK_BFS_FWD_LOOP);
+    k_bfs_loop<G><<<1, kBlock, 0, s>>>(g, 0, pb->opt.tail_threshold, ep, side == 0 ? 1 : 2);
+  }
+  hipError_t he = hipGetLastError();
+  if (he != hipSuccess) return hip_fail(he, "growing a reachable set");
+  return FP_OK;
+}
+
+// Finish a growth that grow_side_start left at `level` (nf nodes) with
+// device-wide levels, and clear the BFS counters and FlowCutter outputs.
+template <int G>
+static fp_status grow_side_finish_impl(fp_problem* pb, hipStream_t s, int side, int ep, int level,
+                                       long long nf) {
+  int levels = 0;
+  fp_status st = run_bfs<G>(pb, s, ep, side == 0 ? 1 : 2, &levels, nf, level);
+  if (st) return st;
+  pb->st.bfs_levels += levels - level;
+  k_reset_bfs<<<1, 64, 0, s>>>(pb->dev);
+  return FP_OK;
+}
+
+static fp_status grow_side_start(fp_problem* pb, hipStream_t s, int side, int ep, int p) {
+  switch (pb->opt.group_lanes) {
+    case 4: return grow_side_start_impl<4>(pb, s, side, ep, p);
+    case 16: return grow_side_start_impl<16>(pb, s, side, ep, p);
+    default: return grow_side_start_impl<8>(pb, s, side, ep, p);
+  }
+}
+
+static fp_status grow_side_finish(fp_problem* pb, hipStream_t s, int side, int ep, int level,
+                                  long long nf) {
+  switch (pb->opt.group_lanes) {
+    case 4: return grow_side_finish_impl<4>(pb, s, side, ep, level, nf);
+    case 16: return grow_side_finish_impl<16>(pb, s, side, ep, level, nf);
+    default: return grow_side_finish_impl<8>(pb, s, side, ep, level, nf);
+  }
+}
+
 static fp_status sides(fp_problem* pb, hipStream_t s, int want, int* ep_s, int* ep_t) {
   switch (pb->opt.group_lanes) {
     case 4: return sides_impl<4>(pb, s, want, ep_s, ep_t);
@@ -994,10 +1045,14 @@ fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src,
     }
     last_F = F;
     int ep_s = 0, ep_t = 0;
+    const int grown = grow;
+    const bool spec = grow >= 0 && !pb->opt.debug_checks;  // growth without round trips
     if (grow >= 0) {
       ep_s = prev_ep_s;
       ep_t = prev_ep_t;
-      st = grow_side(pb, s, grow, grow == 0 ? ep_s : ep_t, grow_vertex);
+      const int ep = grow == 0 ? ep_s : ep_t;
+      st = spec ? grow_side_start(pb, s, grow, ep, grow_vertex)
+                : grow_side(pb, s, grow, ep, grow_vertex);
     } else {
       st = sides(pb, s, 3, &ep_s, &ep_t);
     }
@@ -1009,6 +1064,19 @@ fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src,
     k_fc_candidates<<<sweep_grid(pb->E), kThreads, 0, s>>>(g, ep_s, ep_t);
     st = sync_ctl(pb, s);
     if (st) return st;
+    if (spec) {
+      const int lv = pb->ctl_h->loop_levels;
+      const long long nf = host_count(pb->ctl_h->bcnt[lv % 3]);
+      pb->st.bfs_levels += lv;
+      if (nf > 0) {  // the growth outgrew the single-workgroup loop
+        st = grow_side_finish(pb, s, grown, grown == 0 ? ep_s : ep_t, lv, nf);
+        if (st) return st;
+        k_fc_weights<<<sweep_grid(pb->V), kThreads, 0, s>>>(g, pb->cw, ep_s, ep_t);
+        k_fc_candidates<<<sweep_grid(pb->E), kThreads, 0, s>>>(g, ep_s, ep_t);
+        st = sync_ctl(pb, s);
+        if (st) return st;
+      }
+    }
     if (pb->ctl_h->err & (ERR_SINK_REACHED | ERR_SOURCE_REACHED)) {
       set_error("internal check: a pierce without augmenting path connected a source and a sink");
       return FP_ERR_DEVICE;
