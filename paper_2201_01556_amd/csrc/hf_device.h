@@ -1959,6 +1959,49 @@ __device__ void phase_pierce_sources(const Dev& g, int ep_s, int t0, int tstride
   }
 }
 
+// The source pierce above that also lists the seeds of the source side's
+// growth (a pierce that avoids augmenting paths keeps S_r, which the growth
+// extends): converting a vertex gives e_in of each of its nets a source arc
+// and, where flow came back, e_out excess; no other node gains excess or a
+// source arc, and every node that held them before is already in S_r.  Each
+// such net node not yet stamped ep_s is stamped and listed once (exchange on
+// the stamp), so level 0 is exactly what the seed sweep over all nodes would
+// find.  Thread per vertex in tiles of blockDim; level 0's count and lists
+// must be empty.
+__device__ void phase_pierce_sources_seed(const Dev& g, int ep_s, int tile0, int tstride,
+                                          lds_int* lds) {
+  const BlockQ q = bq_bind(lds, g.ctl->bcnt[0], g.list[0]);
+  const int ntiles = (g.V + (int)blockDim.x - 1) / (int)blockDim.x;
+  for (int tile = tile0; tile < ntiles; tile += tstride) {
+    const int v = tile * (int)blockDim.x + (int)threadIdx.x;
+    int beg = 0, end = 0;
+    if (v < g.V && g.role[v] == 0 && g.stamp[v] == ep_s) {
+      g.role[v] = 1;
+      beg = g.vtx_off[v];
+      end = g.vtx_off[v + 1];
+    }
+    for (int i = beg; i < end; ++i) {
+      const int2 ep = g.vinc[i];
+      const int e = ep.x;
+      const int we = g.w[e];
+      const int fin = we - g.fpin[2 * ep.y];
+      const int fout = g.fpin[2 * ep.y + 1];
+      int add_in = -fin;
+      const int old = atomicOr(&g.nflag[e], 1);
+      if (!(old & 1)) add_in += we;
+      if (add_in) atomicAdd(&g.x[g.NB + 2 * e], add_in);
+      if (fout) atomicAdd(&g.x[g.NB + 2 * e + 1], fout);
+      g.fpin[2 * ep.y] = we;
+      g.fpin[2 * ep.y + 1] = 0;
+      const int ein = g.NB + 2 * e;
+      qpush(g, q, ein, stamp_first(g, ein, ep_s));
+      qpush(g, q, ein + 1, fout > 0 && stamp_first(g, ein + 1, ep_s));
+    }
+    bq_tile_end(q, q.cap / 2);
+  }
+  bq_flush(q);
+}
+
 // Every free vertex with stamp ep_t becomes a sink; excess it holds joins
 // the flow value (paragraph "Sink-Side Piercing").
 __device__ void phase_pierce_sinks(const Dev& g, int ep_t, int t0, int tstride) {

@@ -193,6 +193,11 @@ __global__ void k_stamp_vertex(Dev g, int p, int ep) {
   if (threadIdx.x == 0) g.stamp[p] = ep;
 }
 
+__global__ void __launch_bounds__(kBlock) k_pierce_sources_seed(Dev g, int ep_s) {
+  HF_QUEUE_LDS;
+  phase_pierce_sources_seed(g, ep_s, blockIdx.x, gridDim.x, lds);
+}
+
 __global__ void __launch_bounds__(kThreads) k_pierce_sources(Dev g, int ep_s) {
   phase_pierce_sources(g, ep_s, gthread(), gthreads());
 }
@@ -831,11 +836,14 @@ static fp_status grow_side(fp_problem* pb, hipStream_t s, int side, int ep, int 
 // everything in one round trip, and calls grow_side_finish when the loop
 // stopped at a level too large for it (its count is then nonzero).
 template <int G>
-static fp_status grow_side_start_impl(fp_problem* pb, hipStream_t s, int side, int ep, int p) {
+static fp_status grow_side_start_impl(fp_problem* pb, hipStream_t s, int side, int ep, int p,
+                                      bool seeded) {
   Dev& g = pb->dev;
-  k_reset_bfs<<<1, 64, 0, s>>>(g);
-  if (side == 0) k_cut_seed<<<sweep_blocks(g.N), kBlock, 0, s>>>(g, ep, 1);
-  else k_seed_vertex<<<1, 64, 0, s>>>(g, p);
+  if (!seeded) {  // else the source pierce listed level 0 (apply_pierce)
+    k_reset_bfs<<<1, 64, 0, s>>>(g);
+    if (side == 0) k_cut_seed<<<sweep_blocks(g.N), kBlock, 0, s>>>(g, ep, 1);
+    else k_seed_vertex<<<1, 64, 0, s>>>(g, p);
+  }
   {
     Launch L(pb, s, KK_BFS_FWD_LOOP);
     k_bfs_loop<G><<<1, kBlock, 0, s>>>(g, 0, pb->opt.tail_threshold, ep, side == 0 ? 1 : 2);
@@ -858,11 +866,12 @@ static fp_status grow_side_finish_impl(fp_problem* pb, hipStream_t s, int side, 
   return FP_OK;
 }
 
-static fp_status grow_side_start(fp_problem* pb, hipStream_t s, int side, int ep, int p) {
+static fp_status grow_side_start(fp_problem* pb, hipStream_t s, int side, int ep, int p,
+                                 bool seeded) {
   switch (pb->opt.group_lanes) {
-    case 4: return grow_side_start_impl<4>(pb, s, side, ep, p);
-    case 16: return grow_side_start_impl<16>(pb, s, side, ep, p);
-    default: return grow_side_start_impl<8>(pb, s, side, ep, p);
+    case 4: return grow_side_start_impl<4>(pb, s, side, ep, p, seeded);
+    case 16: return grow_side_start_impl<16>(pb, s, side, ep, p, seeded);
+    default: return grow_side_start_impl<8>(pb, s, side, ep, p, seeded);
   }
 }
 
@@ -902,11 +911,22 @@ fp_status sink_side_problem(fp_problem* pb, hipStream_t s, int32_t mem_kind, uin
 }
 
 // Turn S_r (side 0) or T_r (side 1), stamped ep, plus the stamped piercing
-// vertices into terminals.
-static fp_status apply_pierce(fp_problem* pb, hipStream_t s, int side, int ep) {
+// vertices into terminals.  With seed_growth (a source pierce that avoids
+// augmenting paths, whose S_r the next iteration grows) the pierce also lists
+// the growth's level 0, after clearing the BFS counters and FlowCutter outputs.
+static fp_status apply_pierce(fp_problem* pb, hipStream_t s, int side, int ep,
+                              bool seed_growth = false) {
   Dev& g = pb->dev;
-  if (side == 0) k_pierce_sources<<<sweep_grid(g.V), kThreads, 0, s>>>(g, ep);
-  else k_pierce_sinks<<<sweep_grid(g.V), kThreads, 0, s>>>(g, ep);
+  if (side == 0 && seed_growth) {
+    k_reset_bfs<<<1, 64, 0, s>>>(g);
+    const long long tiles = ((long long)g.V + kBlock - 1) / kBlock;
+    k_pierce_sources_seed<<<(int)std::max<long long>(1, std::min<long long>(tiles, kMaxSweepBlocks)),
+                            kBlock, 0, s>>>(g, ep);
+  } else if (side == 0) {
+    k_pierce_sources<<<sweep_grid(g.V), kThreads, 0, s>>>(g, ep);
+  } else {
+    k_pierce_sinks<<<sweep_grid(g.V), kThreads, 0, s>>>(g, ep);
+  }
   hipError_t he = hipGetLastError();
   if (he != hipSuccess) return hip_fail(he, "piercing");
   pb->solved = false;
@@ -1024,6 +1044,7 @@ fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src,
   r.status = 2;  // iteration cap unless a branch below decides
   // reachable sets kept across a pierce without augmenting path (grow_side)
   int prev_ep_s = -1, prev_ep_t = -1, grow = -1, grow_vertex = -1;
+  bool seeded = false;  // the last source pierce listed the growth's level 0
   int64_t last_F = 0;
   for (int32_t it = 1; it <= max_iters; ++it) {
     int64_t F = 0;
@@ -1047,11 +1068,12 @@ fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src,
     int ep_s = 0, ep_t = 0;
     const int grown = grow;
     const bool spec = grow >= 0 && !pb->opt.debug_checks;  // growth without round trips
+    seeded = seeded && spec;
     if (grow >= 0) {
       ep_s = prev_ep_s;
       ep_t = prev_ep_t;
       const int ep = grow == 0 ? ep_s : ep_t;
-      st = spec ? grow_side_start(pb, s, grow, ep, grow_vertex)
+      st = spec ? grow_side_start(pb, s, grow, ep, grow_vertex, seeded)
                 : grow_side(pb, s, grow, ep, grow_vertex);
     } else {
       st = sides(pb, s, 3, &ep_s, &ep_t);
@@ -1156,7 +1178,8 @@ fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src,
         k_stamp_vertex<<<1, 64, 0, s>>>(g, p, side == 0 ? ep_s : ep_t);
         he = hipGetLastError();
         if (he != hipSuccess) return hip_fail(he, "marking the piercing vertex");
-        st = apply_pierce(pb, s, side, side == 0 ? ep_s : ep_t);
+        seeded = side == 0 && !pb->opt.debug_checks;
+        st = apply_pierce(pb, s, side, side == 0 ? ep_s : ep_t, seeded);
         if (st) return st;
       }
     } else {
@@ -1229,7 +1252,8 @@ fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src,
         pend_before = weight;
         pend_count = count;
         pend_goal = goal;
-        st = apply_pierce(pb, s, side, ep);
+        seeded = !aug && side == 0 && !pb->opt.debug_checks;
+        st = apply_pierce(pb, s, side, ep, seeded);
         if (st) return st;
       }
     }
