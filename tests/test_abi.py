@@ -63,3 +63,36 @@ def test_options_struct_matches_header():
     from paper_2201_01556_amd import hyperflow
     assert ctypes.sizeof(hyperflow.Options) == 16 * 4
     assert ctypes.sizeof(hyperflow.Stats) == 16 * 8
+
+
+def test_binding_struct_layouts_match_the_header(tmp_path):
+    """Every field of every struct the binding mirrors sits at the offset and
+    has the size the C compiler gives it from the header."""
+    from paper_2201_01556_amd import hyperflow
+    structs = {"fp_options": hyperflow.Options, "fp_stats": hyperflow.Stats,
+               "fp_batch_config": hyperflow.BatchConfig,
+               "fp_cutter_result": hyperflow.CutterResult,
+               "fp_cutter_step": hyperflow.CutterStep}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "hyperflow.h"',
+             "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu %zu\\n", offsetof({cname}, {fname}), '
+                         f'sizeof((({cname}*)0)->{fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    exe = tmp_path / "layout"
+    src.write_text("\n".join(lines) + "\n")
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for line in out.splitlines():
+        parts = line.split()
+        got[(parts[0], parts[1])] = tuple(int(x) for x in parts[2:])
+    for cname, cls in structs.items():
+        assert got[(cname, "sizeof")] == (ctypes.sizeof(cls),), cname
+        for fname, _ in cls._fields_:
+            f = getattr(cls, fname)
+            assert got[(cname, fname)] == (f.offset, f.size), (cname, fname)
