@@ -1938,24 +1938,31 @@ __device__ void phase_fc_candidates(const Dev& g, int ep_s, int ep_t, int t0, in
 // (e_out, u) back into e_out's excess), and a net that gains its first
 // source pin receives w(e) through its contracted source arc, so the state
 // stays a preflow of the new network with the same flow value.
+// Incidence i (net e) of a vertex u that becomes a source: the flows of u's
+// pin arcs are cancelled -- e_in loses the flow u sent it and, when e gets its
+// first source pin, gains w(e) from the contracted source arc; e_out keeps as
+// excess the flow it sent to u.  Returns e and the flow returned to e_out.
+__device__ __forceinline__ int2 cancel_source_pin(const Dev& g, int i) {
+  const int2 ep = g.vinc[i];
+  const int e = ep.x;
+  const int we = g.w[e];
+  const int fin = we - g.fpin[2 * ep.y];
+  const int fout = g.fpin[2 * ep.y + 1];
+  int add_in = -fin;
+  const int old = atomicOr(&g.nflag[e], 1);
+  if (!(old & 1)) add_in += we;
+  if (add_in) atomicAdd(&g.x[g.NB + 2 * e], add_in);
+  if (fout) atomicAdd(&g.x[g.NB + 2 * e + 1], fout);
+  g.fpin[2 * ep.y] = we;
+  g.fpin[2 * ep.y + 1] = 0;
+  return make_int2(e, fout);
+}
+
 __device__ void phase_pierce_sources(const Dev& g, int ep_s, int t0, int tstride) {
   for (int v = t0; v < g.V; v += tstride) {
     if (g.role[v] != 0 || g.stamp[v] != ep_s) continue;
     g.role[v] = 1;
-    for (int i = g.vtx_off[v]; i < g.vtx_off[v + 1]; ++i) {
-      const int2 ep = g.vinc[i];
-      const int e = ep.x;
-      const int we = g.w[e];
-      const int fin = we - g.fpin[2 * ep.y];
-      const int fout = g.fpin[2 * ep.y + 1];
-      int add_in = -fin;
-      const int old = atomicOr(&g.nflag[e], 1);
-      if (!(old & 1)) add_in += we;
-      if (add_in) atomicAdd(&g.x[g.NB + 2 * e], add_in);
-      if (fout) atomicAdd(&g.x[g.NB + 2 * e + 1], fout);
-      g.fpin[2 * ep.y] = we;
-      g.fpin[2 * ep.y + 1] = 0;
-    }
+    for (int i = g.vtx_off[v]; i < g.vtx_off[v + 1]; ++i) cancel_source_pin(g, i);
   }
 }
 
@@ -1981,21 +1988,10 @@ __device__ void phase_pierce_sources_seed(const Dev& g, int ep_s, int tile0, int
       end = g.vtx_off[v + 1];
     }
     for (int i = beg; i < end; ++i) {
-      const int2 ep = g.vinc[i];
-      const int e = ep.x;
-      const int we = g.w[e];
-      const int fin = we - g.fpin[2 * ep.y];
-      const int fout = g.fpin[2 * ep.y + 1];
-      int add_in = -fin;
-      const int old = atomicOr(&g.nflag[e], 1);
-      if (!(old & 1)) add_in += we;
-      if (add_in) atomicAdd(&g.x[g.NB + 2 * e], add_in);
-      if (fout) atomicAdd(&g.x[g.NB + 2 * e + 1], fout);
-      g.fpin[2 * ep.y] = we;
-      g.fpin[2 * ep.y + 1] = 0;
-      const int ein = g.NB + 2 * e;
+      const int2 ef = cancel_source_pin(g, i);
+      const int ein = g.NB + 2 * ef.x;
       qpush(g, q, ein, stamp_first(g, ein, ep_s));
-      qpush(g, q, ein + 1, fout > 0 && stamp_first(g, ein + 1, ep_s));
+      qpush(g, q, ein + 1, ef.y > 0 && stamp_first(g, ein + 1, ep_s));
     }
     bq_tile_end(q, q.cap / 2);
   }
