@@ -59,6 +59,10 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run one plain elementwise copy of BYTES bytes (counter "
                          "calibration for the traffic figure) and exit")
+    ap.add_argument("--bfs-flat", type=int, default=0,
+                    help="reverse-BFS levels: 1 flattened arcs per wave, -1 lane groups, 0 default")
+    ap.add_argument("--bfs-marks", type=int, default=0,
+                    help="expanded reverse-BFS levels: 1 byte marks, -1 labels, 0 default")
     ap.add_argument("--profile", type=int, default=2,
                     help="HIP-event timing inside the timed steps: 0 off, 1 every kernel, "
                          "2 only the reverse-BFS level kernel (the dominant one)")
@@ -103,7 +107,8 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step(profile):
-        opts = hyperflow.Options(profile=profile)
+        opts = hyperflow.Options(profile=profile, bfs_flat=args.bfs_flat,
+                                 bfs_marks=args.bfs_marks)
         h = hyperflow.flow_problem_create(V, *arrays, options=opts, stream=stream)
         try:
             F = hyperflow.maxflow_solve(h, stream)

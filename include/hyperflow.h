@@ -105,7 +105,15 @@ typedef struct {
                                  frontier fits the single-workgroup loop
                                  (tail_threshold); default 4 * gr_interval,
                                  -1 = gr_interval                            */
-  int32_t reserved[3];
+  int32_t bfs_flat;           /* reverse-BFS levels spread the arcs of a
+                                 wave's 64 nodes over its lanes; 1 = on
+                                 (default), -1 = a fixed group of lanes per
+                                 node (group_lanes)                          */
+  int32_t bfs_marks;          /* expanded reverse-BFS levels mark reached
+                                 nodes in a byte array and the collect sweep
+                                 writes their labels; 1 = on (default),
+                                 -1 = labels written during the expansion   */
+  int32_t reserved[1];
 } fp_options;
 
 /* Counters of the last solve (cumulative over warm-started solves). */

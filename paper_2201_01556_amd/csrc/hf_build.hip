@@ -265,6 +265,8 @@ fp_options resolve_options(const fp_options* o) {
   if (r.gr_interval < 0) r.gr_interval = 0;
   if (r.stale_rounds == 0) r.stale_rounds = 500;
   if (r.stale_rounds < 0) r.stale_rounds = 0;
+  if (r.bfs_flat == 0) r.bfs_flat = 1;
+  if (r.bfs_marks == 0) r.bfs_marks = 1;
   return r;
 }
 
@@ -331,6 +333,7 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
   add(((N + 31) / 32) * 4ull); // labelled hint bitmap
   add(((P + 31) / 32) * 4ull); // residual bits of the pin arcs (global relabel)
   add(((E + 7) / 8) * 4ull);   // residual bits of the nets (global relabel)
+  add(N);                      // reverse-BFS byte marks
   add(sizeof(Ctl));           // ctl
   add(64);                    // scratch for the weight sum
   he = pool_acquire(pb->device, bytes, &pb->pool, &pb->pool_bytes);
@@ -380,6 +383,9 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
   g.seen = c.take<uint32_t>((N + 31) / 32);
   g.pinres = c.take<uint32_t>((P + 31) / 32);
   g.netres = c.take<uint32_t>((E + 7) / 8);
+  uint8_t* lev = c.take<uint8_t>(N);
+  g.lev = pb->opt.bfs_marks > 0 ? lev : nullptr;
+  g.bfs_flat = pb->opt.bfs_flat > 0 ? 1 : 0;
   g.bfs_arc = pb->opt.bfs_arc_parallel;
   g.ctl = c.take<Ctl>(1);
   unsigned long long* wsum = c.take<unsigned long long>(1);

@@ -115,6 +115,8 @@ struct Ctl {
 
 struct Dev {
   int32_t V, E, P, NB, N, nT, big_deg, bfs_arc;  // bfs_arc: arc-parallel BFS levels
+  int32_t bfs_flat;        // reverse-BFS levels spread each wave's 64 nodes' arcs over its lanes
+  int32_t pad_;
   const int32_t* net_off;  // E+1
   const int32_t* pin_v;    // P
   const int32_t* pin_net;  // P   net of each pin slot
@@ -133,6 +135,8 @@ struct Dev {
   const uint32_t* bigbits; // ceil(N/32) words: bit v set when node v has more than big_deg arcs
   const uint32_t* hugebits;  // ceil(N/32) words: bit v set when node v has more than kHugeDeg arcs
   uint32_t* seen;          // ceil(N/32) words: reverse BFS hint "node has a label" (see label_rev)
+  uint8_t* lev;            // N bytes or null: reverse BFS marks, 0 unlabelled, 1 reached by
+                           // the level being expanded, 2 labelled (see label_rev)
   uint32_t* pinres;        // ceil(P/32) words: bit of pin slot p = flow(u, e_in) > 0
   uint32_t* netres;        // ceil(E/8) words, 4 bits per net: bit0 = e_in -> e_out
                            // residual (fb < w), bit1 = pins carry flow out of
@@ -841,18 +845,27 @@ __device__ __forceinline__ void set_seen(const Dev& g, int v) {
 
 // Label v with lvl if it is unlabelled.  With kClaim the first writer wins
 // by compare-and-swap on the label and reports it; otherwise a plain store
-// (all writers of a level store the same value).
+// (all writers of a level store the same value).  With the byte marks `lev`
+// an expanded level only marks v (byte 1, a 5 MB array for 5 M nodes
+// instead of the 20 MB label array) and the collect sweep writes the label
+// and lists v; a claimed node gets byte 2 at once.
 // kChecked: the caller has just read v's hint bit and found it clear.
 template <bool kClaim, bool kChecked = false>
 __device__ __forceinline__ bool label_rev(const Dev& g, int v, int lvl) {
   if (!kChecked && seen_bit(g, v)) return false;
   if (!kClaim) {
-    if (g.d[v] != g.N) return false;
-    g.d[v] = lvl;
+    if (g.lev) {
+      if (g.lev[v] != 0) return false;
+      g.lev[v] = 1;
+    } else {
+      if (g.d[v] != g.N) return false;
+      g.d[v] = lvl;
+    }
     set_seen(g, v);
     return false;
   }
   if (atomicCAS(&g.d[v], g.N, lvl) != g.N) return false;
+  if (g.lev) g.lev[v] = 2;
   set_seen(g, v);
   return true;
 }
@@ -1128,6 +1141,139 @@ template <int G, bool kClaim>
 __device__ void phase_bfs_rev_node(const Dev& g, int level, int tile0, int tstride, int kc,
                                    lds_int* lds) {
   phase_bfs_node<G, kClaim, kDirRelabel>(g, level, 0, 0, tile0, tstride, kc, lds);
+}
+
+// ---------------------------------------------------------------------------
+// flattened reverse-BFS levels
+//
+// A wave takes 64 consecutive entries of one small-node list, one node per
+// lane, and spreads the nodes' arcs over its 64 lanes: a wave prefix sum of
+// the arc counts, then in every step each lane finds the node owning its arc
+// by a binary search over the lanes' offsets (shuffles, no LDS, no barrier).
+// All loads of a step are independent and every lane has an arc until the
+// last step, so a level's latency chains overlap far more than with a fixed
+// group of lanes per node (a net node holds 3.7 arcs on average, a vertex
+// 7.4, and most e_out nodes only their bridge).  Big nodes keep a wave each,
+// huge nodes the workgroup, as in the node-grouped levels.
+// ---------------------------------------------------------------------------
+
+template <bool kClaim>
+__device__ void phase_bfs_rev_flat(const Dev& g, int level, int tile0, int tstride, int kc,
+                                   lds_int* lds) {
+  const int c3 = level % 3, n3 = (level + 1) % 3, z3 = (level + 2) % 3;
+  if (tile0 == 0 && threadIdx.x < kNL) g.ctl->bcnt[z3][threadIdx.x] = 0;
+  const int cp = level & 1, np = (level + 1) & 1;
+  BlockQ q{};
+  if (kClaim) q = bq_bind(lds, g.ctl->bcnt[n3], g.list[np]);
+  const Quad n = load_counts(g.ctl->bcnt[c3]);
+  // wave items: 64 entries of list 0, of list 1, of list 2, then one big node each
+  const int s1 = (n.v0 + kWave - 1) / kWave;
+  const int s2 = s1 + (n.v1 + kWave - 1) / kWave;
+  const int s3 = s2 + (n.v2 + kWave - 1) / kWave;
+  const int total = s3 + n.v3;
+  const int wpb = blockDim.x >> 6, wid = threadIdx.x >> 6, lane = lane_id();
+  const int ntiles = (total + wpb - 1) / wpb;
+  const int lvl = level + 1;
+  uint32_t nbytes = 0, nitems = 0;
+  for (int tile = tile0; tile < ntiles + n.v3; tile += tstride) {
+    if (tile < ntiles) {
+      const int it = tile * wpb + wid;
+      if (it < s3) {
+        const int k = (it >= s1) + (it >= s2);  // wave-uniform list
+        const int idx = (it - (k == 0 ? 0 : (k == 1 ? s1 : s2))) * kWave + lane;
+        int x = 0, beg = 0, deg = 0;
+        uint32_t nb = 0;
+        if (idx < n[k]) {
+          x = g.list[cp][k][idx];
+          if (k == 0) {
+            beg = g.vtx_off[x];
+            deg = g.vtx_off[x + 1] - beg;
+          } else {
+            const int e = (x - g.NB) >> 1;
+            nb = net_bits(g, e);
+            beg = g.net_off[e];
+            int sz = g.net_off[e + 1] - beg;
+            // in-arcs of e_out from pins carry flow(e_out, u) > 0; a net
+            // without outflow has none
+            if (k == 2 && !(nb & 2u)) sz = 0;
+            deg = 1 + sz;  // arc 0 is the bridge
+            nbytes += 16;
+          }
+          nitems += 1;
+        }
+        int incl = deg;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+          const int t = __shfl_up(incl, o);
+          if (lane >= o) incl += t;
+        }
+        const int excl = incl - deg;
+        const int A = __shfl(incl, kWave - 1);
+        for (int a0 = 0; a0 < A; a0 += kWave) {
+          const int a = a0 + lane;
+          // owner: the last lane whose offset is <= a (lanes without arcs
+          // share the next lane's offset, so the last one owns the arc)
+          int lo = 0;
+#pragma unroll
+          for (int st = kWave / 2; st > 0; st >>= 1) {
+            const int c = lo + st;
+            if (__shfl(excl, c) <= a) lo = c;
+          }
+          const int xo = __shfl(x, lo), bo = __shfl(beg, lo);
+          const int j = a - __shfl(excl, lo);
+          const uint32_t nbo = __shfl((int)nb, lo);
+          int t1 = 0, t2 = 0;
+          bool v1 = false, v2 = false;
+          if (a < A) {
+            if (k == 0) {
+              const int2 ep = g.vinc[bo + j];
+              t1 = g.NB + 2 * ep.x;
+              t2 = t1 + 1;
+              // bits of e_in and e_out share a word (NB and 2e are even)
+              const uint32_t sw = g.seen[t1 >> 5] >> (t1 & 31);
+              nbytes += 12;
+              if (!(sw & 2u)) v2 = label_rev<kClaim, true>(g, t2, lvl);  // e_out -> x infinite
+              if (!(sw & 1u) && pin_flow_in(g, ep.y))                    // e_in -> x reverse
+                v1 = label_rev<kClaim, true>(g, t1, lvl);
+            } else if (j == 0) {
+              if (k == 1) {
+                t1 = xo + 1;  // e_out -> e_in residual fb
+                v1 = (nbo & 4u) && label_rev<kClaim>(g, t1, lvl);
+              } else {
+                t1 = xo - 1;  // e_in -> e_out residual w - fb
+                v1 = (nbo & 1u) && label_rev<kClaim>(g, t1, lvl);
+              }
+            } else {
+              const int i = bo + j - 1;
+              t1 = g.pin_v[i];
+              // r_in (u -> e_in) or f_out (u -> e_out)
+              const int f = g.fpin[2 * i + (k == 1 ? 0 : 1)];
+              nbytes += 12;
+              if (f > 0) v1 = label_rev<kClaim>(g, t1, lvl);
+            }
+          }
+          if (kClaim) {
+            qpush(g, q, t1, v1);
+            qpush(g, q, t2, v2);
+          }
+        }
+      } else if (it < total) {
+        const int v = g.list[cp][kBigList][it - s3];
+        const bool has = !is_huge(g, v);
+        nitems += has && lane == 0;
+        bfs_rev_node<kClaim>(g, q, v, has, lane, kWave, lvl, nbytes);
+      }
+    } else {
+      const int v = g.list[cp][kBigList][tile - ntiles];
+      const bool has = is_huge(g, v);  // block-uniform
+      nitems += has && threadIdx.x == 0;
+      bfs_rev_node<kClaim>(g, q, v, has, threadIdx.x, blockDim.x, lvl, nbytes);
+    }
+    if (kClaim) bq_tile_end(q, q.cap / 2);
+  }
+  if (kClaim) bq_flush(q);
+  block_add_u64(&g.ctl->bytes[kc], (unsigned long long)nbytes + 4ull * nitems, &g.ctl->items[kc],
+                nitems);
 }
 
 // ---------------------------------------------------------------------------
@@ -1407,6 +1553,7 @@ __device__ void phase_bfs_rev_pull(const Dev& g, int level, int t0, int tstride,
     }
     if (hit) {
       g.d[v] = lvl;
+      if (g.lev) g.lev[v] = 1;  // listed (and marked 2) by the collect sweep
       set_seen(g, v);
     }
   }
@@ -1417,6 +1564,7 @@ template <int G>
 __device__ void phase_bfs_rev(const Dev& g, int level, int tile0, int tstride, int kc,
                               lds_int* lds) {
   if (g.bfs_arc) phase_bfs_rev_lb<true>(g, level, tile0, tstride, kc, lds);
+  else if (g.bfs_flat) phase_bfs_rev_flat<true>(g, level, tile0, tstride, kc, lds);
   else phase_bfs_rev_node<G, true>(g, level, tile0, tstride, kc, lds);
 }
 
@@ -1428,6 +1576,7 @@ template <int G>
 __device__ void phase_bfs_rev_expand(const Dev& g, int level, int tile0, int tstride, int kc,
                                      lds_int* lds) {
   if (g.bfs_arc) phase_bfs_rev_lb<false>(g, level, tile0, tstride, kc, lds);
+  else if (g.bfs_flat) phase_bfs_rev_flat<false>(g, level, tile0, tstride, kc, lds);
   else phase_bfs_rev_node<G, false>(g, level, tile0, tstride, kc, lds);
 }
 
@@ -1448,7 +1597,17 @@ __device__ void phase_bfs_collect(const Dev& g, int level, int tile0, int tstrid
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int v = (2 * tile + j) * blockDim.x + threadIdx.x;
-      qpush(g, q, v, v < g.N && g.d[v] == lab);
+      bool fresh = false;
+      if (g.lev) {  // byte marks: the level's nodes carry mark 1 and get their label here
+        fresh = v < g.N && g.lev[v] == 1;
+        if (fresh) {
+          g.lev[v] = 2;
+          g.d[v] = lab;
+        }
+      } else {
+        fresh = v < g.N && g.d[v] == lab;
+      }
+      qpush(g, q, v, fresh);
     }
     bq_tile_end(q, 2 * blockDim.x);
   }
@@ -1559,6 +1718,7 @@ __device__ void phase_gr_reset(const Dev& g, int tile0, int tstride, lds_int* ld
           lab = g.N + 1;
         }
         g.d[v] = lab;
+        if (g.lev) g.lev[v] = lab == g.N ? 0 : 2;
       }
       qpush(g, q, v, seed);
     }

@@ -59,7 +59,9 @@ class Options(ctypes.Structure):
         ("bfs_arc_parallel", ctypes.c_int32),
         ("pull_min", ctypes.c_int32),
         ("tail_gr_interval", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("bfs_flat", ctypes.c_int32),
+        ("bfs_marks", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 1),
     ]
 
 

@@ -111,6 +111,9 @@ def test_debug_invariants_every_round(hf, oracle_mod):
     dict(gr_interval=1), dict(pull_min=1), dict(pull_min=1, tail_threshold=1),
     dict(pull_min=5000), dict(tail_gr_interval=-1), dict(tail_gr_interval=1),
     dict(tail_gr_interval=1000, tail_threshold=1 << 30),
+    dict(bfs_flat=-1), dict(bfs_marks=-1), dict(bfs_flat=-1, bfs_marks=-1),
+    dict(bfs_flat=-1, bottom_up_min=1, tail_threshold=1),
+    dict(bfs_marks=-1, bottom_up_min=1, tail_threshold=1), dict(bfs_flat=1, big_degree=2),
 ], ids=str)
 def test_schedule_invariance(hf, oracle_mod, opts):
     """Every tuning knob changes only the schedule, never the result."""
@@ -123,7 +126,10 @@ def test_schedule_invariance(hf, oracle_mod, opts):
 
 
 @pytest.mark.parametrize("opts", [dict(), dict(pull_min=1, tail_threshold=1),
-                                  dict(bottom_up_min=1, tail_threshold=1)], ids=str)
+                                  dict(bottom_up_min=1, tail_threshold=1),
+                                  dict(bottom_up_min=1, tail_threshold=1, bfs_marks=-1),
+                                  dict(bottom_up_min=-1, tail_threshold=1),
+                                  dict(bfs_flat=-1, bfs_marks=-1, tail_threshold=1)], ids=str)
 def test_labels_and_preflow_certificate(hf, oracle_mod, opts):
     """After the solve the labels are exact residual distances of the final
     state (the terminating global relabel), the state is a feasible preflow
