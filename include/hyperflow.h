@@ -105,14 +105,14 @@ typedef struct {
                                  frontier fits the single-workgroup loop
                                  (tail_threshold); default 4 * gr_interval,
                                  -1 = gr_interval                            */
-  int32_t bfs_flat;           /* reverse-BFS levels spread the arcs of a
-                                 wave's 64 nodes over its lanes; 1 = on
+  int32_t bfs_flat;           /* expanded reverse-BFS levels spread the arcs
+                                 of a wave's 64 nodes over its lanes; 1 = on
                                  (default), -1 = a fixed group of lanes per
                                  node (group_lanes)                          */
   int32_t bfs_marks;          /* expanded reverse-BFS levels mark reached
                                  nodes in a byte array and the collect sweep
-                                 writes their labels; 1 = on (default),
-                                 -1 = labels written during the expansion   */
+                                 writes their labels; 1 = on, -1 = labels
+                                 written during the expansion (default)     */
   int32_t reserved[1];
 } fp_options;
 
@@ -367,7 +367,8 @@ typedef struct {
   int64_t flow;          /* cut weight of the returned bipartition            */
   int64_t source_weight; /* c(X) of the returned source side X                */
   int64_t sink_weight;   /* c(V \ X)                                         */
-  int32_t iterations;    /* maximum flows computed                            */
+  int32_t iterations;    /* maximum flows computed by the run so far (all
+                            calls of a continued run)                       */
   int32_t status;        /* 0 balanced, 1 no piercing vertex left (the last
                             cut is returned), 2 iteration cap (the last
                             source side is returned)                        */
@@ -376,8 +377,13 @@ typedef struct {
   int32_t augmenting;    /* piercing steps that could not avoid an augmenting
                             path                                             */
   int32_t first_balanced; /* iteration of the first balanced cut, 0 if none  */
+  int32_t slice_iterations; /* iterations run by this call (= trace entries
+                               written)                                     */
+  int32_t resumable;     /* 1 when this call stopped at its iteration limit
+                            before the run ended: flow_problem_flowcutter_
+                            continue resumes it                             */
   int32_t reserved32;
-  int64_t reserved[3];
+  int64_t reserved[2];
 } fp_cutter_result;
 
 /* One FlowCutter iteration. */
@@ -449,6 +455,41 @@ fp_status flow_problem_flowcutter(fp_problem *problem, const int32_t *vertex_wei
                                   int32_t most_balanced, void *hip_stream, int32_t mem_kind,
                                   uint8_t *vertex_side, fp_cutter_result *result,
                                   fp_cutter_step *trace);
+
+/*
+ * flow_problem_flowcutter_continue: resume the FlowCutter run of the last
+ * flow_problem_flowcutter call on this handle after it stopped at its
+ * iteration limit (result->resumable = 1), for up to max_iterations more
+ * iterations, exactly as one uninterrupted run would go on: the bounds,
+ * bulk-piercing goals and most balanced cut so far are kept in the handle
+ * (a caller can so run FlowCutter in slices, e.g. under a time limit as the
+ * paper's scheduler aborts long flow computations, section "Parallel
+ * Active Block Scheduling", paragraph "Implementation Details").  The
+ * vertex weights are those of the starting call.  trace receives this
+ * call's iterations (result->slice_iterations entries); result->iterations
+ * counts the whole run.  Other calls on the handle in between are allowed
+ * (the next iteration then re-derives its sides).
+ *
+ * Errors: FP_ERR_STATE when there is no run to continue, FP_ERR_INVALID,
+ * FP_ERR_ABORTED, FP_ERR_DEVICE.
+ */
+fp_status flow_problem_flowcutter_continue(fp_problem *problem, int32_t max_iterations,
+                                           void *hip_stream, int32_t mem_kind,
+                                           uint8_t *vertex_side, fp_cutter_result *result,
+                                           fp_cutter_step *trace);
+
+/*
+ * flow_problem_terminals: the current terminal sets (after piercing, section
+ * "Flow-Based Refinement", algorithm "FlowCutter Core": the pierced side's
+ * reachable set plus the piercing vertices become terminals).
+ *
+ *   mem_kind  memory kind of roles
+ *   roles     |V| bytes: 0 free, 1 source, 2 sink
+ *
+ * Errors: FP_ERR_INVALID, FP_ERR_DEVICE.
+ */
+fp_status flow_problem_terminals(fp_problem *problem, void *hip_stream, int32_t mem_kind,
+                                 uint8_t *roles);
 
 /*
  * Learned pruning scorer (pattern of the paper's pruning rules, section

@@ -30,6 +30,7 @@ Contents
                        network (capacities, non-negative excess, value).
 ``residual_labels``    exact residual distances to the sink in the capped
                        network for a given flow state (plain BFS).
+``maxflow_many``       ``maxflow`` of many hypergraphs on a process pool.
 
 The paper prints no worked example for this path (its two illustrative
 figures are not part of the text), so the pins of this oracle are
@@ -147,6 +148,41 @@ def maxflow(hg, selfcheck: bool = False, sink_side: bool = False) -> OracleResul
 # ---------------------------------------------------------------------------
 # plain definitions
 # ---------------------------------------------------------------------------
+
+class _Plain:
+    """Minimal hypergraph record passed to worker processes."""
+
+    def __init__(self, t):
+        (self.num_vertices, self.net_offsets, self.pins, self.net_weights, self.sources,
+         self.sinks) = t
+
+    @property
+    def num_nets(self):
+        return int(self.net_offsets.shape[0] - 1)
+
+
+def _maxflow_worker(t):
+    r = maxflow(_Plain(t))
+    return r.flow, r.vertex_side, r.net_side
+
+
+def maxflow_many(hgs, workers=None):
+    """``maxflow`` of every hypergraph in ``hgs`` on a pool of ``workers``
+    processes (started fresh, so a parent that holds a GPU context shares
+    nothing with them).  Returns a list of (F, vertex_side, net_side)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1)
+    args = [(int(h.num_vertices), np.ascontiguousarray(h.net_offsets), np.ascontiguousarray(h.pins),
+             np.ascontiguousarray(h.net_weights), np.ascontiguousarray(h.sources),
+             np.ascontiguousarray(h.sinks)) for h in hgs]
+    if workers <= 1 or len(args) <= 1:
+        return [_maxflow_worker(a) for a in args]
+    with cf.ProcessPoolExecutor(max_workers=workers,
+                                mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_maxflow_worker, args, chunksize=max(1, len(args) // (4 * workers))))
+
 
 def _pins_inside(hg, x):
     """Number of pins of each net that lie in x."""

@@ -285,6 +285,37 @@ fp_status flow_problem_flowcutter(fp_problem* problem, const int32_t* vertex_wei
                             trace);
 }
 
+fp_status flow_problem_flowcutter_continue(fp_problem* problem, int32_t max_iterations,
+                                           void* hip_stream, int32_t mem_kind,
+                                           uint8_t* vertex_side, fp_cutter_result* result,
+                                           fp_cutter_step* trace) {
+  g_last_error.clear();
+  if (!problem) {
+    set_error("NULL handle");
+    return FP_ERR_STATE;
+  }
+  if (!vertex_side || !result || max_iterations < 1 || (mem_kind != 0 && mem_kind != 1)) {
+    set_error("invalid FlowCutter arguments");
+    return FP_ERR_INVALID;
+  }
+  return flowcutter_continue(problem, max_iterations, static_cast<hipStream_t>(hip_stream),
+                             mem_kind, vertex_side, result, trace);
+}
+
+fp_status flow_problem_terminals(fp_problem* problem, void* hip_stream, int32_t mem_kind,
+                                 uint8_t* roles) {
+  g_last_error.clear();
+  if (!problem) {
+    set_error("NULL handle");
+    return FP_ERR_STATE;
+  }
+  if (!roles || (mem_kind != 0 && mem_kind != 1)) {
+    set_error("roles must be non-NULL and mem_kind 0 or 1");
+    return FP_ERR_INVALID;
+  }
+  return terminals_problem(problem, static_cast<hipStream_t>(hip_stream), mem_kind, roles);
+}
+
 static fp_status check_samples(const void* f, int32_t n, int32_t mem_kind) {
   if (!f || n < 1 || (mem_kind != 0 && mem_kind != 1)) {
     set_error("need features, n >= 1 and mem_kind 0 or 1");

@@ -266,7 +266,7 @@ fp_options resolve_options(const fp_options* o) {
   if (r.stale_rounds == 0) r.stale_rounds = 500;
   if (r.stale_rounds < 0) r.stale_rounds = 0;
   if (r.bfs_flat == 0) r.bfs_flat = 1;
-  if (r.bfs_marks == 0) r.bfs_marks = 1;
+  if (r.bfs_marks == 0) r.bfs_marks = -1;
   return r;
 }
 
@@ -537,6 +537,8 @@ void release_problem(fp_problem* pb) {
   for (auto e : pb->free_events) hipEventDestroy(e);
   pool_release(pb->device, pb->pool, pb->pool_bytes);
   if (pb->cw) hipFree(pb->cw);
+  if (pb->fc_mem) hipFree(pb->fc_mem);
+  pb->fc_mem = nullptr;
   ctl_release(pb->ctl_h);
   pb->pool = nullptr;
   pb->cw = nullptr;

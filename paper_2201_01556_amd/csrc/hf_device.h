@@ -1158,13 +1158,12 @@ __device__ void phase_bfs_rev_node(const Dev& g, int level, int tile0, int tstri
 // ---------------------------------------------------------------------------
 
 template <bool kClaim>
-__device__ void phase_bfs_rev_flat(const Dev& g, int level, int tile0, int tstride, int kc,
+__device__ __forceinline__ void phase_bfs_rev_flat(const Dev& g, int level, int tile0, int tstride, int kc,
                                    lds_int* lds) {
   const int c3 = level % 3, n3 = (level + 1) % 3, z3 = (level + 2) % 3;
   if (tile0 == 0 && threadIdx.x < kNL) g.ctl->bcnt[z3][threadIdx.x] = 0;
   const int cp = level & 1, np = (level + 1) & 1;
-  BlockQ q{};
-  if (kClaim) q = bq_bind(lds, g.ctl->bcnt[n3], g.list[np]);
+  const BlockQ q = bq_bind(lds, g.ctl->bcnt[n3], g.list[np]);
   const Quad n = load_counts(g.ctl->bcnt[c3]);
   // wave items: 64 entries of list 0, of list 1, of list 2, then one big node each
   const int s1 = (n.v0 + kWave - 1) / kWave;
@@ -1564,7 +1563,6 @@ template <int G>
 __device__ void phase_bfs_rev(const Dev& g, int level, int tile0, int tstride, int kc,
                               lds_int* lds) {
   if (g.bfs_arc) phase_bfs_rev_lb<true>(g, level, tile0, tstride, kc, lds);
-  else if (g.bfs_flat) phase_bfs_rev_flat<true>(g, level, tile0, tstride, kc, lds);
   else phase_bfs_rev_node<G, true>(g, level, tile0, tstride, kc, lds);
 }
 
@@ -1576,7 +1574,6 @@ template <int G>
 __device__ void phase_bfs_rev_expand(const Dev& g, int level, int tile0, int tstride, int kc,
                                      lds_int* lds) {
   if (g.bfs_arc) phase_bfs_rev_lb<false>(g, level, tile0, tstride, kc, lds);
-  else if (g.bfs_flat) phase_bfs_rev_flat<false>(g, level, tile0, tstride, kc, lds);
   else phase_bfs_rev_node<G, false>(g, level, tile0, tstride, kc, lds);
 }
 

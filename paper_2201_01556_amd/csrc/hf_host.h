@@ -39,6 +39,36 @@ struct Timer {
   hipEvent_t a, b;
 };
 
+// State of a FlowCutter run between calls: flow_problem_flowcutter starts a
+// run, flow_problem_flowcutter_continue resumes one that stopped at its
+// iteration limit (the loop variables below are exactly those of one
+// uninterrupted run).
+struct FcRun {
+  bool active = false;  // stopped at the iteration limit; may be continued
+  int64_t max_src = 0, max_snk = 0;
+  int32_t bulk_percent = 0, most_balanced = 0;
+  long long total = 0;  // c(V)
+  int32_t it = 0;       // iterations done
+  fp_cutter_result r{};
+  // most balanced cut so far
+  long long best_heavier = -1, best_src = 0, best_snk = 0;
+  int best_kind = 0;
+  int64_t best_F = 0;
+  int32_t first_balanced = 0;
+  // bulk piercing bookkeeping per side
+  long long pierces[2] = {0, 0}, gained[2] = {0, 0}, pierced[2] = {0, 0};
+  long long term[2] = {-1, -1}, missed[2] = {0, 0};
+  int pend_side = -1;
+  long long pend_before = 0, pend_count = 0, pend_goal = -1;
+  // reachable sets kept across a pierce without augmenting path
+  int prev_ep_s = -1, prev_ep_t = -1, grow = -1, grow_vertex = -1;
+  bool seeded = false;
+  int64_t last_F = 0;
+  long long last_cs = 0;
+  int out_ep = -1, out_invert = 0;
+  int32_t epoch_end = 0;  // handle epoch when the last call returned
+};
+
 }  // namespace hf
 
 struct fp_problem {
@@ -57,6 +87,8 @@ struct fp_problem {
   bool inited = false;
   bool solved = false;
   int32_t* cw = nullptr;     // vertex weights of the last FlowCutter run (device)
+  void* fc_mem = nullptr;    // FlowCutter scratch: candidate flags, tile counts, best side
+  hf::FcRun fc;
   fp_stats st{};
   // profiling
   std::vector<hf::Timer> pending;
@@ -112,6 +144,9 @@ fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src,
                              int32_t max_iters, int32_t bulk_percent, int32_t most_balanced,
                              hipStream_t s, int32_t mem_kind, uint8_t* vside,
                              fp_cutter_result* res, fp_cutter_step* trace);
+fp_status flowcutter_continue(fp_problem* pb, int32_t max_iters, hipStream_t s, int32_t mem_kind,
+                              uint8_t* vside, fp_cutter_result* res, fp_cutter_step* trace);
+fp_status terminals_problem(fp_problem* pb, hipStream_t s, int32_t mem_kind, uint8_t* roles);
 fp_status export_state(fp_problem* pb, hipStream_t s, int32_t* f_in, int32_t* f_out,
                        int32_t* f_b, int32_t* labels, int32_t* excess);
 void release_problem(fp_problem* pb);

@@ -69,6 +69,29 @@ k_bfs_rev(Dev g, int level, int big_min, int pull_min, int tail) {
   else phase_bfs_rev<G>(g, level, blockIdx.x, gridDim.x, KC_BFS_REV, lds);
 }
 
+// The same level with the expanded (large) levels' arcs flattened per wave
+// (phase_bfs_rev_flat), a kernel of its own so that neither variant's
+// register and inlining budget weighs on the other.  Claiming levels stay
+// node-grouped: they are the smaller ones, and 64 nodes per wave leave most
+// of the grid idle there.
+template <int G>
+__global__ void __launch_bounds__(kBlock) HF_TWO_WORKGROUPS_PER_CU
+k_bfs_rev_flat(Dev g, int level, int big_min, int pull_min, int tail) {
+  HF_QUEUE_LDS;
+  const int c3 = level % 3;
+  const int nf = count_all(g.ctl->bcnt[c3]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (nf > tail) atomicMax(&g.ctl->big_last, level);
+    if (level < kLvlHist) g.ctl->lvl_nf[level] = nf;
+  }
+  if (nf >= pull_min)
+    phase_bfs_rev_pull(g, level, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x,
+                       KC_BFS_REV);
+  else if (nf >= big_min)
+    phase_bfs_rev_flat<false>(g, level, blockIdx.x, gridDim.x, KC_BFS_REV, lds);
+  else phase_bfs_rev_node<G, true>(g, level, blockIdx.x, gridDim.x, KC_BFS_REV, lds);
+}
+
 // Expanded and pulled levels list their new nodes by a sweep over the labels.
 __global__ void __launch_bounds__(kBlock) k_bfs_collect(Dev g, int level, int big_min,
                                                         int pull_min) {
@@ -389,7 +412,8 @@ static void launch_levels(fp_problem* pb, hipStream_t s, int ep, int ep_tmp, int
       }
       {
         Launch L(pb, s, KK_BFS_REV);
-        k_bfs_rev<G><<<grid, kBlock, 0, s>>>(g, lv, bmin, pmin, cap);
+        if (g.bfs_flat && !g.bfs_arc) k_bfs_rev_flat<G><<<grid, kBlock, 0, s>>>(g, lv, bmin, pmin, cap);
+        else k_bfs_rev<G><<<grid, kBlock, 0, s>>>(g, lv, bmin, pmin, cap);
       }
       if (bmin != off || pmin != off) {
         Launch L(pb, s, KK_BFS_COLLECT);
@@ -979,109 +1003,84 @@ fp_status pierce_problem(fp_problem* pb, int32_t side, const int32_t* vertices, 
 // (paragraph "Bulk Piercing": one node for the first few rounds).
 constexpr int kBulkWarmup = 3;
 
-// Scratch of the bulk selection: candidate flags, then tile counts.
-struct BulkScratch {
-  void* mem = nullptr;
-  hipStream_t s = nullptr;
-  ~BulkScratch() {
-    if (mem) (void)hipFreeAsync(mem, s);
-  }
-};
+// Roles as bytes (0 free, 1 source, 2 sink).
+__global__ void __launch_bounds__(kThreads) k_roles_out(Dev g, uint8_t* roles) {
+  for (int v = gthread(); v < g.V; v += gthreads()) roles[v] = (uint8_t)g.role[v];
+}
 
-fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src, int64_t max_snk,
-                             int32_t max_iters, int32_t bulk_percent, int32_t most_balanced,
-                             hipStream_t s, int32_t mem_kind, uint8_t* vside,
-                             fp_cutter_result* res, fp_cutter_step* trace) {
+fp_status terminals_problem(fp_problem* pb, hipStream_t s, int32_t mem_kind, uint8_t* roles) {
   Dev& g = pb->dev;
-  long long total = 0;
-  for (int32_t v = 0; v < pb->V; ++v) {
-    if (vw[v] < 0) {
-      set_error("vertex weight of %d is negative", v);
-      return FP_ERR_INVALID;
-    }
-    total += vw[v];
-  }
+  // host outputs are staged in the big-node list of parity 1 (4N bytes >= V)
+  uint8_t* out = mem_kind == 0 ? reinterpret_cast<uint8_t*>(g.list[1][kBigList]) : roles;
+  k_roles_out<<<sweep_grid(pb->V), kThreads, 0, s>>>(g, out);
+  hipError_t he = hipGetLastError();
+  if (he == hipSuccess && mem_kind == 0)
+    he = hipMemcpyAsync(roles, out, pb->V, hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  if (he != hipSuccess) return hip_fail(he, "exporting the terminals");
+  return FP_OK;
+}
+
+// Up to `slice` more iterations of the FlowCutter run held in pb->fc (see
+// flowcutter_problem); trace[0 .. slice) receives this call's iterations.
+static fp_status flowcutter_run(fp_problem* pb, int32_t slice, hipStream_t s, int32_t mem_kind,
+                                uint8_t* vside, fp_cutter_result* res, fp_cutter_step* trace) {
+  Dev& g = pb->dev;
+  FcRun& f = pb->fc;
+  f.active = false;  // set again below if the slice ends at its limit
+  const long long total = f.total;
+  const int64_t max_src = f.max_src, max_snk = f.max_snk;
+  const int32_t bulk_percent = f.bulk_percent, most_balanced = f.most_balanced;
   hipError_t he = hipSuccess;
-  if (!pb->cw) {
-    he = hipMalloc(reinterpret_cast<void**>(&pb->cw), (size_t)pb->V * sizeof(int32_t));
-    if (he != hipSuccess) {
-      pb->cw = nullptr;
-      return hip_fail(he, "allocating vertex weights");
-    }
-  }
-  he = hipMemcpyAsync(pb->cw, vw, (size_t)pb->V * sizeof(int32_t), hipMemcpyHostToDevice, s);
-  if (he != hipSuccess) return hip_fail(he, "copying vertex weights");
   const int ntiles = (pb->V + kBlock - 1) / kBlock;
   const size_t flag_bytes = ((size_t)pb->V + 3) & ~(size_t)3;
   const size_t count_bytes = 4 * ((size_t)ntiles + 1);
-  BulkScratch bulk;
-  bulk.s = s;
-  if (bulk_percent > 0 || most_balanced) {
-    he = hipMallocAsync(&bulk.mem, 2 * flag_bytes + count_bytes, s);
-    if (he != hipSuccess) {
-      bulk.mem = nullptr;
-      return hip_fail(he, "allocating the FlowCutter scratch");
-    }
-  }
   // [flags: V bytes][tile counts][most balanced side so far: V bytes]
-  uint8_t* flags = static_cast<uint8_t*>(bulk.mem);
-  int32_t* tile_counts = bulk.mem ? reinterpret_cast<int32_t*>(flags + flag_bytes) : nullptr;
-  uint8_t* best_side = bulk.mem ? flags + flag_bytes + count_bytes : nullptr;
-  // most balanced cut: heavier side, kind and weights of the best cut so far
-  long long best_heavier = -1, best_src = 0, best_snk = 0;
-  int best_kind = 0;
-  int64_t best_F = 0;
-  int32_t first_balanced = 0;
-  // bulk piercing bookkeeping per side, integer arithmetic (see the header)
-  long long pierces[2] = {0, 0}, gained[2] = {0, 0}, pierced[2] = {0, 0};
-  long long term[2] = {-1, -1}, missed[2] = {0, 0};
-  int pend_side = -1;
-  long long pend_before = 0, pend_count = 0, pend_goal = -1;
-  fp_cutter_result r{};
+  uint8_t* flags = static_cast<uint8_t*>(pb->fc_mem);
+  int32_t* tile_counts = flags ? reinterpret_cast<int32_t*>(flags + flag_bytes) : nullptr;
+  uint8_t* best_side = flags ? flags + flag_bytes + count_bytes : nullptr;
   uint8_t* vs = mem_kind == 0 ? reinterpret_cast<uint8_t*>(pb->dev.list[1][kBigList]) : vside;
-  int out_ep = -1, out_invert = 0;
-  long long last_cs = 0;
-  r.status = 2;  // iteration cap unless a branch below decides
-  // reachable sets kept across a pierce without augmenting path (grow_side)
-  int prev_ep_s = -1, prev_ep_t = -1, grow = -1, grow_vertex = -1;
-  bool seeded = false;  // the last source pierce listed the growth's level 0
-  int64_t last_F = 0;
-  for (int32_t it = 1; it <= max_iters; ++it) {
+  fp_cutter_result& r = f.r;
+  r.status = 2;  // iteration limit unless a branch below decides
+  int32_t done_here = 0;
+  for (int32_t n = 0; n < slice; ++n) {
+    const int32_t it = ++f.it;
+    ++done_here;
     int64_t F = 0;
     fp_status st = FP_OK;
-    if (grow >= 0 && !pb->opt.debug_checks) {
+    if (f.grow >= 0 && !pb->opt.debug_checks) {
       // the last pierce took a vertex outside S_r and T_r: no residual path
       // joins it to the other side (paragraph "Piercing"), so the preflow
       // stays maximum and the flow value unchanged; no solve is needed
-      F = last_F;
+      F = f.last_F;
       pb->solved = true;
     } else {
       const int64_t rounds0 = pb->st.rounds;
       st = solve_problem(pb, s, &F);
       if (st) return st;
-      if (grow >= 0 && (pb->st.rounds != rounds0 || F != last_F)) {
+      if (f.grow >= 0 && (pb->st.rounds != rounds0 || F != f.last_F)) {
         set_error("internal check: a pierce without augmenting path changed the flow");
         return FP_ERR_DEVICE;
       }
     }
-    last_F = F;
+    f.last_F = F;
     int ep_s = 0, ep_t = 0;
-    const int grown = grow;
-    const bool spec = grow >= 0 && !pb->opt.debug_checks;  // growth without round trips
-    seeded = seeded && spec;
-    if (grow >= 0) {
-      ep_s = prev_ep_s;
-      ep_t = prev_ep_t;
-      const int ep = grow == 0 ? ep_s : ep_t;
-      st = spec ? grow_side_start(pb, s, grow, ep, grow_vertex, seeded)
-                : grow_side(pb, s, grow, ep, grow_vertex);
+    const int grown = f.grow;
+    const bool spec = f.grow >= 0 && !pb->opt.debug_checks;  // growth without round trips
+    f.seeded = f.seeded && spec;
+    if (f.grow >= 0) {
+      ep_s = f.prev_ep_s;
+      ep_t = f.prev_ep_t;
+      const int ep = f.grow == 0 ? ep_s : ep_t;
+      st = spec ? grow_side_start(pb, s, f.grow, ep, f.grow_vertex, f.seeded)
+                : grow_side(pb, s, f.grow, ep, f.grow_vertex);
     } else {
       st = sides(pb, s, 3, &ep_s, &ep_t);
     }
     if (st) return st;
-    grow = -1;
-    prev_ep_s = ep_s;
-    prev_ep_t = ep_t;
+    f.grow = -1;
+    f.prev_ep_s = ep_s;
+    f.prev_ep_t = ep_t;
     k_fc_weights<<<sweep_grid(pb->V), kThreads, 0, s>>>(g, pb->cw, ep_s, ep_t);
     k_fc_candidates<<<sweep_grid(pb->E), kThreads, 0, s>>>(g, ep_s, ep_t);
     st = sync_ctl(pb, s);
@@ -1105,17 +1104,18 @@ fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src,
     }
     const long long cs = (long long)pb->ctl_h->side_weight[0];
     const long long ct = (long long)pb->ctl_h->side_weight[1];
-    if (pend_side >= 0) {  // gain of the side pierced last iteration
-      const long long gain = std::max(0ll, (pend_side == 0 ? cs : ct) - pend_before);
-      gained[pend_side] += gain;
-      pierced[pend_side] += pend_count;
-      if (pend_goal >= 0) missed[pend_side] = std::max(0ll, pend_goal - gain);
-      pend_side = -1;
+    if (f.pend_side >= 0) {  // gain of the side pierced last iteration
+      const int ps = f.pend_side;
+      const long long gain = std::max(0ll, (ps == 0 ? cs : ct) - f.pend_before);
+      f.gained[ps] += gain;
+      f.pierced[ps] += f.pend_count;
+      if (f.pend_goal >= 0) f.missed[ps] = std::max(0ll, f.pend_goal - gain);
+      f.pend_side = -1;
     }
     r.iterations = it;
     r.flow = F;
-    out_ep = ep_s;  // the iteration cap reports this iteration's S_r
-    last_cs = cs;
+    f.out_ep = ep_s;  // the iteration limit reports this iteration's S_r
+    f.last_cs = cs;
     fp_cutter_step step{};
     step.flow = F;
     step.source_weight = cs;
@@ -1131,34 +1131,34 @@ fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src,
       r.side = 0;
       r.source_weight = cs;
       r.sink_weight = total - cs;
-      out_ep = ep_s;
-      out_invert = 0;
-      first_balanced = it;
+      f.out_ep = ep_s;
+      f.out_invert = 0;
+      f.first_balanced = it;
       done = true;
     } else if (!most_balanced && bal1) {
       r.status = 0;
       r.side = 1;
       r.source_weight = total - ct;
       r.sink_weight = ct;
-      out_ep = ep_t;
-      out_invert = 1;
-      first_balanced = it;
+      f.out_ep = ep_t;
+      f.out_invert = 1;
+      f.first_balanced = it;
       done = true;
-    } else if (most_balanced && (bal0 || bal1 || best_heavier >= 0)) {
+    } else if (most_balanced && (bal0 || bal1 || f.best_heavier >= 0)) {
       // most balanced cut: keep the best balanced cut offered so far (its
       // side is copied now: later pierces grow the stamped sets) and pierce
       // on while a vertex outside S_r and T_r is left
-      if (first_balanced == 0) first_balanced = it;
+      if (f.first_balanced == 0) f.first_balanced = it;
       for (int kind = 0; kind < 2; ++kind) {
         if (!(kind == 0 ? bal0 : bal1)) continue;
         const long long src = kind == 0 ? cs : total - ct;
         const long long heavier = std::max(src, total - src);
-        if (best_heavier >= 0 && heavier >= best_heavier) continue;
-        best_heavier = heavier;
-        best_kind = kind;
-        best_src = src;
-        best_snk = total - src;
-        best_F = F;
+        if (f.best_heavier >= 0 && heavier >= f.best_heavier) continue;
+        f.best_heavier = heavier;
+        f.best_kind = kind;
+        f.best_src = src;
+        f.best_snk = total - src;
+        f.best_F = F;
         k_side_out<<<sweep_grid(pb->V), kThreads, 0, s>>>(g, kind == 0 ? ep_s : ep_t, kind,
                                                           best_side);
         he = hipGetLastError();
@@ -1173,13 +1173,13 @@ fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src,
         step.side = side;
         step.node = p;
         step.count = 1;
-        grow = side;
-        grow_vertex = p;
+        f.grow = side;
+        f.grow_vertex = p;
         k_stamp_vertex<<<1, 64, 0, s>>>(g, p, side == 0 ? ep_s : ep_t);
         he = hipGetLastError();
         if (he != hipSuccess) return hip_fail(he, "marking the piercing vertex");
-        seeded = side == 0 && !pb->opt.debug_checks;
-        st = apply_pierce(pb, s, side, side == 0 ? ep_s : ep_t, seeded);
+        f.seeded = side == 0 && !pb->opt.debug_checks;
+        st = apply_pierce(pb, s, side, side == 0 ? ep_s : ep_t, f.seeded);
         if (st) return st;
       }
     } else {
@@ -1200,29 +1200,29 @@ fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src,
         if (side == 0) {
           r.source_weight = cs;
           r.sink_weight = total - cs;
-          out_ep = ep_s;
-          out_invert = 0;
+          f.out_ep = ep_s;
+          f.out_invert = 0;
         } else {
           r.source_weight = total - ct;
           r.sink_weight = ct;
-          out_ep = ep_t;
-          out_invert = 1;
+          f.out_ep = ep_t;
+          f.out_invert = 1;
         }
         done = true;
       } else {
         if (aug) r.augmenting++;
         else {
-          grow = side;
-          grow_vertex = p;
+          f.grow = side;
+          f.grow_vertex = p;
         }
         const int ep = side == 0 ? ep_s : ep_t;
         const long long weight = side == 0 ? cs : ct;
         long long k = 1, goal = -1;
-        if (aug && bulk_percent > 0 && pierces[side] >= kBulkWarmup && gained[side] > 0) {
-          if (term[side] < 0) term[side] = std::max(0ll, total / 2 - weight);
-          term[side] = term[side] * bulk_percent / 100;
-          goal = term[side] + missed[side];
-          k = std::max(1ll, goal * pierced[side] / gained[side]);
+        if (aug && bulk_percent > 0 && f.pierces[side] >= kBulkWarmup && f.gained[side] > 0) {
+          if (f.term[side] < 0) f.term[side] = std::max(0ll, total / 2 - weight);
+          f.term[side] = f.term[side] * bulk_percent / 100;
+          goal = f.term[side] + f.missed[side];
+          k = std::max(1ll, goal * f.pierced[side] / f.gained[side]);
         }
         long long count = 1;
         if (k > 1) {
@@ -1247,48 +1247,112 @@ fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src,
           if (he != hipSuccess) return hip_fail(he, "marking the piercing vertex");
         }
         step.count = (int32_t)count;
-        pierces[side] += 1;
-        pend_side = side;
-        pend_before = weight;
-        pend_count = count;
-        pend_goal = goal;
-        seeded = !aug && side == 0 && !pb->opt.debug_checks;
-        st = apply_pierce(pb, s, side, ep, seeded);
+        f.pierces[side] += 1;
+        f.pend_side = side;
+        f.pend_before = weight;
+        f.pend_count = count;
+        f.pend_goal = goal;
+        f.seeded = !aug && side == 0 && !pb->opt.debug_checks;
+        st = apply_pierce(pb, s, side, ep, f.seeded);
         if (st) return st;
       }
     }
-    if (trace) trace[it - 1] = step;
+    if (trace) trace[n] = step;
     if (done) break;
   }
-  if (out_ep < 0) {
-    set_error("max_iterations must be at least 1");
-    return FP_ERR_INVALID;
-  }
-  r.first_balanced = first_balanced;
-  if (best_heavier >= 0) {  // most balanced cut (also when the cap ended the run)
-    r.status = 0;
-    r.side = best_kind;
-    r.flow = best_F;
-    r.source_weight = best_src;
-    r.sink_weight = best_snk;
+  fp_cutter_result out = r;
+  out.first_balanced = f.first_balanced;
+  out.slice_iterations = done_here;
+  out.resumable = r.status == 2 ? 1 : 0;
+  if (f.best_heavier >= 0) {  // most balanced cut (also when the limit ended the call)
+    out.status = 0;
+    out.side = f.best_kind;
+    out.flow = f.best_F;
+    out.source_weight = f.best_src;
+    out.sink_weight = f.best_snk;
     he = hipMemcpyAsync(vside, best_side, pb->V,
                         mem_kind == 0 ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s);
   } else {
-    if (r.status == 2) {  // iteration cap: the last iteration's S_r (its stamps survive piercing)
-      r.side = 0;
-      r.source_weight = last_cs;
-      r.sink_weight = total - last_cs;
-      out_invert = 0;
+    int invert = f.out_invert;
+    if (r.status == 2) {  // iteration limit: the last iteration's S_r (its stamps survive piercing)
+      out.side = 0;
+      out.source_weight = f.last_cs;
+      out.sink_weight = total - f.last_cs;
+      invert = 0;
     }
-    k_side_out<<<sweep_grid(pb->V), kThreads, 0, s>>>(g, out_ep, out_invert, vs);
+    k_side_out<<<sweep_grid(pb->V), kThreads, 0, s>>>(g, f.out_ep, invert, vs);
     he = hipGetLastError();
     if (he == hipSuccess && mem_kind == 0)
       he = hipMemcpyAsync(vside, vs, pb->V, hipMemcpyDeviceToHost, s);
   }
   if (he == hipSuccess) he = hipStreamSynchronize(s);
   if (he != hipSuccess) return hip_fail(he, "writing the FlowCutter side");
-  *res = r;
+  f.active = r.status == 2;
+  f.epoch_end = pb->epoch;
+  *res = out;
   return FP_OK;
+}
+
+fp_status flowcutter_problem(fp_problem* pb, const int32_t* vw, int64_t max_src, int64_t max_snk,
+                             int32_t max_iters, int32_t bulk_percent, int32_t most_balanced,
+                             hipStream_t s, int32_t mem_kind, uint8_t* vside,
+                             fp_cutter_result* res, fp_cutter_step* trace) {
+  long long total = 0;
+  for (int32_t v = 0; v < pb->V; ++v) {
+    if (vw[v] < 0) {
+      set_error("vertex weight of %d is negative", v);
+      return FP_ERR_INVALID;
+    }
+    total += vw[v];
+  }
+  if (max_iters < 1) {
+    set_error("max_iterations must be at least 1");
+    return FP_ERR_INVALID;
+  }
+  hipError_t he = hipSuccess;
+  if (!pb->cw) {
+    he = hipMalloc(reinterpret_cast<void**>(&pb->cw), (size_t)pb->V * sizeof(int32_t));
+    if (he != hipSuccess) {
+      pb->cw = nullptr;
+      return hip_fail(he, "allocating vertex weights");
+    }
+  }
+  he = hipMemcpyAsync(pb->cw, vw, (size_t)pb->V * sizeof(int32_t), hipMemcpyHostToDevice, s);
+  if (he != hipSuccess) return hip_fail(he, "copying vertex weights");
+  if ((bulk_percent > 0 || most_balanced) && !pb->fc_mem) {
+    const int ntiles = (pb->V + kBlock - 1) / kBlock;
+    const size_t flag_bytes = ((size_t)pb->V + 3) & ~(size_t)3;
+    const size_t count_bytes = 4 * ((size_t)ntiles + 1);
+    he = hipMalloc(&pb->fc_mem, 2 * flag_bytes + count_bytes);
+    if (he != hipSuccess) {
+      pb->fc_mem = nullptr;
+      return hip_fail(he, "allocating the FlowCutter scratch");
+    }
+  }
+  pb->fc = FcRun{};
+  FcRun& f = pb->fc;
+  f.max_src = max_src;
+  f.max_snk = max_snk;
+  f.bulk_percent = bulk_percent;
+  f.most_balanced = most_balanced;
+  f.total = total;
+  return flowcutter_run(pb, max_iters, s, mem_kind, vside, res, trace);
+}
+
+fp_status flowcutter_continue(fp_problem* pb, int32_t max_iters, hipStream_t s, int32_t mem_kind,
+                              uint8_t* vside, fp_cutter_result* res, fp_cutter_step* trace) {
+  if (!pb->fc.active) {
+    set_error("no FlowCutter run to continue (none started, or the last one finished)");
+    return FP_ERR_STATE;
+  }
+  if (max_iters < 1) {
+    set_error("max_iterations must be at least 1");
+    return FP_ERR_INVALID;
+  }
+  // another call on the handle may have run a BFS since: the reachable sets
+  // kept across a free pierce are then recomputed (a warm solve, same result)
+  if (pb->epoch != pb->fc.epoch_end) pb->fc.grow = -1;
+  return flowcutter_run(pb, max_iters, s, mem_kind, vside, res, trace);
 }
 
 // ---------------------------------------------------------------------------

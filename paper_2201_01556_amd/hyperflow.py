@@ -106,8 +106,10 @@ class CutterResult(ctypes.Structure):
         ("side", ctypes.c_int32),
         ("augmenting", ctypes.c_int32),
         ("first_balanced", ctypes.c_int32),
+        ("slice_iterations", ctypes.c_int32),
+        ("resumable", ctypes.c_int32),
         ("reserved32", ctypes.c_int32),
-        ("reserved", ctypes.c_int64 * 3),
+        ("reserved", ctypes.c_int64 * 2),
     ]
 
 
@@ -139,6 +141,8 @@ EXPORTED = [
     "flow_problem_sink_side",
     "flow_problem_pierce",
     "flow_problem_flowcutter",
+    "flow_problem_flowcutter_continue",
+    "flow_problem_terminals",
     "flow_problem_stats",
     "flow_problem_kernel_times",
     "flow_problem_export_state",
@@ -200,6 +204,11 @@ def load_library(path: str = LIB_PATH):
     lib.flow_problem_flowcutter.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int64, i32, i32, i32,
                                             vp, i32, vp, ctypes.POINTER(CutterResult), vp]
     lib.flow_problem_flowcutter.restype = ctypes.c_int
+    lib.flow_problem_flowcutter_continue.argtypes = [vp, i32, vp, i32, vp,
+                                                     ctypes.POINTER(CutterResult), vp]
+    lib.flow_problem_flowcutter_continue.restype = ctypes.c_int
+    lib.flow_problem_terminals.argtypes = [vp, vp, i32, vp]
+    lib.flow_problem_terminals.restype = ctypes.c_int
     lib.flow_problem_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     lib.flow_problem_stats.restype = ctypes.c_int
     lib.flow_problem_kernel_times.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_char_p),
@@ -441,17 +450,51 @@ def flow_problem_flowcutter(handle, num_vertices, vertex_weights, max_source_wei
                                        _stream_ptr(stream), vk, vp,
                                        ctypes.byref(res),
                                        ctypes.cast(steps, ctypes.c_void_p) if steps else None))
+    return _cutter_out(res, steps, vertex_side, vk, num_vertices)
+
+
+def _cutter_out(res, steps, vertex_side, vk, num_vertices):
     out = dict(flow=int(res.flow), source_weight=int(res.source_weight),
                sink_weight=int(res.sink_weight), iterations=int(res.iterations),
                status=CUTTER_STATUS.get(res.status, str(res.status)), side=int(res.side),
-               augmenting=int(res.augmenting), first_balanced=int(res.first_balanced))
+               augmenting=int(res.augmenting), first_balanced=int(res.first_balanced),
+               slice_iterations=int(res.slice_iterations), resumable=bool(res.resumable))
     trace = []
+    n = int(res.slice_iterations)
     if steps is not None:
         trace = [(int(t.side), int(t.node), int(t.flow), int(t.source_weight),
-                  int(t.sink_weight)) for t in steps[:res.iterations]]
-        out["counts"] = [int(t.count) for t in steps[:res.iterations]]
+                  int(t.sink_weight)) for t in steps[:n]]
+        out["counts"] = [int(t.count) for t in steps[:n]]
     x = np.asarray(vertex_side)[:num_vertices] if vk == 0 else vertex_side
     return out, x, trace
+
+
+def flow_problem_flowcutter_continue(handle, num_vertices, max_iterations=100000,
+                                     vertex_side=None, stream=None, want_trace=True):
+    """Resume the handle's FlowCutter run after its last call stopped at its
+    iteration limit; same return values as flow_problem_flowcutter, the
+    trace holding this call's iterations."""
+    lib = load_library()
+    if vertex_side is None:
+        vertex_side = np.zeros(max(num_vertices, 1), dtype=np.uint8)
+    vp, vk, _ = _ptr(vertex_side, np.uint8)
+    res = CutterResult()
+    steps = (CutterStep * max(int(max_iterations), 1))() if want_trace else None
+    _check(lib.flow_problem_flowcutter_continue(
+        handle, int(max_iterations), _stream_ptr(stream), vk, vp, ctypes.byref(res),
+        ctypes.cast(steps, ctypes.c_void_p) if steps else None))
+    return _cutter_out(res, steps, vertex_side, vk, num_vertices)
+
+
+def flow_problem_terminals(handle, num_vertices, roles=None, stream=None):
+    """Current terminal roles per vertex (0 free, 1 source, 2 sink)."""
+    if roles is None:
+        roles = np.zeros(max(num_vertices, 1), dtype=np.uint8)
+    vp, vk, _ = _ptr(roles, np.uint8)
+    _check(load_library().flow_problem_terminals(handle, _stream_ptr(stream), vk, vp))
+    if vk == 0:
+        return np.asarray(roles)[:num_vertices]
+    return roles
 
 
 def flow_problem_pierce(handle, side: int, vertices, stream=None):
@@ -548,6 +591,13 @@ class FlowProblem:
                                        max_source_weight, max_sink_weight, max_iterations,
                                        vertex_side, self.stream, want_trace, bulk_percent,
                                        most_balanced)
+
+    def flowcutter_continue(self, max_iterations=100000, vertex_side=None, want_trace=True):
+        return flow_problem_flowcutter_continue(self.handle, self.num_vertices, max_iterations,
+                                                vertex_side, self.stream, want_trace)
+
+    def terminals(self, roles=None):
+        return flow_problem_terminals(self.handle, self.num_vertices, roles, self.stream)
 
     def stats(self) -> dict:
         return flow_problem_stats(self.handle)

@@ -318,34 +318,33 @@ def _cut_weight(hg, side):
 
 
 @pytest.mark.slow
-def test_batch_full_block_pairs_sampled(hf, oracle_mod):
+def test_batch_full_block_pairs_vs_oracle(hf, oracle_mod):
     """The 2M-vertex, 10M-pin, k=64 instance as the benchmark runs it: all
-    500 problems in one plan with the cut; every problem's side is a
-    minimum cut certificate (cut weight = flow <= cut before), and sampled
-    problems match the oracle exactly."""
+    500 problems in one union plan with the cut, every problem's flow value,
+    vertex side and net side compared with the oracle (run on a process
+    pool), and every side a minimum cut certificate (cut weight = flow <=
+    cut before)."""
     import torch
     _say("building the 10M-pin block-pair set")
     bp = inputs.block_pair_problems(0)
     hgs = bp.problems
-    _say(f"{len(hgs)} problems, creating on the device")
+    _say(f"{len(hgs)} problems, oracle on a process pool")
+    refs = oracle_mod.maxflow_many(hgs)
+    _say("creating on the device")
     probs = [hf.FlowProblem.from_hypergraph(h, device=True) for h in hgs]
     try:
-        with hf.FlowBatch(probs, with_cut=True) as b:
-            _say("batched solve + cut")
+        with hf.FlowBatch(probs, with_cut=True, schedule=1, group_lanes=8,
+                          gr_interval=8) as b:
+            _say("union solve + cut")
             flows = b.run(with_cut=True)
             torch.cuda.synchronize()
-            for i, h in enumerate(hgs):
-                vs, _ = b.sides(i)
-                assert vs[h.sources[0]] == 1 and vs[h.sinks[0]] == 0
+            for i, (h, (F, rvs, rns)) in enumerate(zip(hgs, refs)):
+                vs, ns = b.sides(i)
+                assert flows[i] == F, f"problem {i}: flow {flows[i]} != oracle {F}"
+                assert (vs.astype(bool) == rvs.astype(bool)).all(), f"problem {i}: vertex side"
+                assert (ns == rns).all(), f"problem {i}: net side"
                 assert _cut_weight(h, vs) == flows[i], f"problem {i}"
                 assert 0 <= flows[i] <= h.meta["cut_before"]
-            for i in (0, 137, len(hgs) - 1):
-                _say(f"oracle on problem {i}")
-                r = oracle_mod.maxflow(hgs[i])
-                vs, ns = b.sides(i)
-                assert flows[i] == r.flow
-                assert (vs.astype(bool) == r.vertex_side.astype(bool)).all()
-                assert (ns == r.net_side).all()
     finally:
         for p in probs:
             p.close()

@@ -343,3 +343,80 @@ def test_flowcutter_expanded_levels_vs_oracle(hf, oracle_mod, seed):
     _compare_cutter(hf, oracle_mod, hg, c, L, L, 5000, f"expanded levels {seed}",
                     bulk_percent=55 * seed, most_balanced=True, bottom_up_min=1,
                     tail_threshold=1)
+
+
+@pytest.mark.parametrize("bulk,most_balanced", [(0, False), (55, False), (0, True), (55, True)])
+def test_flowcutter_slices_equal_one_run(hf, oracle_mod, bulk, most_balanced):
+    """A run cut into slices of 7 iterations (flow_problem_flowcutter_continue)
+    gives the same trace, result and side as one uninterrupted run, and a
+    finished run cannot be continued."""
+    hg = inputs.uniform_hypergraph(5)
+    c = np.random.default_rng(5).integers(1, 4, hg.num_vertices)
+    L = balance_limit(c.sum())
+    _say(f"slices bulk={bulk} most_balanced={most_balanced}")
+    with hf.FlowProblem.from_hypergraph(hg) as p:
+        r1, x1, t1 = p.flowcutter(c, L, L, max_iterations=5000, bulk_percent=bulk,
+                                  most_balanced=most_balanced)
+    with hf.FlowProblem.from_hypergraph(hg) as p:
+        r2, x2, t2 = p.flowcutter(c, L, L, max_iterations=7, bulk_percent=bulk,
+                                  most_balanced=most_balanced)
+        trace, slices = list(t2), 1
+        while r2["resumable"]:
+            assert r2["iterations"] == len(trace)
+            r2, x2, t2 = p.flowcutter_continue(max_iterations=7)
+            trace += t2
+            slices += 1
+        with pytest.raises(hf.HyperflowError) as ei:
+            p.flowcutter_continue(max_iterations=7)
+        assert ei.value.name == "FP_ERR_STATE"
+    assert slices > 3
+    assert trace == t1
+    for k in ("flow", "source_weight", "sink_weight", "iterations", "status", "side",
+              "augmenting", "first_balanced"):
+        assert r1[k] == r2[k], k
+    assert (x1 == x2).all()
+
+
+def _checkpoint_vs_oracle(oracle_mod, hg, c, L, roles, step, tag):
+    """The oracle solves the terminal sets of a checkpoint from scratch; its
+    first FlowCutter iteration must be the GPU's next trace entry (flow
+    value, c(S_r), c(T_r), side and smallest piercing vertex)."""
+    hw = _with_terminals(hg, np.nonzero(roles == 1)[0], np.nonzero(roles == 2)[0])
+    ref = oracle_mod.flowcutter(hw, c, L, L, max_iterations=1)
+    assert tuple(ref.trace[0]) == tuple(step), f"{tag}: {ref.trace[0]} != {step}"
+    return ref
+
+
+@pytest.mark.parametrize("bulk", [55])
+def test_flowcutter_zipf_checkpoints_vs_oracle(hf, oracle_mod, bulk):
+    """The 200k-vertex incremental instance (Zipf sizes clamped to 200,
+    vertex weights U{1..3}) run in slices to its balanced cut: at
+    checkpoints spread over the run and at its last iteration, the oracle
+    solves the GPU's current terminal sets from scratch and reproduces the
+    next trace entry; at the end it reproduces the returned side."""
+    hg = inputs.zipf_hypergraph(0, 200_000, 400_000, size_hi=200, vertex_weight_hi=3)
+    c = hg.vertex_weights
+    L = balance_limit(c.sum())
+    _say(f"zipf 200k checkpoints bulk={bulk}")
+    points = []
+    with hf.FlowProblem.from_hypergraph(hg) as p:
+        res, x, tr = p.flowcutter(c, L, L, max_iterations=1, bulk_percent=bulk)
+        trace = list(tr)
+        size = 1
+        while res["resumable"]:
+            roles = p.terminals()
+            res, x, tr = p.flowcutter_continue(max_iterations=size)
+            points.append((res["iterations"] - len(tr), roles, tr[0]))
+            trace += tr
+            size *= 4
+        final_roles = p.terminals()
+    _say(f"{len(trace)} iterations, {len(points)} checkpoints; {res['status']}")
+    assert res["status"] == "balanced" and len(points) >= 3
+    for it0, roles, step in points:
+        _say(f"checkpoint after iteration {it0}")
+        _checkpoint_vs_oracle(oracle_mod, hg, c, L, roles, step, f"after {it0}")
+    _say("last iteration")
+    ref = _checkpoint_vs_oracle(oracle_mod, hg, c, L, final_roles, trace[-1], "last")
+    assert ref.status == "balanced"
+    assert (x.astype(bool) == ref.vertex_side.astype(bool)).all()
+    assert oracle_mod.cut_weight(hg, x.astype(bool)) == res["flow"]
