@@ -511,7 +511,7 @@ def bench_batch(args, hyperflow, inputs, torch, np):
                         f"k=64 random + 3 label-propagation sweeps, {n} heaviest pairs",
                problems=n, pins=pins, generate_s=round(gen_s, 2), unit="refinements/s")
     try:
-        plain = hyperflow.FlowBatch(probs, with_cut=True, streams=1)
+        plain = hyperflow.FlowBatch(probs, with_cut=True, schedule=2, streams=1)
         batched = hyperflow.FlowBatch(probs, with_cut=True)
         _log("tuning the batch plan")
         t0 = time.perf_counter()

@@ -196,8 +196,8 @@ fp_status mincut_source_side(fp_problem *problem, void *hip_stream, int32_t mem_
 
 /*
  * flow_batch_solve: solve many independent problems with the same device
- * phases as maxflow_solve, concurrently (default batch plan below, largest
- * problems first).  Problems may differ in size.  Equivalent to
+ * phases as maxflow_solve, all at once (default batch plan below: the
+ * union schedule).  Problems may differ in size.  Equivalent to
  * flow_batch_create (no cut outputs, default configuration),
  * flow_batch_run and flow_batch_destroy.
  *
@@ -207,8 +207,11 @@ fp_status mincut_source_side(fp_problem *problem, void *hip_stream, int32_t mem_
  *                and reports flow_values[i] = -1
  *   flow_values  host out, count entries
  *
- * After FP_OK every solved handle behaves as after maxflow_solve
- * (mincut_source_side may be called on it).  Errors: FP_ERR_INVALID,
+ * The union schedule leaves the handles as they were (each problem is
+ * solved inside the union network from the zero flow of its current
+ * terminals); a batch plan with vertex_sides returns the minimal source
+ * sides as well, and the workers schedule (schedule = 2) leaves every
+ * solved handle as after maxflow_solve.  Errors: FP_ERR_INVALID,
  * FP_ERR_ABORTED (a problem's round budget ran out; the others are solved),
  * FP_ERR_DEVICE.
  */
@@ -217,44 +220,44 @@ fp_status flow_batch_solve(fp_problem *const *problems, int32_t count,
                            int64_t *flow_values);
 
 /*
- * Batch plans: many independent problems solved concurrently, the pattern of
+ * Batch plans: many independent problems solved at once, the pattern of
  * the paper's refinement scheduler (section "Parallel Active Block
  * Scheduling").  Two schedules:
- *   0 (workers)  problems are taken from a shared queue, largest (pins +
+ *   1 (union, the default)  the kept problems are copied into one network,
+ *                their disjoint union, and solved once with the device-wide
+ *                kernels: every launch of the solve works on all problems
+ *                at once (one global relabel is one BFS over every problem,
+ *                one round discharges all of their frontiers), and small
+ *                problems cost no launches of their own.  The union's
+ *                minimal minimum cut is the union of the problems' minimal
+ *                minimum cuts, and a problem's flow value is the weight of
+ *                its nets that cut cuts (checked against the union's flow
+ *                value).  Kept problems that do not fit one union
+ *                (union_pins, 31-bit ids) go to several, in index order.
+ *                Each run starts from the zero flow of every problem's
+ *                current terminals (same results as a warm start) and leaves
+ *                the problems' own handles untouched; the problems' round
+ *                budgets do not apply to it.
+ *   2 (workers)  problems are taken from a shared queue, largest (pins +
  *                network nodes) first, by `streams` host workers, each
  *                driving the single-problem path on a HIP stream of its own,
  *                so the kernels and host round trips of different problems
- *                overlap;
- *   1 (union)    the kept problems are copied into one network, their
- *                disjoint union, and solved once with the device-wide
- *                kernels: the union's minimal minimum cut is the union of
- *                the problems' minimal minimum cuts, and a problem's flow
- *                value is the weight of its nets that cut cuts (checked
- *                against the union's flow value).  Kept problems that do
- *                not fit one union (union_pins, 31-bit ids) go to several,
- *                in index order.  Each run starts from the
- *                zero flow of every problem's current terminals (same
- *                results as a warm start) and leaves the problems' own
- *                handles untouched.
- * (A persistent kernel that
- * runs each problem inside one workgroup, replayed from a captured HIP
- * graph, is built but switched off: its first GPU run ended in a memory
- * access fault whose cause has not been found; block_threads and workgroups
- * only apply to it.)
+ *                overlap; every solved handle then behaves as after
+ *                maxflow_solve.
  */
 typedef struct fp_batch fp_batch; /* opaque, library-owned */
 
 typedef struct {
   int32_t group_lanes;   /* lanes per small frontier node: 4, 8 or 16;
-                            0 = 4                                          */
-  int32_t block_threads; /* threads per workgroup: 256 or 1024; 0 = 1024    */
+                            0 = 8                                          */
+  int32_t reserved0;     /* must be 0                                       */
   int32_t gr_interval;   /* rounds between global relabels, -1 = off;
-                            0 = each problem's own option                  */
-  int32_t workgroups;    /* persistent workgroups; 0 = as many as fit on
-                            the device at once (at most one per problem)   */
-  int32_t streams;       /* concurrent workers (streams), 1..64; 0 = 4      */
-  int32_t schedule;      /* 0 = concurrent workers; 1 = union: the kept
-                            problems solved as one network (see below)     */
+                            0 = 8 for the union, each problem's own option
+                            for the workers                                */
+  int32_t reserved1;     /* must be 0                                       */
+  int32_t streams;       /* workers schedule: concurrent workers (streams),
+                            1..64; 0 = 4                                   */
+  int32_t schedule;      /* 1 = union, 2 = workers; 0 = union              */
   int32_t union_pins;    /* union schedule: at most this many pins per
                             union (bounds its device memory); 0 = as many
                             as 31-bit ids allow                            */
@@ -578,6 +581,7 @@ fp_status flow_problem_export_state(fp_problem *problem, void *hip_stream, int32
 
 /* Release all device memory of the handle.  NULL is ignored. */
 void flow_problem_destroy(fp_problem *problem);
+
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *fp_last_error(void);

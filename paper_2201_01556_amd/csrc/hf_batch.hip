@@ -1,19 +1,16 @@
-// Batched solve of many independent flow problems.
-//
-// The paper's refinement runs many block-pair flow problems at once (section
-// "Parallel Active Block Scheduling").  The persistent kernel below takes
-// problems from a shared queue, largest first, and each workgroup runs a
-// whole problem -- initialisation, global relabels, discharge rounds,
-// termination check and, optionally, the source-side cut -- with workgroup
-// barriers as the only ordering points, replayed from a captured HIP graph.
-//
-// That persistent path is switched off (kPersistentBatch): its first GPU run
-// ended in a memory access fault whose cause has not been found.  Until it
-// is, a plan runs its problems concurrently with the single-problem path
-// (same device phases, device-wide kernels and single-workgroup tail loops):
-// `streams` host workers take problems from a shared queue, largest first,
-// and drive each on a HIP stream of their own, so the kernels and host
-// round trips of different problems overlap.  Results are identical.
+// Batched solve of many independent flow problems (the paper's refinement
+// runs many block-pair flow problems at once, section "Parallel Active Block
+// Scheduling").  Two schedules, both with the single-problem device phases:
+//   union    the kept problems are copied into one network, their disjoint
+//            union, solved once with the device-wide kernels: one global
+//            relabel is one BFS over every problem, one round discharges all
+//            of their frontiers (the default, and the tuner's choice on
+//            large batches);
+//   workers  host workers take problems from a shared queue, largest first,
+//            and drive the single-problem path on HIP streams of their own,
+//            so the kernels and host round trips of different problems
+//            overlap.
+// Results are identical.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -27,256 +24,6 @@
 
 #include "hf_host.h"
 
-namespace hf {
-
-struct BatchParam {
-  int32_t epoch0;        // stamp value of the first round
-  int32_t init;          // start from the zero flow
-  int32_t skip;          // leave the problem alone
-  int32_t gr_interval;   // rounds between global relabels (<= 0: off)
-  int32_t stale_rounds;  // stale-flow global relabel trigger (<= 0: off)
-  int32_t want_cut;      // also write the minimal source side
-  int32_t pad0, pad1;
-  unsigned long long relabel_budget;  // relabels between global relabels
-  long long round_budget;             // rounds of this solve (<= 0: no limit)
-  long long round_guard;              // give up (no convergence) after this many rounds
-};
-
-enum BatchStatus : int32_t {
-  BST_OK = 0,
-  BST_BUDGET = 1,   // round budget exhausted
-  BST_GUARD = 2,    // no convergence
-  BST_LABEL = 3,    // a relabel did not raise a label
-  BST_SINK = 4,     // the cut BFS reached a sink
-  BST_SKIPPED = 5,
-};
-
-struct BatchResult {
-  long long flow;
-  long long rounds;
-  unsigned long long relabels;
-  int32_t epoch_end;  // stamp value of the next round
-  int32_t global_relabels;
-  int32_t bfs_levels;
-  int32_t restarts;
-  int32_t status;
-  int32_t pad;
-};
-
-// Rounds per problem before a batched solve gives up; far above what any
-// converging solve needs, and small enough that a workgroup never spins for
-// long.
-constexpr long long kBatchGuardBase = 1000000ll;
-constexpr bool kPersistentBatch = false;  // see the note at the top of the file
-constexpr long long kBatchGuardPerNode = 20ll;
-constexpr int kStaleFrontier = 1500;  // "only few active nodes" (paper)
-
-// Global relabel inside one workgroup: reset labels, reverse BFS level by
-// level, gather the active nodes.  Returns the size of the new frontier
-// (the same value in every thread).
-template <int G>
-__device__ int wg_global_relabel(const Dev& g, int epoch, lds_int* lds, int* levels) {
-  phase_gr_reset(g, 0, 1, lds);
-  phase_gr_bits(g, threadIdx.x, blockDim.x);
-  __syncthreads();
-  int level = 0;
-  for (;;) {
-    const int nf = count_all_vol(g.ctl->bcnt[level % 3]);
-    if (nf == 0) break;
-    __syncthreads();  // every thread has read the count before it changes
-    phase_bfs_rev<G>(g, level, 0, 1, KC_BATCH, lds);
-    __syncthreads();
-    ++level;
-  }
-  *levels += level;
-  phase_gather(g, epoch, 0, 1, lds);
-  __syncthreads();
-  const int nf = count_all_vol(g.ctl->fcnt[epoch % 3]);
-  __syncthreads();
-  return nf;
-}
-
-// Push-relabel to a maximum preflow inside one workgroup, with the global
-// relabel triggers of the single-problem path: relabel work, rounds since
-// the last global relabel, stale flow value, and the terminating relabel
-// when the frontier empties (paper, section "A Bug in the Synchronous
-// Algorithm").  Every decision reads counters after a barrier, so all
-// threads take the same branch.
-template <int G>
-__device__ void wg_solve(const Dev& g, const BatchParam& p, BatchResult& r, int* epoch_io,
-                         lds_int* lds) {
-  int epoch = *epoch_io;
-  if (p.init) {
-    phase_init(g, threadIdx.x, blockDim.x);
-    __syncthreads();
-  }
-  int levels = 0, grs = 1, restarts = 0, status = BST_OK;
-  long long rounds = 0;
-  int nf = wg_global_relabel<G>(g, epoch, lds, &levels);
-  unsigned long long rel_at_gr = ld_vol64(&g.ctl->relabels);
-  unsigned long long last_flow = ld_vol64(&g.ctl->flow);
-  int stale = 0, since = 0;
-  bool fresh = true;
-  for (;;) {
-    if (ld_vol(&g.ctl->err) & ERR_LABEL) {
-      status = BST_LABEL;
-      break;
-    }
-    if (nf == 0) {
-      if (fresh) break;
-      nf = wg_global_relabel<G>(g, epoch, lds, &levels);
-      ++grs;
-      if (nf > 0) ++restarts;
-      rel_at_gr = ld_vol64(&g.ctl->relabels);
-      last_flow = ld_vol64(&g.ctl->flow);
-      since = stale = 0;
-      fresh = true;
-      __syncthreads();
-      continue;
-    }
-    if (p.round_budget > 0 && rounds >= p.round_budget) {
-      status = BST_BUDGET;
-      break;
-    }
-    if (rounds >= p.round_guard) {
-      status = BST_GUARD;
-      break;
-    }
-    fresh = false;
-    phase_push<G>(g, epoch, 0, 1, KC_BATCH, lds);
-    __syncthreads();
-    phase_apply(g, epoch, 0, 1, KC_BATCH, lds);
-    __syncthreads();
-    ++epoch;
-    ++rounds;
-    ++since;
-    const unsigned long long fl = ld_vol64(&g.ctl->flow);
-    if (fl != last_flow) {
-      last_flow = fl;
-      stale = 0;
-    } else if (nf < kStaleFrontier) {
-      ++stale;
-    }
-    const bool gr = (p.stale_rounds > 0 && stale >= p.stale_rounds) ||
-                    ld_vol64(&g.ctl->relabels) - rel_at_gr >= p.relabel_budget ||
-                    (p.gr_interval > 0 && since >= p.gr_interval);
-    if (gr) {
-      nf = wg_global_relabel<G>(g, epoch, lds, &levels);
-      ++grs;
-      rel_at_gr = ld_vol64(&g.ctl->relabels);
-      last_flow = ld_vol64(&g.ctl->flow);
-      since = stale = 0;
-      fresh = true;
-    } else {
-      nf = count_all_vol(g.ctl->fcnt[epoch % 3]);
-    }
-    __syncthreads();  // counters read before the next phase changes them
-  }
-  r.flow = (long long)ld_vol64(&g.ctl->flow);
-  r.rounds = rounds;
-  r.relabels = ld_vol64(&g.ctl->relabels);
-  r.global_relabels = grs;
-  r.bfs_levels = levels;
-  r.restarts = restarts;
-  r.status = status;
-  *epoch_io = epoch;
-  __syncthreads();
-}
-
-// Source side inside one workgroup: seeds, forward BFS of the uncapped
-// residual network, side bitmaps (paper, paragraph "Source-Side Cut").
-// Returns true if the BFS reached a sink.
-template <int G>
-__device__ bool wg_cut(const Dev& g, int ep, uint8_t* vs, uint8_t* ns, lds_int* lds,
-                       int* levels) {
-  phase_cut_seed(g, ep, false, 0, 1, lds);
-  __syncthreads();
-  int level = 0;
-  for (;;) {
-    const int nf = count_all_vol(g.ctl->bcnt[level % 3]);
-    if (nf == 0) break;
-    __syncthreads();
-    phase_bfs_fwd<G>(g, level, ep, 0, 1, KC_BATCH, lds);
-    __syncthreads();
-    ++level;
-  }
-  *levels += level;
-  const int err = ld_vol(&g.ctl->err);
-  __syncthreads();
-  phase_cut_out(g, ep, vs, ns, threadIdx.x, blockDim.x);
-  __syncthreads();
-  return (err & ERR_SINK_REACHED) != 0;
-}
-
-// Persistent batch kernel: workgroups take problem indices from *head in
-// the order `order` (largest first) until the queue is exhausted.  Every
-// workgroup leaves once the queue is empty, so the grid always drains.
-template <int G, int BS>
-__global__ void __launch_bounds__(BS)
-    k_batch(const Dev* __restrict__ devs, const BatchParam* __restrict__ params,
-            const int32_t* __restrict__ order, int32_t count, int32_t* head,
-            BatchResult* __restrict__ res, uint8_t* const* __restrict__ vsides,
-            uint8_t* const* __restrict__ nsides) {
-  __shared__ int32_t hf_bq[lds_words(BS)];
-  __shared__ int32_t s_next;
-  lds_int* const lds = (lds_int*)hf_bq;
-  for (;;) {
-    if (threadIdx.x == 0) s_next = atomicAdd(head, 1);
-    __syncthreads();
-    const int k = __builtin_amdgcn_readfirstlane(s_next);
-    __syncthreads();  // s_next is rewritten only after every thread read it
-    if (k >= count) break;
-    const int pid = __builtin_amdgcn_readfirstlane(order[k]);
-    const BatchParam& p = params[pid];
-    BatchResult r{};
-    if (p.skip) {
-      if (threadIdx.x == 0) {
-        r.status = BST_SKIPPED;
-        r.epoch_end = p.epoch0;
-        r.flow = -1;
-        res[pid] = r;
-      }
-      continue;
-    }
-    const Dev& g = devs[pid];
-    int epoch = p.epoch0;
-    wg_solve<G>(g, p, r, &epoch, lds);
-    if (r.status == BST_OK && p.want_cut) {
-      int levels = 0;
-      const bool sink = wg_cut<G>(g, epoch, vsides[pid], nsides ? nsides[pid] : nullptr, lds,
-                                  &levels);
-      ++epoch;
-      r.bfs_levels += levels;
-      if (sink) r.status = BST_SINK;
-    }
-    r.epoch_end = epoch;
-    if (threadIdx.x == 0) res[pid] = r;
-  }
-}
-
-__global__ void k_fill_i32(int32_t* p, int32_t n, int32_t v) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    p[i] = v;
-}
-
-typedef void (*BatchKernel)(const Dev*, const BatchParam*, const int32_t*, int32_t, int32_t*,
-                            BatchResult*, uint8_t* const*, uint8_t* const*);
-
-static BatchKernel batch_kernel(int G, int BS) {
-  if (BS == 256) {
-    if (G == 4) return k_batch<4, 256>;
-    if (G == 8) return k_batch<8, 256>;
-    if (G == 16) return k_batch<16, 256>;
-  } else if (BS == 1024) {
-    if (G == 4) return k_batch<4, 1024>;
-    if (G == 8) return k_batch<8, 1024>;
-    if (G == 16) return k_batch<16, 1024>;
-  }
-  return nullptr;
-}
-
-}  // namespace hf
-
 struct fp_batch {
   int device = 0;
   int32_t count = 0;
@@ -285,68 +32,51 @@ struct fp_batch {
   fp_batch_config cfg{};
   bool has_vs = false;
   bool has_ns = false;
-  void* dmem = nullptr;
+  void* dmem = nullptr;  // device: the problems' layouts and side pointers
   hf::Dev* devs_d = nullptr;
-  hf::BatchParam* params_d = nullptr;
-  int32_t* order_d = nullptr;
-  int32_t* head_d = nullptr;
-  hf::BatchResult* res_d = nullptr;
   uint8_t** vs_d = nullptr;
   uint8_t** ns_d = nullptr;
-  void* hmem = nullptr;  // pinned: devs_h, params_h, res_h
+  void* hmem = nullptr;  // pinned: devs_h
   hf::Dev* devs_h = nullptr;
-  hf::BatchParam* params_h = nullptr;
-  hf::BatchResult* res_h = nullptr;
-  hipStream_t cap = nullptr;
-  hipGraphExec_t exec[2] = {nullptr, nullptr};
-  fp_batch_config exec_cfg[2]{};
-  int cus = 0;
-  std::vector<hipStream_t> workers;  // streams of the concurrent schedule
+  std::vector<hipStream_t> workers;  // streams of the workers schedule
   void* umem = nullptr;              // scratch of the union schedule
   size_t umem_bytes = 0;
 };
 
 namespace hf {
 
+constexpr int32_t kScheduleUnion = 1;
+constexpr int32_t kScheduleWorkers = 2;
+
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static fp_batch_config resolve_batch_config(const fp_batch_config* c) {
   fp_batch_config r{};
   if (c) r = *c;
-  if (r.group_lanes == 0) r.group_lanes = 4;
-  if (r.block_threads == 0) r.block_threads = 1024;
+  if (r.schedule == 0) r.schedule = kScheduleUnion;
+  if (r.group_lanes == 0) r.group_lanes = 8;
+  if (r.gr_interval == 0 && r.schedule == kScheduleUnion) r.gr_interval = 8;
   if (r.streams == 0) r.streams = 4;
   return r;
 }
 
 static bool batch_config_valid(const fp_batch_config& c) {
   return (c.group_lanes == 4 || c.group_lanes == 8 || c.group_lanes == 16) &&
-         (c.block_threads == 256 || c.block_threads == 1024) && c.gr_interval >= -1 &&
-         c.workgroups >= 0 && c.streams >= 1 && c.streams <= 64 &&
-         (c.schedule == 0 || c.schedule == 1) && c.union_pins >= 0;
+         c.gr_interval >= -1 && c.streams >= 1 && c.streams <= 64 &&
+         (c.schedule == kScheduleUnion || c.schedule == kScheduleWorkers) && c.union_pins >= 0 &&
+         c.reserved0 == 0 && c.reserved1 == 0;
 }
 
 bool batch_config_ok(const fp_batch_config* c) {
   return batch_config_valid(resolve_batch_config(c));
 }
 
-static void drop_graphs(fp_batch* b) {
-  for (int i = 0; i < 2; ++i)
-    if (b->exec[i]) {
-      (void)hipGraphExecDestroy(b->exec[i]);
-      b->exec[i] = nullptr;
-    }
-}
-
 void release_batch(fp_batch* b) {
-  drop_graphs(b);
   for (hipStream_t w : b->workers) (void)hipStreamDestroy(w);
   b->workers.clear();
-  if (b->cap) (void)hipStreamDestroy(b->cap);
   if (b->dmem) (void)hipFree(b->dmem);
   if (b->hmem) (void)hipHostFree(b->hmem);
   if (b->umem) (void)hipFree(b->umem);
-  b->cap = nullptr;
   b->dmem = b->hmem = b->umem = nullptr;
   b->umem_bytes = 0;
 }
@@ -377,14 +107,6 @@ fp_status create_batch(fp_problem* const* pbs, int32_t count, uint8_t* const* vs
   size_t off = 0;
   const size_t o_devs = off;
   off = align_up(off + n * sizeof(Dev));
-  const size_t o_params = off;
-  off = align_up(off + n * sizeof(BatchParam));
-  const size_t o_order = off;
-  off = align_up(off + n * sizeof(int32_t));
-  const size_t o_head = off;
-  off = align_up(off + sizeof(int32_t));
-  const size_t o_res = off;
-  off = align_up(off + n * sizeof(BatchResult));
   const size_t o_vs = off;
   off = align_up(off + n * sizeof(uint8_t*));
   const size_t o_ns = off;
@@ -397,31 +119,13 @@ fp_status create_batch(fp_problem* const* pbs, int32_t count, uint8_t* const* vs
   }
   char* d = static_cast<char*>(b->dmem);
   b->devs_d = reinterpret_cast<Dev*>(d + o_devs);
-  b->params_d = reinterpret_cast<BatchParam*>(d + o_params);
-  b->order_d = reinterpret_cast<int32_t*>(d + o_order);
-  b->head_d = reinterpret_cast<int32_t*>(d + o_head);
-  b->res_d = reinterpret_cast<BatchResult*>(d + o_res);
   b->vs_d = reinterpret_cast<uint8_t**>(d + o_vs);
   b->ns_d = reinterpret_cast<uint8_t**>(d + o_ns);
-  size_t hoff = 0;
-  const size_t h_devs = hoff;
-  hoff = align_up(hoff + n * sizeof(Dev));
-  const size_t h_params = hoff;
-  hoff = align_up(hoff + n * sizeof(BatchParam));
-  const size_t h_res = hoff;
-  hoff = align_up(hoff + n * sizeof(BatchResult));
-  he = hipHostMalloc(&b->hmem, hoff, hipHostMallocDefault);
+  he = hipHostMalloc(&b->hmem, n * sizeof(Dev), hipHostMallocDefault);
   if (he == hipSuccess) {
-    char* h = static_cast<char*>(b->hmem);
-    b->devs_h = reinterpret_cast<Dev*>(h + h_devs);
-    b->params_h = reinterpret_cast<BatchParam*>(h + h_params);
-    b->res_h = reinterpret_cast<BatchResult*>(h + h_res);
-    std::memset(b->hmem, 0, hoff);
-    he = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    b->devs_h = static_cast<Dev*>(b->hmem);
+    std::memset(b->hmem, 0, n * sizeof(Dev));
   }
-  if (he == hipSuccess)
-    he = hipMemcpyAsync(b->order_d, b->order.data(), (size_t)count * sizeof(int32_t),
-                        hipMemcpyHostToDevice, s);
   if (he == hipSuccess && vsides)
     he = hipMemcpyAsync(b->vs_d, vsides, (size_t)count * sizeof(uint8_t*), hipMemcpyHostToDevice,
                         s);
@@ -429,87 +133,18 @@ fp_status create_batch(fp_problem* const* pbs, int32_t count, uint8_t* const* vs
     he = hipMemcpyAsync(b->ns_d, nsides, (size_t)count * sizeof(uint8_t*), hipMemcpyHostToDevice,
                         s);
   if (he == hipSuccess) he = hipStreamSynchronize(s);
-  int cus = 0;
-  if (he == hipSuccess) he = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
-                                                   b->device);
   if (he != hipSuccess) {
     fp_status st = hip_fail(he, "setting up the batch plan");
     release_batch(b);
     delete b;
     return st;
   }
-  b->cus = cus;
   *out = b;
   return FP_OK;
 }
 
-// Capture (or reuse) the graph of one run variant.
-static fp_status batch_graph(fp_batch* b, int with_cut, hipGraphExec_t* exec) {
-  const fp_batch_config& c = b->cfg;
-  if (b->exec[with_cut] && std::memcmp(&b->exec_cfg[with_cut], &c, sizeof(c)) == 0) {
-    *exec = b->exec[with_cut];
-    return FP_OK;
-  }
-  if (b->exec[with_cut]) {
-    (void)hipGraphExecDestroy(b->exec[with_cut]);
-    b->exec[with_cut] = nullptr;
-  }
-  BatchKernel kern = batch_kernel(c.group_lanes, c.block_threads);
-  if (!kern) {
-    set_error("no batch kernel for group_lanes %d, block_threads %d", c.group_lanes,
-              c.block_threads);
-    return FP_ERR_INVALID;
-  }
-  int per_cu = 0;
-  hipError_t he =
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, c.block_threads, 0);
-  if (he != hipSuccess) return hip_fail(he, "batch kernel occupancy");
-  long long grid = (long long)std::max(per_cu, 1) * std::max(b->cus, 1);
-  if (c.workgroups > 0) grid = std::min<long long>(grid, c.workgroups);
-  grid = std::max<long long>(1, std::min<long long>(grid, b->count));
-  const size_t n = (size_t)b->count;
-  hipGraph_t graph = nullptr;
-  he = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
-  if (he != hipSuccess) return hip_fail(he, "beginning the batch graph capture");
-  hipError_t e1 = hipMemcpyAsync(b->devs_d, b->devs_h, n * sizeof(Dev), hipMemcpyHostToDevice,
-                                 b->cap);
-  if (e1 == hipSuccess)
-    e1 = hipMemcpyAsync(b->params_d, b->params_h, n * sizeof(BatchParam), hipMemcpyHostToDevice,
-                        b->cap);
-  if (e1 == hipSuccess) {
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, b->cap, b->head_d, 1, 0);
-    e1 = hipGetLastError();
-  }
-  if (e1 == hipSuccess) {
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(c.block_threads), 0, b->cap,
-                       (const Dev*)b->devs_d, (const BatchParam*)b->params_d,
-                       (const int32_t*)b->order_d, b->count, b->head_d, b->res_d,
-                       (uint8_t* const*)b->vs_d, (uint8_t* const*)(b->has_ns ? b->ns_d : nullptr));
-    e1 = hipGetLastError();
-  }
-  if (e1 == hipSuccess)
-    e1 = hipMemcpyAsync(b->res_h, b->res_d, n * sizeof(BatchResult), hipMemcpyDeviceToHost,
-                        b->cap);
-  he = hipStreamEndCapture(b->cap, &graph);
-  if (e1 != hipSuccess) {
-    if (graph) (void)hipGraphDestroy(graph);
-    return hip_fail(e1, "capturing the batch graph");
-  }
-  if (he != hipSuccess) return hip_fail(he, "ending the batch graph capture");
-  he = hipGraphInstantiate(&b->exec[with_cut], graph, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(graph);
-  if (he != hipSuccess) {
-    b->exec[with_cut] = nullptr;
-    return hip_fail(he, "instantiating the batch graph");
-  }
-  b->exec_cfg[with_cut] = c;
-  *exec = b->exec[with_cut];
-  return FP_OK;
-}
-
-// One replay: fill the parameters from the handles, launch, read results.
-// `force_init` starts every problem from the zero flow (tuning).
-// Problems spread over `streams` workers, each a host thread driving the
+// Workers schedule: `force_init` starts every problem from the zero flow
+// (tuning).  Problems spread over `streams` workers, each a host thread driving the
 // single-problem path on its own stream; problems are taken from a shared
 // counter in the plan's order (largest first).  The batch configuration's
 // lanes per node and relabel interval apply to every problem for the run.
@@ -884,89 +519,8 @@ static fp_status batch_union(fp_batch* b, const uint8_t* skip, int32_t with_cut,
 
 static fp_status batch_replay(fp_batch* b, const uint8_t* skip, int32_t with_cut, bool force_init,
                               hipStream_t s, int64_t* flows, float* ms) {
-  if (b->cfg.schedule == 1) return batch_union(b, skip, with_cut, s, flows, ms);
-  if (!kPersistentBatch) return batch_concurrent(b, skip, with_cut, force_init, s, flows, ms);
-  hipGraphExec_t exec = nullptr;
-  fp_status st = batch_graph(b, with_cut ? 1 : 0, &exec);
-  if (st) return st;
-  for (int32_t i = 0; i < b->count; ++i) {
-    fp_problem* pb = b->pbs[i];
-    Dev d = pb->dev;
-    d.bfs_arc = 0;  // node-grouped reverse BFS levels inside a workgroup
-    b->devs_h[i] = d;
-    BatchParam& p = b->params_h[i];
-    p = BatchParam{};
-    p.epoch0 = pb->epoch;
-    p.init = (force_init || !pb->inited) ? 1 : 0;
-    p.skip = skip && skip[i] ? 1 : 0;
-    p.gr_interval = b->cfg.gr_interval != 0 ? b->cfg.gr_interval : pb->opt.gr_interval;
-    p.stale_rounds = pb->opt.stale_rounds;
-    p.want_cut = with_cut ? 1 : 0;
-    p.relabel_budget =
-        (unsigned long long)((double)pb->N * pb->opt.relabel_factor_x16 / 16.0) + 1ull;
-    p.round_budget = pb->opt.round_budget;
-    p.round_guard = kBatchGuardBase + kBatchGuardPerNode * (long long)pb->N;
-  }
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (ms) {
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
-    (void)hipEventRecord(e0, s);
-  }
-  hipError_t he = hipGraphLaunch(exec, s);
-  if (ms && he == hipSuccess) he = hipEventRecord(e1, s);
-  if (he == hipSuccess) he = hipStreamSynchronize(s);
-  if (ms) {
-    if (he == hipSuccess) he = hipEventElapsedTime(ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-  }
-  if (he != hipSuccess) return hip_fail(he, "batched solve");
-  fp_status first = FP_OK;
-  for (int32_t i = 0; i < b->count; ++i) {
-    fp_problem* pb = b->pbs[i];
-    const BatchResult& r = b->res_h[i];
-    if (r.status == BST_SKIPPED) {
-      if (flows) flows[i] = -1;
-      continue;
-    }
-    pb->epoch = r.epoch_end;
-    pb->inited = true;
-    pb->st.rounds += r.rounds;
-    pb->st.tail_rounds += r.rounds;
-    pb->st.relabels = (int64_t)r.relabels;
-    pb->st.global_relabels += r.global_relabels;
-    pb->st.bfs_levels += r.bfs_levels;
-    pb->st.restarts += r.restarts;
-    pb->st.host_syncs += 1;
-    pb->st.flow_value = r.flow;
-    pb->solved = r.status == BST_OK;
-    if (flows) flows[i] = r.status == BST_OK ? r.flow : -1;
-    if (r.status != BST_OK && first == FP_OK) {
-      switch (r.status) {
-        case BST_BUDGET:
-          set_error("problem %d: round budget of %d rounds exhausted", i, pb->opt.round_budget);
-          first = FP_ERR_ABORTED;
-          break;
-        case BST_GUARD:
-          set_error("problem %d: no convergence after %lld rounds", i, (long long)r.rounds);
-          first = FP_ERR_DEVICE;
-          break;
-        case BST_LABEL:
-          set_error("problem %d: internal check: a relabel did not raise a label", i);
-          first = FP_ERR_DEVICE;
-          break;
-        case BST_SINK:
-          set_error("problem %d: internal check: a sink is reachable from the source side", i);
-          first = FP_ERR_DEVICE;
-          break;
-        default:
-          set_error("problem %d: unknown batch status %d", i, r.status);
-          first = FP_ERR_DEVICE;
-      }
-    }
-  }
-  return first;
+  if (b->cfg.schedule == kScheduleUnion) return batch_union(b, skip, with_cut, s, flows, ms);
+  return batch_concurrent(b, skip, with_cut, force_init, s, flows, ms);
 }
 
 fp_status run_batch(fp_batch* b, const uint8_t* skip, int32_t with_cut, hipStream_t s,
@@ -1001,17 +555,15 @@ static bool cache_lookup(const char* path, const std::string& sig, fp_batch_conf
   FILE* f = fopen(path, "r");
   if (!f) return false;
   char line[512], key[256];
-  int g = 0, bs = 0, gr = 0, wg = 0, ns = 0, sc = 0;
+  int g = 0, gr = 0, ns = 0, sc = 0;
   bool found = false;
   while (fgets(line, sizeof(line), f)) {
     // lines of another layout are skipped
-    if (sscanf(line, "%255s %d %d %d %d %d %d", key, &g, &bs, &gr, &wg, &ns, &sc) != 7) continue;
+    if (sscanf(line, "%255s v2 %d %d %d %d", key, &g, &gr, &ns, &sc) != 5) continue;
     if (sig == key) {  // the last entry for a signature wins
       *c = fp_batch_config{};
       c->group_lanes = g;
-      c->block_threads = bs;
       c->gr_interval = gr;
-      c->workgroups = wg;
       c->streams = ns;
       c->schedule = sc;
       found = batch_config_valid(*c);
@@ -1025,8 +577,8 @@ static void cache_store(const char* path, const std::string& sig, const fp_batch
   if (!path) return;
   FILE* f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "%s %d %d %d %d %d %d\n", sig.c_str(), c.group_lanes, c.block_threads,
-          c.gr_interval, c.workgroups, c.streams, c.schedule);
+  fprintf(f, "%s v2 %d %d %d %d\n", sig.c_str(), c.group_lanes, c.gr_interval, c.streams,
+          c.schedule);
   fclose(f);
 }
 
@@ -1060,27 +612,18 @@ fp_status tune_batch(fp_batch* b, hipStream_t s, const char* cache_path, fp_batc
     return FP_OK;
   };
   // one knob at a time, each from the best so far: schedule and concurrency
-  // (worker streams or the union; block size for the persistent kernel),
-  // lanes per node, relabel interval
-  if (kPersistentBatch) {
-    const int blocks[2] = {1024, 256};
-    for (int bs : blocks) {
-      fp_batch_config c = base;
-      c.block_threads = bs;
-      fp_status st = trial(c);
-      if (st) return st;
-    }
-  } else {
+  // (worker streams or the union), lanes per node, relabel interval
+  {
     const int streams[5] = {1, 2, 4, 8, 16};
     for (int ns : streams) {
       fp_batch_config c = base;
-      c.schedule = 0;
+      c.schedule = kScheduleWorkers;
       c.streams = ns;
       fp_status st = trial(c);
       if (st) return st;
     }
     fp_batch_config c = base;
-    c.schedule = 1;
+    c.schedule = kScheduleUnion;
     fp_status st = trial(c);
     if (st) return st;
   }

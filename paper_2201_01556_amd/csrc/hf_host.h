@@ -66,7 +66,6 @@ struct FcRun {
   int64_t last_F = 0;
   long long last_cs = 0;
   int out_ep = -1, out_invert = 0;
-  int32_t epoch_end = 0;  // handle epoch when the last call returned
 };
 
 }  // namespace hf

@@ -1288,7 +1288,6 @@ static fp_status flowcutter_run(fp_problem* pb, int32_t slice, hipStream_t s, in
   if (he == hipSuccess) he = hipStreamSynchronize(s);
   if (he != hipSuccess) return hip_fail(he, "writing the FlowCutter side");
   f.active = r.status == 2;
-  f.epoch_end = pb->epoch;
   *res = out;
   return FP_OK;
 }
@@ -1349,9 +1348,11 @@ fp_status flowcutter_continue(fp_problem* pb, int32_t max_iters, hipStream_t s, 
     set_error("max_iterations must be at least 1");
     return FP_ERR_INVALID;
   }
-  // another call on the handle may have run a BFS since: the reachable sets
-  // kept across a free pierce are then recomputed (a warm solve, same result)
-  if (pb->epoch != pb->fc.epoch_end) pb->fc.grow = -1;
+  // the sides of the next iteration are derived afresh (a warm solve, same
+  // result): the growth a free pierce left pending lists its first level in
+  // the frontier memory, which the previous call's output may have used as
+  // staging, and other calls on the handle may have run a BFS since
+  pb->fc.grow = -1;
   return flowcutter_run(pb, max_iters, s, mem_kind, vside, res, trace);
 }
 

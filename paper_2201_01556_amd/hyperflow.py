@@ -83,9 +83,9 @@ class Stats(ctypes.Structure):
 class BatchConfig(ctypes.Structure):
     _fields_ = [
         ("group_lanes", ctypes.c_int32),
-        ("block_threads", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
         ("gr_interval", ctypes.c_int32),
-        ("workgroups", ctypes.c_int32),
+        ("reserved1", ctypes.c_int32),
         ("streams", ctypes.c_int32),
         ("schedule", ctypes.c_int32),
         ("union_pins", ctypes.c_int32),
@@ -93,7 +93,7 @@ class BatchConfig(ctypes.Structure):
     ]
 
     def as_dict(self) -> dict:
-        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
+        return {k: int(getattr(self, k)) for k, _ in self._fields_ if not k.startswith("reserved")}
 
 
 class CutterResult(ctypes.Structure):

@@ -3,11 +3,9 @@ the CPU oracle, through the C ABI.
 
 A batch runs the same device phases as the single-problem path under a
 different schedule, so flow values and minimal source sides must match the
-oracle bit-exactly for every configuration: concurrent workers (each
-problem on its own stream) and the union schedule (the kept problems as one
-network).  The persistent one-workgroup-per-problem kernel is switched off
-in the library (its first GPU run ended in a memory fault whose cause is
-not found yet).
+oracle bit-exactly for every configuration: the union schedule (the kept
+problems as one network, the default) and the workers schedule (each
+problem on its own stream).
 """
 import os
 import sys
@@ -73,7 +71,13 @@ def test_batch_solve_uneven_vs_oracle(hf, oracle_mod):
         _say("flow_batch_solve, 40 uneven problems")
         flows = hf.flow_batch_solve([p.handle for p in probs])
         assert list(flows) == [r.flow for r in refs]
-        # a batch-solved handle behaves as after maxflow_solve
+        # the default (union) schedule leaves the handles as they were
+        with pytest.raises(hf.HyperflowError) as ei:
+            probs[0].source_side()
+        assert ei.value.name == "FP_ERR_STATE"
+        # with the workers schedule a solved handle behaves as after maxflow_solve
+        with hf.FlowBatch(probs, schedule=2, streams=4) as b:
+            assert list(b.run()) == [r.flow for r in refs]
         for i in (0, 13, 39):
             vs, ns = probs[i].source_side()
             assert (vs.astype(bool) == refs[i].vertex_side.astype(bool)).all()
@@ -84,19 +88,19 @@ def test_batch_solve_uneven_vs_oracle(hf, oracle_mod):
             p.close()
 
 
-@pytest.mark.parametrize("lanes,block,streams", [(4, 1024, 1), (8, 1024, 4), (16, 1024, 16),
-                                                 (4, 256, 2), (8, 256, 8), (16, 256, 3)])
-def test_batch_plan_configs_with_cut(hf, oracle_mod, lanes, block, streams):
+@pytest.mark.parametrize("lanes,schedule,streams", [(4, 2, 1), (8, 2, 4), (16, 2, 16),
+                                                    (4, 1, 0), (8, 1, 0), (16, 0, 0)])
+def test_batch_plan_configs_with_cut(hf, oracle_mod, lanes, schedule, streams):
     hgs = uneven_set(24, seed0=100)
     refs = _oracle_all(oracle_mod, hgs)
     probs = [hf.FlowProblem.from_hypergraph(h) for h in hgs]
     try:
-        _say(f"plan lanes={lanes} block={block} streams={streams}")
-        with hf.FlowBatch(probs, with_cut=True, group_lanes=lanes, block_threads=block,
+        _say(f"plan lanes={lanes} schedule={schedule} streams={streams}")
+        with hf.FlowBatch(probs, with_cut=True, group_lanes=lanes, schedule=schedule,
                           streams=streams) as b:
             flows = b.run(with_cut=True)
             assert list(flows) == [r.flow for r in refs]
-            _check_sides(b, hgs, refs, f"lanes={lanes} block={block}")
+            _check_sides(b, hgs, refs, f"lanes={lanes} schedule={schedule}")
     finally:
         for p in probs:
             p.close()
@@ -109,10 +113,12 @@ def test_batch_relabel_intervals(hf, oracle_mod, gr):
     probs = [hf.FlowProblem.from_hypergraph(h) for h in hgs]
     try:
         _say(f"gr_interval={gr}")
-        with hf.FlowBatch(probs, with_cut=True, gr_interval=gr, workgroups=5, streams=5) as b:
-            flows = b.run(with_cut=True)
-            assert list(flows) == [r.flow for r in refs]
-            _check_sides(b, hgs, refs, f"gr={gr}")
+        for schedule in (1, 2):
+            with hf.FlowBatch(probs, with_cut=True, gr_interval=gr, schedule=schedule,
+                              streams=5) as b:
+                flows = b.run(with_cut=True)
+                assert list(flows) == [r.flow for r in refs]
+                _check_sides(b, hgs, refs, f"gr={gr} schedule={schedule}")
     finally:
         for p in probs:
             p.close()
@@ -130,7 +136,7 @@ def test_batch_block_pairs_vs_oracle(hf, oracle_mod, small_pairs):
             _check_sides(b, hgs, refs, "block pairs")
             for h, f in zip(hgs, flows):
                 assert 0 <= f <= h.meta["cut_before"]
-            # replay of the captured graph: warm problems finish at once
+            # a second run of the plan
             flows2 = b.run(with_cut=True)
             assert list(flows2) == list(flows)
             _check_sides(b, hgs, refs, "block pairs replay")
@@ -175,7 +181,7 @@ def test_batch_tune_and_cache(hf, oracle_mod):
             with hf.FlowBatch(probs, with_cut=True) as b:
                 cfg = b.tune(cache)
                 assert cfg["group_lanes"] in (4, 8, 16)
-                assert cfg["block_threads"] in (256, 1024)
+                assert cfg["schedule"] in (1, 2)
                 assert 1 <= cfg["streams"] <= 64
                 assert b.config() == cfg
                 flows = b.run(with_cut=True)
@@ -283,13 +289,13 @@ def test_batch_errors(hf):
             hf.flow_batch_solve([probs[0].handle, probs[0].handle])
         assert ei.value.name == "FP_ERR_INVALID"
         with pytest.raises(hf.HyperflowError) as ei:
-            hf.FlowBatch(probs, block_threads=512)
+            hf.FlowBatch(probs, reserved0=512)
         assert ei.value.name == "FP_ERR_INVALID"
         with pytest.raises(hf.HyperflowError) as ei:
             hf.FlowBatch(probs, streams=65)
         assert ei.value.name == "FP_ERR_INVALID"
         with pytest.raises(hf.HyperflowError) as ei:
-            hf.FlowBatch(probs, schedule=2)
+            hf.FlowBatch(probs, schedule=3)
         assert ei.value.name == "FP_ERR_INVALID"
         with pytest.raises(hf.HyperflowError) as ei:
             hf.FlowBatch(probs, schedule=1, union_pins=-1)
@@ -298,6 +304,7 @@ def test_batch_errors(hf):
             with pytest.raises(hf.HyperflowError) as ei:
                 b.run(with_cut=True)  # planned without side buffers
             assert ei.value.name == "FP_ERR_INVALID"
+        with hf.FlowBatch(probs, schedule=2) as b:  # per-problem round budgets
             with pytest.raises(hf.HyperflowError) as ei:
                 b.run()
             assert ei.value.name == "FP_ERR_ABORTED"
