@@ -582,6 +582,34 @@ fp_status flow_problem_export_state(fp_problem *problem, void *hip_stream, int32
 /* Release all device memory of the handle.  NULL is ignored. */
 void flow_problem_destroy(fp_problem *problem);
 
+/*
+ * maxflow_mincut_noalloc: for callers that cannot allocate memory (code
+ * recorded into a HIP graph, tight serving loops, runtimes that forbid
+ * allocation after start-up).  Computes what flow_problem_create,
+ * maxflow_solve, mincut_source_side and flow_problem_destroy compute, in one
+ * call that allocates nothing: all device state lives in a file-scope device
+ * array of 64 MiB per GPU (problems up to roughly 700,000 pins) that the
+ * library holds until the process ends, and the host mirror of its control
+ * block in a file-scope host array.  Default options.
+ *
+ *   inputs       as flow_problem_create, all in memory kind mem_kind
+ *   flow_value   host out: maximum flow value = minimum cut weight
+ *   vertex_side  |V| bytes, net_side |E| bytes or NULL: as
+ *                mincut_source_side, in memory kind mem_kind
+ *
+ * The array is shared by every call on a GPU and keeps the last call's
+ * contents (each call clears what it needs): calls that overlap on one GPU,
+ * from several threads or on several streams, race and must be serialised
+ * by the caller.  Errors: as flow_problem_create, maxflow_solve and
+ * mincut_source_side; FP_ERR_OVERFLOW when the problem needs more than the
+ * array holds (the message gives both sizes).
+ */
+fp_status maxflow_mincut_noalloc(int32_t num_vertices, int32_t num_nets,
+                                 const int32_t *net_offsets, const int32_t *pins,
+                                 const int32_t *net_weights, const int32_t *sources,
+                                 int32_t num_sources, const int32_t *sinks, int32_t num_sinks,
+                                 int32_t mem_kind, void *hip_stream, int64_t *flow_value,
+                                 uint8_t *vertex_side, uint8_t *net_side);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *fp_last_error(void);

@@ -12,15 +12,20 @@
 
 namespace hf {
 
-static thread_local std::string g_last_error;
+// Message of the last failed call on this thread: a fixed buffer, so that
+// reporting an error allocates nothing.
+struct LastError {
+  char buf[512];
+  void clear() { buf[0] = 0; }
+  const char* c_str() const { return buf; }
+};
+static thread_local LastError g_last_error;
 
 void set_error(const char* fmt, ...) {
-  char buf[512];
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(buf, sizeof(buf), fmt, ap);
+  vsnprintf(g_last_error.buf, sizeof(g_last_error.buf), fmt, ap);
   va_end(ap);
-  g_last_error = buf;
 }
 
 fp_status hip_fail(hipError_t e, const char* what) {

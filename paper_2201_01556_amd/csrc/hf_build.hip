@@ -230,6 +230,14 @@ __global__ void k_bigbits(Dev g, uint32_t* bits, uint32_t* huge) {
   }
 }
 
+// Clears n 32-bit words (a kernel rather than hipMemsetAsync, so that
+// nothing in the build records a memset node when a caller captures it).
+__global__ void k_zero_u32(uint32_t* p, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -270,9 +278,20 @@ fp_options resolve_options(const fp_options* o) {
   return r;
 }
 
+// Temporary bytes of the radix sort of P pins by vertex (keys of `bits` bits).
+static hipError_t sort_temp_bytes(const Dev& g, int32_t* keys, int2* vinc, int32_t P,
+                                  unsigned bits, hipStream_t s, size_t* out) {
+  const auto inc = rocprim::make_transform_iterator(rocprim::counting_iterator<int32_t>(0),
+                                                    IncidenceOfSlot{g.pin_net});
+  unsigned long long* vinc_out = reinterpret_cast<unsigned long long*>(vinc);
+  return rocprim::radix_sort_pairs(nullptr, *out, g.pin_v, keys, inc, vinc_out, (size_t)P, 0u,
+                                   bits, s);
+}
+
 fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_t* pins,
                         const int32_t* net_weights, const int32_t* sources, int32_t nS,
-                        const int32_t* sinks, int32_t nT, int32_t mem_kind, hipStream_t s) {
+                        const int32_t* sinks, int32_t nT, int32_t mem_kind, hipStream_t s,
+                        void* ext, size_t ext_bytes) {
   hipError_t he;
   const int32_t V = pb->V, E = pb->E;
   // number of pins
@@ -336,13 +355,35 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
   add(N);                      // reverse-BFS byte marks
   add(sizeof(Ctl));           // ctl
   add(64);                    // scratch for the weight sum
-  he = pool_acquire(pb->device, bytes, &pb->pool, &pb->pool_bytes);
-  if (he != hipSuccess) {
+  unsigned bits = 1;          // key bits of the sort of the pins by vertex
+  while (bits < 31 && (1ll << bits) < (long long)V) ++bits;
+  char* base = nullptr;
+  size_t sort_bytes = 0;      // radix sort temporary: from the caller's memory, or allocated
+  if (ext) {
+    if (P) {
+      Dev q{};  // only the iterator types matter for the size query
+      he = sort_temp_bytes(q, nullptr, nullptr, P, bits, s, &sort_bytes);
+      if (he != hipSuccess) return hip_fail(he, "sizing the pin sort");
+    }
+    const size_t need = bytes + align_up(sort_bytes + 1);
+    if (need > ext_bytes) {
+      set_error("the problem needs %zu bytes of device scratch (|V|=%d |E|=%d pins=%d); the "
+                "limit is %zu bytes", need, V, E, P, ext_bytes);
+      return FP_ERR_OVERFLOW;
+    }
+    base = static_cast<char*>(ext);
     pb->pool = nullptr;
-    set_error("hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(he));
-    return FP_ERR_OOM;
+    pb->pool_bytes = 0;
+  } else {
+    he = pool_acquire(pb->device, bytes, &pb->pool, &pb->pool_bytes);
+    if (he != hipSuccess) {
+      pb->pool = nullptr;
+      set_error("hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(he));
+      return FP_ERR_OOM;
+    }
+    base = static_cast<char*>(pb->pool);
   }
-  Carve c{static_cast<char*>(pb->pool)};
+  Carve c{base};
   Dev& g = pb->dev;
   g.V = V;
   g.E = E;
@@ -402,11 +443,11 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
   if (he == hipSuccess && E) he = hipMemcpyAsync(w, net_weights, E * 4ull, kind, s);
   if (he == hipSuccess) he = hipMemcpyAsync(terms, sources, nS * 4ull, kind, s);
   if (he == hipSuccess) he = hipMemcpyAsync(terms + nS, sinks, nT * 4ull, kind, s);
-  if (he == hipSuccess) he = hipMemsetAsync(g.ctl, 0, sizeof(Ctl), s);
-  if (he == hipSuccess) he = hipMemsetAsync(wsum, 0, 8, s);
-  if (he == hipSuccess) he = hipMemsetAsync(g.role, 0, V * 4ull, s);
-  if (he == hipSuccess && E) he = hipMemsetAsync(g.nflag, 0, E * 4ull, s);
   if (he != hipSuccess) return hip_fail(he, "copying inputs");
+  k_zero_u32<<<1, 256, 0, s>>>(reinterpret_cast<uint32_t*>(g.ctl), (long long)(sizeof(Ctl) / 4));
+  k_zero_u32<<<1, 64, 0, s>>>(reinterpret_cast<uint32_t*>(wsum), 2);
+  k_zero_u32<<<grid_for(V), 256, 0, s>>>(reinterpret_cast<uint32_t*>(g.role), V);
+  if (E) k_zero_u32<<<grid_for(E), 256, 0, s>>>(reinterpret_cast<uint32_t*>(g.nflag), E);
 
   // validation
   if (E) k_check_nets<<<grid_for(E), 256, 0, s>>>(g, wsum);
@@ -450,8 +491,6 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
   int32_t* keys = g.fpin;
   if (P) {
     k_pin_nets<<<grid_for(E), 256, 0, s>>>(g);
-    unsigned bits = 1;
-    while (bits < 31 && (1ll << bits) < (long long)V) ++bits;
     const auto inc = rocprim::make_transform_iterator(rocprim::counting_iterator<int32_t>(0),
                                                       IncidenceOfSlot{g.pin_net});
     unsigned long long* vinc_out = reinterpret_cast<unsigned long long*>(vinc);
@@ -459,10 +498,23 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
     he = rocprim::radix_sort_pairs(nullptr, tb, pin_v, keys, inc, vinc_out, (size_t)P, 0u, bits,
                                    s);
     void* tmp = nullptr;
-    if (he == hipSuccess) he = hipMallocAsync(&tmp, std::max<size_t>(tb, 1), s);
+    bool owned = false;
+    if (he == hipSuccess) {
+      if (ext) {
+        if (tb > sort_bytes) {
+          set_error("internal check: the pin sort asks for %zu temporary bytes, %zu sized",
+                    tb, sort_bytes);
+          return FP_ERR_DEVICE;
+        }
+        tmp = base + bytes;
+      } else {
+        he = hipMallocAsync(&tmp, std::max<size_t>(tb, 1), s);
+        owned = he == hipSuccess;
+      }
+    }
     if (he == hipSuccess)
       he = rocprim::radix_sort_pairs(tmp, tb, pin_v, keys, inc, vinc_out, (size_t)P, 0u, bits, s);
-    if (tmp) (void)hipFreeAsync(tmp, s);
+    if (owned) (void)hipFreeAsync(tmp, s);
     if (he != hipSuccess) return hip_fail(he, "sorting the pins by vertex");
   }
   k_vtx_offsets<<<grid_for((long long)P + 1), 256, 0, s>>>(keys, P, V, vtx_off);
@@ -475,6 +527,10 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
   if (err & ERR_BUILD_DUP) {
     set_error("a vertex appears twice in one net");
     return FP_ERR_INVALID;
+  }
+  if (ext) {  // the caller provides the host mirror of the control block
+    memset(pb->ctl_h, 0, sizeof(Ctl));
+    return FP_OK;
   }
   he = ctl_acquire(&pb->ctl_h);
   if (he != hipSuccess) {

@@ -106,10 +106,15 @@ fp_status hip_fail(hipError_t e, const char* what);
 // defaults filled in
 fp_options resolve_options(const fp_options* o);
 
+// Validate the inputs and build the device layout.  With `ext` the layout
+// (and the temporary memory of the build) is carved from the caller's
+// ext_bytes of device memory and pb->ctl_h must point to the caller's host
+// mirror of the control block; otherwise the handle's pool and control
+// block are allocated (or taken from the cache).
 fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_t* pins,
                         const int32_t* net_weights, const int32_t* sources, int32_t nS,
                         const int32_t* sinks, int32_t nT, int32_t mem_kind,
-                        hipStream_t s);
+                        hipStream_t s, void* ext = nullptr, size_t ext_bytes = 0);
 fp_status solve_problem(fp_problem* pb, hipStream_t s, int64_t* flow);
 fp_status cut_problem(fp_problem* pb, hipStream_t s, int32_t mem_kind, uint8_t* vside,
                       uint8_t* nside);

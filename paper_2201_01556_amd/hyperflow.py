@@ -147,6 +147,7 @@ EXPORTED = [
     "flow_problem_kernel_times",
     "flow_problem_export_state",
     "flow_problem_destroy",
+    "maxflow_mincut_noalloc",
     "scorer_create",
     "scorer_fit_normalization",
     "scorer_gradient",
@@ -218,6 +219,9 @@ def load_library(path: str = LIB_PATH):
     lib.flow_problem_export_state.restype = ctypes.c_int
     lib.flow_problem_destroy.argtypes = [vp]
     lib.flow_problem_destroy.restype = None
+    lib.maxflow_mincut_noalloc.argtypes = [i32, i32, vp, vp, vp, vp, i32, vp, i32, i32, vp,
+                                           ctypes.POINTER(ctypes.c_int64), vp, vp]
+    lib.maxflow_mincut_noalloc.restype = ctypes.c_int
     lib.scorer_create.argtypes = [vp, vp, ctypes.POINTER(vp)]
     lib.scorer_create.restype = ctypes.c_int
     lib.scorer_fit_normalization.argtypes = [vp, vp, i32, i32, vp]
@@ -539,6 +543,36 @@ def flow_problem_export_state(handle, num_vertices, num_nets, num_pins, stream=N
     out["f_b"] = out["f_b"][:E]
     out["labels"], out["excess"] = out["labels"][:M], out["excess"][:M]
     return out
+
+
+def maxflow_mincut_noalloc(num_vertices, net_offsets, pins, net_weights, sources, sinks,
+                           vertex_side=None, net_side=None, stream=None):
+    """Flow value and minimal source side in one call that allocates nothing
+    (device state in the library's fixed scratch array).  Inputs and outputs
+    share one memory kind: host numpy arrays, or CUDA tensors throughout.
+    Returns (flow, vertex_side, net_side)."""
+    lib = load_library()
+    ptrs = [_ptr(a, np.int32) for a in (net_offsets, pins, net_weights, sources, sinks)]
+    kinds = {k for _, k, _ in ptrs}
+    num_nets = len(ptrs[0][2]) - 1
+    if vertex_side is None:
+        vertex_side = np.zeros(max(num_vertices, 1), dtype=np.uint8)
+    if net_side is None:
+        net_side = np.zeros(max(num_nets, 1), dtype=np.uint8)
+    vp_, vk, _ = _ptr(vertex_side, np.uint8)
+    np_, nk, _ = _ptr(net_side, np.uint8)
+    kinds |= {vk, nk}
+    if len(kinds) != 1:
+        raise ValueError("inputs and outputs must all be host arrays or all device tensors")
+    F = ctypes.c_int64(0)
+    _check(lib.maxflow_mincut_noalloc(int(num_vertices), num_nets, ptrs[0][0], ptrs[1][0],
+                                      ptrs[2][0], ptrs[3][0], len(ptrs[3][2]), ptrs[4][0],
+                                      len(ptrs[4][2]), kinds.pop(), _stream_ptr(stream),
+                                      ctypes.byref(F), vp_, np_))
+    if vk == 0:
+        vertex_side = np.asarray(vertex_side)[:num_vertices]
+        net_side = np.asarray(net_side)[:num_nets]
+    return int(F.value), vertex_side, net_side
 
 
 def flow_problem_destroy(handle):
