@@ -31,6 +31,7 @@ Contents
 ``residual_labels``    exact residual distances to the sink in the capped
                        network for a given flow state (plain BFS).
 ``maxflow_many``       ``maxflow`` of many hypergraphs on a process pool.
+``maxflow_pinned``     ``maxflow`` timed in a process pinned to one core.
 
 The paper prints no worked example for this path (its two illustrative
 figures are not part of the text), so the pins of this oracle are
@@ -164,6 +165,37 @@ class _Plain:
 def _maxflow_worker(t):
     r = maxflow(_Plain(t))
     return r.flow, r.vertex_side, r.net_side
+
+
+def _pin_to(cpu):
+    os.sched_setaffinity(0, {cpu})
+
+
+def _maxflow_timed_worker(t):
+    import time
+    h = _Plain(t)
+    t0 = time.perf_counter()
+    r = maxflow(h)
+    dt = time.perf_counter() - t0
+    return r.flow, r.vertex_side, r.net_side, dt
+
+
+def maxflow_pinned(hg, cpu=None):
+    """``maxflow`` of one hypergraph in a fresh process pinned to one core
+    (``cpu``, default the last core this process may use), timed there
+    around the solve and the source-side BFS only.  Returns (F, vertex_side,
+    net_side, seconds, cpu)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    if cpu is None:
+        cpu = max(os.sched_getaffinity(0))
+    t = (int(hg.num_vertices), np.ascontiguousarray(hg.net_offsets), np.ascontiguousarray(hg.pins),
+         np.ascontiguousarray(hg.net_weights), np.ascontiguousarray(hg.sources),
+         np.ascontiguousarray(hg.sinks))
+    with cf.ProcessPoolExecutor(max_workers=1, mp_context=mp.get_context("spawn"),
+                                initializer=_pin_to, initargs=(cpu,)) as ex:
+        F, vs, ns, dt = ex.submit(_maxflow_timed_worker, t).result()
+    return F, vs, ns, dt, cpu
 
 
 def maxflow_many(hgs, workers=None):

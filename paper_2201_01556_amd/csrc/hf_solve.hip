@@ -664,13 +664,18 @@ static fp_status solve_impl(fp_problem* pb, hipStream_t s, int64_t* flow) {
     pb->st.rounds += ran;
     rounds_this_solve += ran;
     rounds_since_gr += ran;
-    // stale-flow bookkeeping for device-wide rounds (the loop kernel keeps
-    // its own count and reports exit 5)
+    // stale-flow bookkeeping (paragraph "Avoid Pushing Flow Back": the flow
+    // value unchanged over consecutive rounds that each had few active
+    // nodes); the loop kernel keeps its own count of such rounds and
+    // reports exit 5.  A batch of device-wide rounds is judged by the
+    // frontier it started from; a large one ends the run of small rounds.
     if (pb->ctl_h->flow != last_flow) {
       last_flow = pb->ctl_h->flow;
       stale = 0;
     } else if (nf < kStaleFrontier) {
       stale += ran;
+    } else {
+      stale = 0;
     }
     if (stale_limit > 0 && stale >= stale_limit) do_gr = true;
     if (pb->ctl_h->relabels - rel_at_gr >= budget) do_gr = true;
@@ -1260,6 +1265,15 @@ static fp_status flowcutter_run(fp_problem* pb, int32_t slice, hipStream_t s, in
     if (trace) trace[n] = step;
     if (done) break;
   }
+  if (f.grow >= 0) {
+    // the call ends with a growth pending for the next iteration: the seeds
+    // a source pierce listed for it would otherwise stay in the BFS
+    // counters for whatever runs next on the handle, so they are dropped
+    // and a continued run re-derives its sides (a warm solve, same result)
+    k_reset_bfs<<<1, 64, 0, s>>>(g);
+    f.grow = -1;
+    f.seeded = false;
+  }
   fp_cutter_result out = r;
   out.first_balanced = f.first_balanced;
   out.slice_iterations = done_here;
@@ -1348,11 +1362,8 @@ fp_status flowcutter_continue(fp_problem* pb, int32_t max_iters, hipStream_t s, 
     set_error("max_iterations must be at least 1");
     return FP_ERR_INVALID;
   }
-  // the sides of the next iteration are derived afresh (a warm solve, same
-  // result): the growth a free pierce left pending lists its first level in
-  // the frontier memory, which the previous call's output may have used as
-  // staging, and other calls on the handle may have run a BFS since
-  pb->fc.grow = -1;
+  // the sides of the next iteration are derived afresh (the previous call
+  // dropped any growth it left pending)
   return flowcutter_run(pb, max_iters, s, mem_kind, vside, res, trace);
 }
 

@@ -275,12 +275,6 @@ def test_batch_union_block_pairs_and_pierced(hf, oracle_mod, small_pairs):
             p.close()
 
 
-@pytest.mark.skip(reason="persistent batch kernel switched off: its first GPU run ended in a "
-                         "memory access fault whose cause has not been found")
-def test_persistent_batch_kernel():
-    """Placeholder for the persistent kernel's own parity runs."""
-
-
 def test_batch_errors(hf):
     hgs = uneven_set(3, seed0=500)
     probs = [hf.FlowProblem.from_hypergraph(h, round_budget=1) for h in hgs]
