@@ -46,6 +46,10 @@ def main():
     ap.add_argument("--size-hi", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the block-pair batch workload")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the 2,000-vertex solves-per-second leg")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the side-by-side of the two relabel variants")
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--batch-problems", type=int, default=500)
     ap.add_argument("--no-cutter", action="store_true",
@@ -56,8 +60,9 @@ def main():
                          "(0 skips it)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-pruning workload")
-    ap.add_argument("--learned-seeds", type=int, default=4,
-                    help="block-pair instances for the learned scorer (3/4 train, 1/4 eval)")
+    ap.add_argument("--learned-seeds", type=int, default=32,
+                    help="block-pair instances per learned-pruning workload (3/4 train, "
+                         "1/4 eval)")
     ap.add_argument("--learned-steps", type=int, default=2000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run one plain elementwise copy of BYTES bytes (counter "
@@ -66,6 +71,12 @@ def main():
                     help="reverse-BFS levels: 1 flattened arcs per wave, -1 lane groups, 0 default")
     ap.add_argument("--bfs-marks", type=int, default=0,
                     help="expanded reverse-BFS levels: 1 byte marks, -1 labels, 0 default")
+    ap.add_argument("--gather-probe", type=int, default=0, metavar="READS",
+                    help="only run one gather of READS random 4-byte words (counter "
+                         "calibration for scattered reads) and exit")
+    ap.add_argument("--relabel-blocking", type=int, default=0,
+                    help="1: the blocking variant of the round (a node pushed to does not "
+                         "relabel in that round)")
     ap.add_argument("--profile", type=int, default=2,
                     help="HIP-event timing inside the timed steps: 0 off, 1 every kernel, "
                          "2 only the reverse-BFS level kernel (the dominant one)")
@@ -79,6 +90,23 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.gather_probe:
+        # one gather kernel: GATHER random 4-byte reads from a 256 MiB table,
+        # the indices read and the values written sequentially; its counters
+        # give the bytes a scattered 4-byte read fetches
+        n = args.gather_probe
+        table = torch.ones((1 << 26), dtype=torch.int32, device="cuda")
+        g = torch.Generator(device="cuda")
+        g.manual_seed(0)
+        idx = torch.randint(0, 1 << 26, (n,), dtype=torch.int64, device="cuda", generator=g)
+        idx = idx.to(torch.int32)
+        out = torch.empty(n, dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        torch.index_select(table, 0, idx, out=out)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(gather_probe_reads=n, table_bytes=4 << 26)), flush=True)
+        return
 
     if args.copy_probe:
         # one kernel that reads BYTES and writes BYTES: the HBM counters of
@@ -111,7 +139,8 @@ def main():
 
     def step(profile):
         opts = hyperflow.Options(profile=profile, bfs_flat=args.bfs_flat,
-                                 bfs_marks=args.bfs_marks)
+                                 bfs_marks=args.bfs_marks,
+                                 relabel_blocking=args.relabel_blocking)
         h = hyperflow.flow_problem_create(V, *arrays, options=opts, stream=stream)
         try:
             F = hyperflow.maxflow_solve(h, stream)
@@ -173,6 +202,29 @@ def main():
                             bytes_per_launch=bpl, avg_launch_us=round(avg_s * 1e6, 3),
                             share_of_step=round(d["ms"] / args.steps / ms_per_step, 4))
 
+    # the round's two fixes of the push-relabel conflict side by side (the
+    # paper's blocking fix, against the default bounded relabel)
+    variants = {}
+    for blk in (() if args.no_variants else (0, 1)):
+        ts = []
+        for _ in range(3):
+            o = hyperflow.Options(relabel_blocking=blk)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            h = hyperflow.flow_problem_create(V, *arrays, options=o, stream=stream)
+            try:
+                Fv = hyperflow.maxflow_solve(h, stream)
+                hyperflow.mincut_source_side(h, V, E, vs, ns, stream)
+                sv = hyperflow.flow_problem_stats(h)
+            finally:
+                hyperflow.flow_problem_destroy(h)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        variants["blocking" if blk else "bounded_relabel"] = dict(
+            ms=round(1e3 * min(ts), 3), flow=Fv, rounds=sv["rounds"],
+            global_relabels=sv["global_relabels"], relabels=sv["relabels"],
+            restarts=sv["restarts"])
+
     copy = copy_ceiling(torch)
     _log(f"copy ceiling {copy['GBps']} GB/s")
     if roofline is not None:
@@ -192,7 +244,7 @@ def main():
         parity = bool(F == Fo and np.array_equal(vs.cpu().numpy(), vso) and
                       np.array_equal(ns.cpu().numpy(), nso))
 
-    small = bench_small(args, hyperflow, inputs, torch, np)
+    small = None if args.no_small else bench_small(args, hyperflow, inputs, torch, np)
 
     cutter = None
     if not args.no_cutter:
@@ -241,6 +293,7 @@ def main():
         "host": host_info(),
         "copy_ceiling": copy,
         "small": small,
+        "relabel_variants": variants,
         "paper_context": PAPER_CONTEXT,
         "kernels": kernels,
         "batch": batch,
@@ -481,119 +534,168 @@ def _pairs(inputs, seed, max_problems):
     return _PAIRS[key]
 
 
+def _gen_pairs(job):
+    """One seed's block-pair problems, built in a worker process (one
+    builder thread each)."""
+    kind, seed, nprob = job
+    from paper_2201_01556_amd import inputs
+    gen = inputs.planted_block_pair_problems if kind == "planted" else inputs.block_pair_problems
+    bp = gen(seed, max_problems=nprob, threads=1)
+    for h in bp.problems:
+        h.meta.pop("gid", None)
+    return seed, bp.problems
+
+
+SWEEP = (1.0, 0.1, 0.01, 0.001)
+
+
 def bench_learned(args, hyperflow, inputs, torch, np, config):
-    """Learned pruning: block-pair instances for seeds 0..K-1 (3/4 train,
-    1/4 eval).  Labels come from the plain schedule: a problem improves when
-    its minimum cut is lighter than the cut it had (cut_before - F > 0).
-    The scorer trains on the device (full-batch Adam); its threshold is the
-    largest one that skips no improving training problem.  On the eval
-    instances the plain batch (every problem), the learned schedule
-    (inference, then the batch of the kept problems) and the paper's
-    cut < 10 rule are timed, all with the source-side cut."""
+    """Learned pruning (seeds 0..K-1, the first 3/4 train, the rest
+    evaluate) on two block-pair workloads: the block pairs of a random k=64
+    partition refined by label propagation (the batch workload), and the
+    same construction on a hypergraph with planted blocks whose partition
+    is good except around perturbed block pairs.  Labels come from the plain
+    schedule (the union batch, every problem solved): a problem improves
+    when its minimum cut is lighter than the cut it had (cut_before - F >
+    0).  The scorer trains on the device (full-batch Adam); its threshold is
+    the largest one that skips no improving training problem.  On the
+    evaluation seeds the plain batch, the learned schedule (inference, then
+    the batch of the kept problems) and the paper's cut < 10 rule are timed,
+    all with the source-side cut.  Seeds are built on a pool of worker
+    processes while the device labels and evaluates earlier ones."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
     K = max(2, args.learned_seeds)
     n_train = max(1, (3 * K) // 4)
-    cfg = dict(config or {})
-    cfg = {k: v for k, v in cfg.items() if k in ("group_lanes", "gr_interval", "streams", "schedule")}
-
-    def instance(seed):
-        bp = _pairs(inputs, seed, args.batch_problems)
-        hgs = bp.problems
-        feats = inputs.scorer_features(hgs)
-        cut_before = np.array([h.meta["cut_before"] for h in hgs], dtype=np.int64)
-        pair_cut = np.array([h.meta["cut"] for h in hgs], dtype=np.int64)
-        return hgs, feats, cut_before, pair_cut
-
-    def solve_all(hgs, skip=None):
-        probs = [hyperflow.FlowProblem.from_hypergraph(h, device=True) for h in hgs]
-        torch.cuda.synchronize()
-        try:
-            with hyperflow.FlowBatch(probs, with_cut=True, **cfg) as plan:
-                t = time.perf_counter()
-                flows = plan.run(skip=skip, with_cut=True)
-                torch.cuda.synchronize()
-                dt = time.perf_counter() - t
-        finally:
-            for p in probs:
-                p.close()
-        return flows, dt
-
-    _log(f"learned pruning: {n_train} training instances")
-    Xtr, ytr, gtr = [], [], []
-    for seed in range(n_train):
-        hgs, feats, cb, _ = instance(seed)
-        flows, _ = solve_all(hgs)
-        gain = cb - flows
-        Xtr.append(feats)
-        ytr.append((gain > 0).astype(np.float32))
-        gtr.append(gain)
-        _log(f"  seed {seed}: {len(hgs)} problems, {int((gain > 0).sum())} improve")
-    Xtr = np.concatenate(Xtr)
-    ytr = np.concatenate(ytr)
-    out = dict(workload=f"block-pair instances, seeds 0..{K - 1}: train {n_train}, "
-                        f"eval {K - n_train}; labels = minimum cut lighter than the cut before",
-               unit="refinements/s", train_problems=int(len(ytr)),
-               train_positive_fraction=round(float(ytr.mean()), 4))
-    init = inputs.scorer_init_params(0)
-    with hyperflow.Scorer(init) as sc:
-        sc.fit_normalization(Xtr)
-        if not args.no_cpu_baseline:
-            # the oracle's inputs never come from the device path: the check
-            # uses the training features with seeded coin-flip labels
-            from oracle import mlp as omlp
-            ychk = np.random.default_rng(0).integers(0, 2, len(Xtr)).astype(np.float32)
-            loss_gpu, g_gpu = sc.gradient(Xtr, ychk)
-            xn, _, _ = omlp.normalize(Xtr)
-            loss_ref, g_ref = omlp.grad(init.astype(np.float64), xn, ychk)
-            out["gradient_rel_err_vs_oracle"] = float(
-                np.linalg.norm(g_gpu - g_ref) / max(np.linalg.norm(g_ref), 1e-30))
-            out["loss_vs_oracle"] = [float(loss_gpu), float(loss_ref)]
-        t = time.perf_counter()
-        losses = sc.train(Xtr, ytr, args.learned_steps, lr=1e-3)
-        torch.cuda.synchronize()
-        out["train_s"] = round(time.perf_counter() - t, 3)
-        out["loss_first_last"] = [float(losses[0]), float(losses[-1])]
-        params, ms = sc.params()
-        usable = bool(np.all(np.isfinite(params)))
-        ptr = sc.predict(Xtr)
-        pos = ytr > 0
-        theta = float(ptr[pos].min()) if pos.any() else 1.0
-        out["threshold"] = theta
-        out["train_skip_rate"] = round(float((ptr < theta).mean()), 4)
-        out["fallback_to_plain"] = not usable
+    workers = max(1, min(16, len(os.sched_getaffinity(0)) - 1))
+    out = {}
+    for kind in ("c4", "planted"):
+        _log(f"learned pruning, {kind} workload: {K} seeds, built on {workers} processes")
+        res = dict(workload=(
+            "block pairs of a random k=64 partition refined by 3 label-propagation sweeps "
+            "(2M vertices, 10M pins, Zipf(2.2) sizes clamped to [2,2000], 500 heaviest pairs)"
+            if kind == "c4" else
+            "block pairs of a planted 64-block hypergraph (2M vertices, 10M pins, Zipf(2.2) "
+            "sizes clamped to [2,2000], 98% of the nets inside one block), the planted "
+            "partition with 2% of the vertices swapped across 150 random block pairs, 3 "
+            "label-propagation sweeps, 500 heaviest pairs"),
+            seeds=f"0..{K - 1}: train 0..{n_train - 1}, evaluate {n_train}..{K - 1}",
+            label="minimum cut lighter than the cut before (plain union schedule)",
+            unit="refinements/s")
+        t0 = time.perf_counter()
+        Xtr, ytr = [], []
         ev = dict(problems=0, positive=0, plain_s=0.0, learned_s=0.0, rule_s=0.0, skipped=0,
                   missed_gain=0, total_gain=0, rule_skipped=0, rule_missed_gain=0)
-        for seed in range(n_train, K):
-            hgs, feats, cb, pair_cut = instance(seed)
-            flows, t_plain = solve_all(hgs)
-            gain = cb - flows
-            t0 = time.perf_counter()
-            p = sc.predict(feats) if usable else np.ones(len(hgs), dtype=np.float32)
-            skip = (p < theta).astype(np.uint8)
-            t_inf = time.perf_counter() - t0
-            _, t_kept = solve_all(hgs, skip)
-            rule = (pair_cut < 10).astype(np.uint8)
-            _, t_rule = solve_all(hgs, rule)
-            ev["problems"] += len(hgs)
-            ev["positive"] += int((gain > 0).sum())
-            ev["plain_s"] += t_plain
-            ev["learned_s"] += t_inf + t_kept
-            ev["rule_s"] += t_rule
-            ev["skipped"] += int(skip.sum())
-            ev["missed_gain"] += int(gain[(skip > 0) & (gain > 0)].sum())
-            ev["total_gain"] += int(gain[gain > 0].sum())
-            ev["rule_skipped"] += int(rule.sum())
-            ev["rule_missed_gain"] += int(gain[(rule > 0) & (gain > 0)].sum())
-            _log(f"  eval seed {seed}: skipped {int(skip.sum())} of {len(hgs)}")
-    n = ev["problems"]
-    out.update(eval_problems=n, eval_positive_fraction=round(ev["positive"] / max(n, 1), 4),
-               skip_rate=round(ev["skipped"] / max(n, 1), 4),
-               missed_gain=ev["missed_gain"],
-               missed_gain_pct=round(100.0 * ev["missed_gain"] / max(ev["total_gain"], 1), 3),
-               value=round(n / ev["learned_s"], 2) if ev["learned_s"] else None,
-               plain_value=round(n / ev["plain_s"], 2) if ev["plain_s"] else None,
-               rule_value=round(n / ev["rule_s"], 2) if ev["rule_s"] else None,
-               rule_skip_rate=round(ev["rule_skipped"] / max(n, 1), 4),
-               rule_missed_gain=ev["rule_missed_gain"])
+        sc = None
+        theta, usable = 1.0, False
+        try:
+            with cf.ProcessPoolExecutor(max_workers=workers,
+                                        mp_context=mp.get_context("spawn")) as ex:
+                jobs = [(kind, sd, args.batch_problems) for sd in range(K)]
+                for seed, hgs in ex.map(_gen_pairs, jobs):
+                    feats = inputs.scorer_features(hgs)
+                    cb = np.array([h.meta["cut_before"] for h in hgs], dtype=np.int64)
+                    pair_cut = np.array([h.meta["cut"] for h in hgs], dtype=np.int64)
+                    probs = [hyperflow.FlowProblem.from_hypergraph(h, device=True) for h in hgs]
+                    del hgs
+                    torch.cuda.synchronize()
+                    try:
+                        with hyperflow.FlowBatch(probs, with_cut=True) as plan:
+                            def timed(skip=None):
+                                torch.cuda.synchronize()
+                                t = time.perf_counter()
+                                f = plan.run(skip=skip, with_cut=True)
+                                torch.cuda.synchronize()
+                                return f, time.perf_counter() - t
+                            flows, t_plain = timed()
+                            gain = cb - flows
+                            if seed < n_train:
+                                Xtr.append(feats)
+                                ytr.append((gain > 0).astype(np.float32))
+                                _log(f"  {kind} seed {seed}: {len(gain)} problems, "
+                                     f"{int((gain > 0).sum())} improve")
+                            else:
+                                ts = time.perf_counter()
+                                pr = sc.predict(feats) if usable else np.ones(len(gain),
+                                                                                np.float32)
+                                skip = (pr < theta).astype(np.uint8)
+                                t_inf = time.perf_counter() - ts
+                                for f in SWEEP:  # lower thresholds skip less
+                                    sk = pr < theta * f
+                                    sw = ev.setdefault(f"theta_x{f}", [0, 0])
+                                    sw[0] += int(sk.sum())
+                                    sw[1] += int(gain[sk & (gain > 0)].sum())
+                                _, t_kept = timed(skip)
+                                rule = (pair_cut < 10).astype(np.uint8)
+                                _, t_rule = timed(rule)
+                                ev["problems"] += len(gain)
+                                ev["positive"] += int((gain > 0).sum())
+                                ev["plain_s"] += t_plain
+                                ev["learned_s"] += t_inf + t_kept
+                                ev["rule_s"] += t_rule
+                                ev["skipped"] += int(skip.sum())
+                                ev["missed_gain"] += int(gain[(skip > 0) & (gain > 0)].sum())
+                                ev["total_gain"] += int(gain[gain > 0].sum())
+                                ev["rule_skipped"] += int(rule.sum())
+                                ev["rule_missed_gain"] += int(gain[(rule > 0) & (gain > 0)].sum())
+                                _log(f"  {kind} eval seed {seed}: {int((gain > 0).sum())} "
+                                     f"improve, skipped {int(skip.sum())} of {len(gain)}")
+                    finally:
+                        for p in probs:
+                            p.close()
+                    if seed == n_train - 1:  # every training seed is labelled: train
+                        res["build_and_label_s"] = round(time.perf_counter() - t0, 2)
+                        Xtr = np.concatenate(Xtr)
+                        ytr = np.concatenate(ytr)
+                        res.update(train_problems=int(len(ytr)),
+                                   train_positive_fraction=round(float(ytr.mean()), 4))
+                        init = inputs.scorer_init_params(0)
+                        sc = hyperflow.Scorer(init)
+                        sc.fit_normalization(Xtr)
+                        if kind == "c4" and not args.no_cpu_baseline:
+                            # the oracle's inputs never come from the device path:
+                            # the check uses the training features with seeded
+                            # coin-flip labels
+                            from oracle import mlp as omlp
+                            ychk = np.random.default_rng(0).integers(0, 2, len(Xtr))
+                            ychk = ychk.astype(np.float32)
+                            loss_gpu, g_gpu = sc.gradient(Xtr, ychk)
+                            xn, _, _ = omlp.normalize(Xtr)
+                            loss_ref, g_ref = omlp.grad(init.astype(np.float64), xn, ychk)
+                            res["gradient_rel_err_vs_oracle"] = float(
+                                np.linalg.norm(g_gpu - g_ref) / max(np.linalg.norm(g_ref), 1e-30))
+                        ts = time.perf_counter()
+                        losses = sc.train(Xtr, ytr, args.learned_steps, lr=1e-3)
+                        torch.cuda.synchronize()
+                        res["train_s"] = round(time.perf_counter() - ts, 3)
+                        res["loss_first_last"] = [float(losses[0]), float(losses[-1])]
+                        params, _ = sc.params()
+                        usable = bool(np.all(np.isfinite(params)))
+                        ptr = sc.predict(Xtr)
+                        pos = ytr > 0
+                        theta = float(ptr[pos].min()) if pos.any() else 1.0
+                        res["threshold"] = theta
+                        res["train_skip_rate"] = round(float((ptr < theta).mean()), 4)
+                        res["fallback_to_plain"] = not usable
+        finally:
+            if sc is not None:
+                sc.close()
+        n = ev["problems"]
+        res.update(eval_problems=n,
+                   eval_positive_fraction=round(ev["positive"] / max(n, 1), 4),
+                   skip_rate=round(ev["skipped"] / max(n, 1), 4),
+                   missed_gain=ev["missed_gain"], total_gain=ev["total_gain"],
+                   missed_gain_pct=round(100.0 * ev["missed_gain"] / max(ev["total_gain"], 1), 3),
+                   value=round(n / ev["learned_s"], 2) if ev["learned_s"] else None,
+                   plain_value=round(n / ev["plain_s"], 2) if ev["plain_s"] else None,
+                   rule_value=round(n / ev["rule_s"], 2) if ev["rule_s"] else None,
+                   rule_skip_rate=round(ev["rule_skipped"] / max(n, 1), 4),
+                   rule_missed_gain=ev["rule_missed_gain"],
+                   threshold_sweep={k: dict(skip_rate=round(v[0] / max(n, 1), 4),
+                                            missed_gain=v[1])
+                                    for k, v in ev.items() if k.startswith("theta_x")},
+                   seconds=round(time.perf_counter() - t0, 2))
+        out[kind] = res
     return out
 
 

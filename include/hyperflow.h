@@ -113,7 +113,12 @@ typedef struct {
                                  nodes in a byte array and the collect sweep
                                  writes their labels; 1 = on, -1 = labels
                                  written during the expansion (default)     */
-  int32_t reserved[1];
+  int32_t relabel_blocking;   /* 1 = a node pushed to in a round does not
+                                 relabel in that round (the paper's blocking
+                                 fix of the push-relabel conflict, section
+                                 "A Bug in the Synchronous Algorithm");
+                                 0 = it relabels to at most its label + 2,
+                                 which keeps every label valid (default)    */
 } fp_options;
 
 /* Counters of the last solve (cumulative over warm-started solves). */

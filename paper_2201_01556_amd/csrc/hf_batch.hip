@@ -483,12 +483,13 @@ static fp_status union_chunk(fp_batch* b, const std::vector<int32_t>& ids, int32
 }
 
 // The kept problems in unions that fit 31-bit ids (a handle holds fewer than
-// 2^30 pins and 2^31 network nodes) and union_pins, in index order.
+// 2^30 pins and 2^31 network nodes), union_pins and a net-weight sum of at
+// most INT32_MAX, in index order.
 static fp_status batch_union(fp_batch* b, const uint8_t* skip, int32_t with_cut, hipStream_t s,
                              int64_t* flows, float* ms) {
   const auto t0 = std::chrono::steady_clock::now();
   std::vector<int32_t> chunk;
-  long long V = 0, E = 0, P = 0;
+  long long V = 0, E = 0, P = 0, W = 0;
   const long long max_pins = b->cfg.union_pins > 0 ? b->cfg.union_pins : (1ll << 30) - 1;
   for (int32_t i = 0; i <= b->count; ++i) {
     const bool last = i == b->count;
@@ -497,20 +498,24 @@ static fp_status batch_union(fp_batch* b, const uint8_t* skip, int32_t with_cut,
       continue;
     }
     const fp_problem* pb = last ? nullptr : b->pbs[i];
+    // a union must fit 31-bit ids, the pin bound and (like every problem)
+    // a sum of net weights of at most INT32_MAX
     const bool full = !last && !chunk.empty() &&
                       (P + pb->P > max_pins ||
-                       V + pb->V + 2 + 2 * (E + pb->E) >= (1ll << 31) - 16);
+                       V + pb->V + 2 + 2 * (E + pb->E) >= (1ll << 31) - 16 ||
+                       W + pb->wsum > 0x7fffffffll);
     if ((last || full) && !chunk.empty()) {
       fp_status st = union_chunk(b, chunk, with_cut, s, flows);
       if (st) return st;
       chunk.clear();
-      V = E = P = 0;
+      V = E = P = W = 0;
     }
     if (last) break;
     chunk.push_back(i);
     V += pb->V;
     E += pb->E;
     P += pb->P;
+    W += pb->wsum;
   }
   if (ms)
     *ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();

@@ -427,6 +427,7 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
   uint8_t* lev = c.take<uint8_t>(N);
   g.lev = pb->opt.bfs_marks > 0 ? lev : nullptr;
   g.bfs_flat = pb->opt.bfs_flat > 0 ? 1 : 0;
+  g.relabel_block = pb->opt.relabel_blocking > 0 ? 1 : 0;
   g.bfs_arc = pb->opt.bfs_arc_parallel;
   g.ctl = c.take<Ctl>(1);
   unsigned long long* wsum = c.take<unsigned long long>(1);
@@ -484,6 +485,7 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
     set_error("sum of net weights %llu exceeds INT32_MAX", wtot);
     return FP_ERR_OVERFLOW;
   }
+  pb->wsum = (int64_t)wtot;
 
   // vertex incidence CSR: stable radix sort of the pins by vertex carrying
   // their {net, slot} incidence straight into vinc; the pin-flow array is

@@ -116,7 +116,7 @@ struct Ctl {
 struct Dev {
   int32_t V, E, P, NB, N, nT, big_deg, bfs_arc;  // bfs_arc: arc-parallel BFS levels
   int32_t bfs_flat;        // reverse-BFS levels spread each wave's 64 nodes' arcs over its lanes
-  int32_t pad_;
+  int32_t relabel_block;   // a node pushed to in a round does not relabel in it
   const int32_t* net_off;  // E+1
   const int32_t* pin_v;    // P
   const int32_t* pin_net;  // P   net of each pin slot
@@ -762,10 +762,15 @@ __device__ void phase_apply(const Dev& g, int epoch, int tile0, int tstride, int
       v = frontier_node(g, ra.cur, pre, i);
       const int c = g.cand[v];
       nbytes += 8;
-      if (c >= 0) {
+      const bool rec = c >= 0 && g.stamp[v] == ra.epoch;
+      if (c >= 0 && rec && g.relabel_block) {
+        // blocking variant (section "A Bug in the Synchronous Algorithm",
+        // the first fix): a node pushed to in this round keeps its label;
+        // the push listed it for the next round, where it tries again
+        g.cand[v] = -1;
+      } else if (c >= 0) {
         g.cand[v] = -1;
         const int k = g.d[v];
-        const bool rec = g.stamp[v] == ra.epoch;
         int nd = c;
         if (rec) nd = min(nd, k + 2);
         nd = min(nd, g.N);

@@ -74,6 +74,7 @@ struct fp_problem {
   int device = 0;
   int32_t V = 0, E = 0, P = 0, NB = 0, N = 0;
   int32_t nS = 0, nT = 0;
+  int64_t wsum = 0;          // sum of the net weights (at most INT32_MAX)
   fp_options opt{};
   hf::Dev dev{};
   void* pool = nullptr;

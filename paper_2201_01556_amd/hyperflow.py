@@ -61,7 +61,7 @@ class Options(ctypes.Structure):
         ("tail_gr_interval", ctypes.c_int32),
         ("bfs_flat", ctypes.c_int32),
         ("bfs_marks", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 1),
+        ("relabel_blocking", ctypes.c_int32),
     ]
 
 

@@ -46,6 +46,7 @@ __all__ = [
     "zipf_sizes_until",
     "BlockPairSet",
     "block_pair_problems",
+    "planted_block_pair_problems",
     "scorer_init_params",
     "scorer_features",
 ]
@@ -378,6 +379,17 @@ def block_pair_problems(seed: int, num_vertices: int = 2_000_000,
     hg = Hypergraph(int(num_vertices), _i32(off), _i32(pins), np.ones(E, dtype=np.int32),
                     np.ones(num_vertices, dtype=np.int32), _i32([]), _i32([]),
                     dict(kind="block_pairs", seed=seed, V=num_vertices, E=E, k=k))
+    return _pair_problems(hg, block0, seed, k, lp_rounds, eps, alpha, min_cut, max_problems,
+                          threads)
+
+
+def _pair_problems(hg, block0, seed, k, lp_rounds, eps, alpha, min_cut, max_problems, threads,
+                   kind="block_pair"):
+    """Label propagation from ``block0``, the heaviest block pairs and their
+    region flow problems (host C builder, ``regions.c``)."""
+    import ctypes
+    num_vertices = hg.num_vertices
+    E = hg.num_nets
     L = _regions_lib()
 
     def ptr(a):
@@ -424,13 +436,92 @@ def block_pair_problems(seed: int, num_vertices: int = 2_000_000,
                               int(bw[i]), int(bw[j])], dtype=np.int64)
             problems.append(Hypergraph(
                 nv, roff, rpins, rw, rvw, _i32([n]), _i32([n + 1]),
-                dict(kind="block_pair", seed=seed, pair=(i, j), cut=cut,
+                dict(kind=kind, seed=seed, pair=(i, j), cut=cut,
                      cut_before=int(info[3]), boundary=int(info[4]),
                      side_weights=(int(info[5]), int(info[6])),
                      features=feats, gid=gid)))
     finally:
         L.hfr_free(ctx)
     return BlockPairSet(hg, block, bw, lmax, moves, obj0, obj1, problems)
+
+
+
+def planted_block_pair_problems(seed: int, num_vertices: int = 2_000_000,
+                                target_pins: int = 10_000_000, size_hi: int = 2000,
+                                zipf_a: float = 2.2, k: int = 64, local_fraction: float = 0.98,
+                                noisy_pairs: int = 150, swap_fraction: float = 0.02,
+                                lp_rounds: int = 3, eps: float = 0.03, alpha: int = 16,
+                                min_cut: int = 10, max_problems: int = 500,
+                                threads: int = 0) -> BlockPairSet:
+    """Block-pair flow problems of a hypergraph with planted blocks, for a
+    partition that is good except around a few block pairs.
+
+    Draw order: net sizes (:func:`zipf_sizes_until`); ``perm =
+    rng.permutation(V)`` and planted blocks ``perm[v] % k``; per net a home
+    block ``U{0..k-1}``; per net a uniform draw deciding whether it is local
+    (probability ``local_fraction``: pins uniform without replacement from
+    the home block) or global (pins uniform over all vertices); the pins of
+    the local nets, then of the global nets; ``noisy_pairs`` pairs of
+    blocks; for each such pair ``swap_fraction`` of a block's vertices
+    (``rng.choice`` without
+    replacement, among vertices not swapped before) swap blocks; the pairs
+    are distinct, drawn by ``rng.choice`` over the k(k-1)/2 pair indices
+    (pair index t of a < b in row-major order).  Unit weights.  Then, as
+    :func:`block_pair_problems`: label propagation, the heaviest pairs and
+    their regions.  The clean pairs' current cut is (nearly always) already
+    a minimum cut of their region; the perturbed pairs can recover most of
+    the swapped vertices.
+    """
+    if num_vertices % k:
+        raise ValueError("num_vertices must be a multiple of k")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sizes = zipf_sizes_until(rng, target_pins, zipf_a, size_hi)
+    E = int(sizes.shape[0])
+    bs = num_vertices // k
+    if int(sizes.max()) > bs:
+        raise ValueError("a net is larger than a block")
+    perm = rng.permutation(num_vertices)
+    planted = (perm % k).astype(np.int64)
+    members = np.argsort(planted, kind="stable").reshape(k, bs)  # increasing ids per block
+    home = rng.integers(0, k, E)
+    local = rng.random(E) < local_fraction
+    off = np.zeros(E + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    pins = np.empty(int(off[-1]), dtype=np.int64)
+
+    def positions(mask):
+        sz = sizes[mask]
+        starts = np.repeat(off[:-1][mask], sz)
+        within = np.arange(int(sz.sum()), dtype=np.int64) - np.repeat(np.cumsum(sz) - sz, sz)
+        return starts + within, sz
+
+    pos, sz = positions(local)
+    loc = _distinct_pins(rng, bs, sz)                          # sorted per net
+    pins[pos] = members[np.repeat(home[local], sz), loc]       # stays sorted per net
+    pos, sz = positions(~local)
+    pins[pos] = _distinct_pins(rng, num_vertices, sz)
+    block0 = planted.copy()
+    npairs = k * (k - 1) // 2
+    if noisy_pairs > npairs:
+        raise ValueError("more noisy pairs than block pairs")
+    m = int(swap_fraction * bs)
+    noisy = []
+    for t in np.sort(rng.choice(npairs, noisy_pairs, replace=False)):
+        a = int(np.searchsorted(np.cumsum(np.arange(k - 1, 0, -1)), t, side="right"))
+        b = int(t - (a * (2 * k - a - 1)) // 2 + a + 1)
+        ea = members[a][block0[members[a]] == a]  # not swapped yet
+        eb = members[b][block0[members[b]] == b]
+        va = rng.choice(ea, min(m, ea.size), replace=False)
+        vb = rng.choice(eb, min(m, eb.size), replace=False)
+        block0[va] = b
+        block0[vb] = a
+        noisy.append((a, b))
+    hg = Hypergraph(int(num_vertices), _i32(off), _i32(pins), np.ones(E, dtype=np.int32),
+                    np.ones(num_vertices, dtype=np.int32), _i32([]), _i32([]),
+                    dict(kind="planted_block_pairs", seed=seed, V=num_vertices, E=E, k=k,
+                         noisy_pairs=noisy))
+    return _pair_problems(hg, _i32(block0), seed, k, lp_rounds, eps, alpha, min_cut,
+                          max_problems, threads, kind="planted_block_pair")
 
 
 def scorer_init_params(seed: int) -> np.ndarray:

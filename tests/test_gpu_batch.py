@@ -241,6 +241,25 @@ def test_batch_union_chunks(hf, oracle_mod):
             p.close()
 
 
+def test_batch_union_weight_sums(hf, oracle_mod):
+    """Problems whose net weights each sum to nearly INT32_MAX go to separate
+    unions (one union would overflow the int32 capacities); flows and sides
+    are the oracle's."""
+    hgs = [inputs.tiny_hypergraph(s) for s in (3, 9, 15, 21, 27)]  # weights near the guard
+    assert sum(int(h.net_weights.astype(np.int64).sum()) for h in hgs) > 2**31
+    refs = _oracle_all(oracle_mod, hgs)
+    probs = [hf.FlowProblem.from_hypergraph(h) for h in hgs]
+    try:
+        _say("union of problems with large weight sums")
+        with hf.FlowBatch(probs, with_cut=True, schedule=1) as b:
+            flows = b.run(with_cut=True)
+            assert list(flows) == [r.flow for r in refs]
+            _check_sides(b, hgs, refs, "weight sums")
+    finally:
+        for p in probs:
+            p.close()
+
+
 def test_batch_union_block_pairs_and_pierced(hf, oracle_mod, small_pairs):
     """Union schedule on block-pair regions, then with one problem pierced:
     the union takes each problem's current terminals."""
