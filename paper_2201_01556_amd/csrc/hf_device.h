@@ -1956,28 +1956,49 @@ __device__ void phase_seed_vertex(const Dev& g, int p) {
 // candidate of side `side` -- a pin of a net cut by that side's bipartition
 // that lies on the opposite side's reachable set and is not a terminal yet.
 // Thread per net; flags are cleared by the caller.
+// Whether net e is cut by (S_r, V - S_r) (.x) and by (V - T_r, T_r) (.y),
+// read from the stamps of its two nodes (e_in, e_out adjacent: one 8-byte
+// load).  In the uncapped network every pin reaches e_in and e_out reaches
+// every pin, so a non-empty net has a pin in S_r iff e_in is in S_r and all
+// its pins in S_r when e_out is; it has a pin in T_r iff e_out is in T_r and
+// all its pins in T_r when e_in is.  A net flagged here may still have all
+// its pins on one side (its bridge blocks); the pin scans that follow then
+// find no pin outside, so the flag changes nothing.
+struct bool2_t {
+  bool a, b;
+};
+
+__device__ __forceinline__ bool2_t net_cut_flags(const Dev& g, int e, int ep_s, int ep_t) {
+  const int2 st = reinterpret_cast<const int2*>(g.stamp + g.NB)[e];
+  return bool2_t{st.x == ep_s && st.y != ep_s, st.y == ep_t && st.x != ep_t};
+}
+
+// Flags the pins of nets cut by side `side`'s bipartition that lie on the
+// other side and are not its terminals yet (the augmenting candidates of a
+// bulk pierce).  Lanes take one net each; the nets that are cut are then
+// scanned by the whole wave, one after another, 64 pins at a time.
 __device__ void phase_fc_mark_augmenting(const Dev& g, int side, int ep_s, int ep_t,
                                          uint8_t* flag, int t0, int tstride) {
-  for (int e = t0; e < g.E; e += tstride) {
-    const int beg = g.net_off[e], end = g.net_off[e + 1];
-    bool cut;
-    if (side == 0) {
-      cut = g.stamp[g.NB + 2 * e] == ep_s && g.stamp[g.NB + 2 * e + 1] != ep_s;
-    } else {
-      bool any_in = false, any_out = false;
-      for (int p = beg; p < end; ++p) {
-        const bool in = g.stamp[g.pin_v[p]] == ep_t;
-        any_in |= in;
-        any_out |= !in;
-      }
-      cut = any_in && any_out;
+  const int lane = lane_id();
+  const int other = side == 0 ? ep_t : ep_s;
+  const int other_role = side == 0 ? 2 : 1;
+  for (int base = t0 - lane; base < g.E; base += tstride) {
+    const int e = base + lane;
+    bool cut = false;
+    if (e < g.E) {
+      const bool2_t c = net_cut_flags(g, e, ep_s, ep_t);
+      cut = side == 0 ? c.a : c.b;
     }
-    if (!cut) continue;
-    const int other = side == 0 ? ep_t : ep_s;
-    const int other_role = side == 0 ? 2 : 1;
-    for (int p = beg; p < end; ++p) {
-      const int u = g.pin_v[p];
-      if (g.stamp[u] == other && g.role[u] != other_role) flag[u] = 1;
+    unsigned long long m = __ballot(cut);
+    while (m) {
+      const int b = __builtin_ctzll(m);
+      m &= m - 1;
+      const int en = base + b;
+      const int beg = g.net_off[en], end = g.net_off[en + 1];
+      for (int p = beg + lane; p < end; p += 64) {
+        const int u = g.pin_v[p];
+        if (g.stamp[u] == other && g.role[u] != other_role) flag[u] = 1;
+      }
     }
   }
 }
@@ -2060,34 +2081,37 @@ __device__ void phase_fc_weights(const Dev& g, const int32_t* cw, int ep_s, int 
   block_min_i32(&g.ctl->pierce[2], first_free, &g.ctl->pierce[2], kInf);
 }
 
-// Piercing candidates of both sides, thread per net.  Side 0: nets cut by
-// (S_r, V - S_r), i.e. with a pin in S_r (e_in reached) and not all pins in
-// it (e_out not reached); side 1: nets with pins in T_r and outside it.  For
-// side s, pierce[3s] = smallest such pin outside S_r and T_r, pierce[3s+1] =
-// smallest such pin on the opposite side that is not a terminal yet.
+// Piercing candidates of both sides.  Side 0: nets cut by (S_r, V - S_r);
+// side 1: nets cut by (V - T_r, T_r) (net_cut_flags).  For side s,
+// pierce[3s] = smallest pin of such a net outside S_r and T_r, pierce[3s+1]
+// = smallest such pin on the opposite side that is not a terminal yet.
+// Lanes take one net each; the cut nets (a small part of all nets) are then
+// scanned by the whole wave, one after another, 64 pins at a time.
 __device__ void phase_fc_candidates(const Dev& g, int ep_s, int ep_t, int t0, int tstride) {
   int free0 = kInf, aug0 = kInf, free1 = kInf, aug1 = kInf;
-  for (int e = t0; e < g.E; e += tstride) {
-    const int beg = g.net_off[e], end = g.net_off[e + 1];
-    const bool cut0 = g.stamp[g.NB + 2 * e] == ep_s && g.stamp[g.NB + 2 * e + 1] != ep_s;
-    bool any_in = false, any_out = false;
-    for (int p = beg; p < end; ++p) {
-      const bool in = g.stamp[g.pin_v[p]] == ep_t;
-      any_in |= in;
-      any_out |= !in;
-    }
-    const bool cut1 = any_in && any_out;
-    if (!cut0 && !cut1) continue;
-    for (int p = beg; p < end; ++p) {
-      const int u = g.pin_v[p];
-      const int st = g.stamp[u];
-      if (st != ep_s && st != ep_t) {
-        if (cut0) free0 = min(free0, u);
-        if (cut1) free1 = min(free1, u);
-      } else if (st == ep_t) {
-        if (cut0 && g.role[u] != 2) aug0 = min(aug0, u);
-      } else if (cut1 && g.role[u] != 1) {
-        aug1 = min(aug1, u);
+  const int lane = lane_id();
+  for (int base = t0 - lane; base < g.E; base += tstride) {
+    const int e = base + lane;
+    bool2_t c{false, false};
+    if (e < g.E) c = net_cut_flags(g, e, ep_s, ep_t);
+    unsigned long long m = __ballot(c.a || c.b);
+    while (m) {
+      const int b = __builtin_ctzll(m);
+      m &= m - 1;
+      const bool cut0 = __shfl((int)c.a, b) != 0, cut1 = __shfl((int)c.b, b) != 0;
+      const int en = base + b;
+      const int beg = g.net_off[en], end = g.net_off[en + 1];
+      for (int p = beg + lane; p < end; p += 64) {
+        const int u = g.pin_v[p];
+        const int st = g.stamp[u];
+        if (st != ep_s && st != ep_t) {
+          if (cut0) free0 = min(free0, u);
+          if (cut1) free1 = min(free1, u);
+        } else if (st == ep_t) {
+          if (cut0 && g.role[u] != 2) aug0 = min(aug0, u);
+        } else if (cut1 && g.role[u] != 1) {
+          aug1 = min(aug1, u);
+        }
       }
     }
   }
