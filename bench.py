@@ -46,6 +46,8 @@ def main():
     ap.add_argument("--size-hi", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the block-pair batch workload")
+    ap.add_argument("--no-regions", action="store_true",
+                    help="skip the device construction of the block-pair problems")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the 2,000-vertex solves-per-second leg")
     ap.add_argument("--no-variants", action="store_true",
@@ -254,8 +256,11 @@ def main():
     learned = None
     del arrays, vs, ns
     torch.cuda.empty_cache()
+    regions = None
     if not args.no_batch:
         batch = bench_batch(args, hyperflow, inputs, torch, np)
+        if not args.no_regions:
+            regions = bench_regions(args, hyperflow, inputs, torch, np)
     if not args.no_learned:
         learned = bench_learned(args, hyperflow, inputs, torch, np,
                                 batch["config"] if batch else None)
@@ -297,6 +302,7 @@ def main():
         "paper_context": PAPER_CONTEXT,
         "kernels": kernels,
         "batch": batch,
+        "regions": regions,
         "cutter": cutter,
         "learned": learned,
     }
@@ -535,6 +541,7 @@ def bench_cutter(args, hyperflow, inputs, torch, np):
 
 
 _PAIRS = {}
+_BATCH_FLOWS = {}
 
 
 def _pairs(inputs, seed, max_problems):
@@ -782,6 +789,7 @@ def bench_batch(args, hyperflow, inputs, torch, np):
             improved += d > 0
         out.update(flows_equal_plain=same, cut_certificates=certs, total_gain=int(gain),
                    improved=int(improved))
+        _BATCH_FLOWS[args.seed] = [int(f) for f in f_batch]
         if not args.no_cpu_baseline:
             import oracle
             sample = [0, n // 2, n - 1]
@@ -814,6 +822,127 @@ def bench_batch(args, hyperflow, inputs, torch, np):
     finally:
         for p in probs:
             p.close()
+    return out
+
+
+def _host_region_build_s(inputs, bp, pairs, cuts, threads):
+    """Seconds of the host input builder (regions.c) for the same pairs on
+    `threads` host threads (context for the device builder; it is input
+    generation, not the oracle)."""
+    import ctypes
+    L = inputs._regions_lib()
+    hg = bp.hypergraph
+
+    def ptr(a):
+        return a.ctypes.data_as(ctypes.c_void_p)
+
+    blk = np.ascontiguousarray(bp.block, dtype=np.int32)
+    ctx = L.hfr_new(hg.num_vertices, hg.num_nets, ptr(hg.net_offsets), ptr(hg.pins),
+                    ptr(hg.net_weights), ptr(hg.vertex_weights), 64, ptr(blk))
+    try:
+        pi = np.ascontiguousarray([p[0] for p in pairs], dtype=np.int32)
+        pj = np.ascontiguousarray([p[1] for p in pairs], dtype=np.int32)
+        pc = np.ascontiguousarray(cuts, dtype=np.int64)
+        t = time.perf_counter()
+        if L.hfr_regions(ctx, len(pairs), ptr(pi), ptr(pj), ptr(pc), 8, 148, 100, threads) != 0:
+            raise MemoryError("region builder: out of memory")
+        return time.perf_counter() - t
+    finally:
+        L.hfr_free(ctx)
+
+
+def bench_regions(args, hyperflow, inputs, torch, np):
+    """Device construction of the block-pair flow problems (section "Network
+    Construction"): the 500 heaviest pairs of the block-pair workload,
+    regions grown by two breadth-first searches, nets built with s and t,
+    identical nets merged.  Timed from hypergraph, partition and pairs
+    resident on the device to the built problems on the device; then the
+    whole refinement step (build, one handle per problem, union solve with
+    the source sides)."""
+    bp = _pairs(inputs, args.seed, args.batch_problems)
+    hg = bp.hypergraph
+    pairs = [p.meta["pair"] for p in bp.problems]
+    cuts = [p.meta["cut"] for p in bp.problems]
+    caps = inputs.region_caps(bp.block_weights, pairs, cuts)
+    n = len(pairs)
+    dev = [torch.from_numpy(np.ascontiguousarray(a)).cuda()
+           for a in (hg.net_offsets, hg.pins, hg.net_weights, hg.vertex_weights, bp.block)]
+    torch.cuda.synchronize()
+    out = dict(workload=f"region construction of the {n} heaviest block pairs of the block-pair "
+                        f"workload ({hg.num_vertices} vertices, {hg.num_pins} pins, k=64), "
+                        "identical nets merged",
+               unit="problems/s", problems=n)
+
+    def build(merge):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rg = hyperflow.FlowRegions(hg.num_vertices, *dev, 64, pairs, caps, merge_identical=merge)
+        torch.cuda.synchronize()
+        return rg, time.perf_counter() - t
+
+    _log("device region construction")
+    times, rg = [], None
+    for _ in range(4):
+        if rg is not None:
+            rg.close()
+        rg, dt = build(True)
+        times.append(dt)
+    ms = sorted(times[1:])[1] * 1e3
+    info = [rg.info(q) for q in range(n)]
+    out.update(value=round(n / (ms / 1e3), 1), ms=round(ms, 2),
+               pins_built=int(sum(i["num_pins"] for i in info)),
+               nets_built=int(sum(i["num_nets"] for i in info)),
+               nets_merged=int(sum(i["merged"] for i in info)))
+    rg2, dt2 = build(False)
+    out["ms_without_merging"] = round(dt2 * 1e3, 2)
+    same = all(int(rg2.info(q)["num_pins"]) == bp.problems[q].num_pins for q in range(n))
+    out["unmerged_equal_host_builder_sizes"] = bool(same)
+    rg2.close()
+    # the refinement step from resident inputs: build, handles, union solve
+    _log("build + union solve")
+    step = []
+    flows = None
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r3 = hyperflow.FlowRegions(hg.num_vertices, *dev, 64, pairs, caps)
+        probs = [r3.problem(q) for q in range(n)]
+        try:
+            with hyperflow.FlowBatch(probs, with_cut=True) as plan:
+                flows = plan.run(with_cut=True)
+            torch.cuda.synchronize()
+            step.append(time.perf_counter() - t)
+        finally:
+            for p in probs:
+                p.close()
+            r3.close()
+    ms_step = sorted(step)[1] * 1e3
+    out["build_and_solve"] = dict(value=round(n / (ms_step / 1e3), 1), unit="refinements/s",
+                                  ms=round(ms_step, 2))
+    out["flows_equal_host_built"] = None
+    if batch_flows := _BATCH_FLOWS.get(args.seed):
+        out["flows_equal_host_built"] = [int(f) for f in flows] == list(batch_flows)
+    rg.close()
+    threads = len(os.sched_getaffinity(0))
+    hs = _host_region_build_s(inputs, bp, pairs, cuts, threads)
+    out["host_builder_all_cores"] = dict(ms=round(hs * 1e3, 1), threads=threads,
+                                         note="regions.c input builder, no identical-net merging")
+    if not args.no_cpu_baseline:
+        from oracle import regions as oreg
+        t = time.perf_counter()
+        vnets = oreg.vertex_nets(hg)
+        t_v = time.perf_counter() - t
+        q = n - 1
+        t = time.perf_counter()
+        oreg.build_region(hg, bp.block, hg.vertex_weights, pairs[q][0], pairs[q][1],
+                          int(caps[q][0]), int(caps[q][1]), remove_identical=True, vnets=vnets)
+        dt = time.perf_counter() - t
+        out["cpu_baseline"] = dict(value=round(1.0 / dt, 4), unit="problems/s", cores=1,
+                                   kind="oracle",
+                                   sample=f"one pair (the lightest of the {n}), plain Python, after "
+                                          f"{t_v:.1f} s for the vertex incidences")
+    del dev
+    torch.cuda.empty_cache()
     return out
 
 

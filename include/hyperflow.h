@@ -616,6 +616,78 @@ fp_status maxflow_mincut_noalloc(int32_t num_vertices, int32_t num_nets,
                                  int32_t mem_kind, void *hip_stream, int64_t *flow_value,
                                  uint8_t *vertex_side, uint8_t *net_side);
 
+/*
+ * Flow problems of block pairs, built on the device (paper, section
+ * "Network Construction": paragraphs "Region Growing", "Construction
+ * Algorithms" and "Identical Net Removal").  For each pair (i, j) of blocks
+ * of a k-way partition two breadth-first searches grow B_i inside block i
+ * and B_j inside block j, starting from the block's pins on the nets with
+ * pins in both blocks; each search visits a level in increasing vertex id
+ * and adds vertices while the side's weight stays within its cap and at
+ * least one vertex of the block stays outside, and stops for good at the
+ * first vertex that does not fit.  The pair's flow problem has the n region
+ * vertices (local ids 0..n-1 in increasing global id), the source s = n
+ * (block i outside the region, contracted) and the sink t = n + 1 (block j
+ * outside); each net with a region pin keeps its region pins and gains s
+ * (t) when it has a pin of block i (j) outside the region; pins of other
+ * blocks are dropped; nets left with fewer than two pins or with both s
+ * and t are discarded; nets keep increasing global id and list their pins
+ * in increasing local id.  With flags bit 0 nets with equal pin sets are
+ * merged into the one of smallest global id, carrying the sum of their
+ * weights (this changes no cut).
+ */
+typedef struct fp_regions fp_regions; /* opaque, library-owned */
+
+/*
+ * flow_regions_build: the flow problems of num_pairs block pairs.
+ *
+ *   num_vertices, num_nets, net_offsets, pins, net_weights   the hypergraph,
+ *                as flow_problem_create (pins of a net distinct)
+ *   vertex_weights  num_vertices weights >= 1
+ *   blocks       num_vertices block ids in [0, k), 2 <= k <= 64
+ *   pairs        host, 2 * num_pairs distinct block ids (i, j) per pair
+ *   caps         host, 2 * num_pairs weight caps (>= 0) of B_i and B_j
+ *                (the caller's policy, e.g. the paper's
+ *                (1 + alpha eps) ceil(c(V_i u V_j) / 2) - c(other block))
+ *   flags        bit 0: merge identical nets; other bits must be 0
+ *   mem_kind     of the hypergraph, vertex weights and blocks
+ *
+ * Every step runs on the device; the call returns when the problems are
+ * built.  Errors: FP_ERR_INVALID (malformed input; the message names it),
+ * FP_ERR_OVERFLOW (more than 2^31 - 1 touched nets or pins in all, or a
+ * merged weight beyond INT32_MAX), FP_ERR_OOM, FP_ERR_DEVICE.
+ */
+fp_status flow_regions_build(int32_t num_vertices, int32_t num_nets,
+                             const int32_t *net_offsets, const int32_t *pins,
+                             const int32_t *net_weights, const int32_t *vertex_weights,
+                             const int32_t *blocks, int32_t k, int32_t num_pairs,
+                             const int32_t *pairs, const int64_t *caps, int32_t flags,
+                             int32_t mem_kind, void *hip_stream, fp_regions **out);
+
+/* Facts of pair `pair`, 16 entries: n, num_vertices (n + 2), num_nets,
+ * num_pins, cut_before (weight of the built nets cut by the current
+ * bipartition: a pin of block i or s and a pin of block j or t), boundary
+ * (level-0 vertices of both searches), c(B_i), c(B_j), seven net-size bins
+ * of the built nets (2, 3-4, 5-8, 9-16, 17-64, 65-256, more), nets merged. */
+fp_status flow_regions_info(const fp_regions *regions, int32_t pair, int64_t *info);
+
+/* Copy pair `pair`'s problem into caller buffers of memory kind mem_kind
+ * (any pointer may be NULL): net_offsets[num_nets + 1], pins[num_pins]
+ * (local ids), net_weights[num_nets], vertex_weights[n + 2] (s and t weigh
+ * what their blocks keep outside the region), vertex_ids[n] (global id of
+ * each region vertex), net_ids[num_nets] (global id of each net). */
+fp_status flow_regions_export(const fp_regions *regions, int32_t pair, int32_t mem_kind,
+                              void *hip_stream, int32_t *net_offsets, int32_t *pins,
+                              int32_t *net_weights, int32_t *vertex_weights,
+                              int32_t *vertex_ids, int32_t *net_ids);
+
+/* A flow problem handle of pair `pair` (sources {n}, sinks {n + 1}),
+ * created from the device copy as flow_problem_create with mem_kind 1. */
+fp_status flow_regions_problem(const fp_regions *regions, int32_t pair, const fp_options *opts,
+                               void *hip_stream, fp_problem **out);
+
+void flow_regions_destroy(fp_regions *regions);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *fp_last_error(void);
 

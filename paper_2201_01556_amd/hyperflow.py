@@ -148,6 +148,11 @@ EXPORTED = [
     "flow_problem_export_state",
     "flow_problem_destroy",
     "maxflow_mincut_noalloc",
+    "flow_regions_build",
+    "flow_regions_info",
+    "flow_regions_export",
+    "flow_regions_problem",
+    "flow_regions_destroy",
     "scorer_create",
     "scorer_fit_normalization",
     "scorer_gradient",
@@ -222,6 +227,17 @@ def load_library(path: str = LIB_PATH):
     lib.maxflow_mincut_noalloc.argtypes = [i32, i32, vp, vp, vp, vp, i32, vp, i32, i32, vp,
                                            ctypes.POINTER(ctypes.c_int64), vp, vp]
     lib.maxflow_mincut_noalloc.restype = ctypes.c_int
+    lib.flow_regions_build.argtypes = [i32, i32, vp, vp, vp, vp, vp, i32, i32, vp, vp, i32, i32,
+                                       vp, ctypes.POINTER(vp)]
+    lib.flow_regions_build.restype = ctypes.c_int
+    lib.flow_regions_info.argtypes = [vp, i32, vp]
+    lib.flow_regions_info.restype = ctypes.c_int
+    lib.flow_regions_export.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, vp]
+    lib.flow_regions_export.restype = ctypes.c_int
+    lib.flow_regions_problem.argtypes = [vp, i32, ctypes.POINTER(Options), vp, ctypes.POINTER(vp)]
+    lib.flow_regions_problem.restype = ctypes.c_int
+    lib.flow_regions_destroy.argtypes = [vp]
+    lib.flow_regions_destroy.restype = None
     lib.scorer_create.argtypes = [vp, vp, ctypes.POINTER(vp)]
     lib.scorer_create.restype = ctypes.c_int
     lib.scorer_fit_normalization.argtypes = [vp, vp, i32, i32, vp]
@@ -580,6 +596,116 @@ def flow_problem_destroy(handle):
         load_library().flow_problem_destroy(handle)
 
 
+REGION_INFO = ("n", "num_vertices", "num_nets", "num_pins", "cut_before", "boundary",
+               "weight_i", "weight_j", "bin_2", "bin_4", "bin_8", "bin_16", "bin_64",
+               "bin_256", "bin_more", "merged")
+
+
+def flow_regions_build(num_vertices, net_offsets, pins, net_weights, vertex_weights, blocks,
+                       k, pairs, caps, merge_identical=True, stream=None):
+    """Build the flow problems of block pairs on the device; hypergraph,
+    vertex weights and blocks all host (numpy) or all device (torch);
+    ``pairs`` (count x 2 block ids) and ``caps`` (count x 2 weight caps) are
+    host arrays.  Returns the handle."""
+    lib = load_library()
+    arrs = [_ptr(a, np.int32) for a in (net_offsets, pins, net_weights, vertex_weights, blocks)]
+    kinds = {m for _, m, _ in arrs}
+    if len(kinds) != 1:
+        raise TypeError("hypergraph, vertex weights and blocks must share one memory kind")
+    pr = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1)
+    cp = np.ascontiguousarray(caps, dtype=np.int64).reshape(-1)
+    if pr.shape[0] != cp.shape[0] or pr.shape[0] % 2:
+        raise ValueError("pairs and caps need two entries per pair")
+    num_nets = len(net_offsets) - 1
+    out = ctypes.c_void_p()
+    _check(lib.flow_regions_build(int(num_vertices), int(num_nets), *[a[0] for a in arrs],
+                                  int(k), pr.shape[0] // 2, pr.ctypes.data, cp.ctypes.data,
+                                  1 if merge_identical else 0, kinds.pop(), _stream_ptr(stream),
+                                  ctypes.byref(out)))
+    return out.value
+
+
+def flow_regions_info(handle, pair) -> dict:
+    lib = load_library()
+    info = np.zeros(16, dtype=np.int64)
+    _check(lib.flow_regions_info(handle, int(pair), info.ctypes.data))
+    return {k: int(v) for k, v in zip(REGION_INFO, info)}
+
+
+def flow_regions_export(handle, pair, stream=None) -> dict:
+    """Pair ``pair``'s problem copied to the host."""
+    lib = load_library()
+    inf = flow_regions_info(handle, pair)
+    n, ne, npins = inf["n"], inf["num_nets"], inf["num_pins"]
+    bufs = dict(net_offsets=np.empty(ne + 1, np.int32), pins=np.empty(max(npins, 1), np.int32),
+                net_weights=np.empty(max(ne, 1), np.int32), vertex_weights=np.empty(n + 2, np.int32),
+                vertex_ids=np.empty(max(n, 1), np.int32), net_ids=np.empty(max(ne, 1), np.int32))
+    _check(lib.flow_regions_export(handle, int(pair), 0, _stream_ptr(stream),
+                                   *[b.ctypes.data for b in bufs.values()]))
+    bufs["pins"] = bufs["pins"][:npins]
+    bufs["net_weights"] = bufs["net_weights"][:ne]
+    bufs["vertex_ids"] = bufs["vertex_ids"][:n]
+    bufs["net_ids"] = bufs["net_ids"][:ne]
+    bufs["info"] = inf
+    return bufs
+
+
+def flow_regions_problem(handle, pair, options: Options | None = None, stream=None):
+    lib = load_library()
+    out = ctypes.c_void_p()
+    _check(lib.flow_regions_problem(handle, int(pair),
+                                    ctypes.byref(options) if options is not None else None,
+                                    _stream_ptr(stream), ctypes.byref(out)))
+    return out.value
+
+
+def flow_regions_destroy(handle):
+    if handle:
+        load_library().flow_regions_destroy(handle)
+
+
+class FlowRegions:
+    """Owner of the device-built flow problems of block pairs."""
+
+    def __init__(self, num_vertices, net_offsets, pins, net_weights, vertex_weights, blocks, k,
+                 pairs, caps, merge_identical=True, stream=None):
+        self.stream = stream
+        self.count = len(np.asarray(pairs).reshape(-1)) // 2
+        self.handle = flow_regions_build(num_vertices, net_offsets, pins, net_weights,
+                                         vertex_weights, blocks, k, pairs, caps, merge_identical,
+                                         stream)
+
+    def info(self, pair) -> dict:
+        return flow_regions_info(self.handle, pair)
+
+    def export(self, pair) -> dict:
+        return flow_regions_export(self.handle, pair, self.stream)
+
+    def problem(self, pair, options: Options | None = None, **opts) -> "FlowProblem":
+        if options is None and opts:
+            options = Options(**opts)
+        inf = self.info(pair)
+        return FlowProblem._adopt(flow_regions_problem(self.handle, pair, options, self.stream),
+                                  inf["num_vertices"], inf["num_nets"], self.stream)
+
+    def close(self):
+        if self.handle:
+            flow_regions_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class FlowProblem:
     """Owner of one problem handle."""
 
@@ -592,6 +718,16 @@ class FlowProblem:
         self.stream = stream
         self.handle = flow_problem_create(num_vertices, net_offsets, pins, net_weights,
                                           sources, sinks, options, stream)
+
+    @classmethod
+    def _adopt(cls, handle, num_vertices, num_nets, stream=None):
+        """Wrap a handle created elsewhere (the caller gives up its ownership)."""
+        self = cls.__new__(cls)
+        self.num_vertices = int(num_vertices)
+        self.num_nets = int(num_nets)
+        self.stream = stream
+        self.handle = handle
+        return self
 
     @classmethod
     def from_hypergraph(cls, hg, device: bool = False, **opts):

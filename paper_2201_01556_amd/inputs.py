@@ -383,6 +383,25 @@ def block_pair_problems(seed: int, num_vertices: int = 2_000_000,
                           threads)
 
 
+def region_caps(block_weights, pairs, cuts, alpha: int = 16, eps: float = 0.03) -> np.ndarray:
+    """Side weight caps of the regions of block pairs (count x 2), the bound
+    the region builders use: ``min(alpha / 2 * cut, (1 + alpha eps) *
+    ceil((c(Vi) + c(Vj)) / 2) - c(other block))``, at least 0, in integer
+    arithmetic (eps in whole percent)."""
+    bw = np.asarray(block_weights, dtype=np.int64)
+    pr = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    cut = np.asarray(cuts, dtype=np.int64).reshape(-1)
+    eps_pct = int(round(eps * 100))
+    scale_num = 100 + alpha * eps_pct
+    out = np.zeros((pr.shape[0], 2), dtype=np.int64)
+    for t, (i, j) in enumerate(pr):
+        cvi, cvj = int(bw[i]), int(bw[j])
+        lim = scale_num * ((cvi + cvj + 1) // 2) // 100
+        out[t, 0] = max(0, min((alpha // 2) * int(cut[t]), lim - cvj))
+        out[t, 1] = max(0, min((alpha // 2) * int(cut[t]), lim - cvi))
+    return out
+
+
 def _pair_problems(hg, block0, seed, k, lp_rounds, eps, alpha, min_cut, max_problems, threads,
                    kind="block_pair"):
     """Label propagation from ``block0``, the heaviest block pairs and their
