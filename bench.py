@@ -261,6 +261,7 @@ def main():
         batch = bench_batch(args, hyperflow, inputs, torch, np)
         if not args.no_regions:
             regions = bench_regions(args, hyperflow, inputs, torch, np)
+            regions["refine"] = bench_refine(args, hyperflow, inputs, torch, np)
     if not args.no_learned:
         learned = bench_learned(args, hyperflow, inputs, torch, np,
                                 batch["config"] if batch else None)
@@ -825,7 +826,43 @@ def bench_batch(args, hyperflow, inputs, torch, np):
     return out
 
 
-def _host_region_build_s(inputs, bp, pairs, cuts, threads):
+def bench_refine(args, hyperflow, inputs, torch, np):
+    """Refinement rounds on the device (flow_partition_refine: quotient
+    graph, regions of the active pairs, union minimum cuts, moves applied
+    with the balance check and revert) on the two block-pair workloads'
+    partitions (random k=64 + label propagation; planted blocks with 150
+    perturbed pairs), timed from the partition on the device to the refined
+    partition."""
+    out = {}
+    for kind, gen in (("c4", inputs.block_pair_problems),
+                      ("planted", inputs.planted_block_pair_problems)):
+        _log(f"refinement rounds, {kind} workload")
+        bp = gen(args.seed, max_problems=1, threads=0)
+        hg = bp.hypergraph
+        dev = [torch.from_numpy(np.ascontiguousarray(a)).cuda()
+               for a in (hg.net_offsets, hg.pins, hg.net_weights, hg.vertex_weights, bp.block)]
+        torch.cuda.synchronize()
+        with hyperflow.FlowPartition(hg.num_vertices, *dev, 64) as part:
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            res, traj = part.refine(max_rounds=8)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            blocks, bw, obj = part.get()
+        cv = int(hg.vertex_weights.sum())
+        lmax = (103 * (-(-cv // 64))) // 100
+        res.update(seconds=round(dt, 3), objective_per_round=[int(x) for x in traj],
+                   pairs_per_s=round(res["pairs_tried"] / dt, 1),
+                   balanced=bool(int(bw.max()) <= lmax),
+                   improvement_pct=round(100.0 * (res["objective_before"] - res["objective_after"])
+                                         / max(res["objective_before"], 1), 3))
+        out[kind] = res
+        del dev
+        torch.cuda.empty_cache()
+    return out
+
+
+def _host_region_build_s(inputs, np, bp, pairs, cuts, threads):
     """Seconds of the host input builder (regions.c) for the same pairs on
     `threads` host threads (context for the device builder; it is input
     generation, not the oracle)."""
@@ -924,7 +961,7 @@ def bench_regions(args, hyperflow, inputs, torch, np):
         out["flows_equal_host_built"] = [int(f) for f in flows] == list(batch_flows)
     rg.close()
     threads = len(os.sched_getaffinity(0))
-    hs = _host_region_build_s(inputs, bp, pairs, cuts, threads)
+    hs = _host_region_build_s(inputs, np, bp, pairs, cuts, threads)
     out["host_builder_all_cores"] = dict(ms=round(hs * 1e3, 1), threads=threads,
                                          note="regions.c input builder, no identical-net merging")
     if not args.no_cpu_baseline:

@@ -688,6 +688,104 @@ fp_status flow_regions_problem(const fp_regions *regions, int32_t pair, const fp
 
 void flow_regions_destroy(fp_regions *regions);
 
+/*
+ * A k-way partition on the device, to which the results of block-pair
+ * refinements are applied (paper, section "Parallel Active Block
+ * Scheduling", paragraph "Apply Moves").  It holds a copy of the
+ * hypergraph, the block of every vertex, the pin count of every net in every
+ * block and the block weights.
+ */
+typedef struct fp_partition fp_partition; /* opaque, library-owned */
+
+/* flow_partition_create: inputs as flow_regions_build (2 <= k <= 4096),
+ * all in memory kind mem_kind; copied.  Device memory: about
+ * 4 (num_nets * k + 3 |pins| + 3 num_vertices) bytes.  Errors:
+ * FP_ERR_INVALID, FP_ERR_OOM, FP_ERR_DEVICE. */
+fp_status flow_partition_create(int32_t num_vertices, int32_t num_nets,
+                                const int32_t *net_offsets, const int32_t *pins,
+                                const int32_t *net_weights, const int32_t *vertex_weights,
+                                const int32_t *blocks, int32_t k, int32_t mem_kind,
+                                void *hip_stream, fp_partition **out);
+
+/*
+ * flow_partition_apply: apply the pairs' results in pair order.
+ *
+ *   regions         built by flow_regions_build on the same hypergraph and k,
+ *                   from the partition the results refine
+ *   vertex_sides    host array of num_pairs device pointers: pair q's
+ *                   minimal source side X over its n region vertices (as
+ *                   written by mincut_source_side or a batch plan)
+ *   expected_gains  host, num_pairs: cut_before - F of each pair
+ *   lmax            the balance bound of every block
+ *   status, gains, moved   host outputs per pair (any may be NULL):
+ *                   status 0 = not tried (expected gain <= 0), 1 = applied,
+ *                   2 = rejected (block i or j would exceed lmax),
+ *                   3 = reverted (exact gain < 0); gains = exact change of
+ *                   sum w(e) (lambda(e) - 1) (0 unless 1 or 3); moved =
+ *                   moves applied (or undone)
+ *
+ * For pair (i, j): a region vertex of block i outside X moves to j, one of
+ * block j inside X moves to i; moves whose vertex left its block since the
+ * regions were built are dropped; if block i or j would exceed lmax nothing
+ * is applied; otherwise all moves are applied and, when the exact gain is
+ * negative, undone.  One workgroup runs the sequences in order on the
+ * device.  Errors: FP_ERR_INVALID, FP_ERR_OOM, FP_ERR_DEVICE.
+ */
+fp_status flow_partition_apply(fp_partition *partition, const fp_regions *regions,
+                               const uint8_t *const *vertex_sides,
+                               const int64_t *expected_gains, int64_t lmax, void *hip_stream,
+                               int32_t *status, int64_t *gains, int32_t *moved);
+
+/* Copy out the blocks (num_vertices, memory kind mem_kind), the k block
+ * weights (host) and the objective sum w(e) (lambda(e) - 1) (host); any
+ * pointer may be NULL. */
+fp_status flow_partition_get(fp_partition *partition, int32_t mem_kind, void *hip_stream,
+                             int32_t *blocks, int64_t *block_weights, int64_t *objective);
+
+/*
+ * flow_partition_refine: refinement rounds around the batched solver (the
+ * paper's algorithm "Parallel Flow-Based Refinement" and section
+ * "Parallel Active Block Scheduling"), as synchronous rounds on the device:
+ * the block pairs with cut weight >= min_cut and an active block (all
+ * blocks are active at first), heaviest cut first (then block ids), get
+ * regions with side caps min(alpha / 2 * cut, (100 + alpha eps) / 100 *
+ * ceil((c(V_i) + c(V_j)) / 2) - c(other block)) (flow_regions_build), are
+ * solved at once by the union schedule (minimum cuts; expected gain =
+ * cut_before - F) and applied in that order by flow_partition_apply with
+ * Lmax = floor((100 + eps) ceil(c(V) / k) / 100); the blocks of every pair
+ * applied with a positive gain are active in the next round.  The rounds
+ * stop when no pair is left, after max_rounds, or when a round improves
+ * sum w(e) (lambda(e) - 1) by less than min_improvement_ppm parts per
+ * million.  k <= 64.
+ *
+ *   objective_per_round   host, max_rounds + 1 entries or NULL: the
+ *                         objective before the first round and after each
+ */
+typedef struct {
+  int32_t max_rounds;          /* 0 = 16                                      */
+  int32_t min_cut;             /* 0 = 10 (the paper's pruning rule)            */
+  int32_t alpha;               /* region scale; 0 = 16                         */
+  int32_t eps_percent;         /* imbalance in percent; 0 = 3                  */
+  int32_t min_improvement_ppm; /* 0 = 1000 (0.1 %, the paper's stop rule)      */
+  int32_t max_pairs;           /* pairs per round at most; 0 = all             */
+  int32_t merge_identical;     /* 1 = merge identical nets in the regions      */
+  int32_t reserved;            /* must be 0                                    */
+} fp_refine_config;
+
+typedef struct {
+  int64_t objective_before, objective_after;
+  int64_t moves;               /* moves applied (not undone)                   */
+  int32_t rounds;
+  int32_t pairs_tried, pairs_applied, pairs_reverted, pairs_unbalanced;
+  int32_t reserved[3];
+} fp_refine_result;
+
+fp_status flow_partition_refine(fp_partition *partition, const fp_refine_config *config,
+                                void *hip_stream, fp_refine_result *result,
+                                int64_t *objective_per_round);
+
+void flow_partition_destroy(fp_partition *partition);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *fp_last_error(void);
 

@@ -19,7 +19,7 @@ OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhyperflow.so")
 
 SOURCES = ["hf_build.hip", "hf_solve.hip", "hf_batch.hip", "hf_mlp.hip", "hf_api.hip",
-           "hf_noalloc.hip", "hf_regions.hip"]
+           "hf_noalloc.hip", "hf_regions.hip", "hf_moves.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -99,6 +99,24 @@ struct fp_problem {
   double k_bytes[hf::KK_COUNT] = {};
 };
 
+// Flow problems of block pairs built on the device (hf_regions.hip).
+struct fp_regions {
+  int device = 0;
+  int32_t npairs = 0, k = 0, V = 0;
+  void* mem = nullptr;                   // device outputs (one allocation)
+  int32_t* off = nullptr;                // per pair ne+1 relative offsets
+  int32_t* pins = nullptr;               // local ids
+  int32_t* w = nullptr;                  // net weights
+  int32_t* ngid = nullptr;               // global net id (smallest of a group)
+  int32_t* vw = nullptr;                 // per pair n+2 vertex weights
+  int32_t* vgid = nullptr;               // per pair n global vertex ids
+  int8_t* vside = nullptr;               // per pair n: 0 = region of block i, 1 = of block j
+  int32_t* terms = nullptr;              // per pair {n, n+1}
+  std::vector<int32_t> pairs;            // 2 per pair
+  std::vector<int64_t> info;             // npairs * 16
+  std::vector<long long> net_base, pin_base, vtx_base, nloc;  // where pair q starts; n
+};
+
 namespace hf {
 
 void set_error(const char* fmt, ...);

@@ -53,21 +53,6 @@ enum : int {
 
 }  // namespace
 
-struct fp_regions {
-  int device = 0;
-  int32_t npairs = 0;
-  void* mem = nullptr;                   // device outputs (one allocation)
-  int32_t* off = nullptr;                // per pair ne+1 relative offsets
-  int32_t* pins = nullptr;               // local ids
-  int32_t* w = nullptr;                  // net weights
-  int32_t* ngid = nullptr;               // global net id (smallest of a group)
-  int32_t* vw = nullptr;                 // per pair n+2 vertex weights
-  int32_t* vgid = nullptr;               // per pair n global vertex ids
-  int32_t* terms = nullptr;              // per pair {n, n+1}
-  std::vector<int64_t> info;             // npairs * kInfoLen
-  std::vector<long long> net_base, pin_base, vtx_base;  // where pair q starts
-};
-
 namespace hf {
 
 // ---------------------------------------------------------------------------
@@ -317,6 +302,7 @@ __global__ void __launch_bounds__(kRegBlock) k_rg_grow(RgGraph g, RgSide r) {
 struct RgOut {
   const long long* vbase;     // per pair: first member slot (vgid), vw starts at vbase + 2 q
   int32_t* vgid;
+  int8_t* vside;              // per member: 0 = from block i, 1 = from block j
   int32_t* vw;
   int32_t* terms;
   int32_t* lmap;              // per side, indexed like lev: local id of an added vertex
@@ -360,6 +346,7 @@ __global__ void __launch_bounds__(kRegBlock) k_rg_members(RgGraph g, RgSide r, R
       const int rank = a + rg_lower_bound(lst[1 - side], bvs[1 - side], n[1 - side], gid);
       lm[side][l] = rank;
       o.vgid[vb + rank] = gid;
+      o.vside[vb + rank] = (int8_t)side;
       o.vw[vb + 2ll * q + rank] = g.cv[gid];
     }
   }
@@ -840,6 +827,9 @@ fp_status regions_build(int32_t V, int32_t E, const int32_t* off_in, const int32
   });
   r->device = dev;
   r->npairs = npairs;
+  r->k = k;
+  r->V = V;
+  r->pairs.assign(pairs, pairs + 2ll * npairs);
   r->info.assign((size_t)npairs * kInfoLen, 0);
   if (npairs == 0) {
     *out = guard.release();
@@ -895,6 +885,7 @@ fp_status regions_build(int32_t V, int32_t E, const int32_t* off_in, const int32
     nv_tot += nloc[q];
   }
   r->vtx_base = vbase;
+  r->nloc = nloc;
   long long *vbase_d, *nloc_d, *ntouch_d;
   RG_TRY(sc.get((size_t)npairs, &vbase_d), "allocating");
   RG_TRY(sc.get((size_t)npairs, &nloc_d), "allocating");
@@ -902,10 +893,12 @@ fp_status regions_build(int32_t V, int32_t E, const int32_t* off_in, const int32
   RG_TRY(hipMemcpyAsync(vbase_d, vbase.data(), npairs * 8ull, hipMemcpyHostToDevice, s), "copy");
   RG_TRY(hipMemcpyAsync(nloc_d, nloc.data(), npairs * 8ull, hipMemcpyHostToDevice, s), "copy");
   int32_t *vgid_d, *vw_d, *terms_d;
+  int8_t* vside_d;
   RG_TRY(sc.get((size_t)std::max(nv_tot, 1ll), &vgid_d), "allocating");
+  RG_TRY(sc.get((size_t)std::max(nv_tot, 1ll), &vside_d), "allocating");
   RG_TRY(sc.get((size_t)(nv_tot + 2ll * npairs), &vw_d), "allocating");
   RG_TRY(sc.get((size_t)(2ll * npairs), &terms_d), "allocating");
-  RgOut ro{vbase_d, vgid_d, vw_d, terms_d, lmap, ntouch_d};
+  RgOut ro{vbase_d, vgid_d, vside_d, vw_d, terms_d, lmap, ntouch_d};
   k_rg_members<<<npairs, kRegBlock, 0, s>>>(g, rs, ro);
   std::vector<long long> ntouch(npairs), tbase(npairs);
   RG_TRY(hipMemcpyAsync(ntouch.data(), ntouch_d, npairs * 8ull, hipMemcpyDeviceToHost, s), "read");
@@ -1065,7 +1058,7 @@ fp_status regions_build(int32_t V, int32_t E, const int32_t* off_in, const int32
   };
   const size_t o_off = add(ne_tot + npairs), o_pins = add(np_tot), o_w = add(ne_tot),
                o_ngid = add(ne_tot), o_vw = add(nv_tot + 2ll * npairs), o_vgid = add(nv_tot),
-               o_terms = add(2ll * npairs);
+               o_terms = add(2ll * npairs), o_vside = add((nv_tot + 3) / 4);
   RG_TRY(hipMalloc(&r->mem, bytes), "allocating the regions");
   char* base = static_cast<char*>(r->mem);
   r->off = reinterpret_cast<int32_t*>(base + o_off);
@@ -1075,6 +1068,7 @@ fp_status regions_build(int32_t V, int32_t E, const int32_t* off_in, const int32
   r->vw = reinterpret_cast<int32_t*>(base + o_vw);
   r->vgid = reinterpret_cast<int32_t*>(base + o_vgid);
   r->terms = reinterpret_cast<int32_t*>(base + o_terms);
+  r->vside = reinterpret_cast<int8_t*>(base + o_vside);
   RG_TRY(hipMemcpyAsync(nbase_d, nbase.data(), npairs * 8ull, hipMemcpyHostToDevice, s), "copy");
   RG_TRY(hipMemcpyAsync(pbase_d, pbase.data(), npairs * 8ull, hipMemcpyHostToDevice, s), "copy");
   RgFinal fo{dead, fidx, fpos, nbase_d, pbase_d, r->off, r->pins, r->w, r->ngid, bins_d, err};
@@ -1086,6 +1080,8 @@ fp_status regions_build(int32_t V, int32_t E, const int32_t* off_in, const int32
   RG_TRY(hipMemcpyAsync(r->vw, vw_d, (nv_tot + 2ll * npairs) * 4ull, hipMemcpyDeviceToDevice, s),
          "copy");
   RG_TRY(hipMemcpyAsync(r->terms, terms_d, 2ll * npairs * 4, hipMemcpyDeviceToDevice, s), "copy");
+  if (nv_tot)
+    RG_TRY(hipMemcpyAsync(r->vside, vside_d, nv_tot, hipMemcpyDeviceToDevice, s), "copy");
   std::vector<unsigned long long> bins_h(7ull * npairs);
   RG_TRY(hipMemcpyAsync(bins_h.data(), bins_d, 56ull * npairs, hipMemcpyDeviceToHost, s), "read");
   RG_TRY(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, s), "reading");

@@ -153,6 +153,11 @@ EXPORTED = [
     "flow_regions_export",
     "flow_regions_problem",
     "flow_regions_destroy",
+    "flow_partition_create",
+    "flow_partition_apply",
+    "flow_partition_get",
+    "flow_partition_refine",
+    "flow_partition_destroy",
     "scorer_create",
     "scorer_fit_normalization",
     "scorer_gradient",
@@ -238,6 +243,19 @@ def load_library(path: str = LIB_PATH):
     lib.flow_regions_problem.restype = ctypes.c_int
     lib.flow_regions_destroy.argtypes = [vp]
     lib.flow_regions_destroy.restype = None
+    lib.flow_partition_create.argtypes = [i32, i32, vp, vp, vp, vp, vp, i32, i32, vp,
+                                          ctypes.POINTER(vp)]
+    lib.flow_partition_create.restype = ctypes.c_int
+    lib.flow_partition_apply.argtypes = [vp, vp, ctypes.POINTER(vp), vp, ctypes.c_int64, vp,
+                                         vp, vp, vp]
+    lib.flow_partition_apply.restype = ctypes.c_int
+    lib.flow_partition_get.argtypes = [vp, i32, vp, vp, vp, vp]
+    lib.flow_partition_get.restype = ctypes.c_int
+    lib.flow_partition_refine.argtypes = [vp, ctypes.POINTER(RefineConfig), vp,
+                                          ctypes.POINTER(RefineResult), vp]
+    lib.flow_partition_refine.restype = ctypes.c_int
+    lib.flow_partition_destroy.argtypes = [vp]
+    lib.flow_partition_destroy.restype = None
     lib.scorer_create.argtypes = [vp, vp, ctypes.POINTER(vp)]
     lib.scorer_create.restype = ctypes.c_int
     lib.scorer_fit_normalization.argtypes = [vp, vp, i32, i32, vp]
@@ -691,6 +709,109 @@ class FlowRegions:
     def close(self):
         if self.handle:
             flow_regions_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+MOVE_STATUS = {0: "not tried", 1: "applied", 2: "unbalanced", 3: "reverted"}
+
+
+class RefineConfig(ctypes.Structure):
+    _fields_ = [("max_rounds", ctypes.c_int32), ("min_cut", ctypes.c_int32),
+                ("alpha", ctypes.c_int32), ("eps_percent", ctypes.c_int32),
+                ("min_improvement_ppm", ctypes.c_int32), ("max_pairs", ctypes.c_int32),
+                ("merge_identical", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class RefineResult(ctypes.Structure):
+    _fields_ = [("objective_before", ctypes.c_int64), ("objective_after", ctypes.c_int64),
+                ("moves", ctypes.c_int64), ("rounds", ctypes.c_int32),
+                ("pairs_tried", ctypes.c_int32), ("pairs_applied", ctypes.c_int32),
+                ("pairs_reverted", ctypes.c_int32), ("pairs_unbalanced", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
+
+
+class FlowPartition:
+    """Owner of a k-way partition on the device to which block-pair results
+    are applied (flow_partition_*)."""
+
+    def __init__(self, num_vertices, net_offsets, pins, net_weights, vertex_weights, blocks, k,
+                 stream=None):
+        lib = load_library()
+        arrs = [_ptr(a, np.int32)
+                for a in (net_offsets, pins, net_weights, vertex_weights, blocks)]
+        kinds = {m for _, m, _ in arrs}
+        if len(kinds) != 1:
+            raise TypeError("hypergraph, vertex weights and blocks must share one memory kind")
+        self.stream = stream
+        self.num_vertices = int(num_vertices)
+        self.k = int(k)
+        out = ctypes.c_void_p()
+        _check(lib.flow_partition_create(int(num_vertices), len(net_offsets) - 1,
+                                         *[a[0] for a in arrs], int(k), kinds.pop(),
+                                         _stream_ptr(stream), ctypes.byref(out)))
+        self.handle = out.value
+
+    def apply(self, regions: "FlowRegions", vertex_sides, expected_gains, lmax):
+        """Apply pair q's source side ``vertex_sides[q]`` (device uint8
+        tensors) in pair order; returns (status, gains, moved) arrays."""
+        lib = load_library()
+        n = regions.count
+        ptrs = (ctypes.c_void_p * max(n, 1))()
+        for q in range(n):
+            ptrs[q] = _ptr(vertex_sides[q], np.uint8)[0]
+        g = np.ascontiguousarray(expected_gains, dtype=np.int64)
+        if g.shape[0] != n:
+            raise ValueError("one expected gain per pair")
+        st = np.zeros(max(n, 1), np.int32)
+        gains = np.zeros(max(n, 1), np.int64)
+        moved = np.zeros(max(n, 1), np.int32)
+        _check(lib.flow_partition_apply(self.handle, regions.handle, ptrs, g.ctypes.data,
+                                        int(lmax), _stream_ptr(self.stream), st.ctypes.data,
+                                        gains.ctypes.data, moved.ctypes.data))
+        return st[:n], gains[:n], moved[:n]
+
+    def refine(self, max_rounds=16, min_cut=10, alpha=16, eps_percent=3,
+               min_improvement_ppm=1000, max_pairs=0, merge_identical=True):
+        """Refinement rounds on the device (flow_partition_refine); returns
+        (result dict, objective after each round, first entry before)."""
+        lib = load_library()
+        max_rounds = int(max_rounds) or 16
+        cfg = RefineConfig(int(max_rounds), int(min_cut), int(alpha), int(eps_percent),
+                           int(min_improvement_ppm), int(max_pairs), int(bool(merge_identical)),
+                           0)
+        res = RefineResult()
+        traj = np.full(int(max_rounds) + 1, -1, np.int64)
+        _check(lib.flow_partition_refine(self.handle, ctypes.byref(cfg), _stream_ptr(self.stream),
+                                         ctypes.byref(res), traj.ctypes.data))
+        out = {name: int(getattr(res, name)) for name, _ in RefineResult._fields_
+               if name != "reserved"}
+        return out, traj[:out["rounds"] + 1]
+
+    def get(self):
+        """(blocks, block weights, objective sum w(e) (lambda(e) - 1))."""
+        lib = load_library()
+        blocks = np.empty(self.num_vertices, np.int32)
+        bw = np.empty(self.k, np.int64)
+        obj = ctypes.c_int64()
+        _check(lib.flow_partition_get(self.handle, 0, _stream_ptr(self.stream),
+                                      blocks.ctypes.data, bw.ctypes.data, ctypes.byref(obj)))
+        return blocks, bw, int(obj.value)
+
+    def close(self):
+        if self.handle:
+            load_library().flow_partition_destroy(self.handle)
             self.handle = None
 
     def __enter__(self):
