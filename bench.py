@@ -73,6 +73,9 @@ def main():
                     help="reverse-BFS levels: 1 flattened arcs per wave, -1 lane groups, 0 default")
     ap.add_argument("--bfs-marks", type=int, default=0,
                     help="expanded reverse-BFS levels: 1 byte marks, -1 labels, 0 default")
+    ap.add_argument("--bfs-xcd", type=int, default=0,
+                    help="expanded reverse-BFS levels labelled per XCD slice: 1 large networks, "
+                         "2 always, -1 off (default)")
     ap.add_argument("--gather-probe", type=int, default=0, metavar="READS",
                     help="only run one gather of READS random 4-byte words (counter "
                          "calibration for scattered reads) and exit")
@@ -142,7 +145,7 @@ def main():
     def step(profile):
         opts = hyperflow.Options(profile=profile, bfs_flat=args.bfs_flat,
                                  bfs_marks=args.bfs_marks,
-                                 relabel_blocking=args.relabel_blocking)
+                                 relabel_blocking=args.relabel_blocking, bfs_xcd=args.bfs_xcd)
         h = hyperflow.flow_problem_create(V, *arrays, options=opts, stream=stream)
         try:
             F = hyperflow.maxflow_solve(h, stream)
@@ -894,8 +897,8 @@ def bench_regions(args, hyperflow, inputs, torch, np):
     regions grown by two breadth-first searches, nets built with s and t,
     identical nets merged.  Timed from hypergraph, partition and pairs
     resident on the device to the built problems on the device; then the
-    whole refinement step (build, one handle per problem, union solve with
-    the source sides)."""
+    whole refinement step (build, then all pairs solved as one union network
+    built from the regions, with the minimal source sides)."""
     bp = _pairs(inputs, args.seed, args.batch_problems)
     hg = bp.hypergraph
     pairs = [p.meta["pair"] for p in bp.problems]
@@ -935,7 +938,8 @@ def bench_regions(args, hyperflow, inputs, torch, np):
     same = all(int(rg2.info(q)["num_pins"]) == bp.problems[q].num_pins for q in range(n))
     out["unmerged_equal_host_builder_sizes"] = bool(same)
     rg2.close()
-    # the refinement step from resident inputs: build, handles, union solve
+    # the refinement step from resident inputs: build, one union solve of
+    # all pairs straight from the regions (flow_regions_solve)
     _log("build + union solve")
     step = []
     flows = None
@@ -943,15 +947,11 @@ def bench_regions(args, hyperflow, inputs, torch, np):
         torch.cuda.synchronize()
         t = time.perf_counter()
         r3 = hyperflow.FlowRegions(hg.num_vertices, *dev, 64, pairs, caps)
-        probs = [r3.problem(q) for q in range(n)]
         try:
-            with hyperflow.FlowBatch(probs, with_cut=True) as plan:
-                flows = plan.run(with_cut=True)
+            flows = r3.solve()
             torch.cuda.synchronize()
             step.append(time.perf_counter() - t)
         finally:
-            for p in probs:
-                p.close()
             r3.close()
     ms_step = sorted(step)[1] * 1e3
     out["build_and_solve"] = dict(value=round(n / (ms_step / 1e3), 1), unit="refinements/s",

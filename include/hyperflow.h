@@ -119,6 +119,15 @@ typedef struct {
                                  "A Bug in the Synchronous Algorithm");
                                  0 = it relabels to at most its label + 2,
                                  which keeps every label valid (default)    */
+  int32_t bfs_xcd;            /* expanded reverse-BFS levels scan their arcs
+                                 and hand each head to the workgroups of the
+                                 XCD that owns its slice of the labels (1024-
+                                 node chunks dealt round-robin to the eight
+                                 XCDs), which label it in their own L2;
+                                 1 = on for networks of 1 M nodes or more
+                                 (about 8 (|pins| + |nets|) bytes of extra
+                                 device memory), 2 = on for every size,
+                                 -1 = off (default: measured slower)         */
 } fp_options;
 
 /* Counters of the last solve (cumulative over warm-started solves). */
@@ -686,6 +695,26 @@ fp_status flow_regions_export(const fp_regions *regions, int32_t pair, int32_t m
 fp_status flow_regions_problem(const fp_regions *regions, int32_t pair, const fp_options *opts,
                                void *hip_stream, fp_problem **out);
 
+/*
+ * flow_regions_solve: the minimum cuts of every pair not skipped, solved as
+ * disjoint-union networks built straight from the regions' device arrays
+ * (one network unless 31-bit ids or a network's INT32_MAX weight sum would
+ * be exceeded), like the union schedule of a batch plan but without a
+ * handle per pair.  flow_values (host, num_pairs): each kept pair's maximum
+ * flow, -1 where skip[q] != 0 (skip may be NULL).  The minimal source sides
+ * are kept with the regions (flow_regions_source_side, flow_partition_apply
+ * with vertex_sides = NULL) until the next solve.  Errors: FP_ERR_INVALID,
+ * FP_ERR_OOM, FP_ERR_DEVICE.
+ */
+fp_status flow_regions_solve(fp_regions *regions, const uint8_t *skip, void *hip_stream,
+                             int64_t *flow_values);
+
+/* Pair `pair`'s minimal source side from the last flow_regions_solve: n
+ * bytes, 1 = region vertex in X, memory kind mem_kind.  FP_ERR_STATE before
+ * any solve. */
+fp_status flow_regions_source_side(const fp_regions *regions, int32_t pair, int32_t mem_kind,
+                                   void *hip_stream, uint8_t *vertex_side);
+
 void flow_regions_destroy(fp_regions *regions);
 
 /*
@@ -714,7 +743,8 @@ fp_status flow_partition_create(int32_t num_vertices, int32_t num_nets,
  *                   from the partition the results refine
  *   vertex_sides    host array of num_pairs device pointers: pair q's
  *                   minimal source side X over its n region vertices (as
- *                   written by mincut_source_side or a batch plan)
+ *                   written by mincut_source_side or a batch plan); NULL =
+ *                   the sides of the regions' last flow_regions_solve
  *   expected_gains  host, num_pairs: cut_before - F of each pair
  *   lmax            the balance bound of every block
  *   status, gains, moved   host outputs per pair (any may be NULL):

@@ -275,6 +275,7 @@ fp_options resolve_options(const fp_options* o) {
   if (r.stale_rounds < 0) r.stale_rounds = 0;
   if (r.bfs_flat == 0) r.bfs_flat = 1;
   if (r.bfs_marks == 0) r.bfs_marks = -1;
+  if (r.bfs_xcd == 0) r.bfs_xcd = -1;
   return r;
 }
 
@@ -353,6 +354,13 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
   add(((P + 31) / 32) * 4ull); // residual bits of the pin arcs (global relabel)
   add(((E + 7) / 8) * 4ull);   // residual bits of the nets (global relabel)
   add(N);                      // reverse-BFS byte marks
+  // slices of the XCD-local expanded levels (large networks only)
+  const bool xcd = !ext && (pb->opt.bfs_xcd > 1 || (pb->opt.bfs_xcd == 1 && N >= (1ll << 20)));
+  const long long xseg = xcd ? std::max<long long>(256, (2ll * P + 2ll * E) / 4096 + 1) : 0;
+  if (xcd) {
+    add((size_t)kMaxSliceGroups * kSlices * xseg * 4ull);
+    add((size_t)kMaxSliceGroups * kSlices * 4ull);
+  }
   add(sizeof(Ctl));           // ctl
   add(64);                    // scratch for the weight sum
   unsigned bits = 1;          // key bits of the sort of the pins by vertex
@@ -426,6 +434,14 @@ fp_status build_problem(fp_problem* pb, const int32_t* net_offsets, const int32_
   g.netres = c.take<uint32_t>((E + 7) / 8);
   uint8_t* lev = c.take<uint8_t>(N);
   g.lev = pb->opt.bfs_marks > 0 ? lev : nullptr;
+  g.xbuf = nullptr;
+  g.xcnt = nullptr;
+  g.xseg = 0;
+  if (xcd) {
+    g.xbuf = c.take<int32_t>((size_t)kMaxSliceGroups * kSlices * xseg);
+    g.xcnt = c.take<int32_t>((size_t)kMaxSliceGroups * kSlices);
+    g.xseg = (int32_t)xseg;
+  }
   g.bfs_flat = pb->opt.bfs_flat > 0 ? 1 : 0;
   g.relabel_block = pb->opt.relabel_blocking > 0 ? 1 : 0;
   g.bfs_arc = pb->opt.bfs_arc_parallel;

@@ -137,6 +137,10 @@ struct Dev {
   uint32_t* seen;          // ceil(N/32) words: reverse BFS hint "node has a label" (see label_rev)
   uint8_t* lev;            // N bytes or null: reverse BFS marks, 0 unlabelled, 1 reached by
                            // the level being expanded, 2 labelled (see label_rev)
+  int32_t* xbuf;           // null, or the per-workgroup, per-slice arc heads of an expanded
+                           // reverse-BFS level (kMaxSliceGroups x 8 x xseg; see xpush)
+  int32_t* xcnt;           // kMaxSliceGroups x 8 counts of xbuf
+  int32_t xseg;            // entries per workgroup and slice
   uint32_t* pinres;        // ceil(P/32) words: bit of pin slot p = flow(u, e_in) > 0
   uint32_t* netres;        // ceil(E/8) words, 4 bits per net: bit0 = e_in -> e_out
                            // residual (fb < w), bit1 = pins carry flow out of
@@ -875,12 +879,56 @@ __device__ __forceinline__ bool label_rev(const Dev& g, int v, int lvl) {
   return true;
 }
 
+// Slices of the node range for the XCD-local expansion of reverse-BFS
+// levels: 1024-node chunks dealt round-robin to the eight XCDs (workgroup b
+// of a grid runs on XCD b mod 8), so each XCD's share of the label array
+// (a quarter of its 4 MB L2 for 5 M nodes) and of the labelled bitmap stays
+// in its own L2.
+constexpr int kSlices = 8;
+constexpr int kMaxSliceGroups = 512;
+__device__ __forceinline__ int xslice(int v) { return (v >> 10) & (kSlices - 1); }
+
+// An arc head of an expanded level: labelled at once (visit_rev = label_rev)
+// or, with kSlice, only pre-checked against the labelled bitmap and handed
+// to its slice (xpush); the slice kernel then labels it on the XCD that
+// owns it.
+template <bool kClaim, bool kChecked = false, bool kSlice = false>
+__device__ __forceinline__ bool visit_rev(const Dev& g, int v, int lvl) {
+  if (kSlice) return kChecked ? true : !seen_bit(g, v);
+  return label_rev<kClaim, kChecked>(g, v, lvl);
+}
+
+// Append arc head t (where pred) to this workgroup's segment of its slice:
+// wave-aggregated LDS counters xc[8]; an entry past the segment's end is
+// labelled here instead.  Called by the active lanes of a wave.
+__device__ __forceinline__ void xpush(const Dev& g, lds_int* xc, int t, bool pred, int lvl) {
+  if (__ballot(pred) == 0ull) return;
+  const int me = xslice(t);
+  int32_t* seg = g.xbuf + (long long)blockIdx.x * kSlices * g.xseg;
+#pragma unroll 1
+  for (int sl = 0; sl < kSlices; ++sl) {
+    const bool mine = pred && me == sl;
+    const unsigned long long m = __ballot(mine);
+    if (m == 0ull) continue;
+    const int leader = __builtin_ctzll(m);
+    int pos = 0;
+    if (lane_id() == leader) pos = lds_add(xc + sl, __popcll(m));
+    pos = __shfl(pos, leader);
+    if (mine) {
+      const int idx = pos + __popcll(m & lanemask_lt());
+      if (idx < g.xseg) seg[sl * g.xseg + idx] = t;
+      else label_rev<false, true>(g, t, lvl);
+    }
+  }
+}
+
 // Node-grouped reverse BFS: a group of `stride` lanes scans node x (G lanes
 // per small node, a wave per big node, the workgroup per huge node); gl is
 // the lane's index in the group.
-template <bool kClaim>
+template <bool kClaim, bool kSlice = false>
 __device__ __forceinline__ void bfs_rev_node(const Dev& g, const BlockQ& q, int x, bool has,
-                                             int gl, int stride, int lvl, uint32_t& nbytes) {
+                                             int gl, int stride, int lvl, uint32_t& nbytes,
+                                             lds_int* xc = nullptr) {
   const bool isv = has && x < g.V;
   const bool isnet = has && x >= g.NB;
   if (!has || isv) {
@@ -900,13 +948,17 @@ __device__ __forceinline__ void bfs_rev_node(const Dev& g, const BlockQ& q, int 
         // bits of e_in and e_out share a word (NB and 2e are even)
         const uint32_t sw = g.seen[t1 >> 5] >> (t1 & 31);
         nbytes += 12;
-        if (!(sw & 2u)) vout = label_rev<kClaim, true>(g, t1 + 1, lvl);  // e_out -> x infinite
+        if (!(sw & 2u)) vout = visit_rev<kClaim, true, kSlice>(g, t1 + 1, lvl);  // e_out -> x infinite
         if (!(sw & 1u) && pin_flow_in(g, ep.y))                    // e_in -> x reverse
-          vin = label_rev<kClaim, true>(g, t1, lvl);
+          vin = visit_rev<kClaim, true, kSlice>(g, t1, lvl);
       }
       if (kClaim) {
         qpush(g, q, t1, vin);
         qpush(g, q, t1 + 1, vout);
+      }
+      if (kSlice) {
+        xpush(g, xc, t1, vin, lvl);
+        xpush(g, xc, t1 + 1, vout, lvl);
       }
     }
   } else if (isnet) {
@@ -920,10 +972,11 @@ __device__ __forceinline__ void bfs_rev_node(const Dev& g, const BlockQ& q, int 
     if (gl == 0) nbytes += 16;
     bool vb = false;
     if (gl == 0) {
-      if (in) vb = (nb & 4u) && label_rev<kClaim>(g, x + 1, lvl);  // e_out -> e_in residual fb
-      else vb = (nb & 1u) && label_rev<kClaim>(g, x - 1, lvl);     // e_in -> e_out residual w - fb
+      if (in) vb = (nb & 4u) && visit_rev<kClaim, false, kSlice>(g, x + 1, lvl);  // e_out -> e_in residual fb
+      else vb = (nb & 1u) && visit_rev<kClaim, false, kSlice>(g, x - 1, lvl);     // e_in -> e_out residual w - fb
     }
     if (kClaim) qpush(g, q, in ? x + 1 : x - 1, vb);
+    if (kSlice) xpush(g, xc, in ? x + 1 : x - 1, vb, lvl);
     for (int base = beg; base < end; base += stride) {
       const int i = base + gl;
       const bool valid = i < end;
@@ -933,9 +986,10 @@ __device__ __forceinline__ void bfs_rev_node(const Dev& g, const BlockQ& q, int 
         u = g.pin_v[i];
         const int f = g.fpin[2 * i + (in ? 0 : 1)];  // r_in (u->e_in) or f_out (u->e_out)
         nbytes += 12;
-        if (f > 0) vu = label_rev<kClaim>(g, u, lvl);
+        if (f > 0) vu = visit_rev<kClaim, false, kSlice>(g, u, lvl);
       }
       if (kClaim) qpush(g, q, u, vu);
+      if (kSlice) xpush(g, xc, u, vu, lvl);
     }
   }
 }
@@ -1162,13 +1216,18 @@ __device__ void phase_bfs_rev_node(const Dev& g, int level, int tile0, int tstri
 // huge nodes the workgroup, as in the node-grouped levels.
 // ---------------------------------------------------------------------------
 
-template <bool kClaim>
+template <bool kClaim, bool kSlice = false>
 __device__ __forceinline__ void phase_bfs_rev_flat(const Dev& g, int level, int tile0, int tstride, int kc,
                                    lds_int* lds) {
   const int c3 = level % 3, n3 = (level + 1) % 3, z3 = (level + 2) % 3;
   if (tile0 == 0 && threadIdx.x < kNL) g.ctl->bcnt[z3][threadIdx.x] = 0;
   const int cp = level & 1, np = (level + 1) & 1;
   const BlockQ q = bq_bind(lds, g.ctl->bcnt[n3], g.list[np]);
+  lds_int* const xc = lds + bq_words();  // slice counts (in the arc-tile area, unused here)
+  if (kSlice) {
+    if (threadIdx.x < kSlices) xc[threadIdx.x] = 0;
+    __syncthreads();
+  }
   const Quad n = load_counts(g.ctl->bcnt[c3]);
   // wave items: 64 entries of list 0, of list 1, of list 2, then one big node each
   const int s1 = (n.v0 + kWave - 1) / kWave;
@@ -1236,16 +1295,16 @@ __device__ __forceinline__ void phase_bfs_rev_flat(const Dev& g, int level, int 
               // bits of e_in and e_out share a word (NB and 2e are even)
               const uint32_t sw = g.seen[t1 >> 5] >> (t1 & 31);
               nbytes += 12;
-              if (!(sw & 2u)) v2 = label_rev<kClaim, true>(g, t2, lvl);  // e_out -> x infinite
+              if (!(sw & 2u)) v2 = visit_rev<kClaim, true, kSlice>(g, t2, lvl);  // e_out -> x infinite
               if (!(sw & 1u) && pin_flow_in(g, ep.y))                    // e_in -> x reverse
-                v1 = label_rev<kClaim, true>(g, t1, lvl);
+                v1 = visit_rev<kClaim, true, kSlice>(g, t1, lvl);
             } else if (j == 0) {
               if (k == 1) {
                 t1 = xo + 1;  // e_out -> e_in residual fb
-                v1 = (nbo & 4u) && label_rev<kClaim>(g, t1, lvl);
+                v1 = (nbo & 4u) && visit_rev<kClaim, false, kSlice>(g, t1, lvl);
               } else {
                 t1 = xo - 1;  // e_in -> e_out residual w - fb
-                v1 = (nbo & 1u) && label_rev<kClaim>(g, t1, lvl);
+                v1 = (nbo & 1u) && visit_rev<kClaim, false, kSlice>(g, t1, lvl);
               }
             } else {
               const int i = bo + j - 1;
@@ -1253,31 +1312,54 @@ __device__ __forceinline__ void phase_bfs_rev_flat(const Dev& g, int level, int 
               // r_in (u -> e_in) or f_out (u -> e_out)
               const int f = g.fpin[2 * i + (k == 1 ? 0 : 1)];
               nbytes += 12;
-              if (f > 0) v1 = label_rev<kClaim>(g, t1, lvl);
+              if (f > 0) v1 = visit_rev<kClaim, false, kSlice>(g, t1, lvl);
             }
           }
           if (kClaim) {
             qpush(g, q, t1, v1);
             qpush(g, q, t2, v2);
           }
+          if (kSlice) {
+            xpush(g, xc, t1, v1, lvl);
+            xpush(g, xc, t2, v2, lvl);
+          }
         }
       } else if (it < total) {
         const int v = g.list[cp][kBigList][it - s3];
         const bool has = !is_huge(g, v);
         nitems += has && lane == 0;
-        bfs_rev_node<kClaim>(g, q, v, has, lane, kWave, lvl, nbytes);
+        bfs_rev_node<kClaim, kSlice>(g, q, v, has, lane, kWave, lvl, nbytes, xc);
       }
     } else {
       const int v = g.list[cp][kBigList][tile - ntiles];
       const bool has = is_huge(g, v);  // block-uniform
       nitems += has && threadIdx.x == 0;
-      bfs_rev_node<kClaim>(g, q, v, has, threadIdx.x, blockDim.x, lvl, nbytes);
+      bfs_rev_node<kClaim, kSlice>(g, q, v, has, threadIdx.x, blockDim.x, lvl, nbytes, xc);
     }
     if (kClaim) bq_tile_end(q, q.cap / 2);
   }
   if (kClaim) bq_flush(q);
+  if (kSlice) {
+    __syncthreads();
+    if (threadIdx.x < kSlices)
+      g.xcnt[blockIdx.x * kSlices + threadIdx.x] = min((int)xc[threadIdx.x], g.xseg);
+  }
   block_add_u64(&g.ctl->bytes[kc], (unsigned long long)nbytes + 4ull * nitems, &g.ctl->items[kc],
                 nitems);
+}
+
+// The labelling half of an XCD-local expanded level: workgroup b serves
+// slice b mod 8 (so it runs on the XCD that owns the slice) and labels the
+// heads that every workgroup of the scan handed to that slice.
+__device__ void phase_bfs_slices(const Dev& g, int level, int nseg) {
+  const int sl = blockIdx.x & (kSlices - 1);
+  const int w = blockIdx.x / kSlices, nw = gridDim.x / kSlices;
+  const int lvl = level + 1;
+  for (int b = w; b < nseg; b += nw) {
+    const int c = g.xcnt[b * kSlices + sl];
+    const int32_t* src = g.xbuf + ((long long)b * kSlices + sl) * g.xseg;
+    for (int i = threadIdx.x; i < c; i += blockDim.x) label_rev<false>(g, src[i], lvl);
+  }
 }
 
 // ---------------------------------------------------------------------------

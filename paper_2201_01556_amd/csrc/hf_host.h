@@ -115,6 +115,9 @@ struct fp_regions {
   std::vector<int32_t> pairs;            // 2 per pair
   std::vector<int64_t> info;             // npairs * 16
   std::vector<long long> net_base, pin_base, vtx_base, nloc;  // where pair q starts; n
+  std::vector<long long> wsum;           // net weight sum per pair (filled by the first solve)
+  uint8_t* sides = nullptr;              // per pair n+2 bytes: minimal source side of the last solve
+  bool solved = false;
 };
 
 namespace hf {

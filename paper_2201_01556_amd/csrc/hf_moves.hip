@@ -432,9 +432,9 @@ static fp_status partition_apply(fp_partition* pt, const fp_regions* rg,
 // "Parallel Flow-Based Refinement" with its section "Parallel Active Block
 // Scheduling"), synchronous rounds: the block pairs with a cut of at least
 // min_cut and an active block, heaviest cut first (then block ids), get
-// their regions built on the device, are solved at once by the union
-// schedule (minimum cuts; the expected gain is cut_before - F) and their
-// results applied in that order; the blocks of every pair applied with a
+// their regions built on the device, are solved at once as one disjoint-
+// union network built from the regions (minimum cuts; the expected gain is
+// cut_before - F) and their results applied in that order; the blocks of every pair applied with a
 // positive gain are active in the next round.  The rounds stop when none is
 // left, after max_rounds, or when a round improves the objective by less
 // than min_improvement_ppm parts per million.
@@ -504,46 +504,14 @@ static fp_status partition_refine(fp_partition* pt, const fp_refine_config& c, h
                             pairs.data(), caps.data(), c.merge_identical ? 1 : 0, 1, s, &rg);
     if (st != FP_OK) return st;
     std::unique_ptr<fp_regions, void (*)(fp_regions*)> rg_guard(rg, flow_regions_destroy);
-    std::vector<fp_problem*> pbs(np, nullptr);
-    auto free_pbs = [&]() {
-      for (fp_problem* p : pbs)
-        if (p) flow_problem_destroy(p);
-    };
-    long long side_bytes = 0;
-    std::vector<long long> side_at(np);
-    for (int q = 0; q < np; ++q) {
-      side_at[q] = side_bytes;
-      side_bytes += rg->nloc[q] + 2;
-    }
-    uint8_t* sides_d = nullptr;
-    {
-      const hipError_t e = hipMalloc(&sides_d, (size_t)side_bytes + 1);
-      if (e != hipSuccess) return mv_fail(e, "allocating the source sides");
-    }
-    std::unique_ptr<void, void (*)(void*)> sides_guard(sides_d,
-                                                       [](void* p) { (void)hipFree(p); });
-    std::vector<uint8_t*> vs(np);
-    for (int q = 0; q < np; ++q) vs[q] = sides_d + side_at[q];
-    for (int q = 0; q < np && st == FP_OK; ++q) st = flow_regions_problem(rg, q, nullptr, s, &pbs[q]);
     std::vector<int64_t> flows(np);
-    if (st == FP_OK) {
-      fp_batch* bt = nullptr;
-      st = flow_batch_create(pbs.data(), np, vs.data(), nullptr, nullptr, s, &bt);
-      if (st == FP_OK) {
-        st = flow_batch_run(bt, nullptr, 1, s, flows.data());
-        flow_batch_destroy(bt);
-      }
-    }
-    if (st != FP_OK) {
-      free_pbs();
-      return st;
-    }
+    st = flow_regions_solve(rg, nullptr, s, flows.data());
+    if (st != FP_OK) return st;
     std::vector<int64_t> gains(np), exact(np);
     std::vector<int32_t> status(np), moved(np);
     for (int q = 0; q < np; ++q) gains[q] = rg->info[(size_t)q * 16 + 4] - flows[q];
-    st = flow_partition_apply(pt, rg, vs.data(), gains.data(), lmax, s, status.data(),
+    st = flow_partition_apply(pt, rg, nullptr, gains.data(), lmax, s, status.data(),
                               exact.data(), moved.data());
-    free_pbs();
     if (st != FP_OK) return st;
     std::vector<char> next(k, 0);
     for (int q = 0; q < np; ++q) {
@@ -617,9 +585,20 @@ fp_status flow_partition_apply(fp_partition* partition, const fp_regions* region
                                int64_t lmax, void* hip_stream, int32_t* status, int64_t* gains,
                                int32_t* moved) {
   set_error("");
-  if (!partition || !regions || (regions->npairs > 0 && (!vertex_sides || !expected_gains))) {
+  if (!partition || !regions || (regions->npairs > 0 && !expected_gains)) {
     set_error("NULL argument");
     return FP_ERR_INVALID;
+  }
+  std::vector<const uint8_t*> own;
+  if (!vertex_sides) {
+    if (!regions->solved) {
+      set_error("vertex_sides is NULL and the regions have not been solved");
+      return FP_ERR_STATE;
+    }
+    own.resize(regions->npairs);
+    for (int q = 0; q < regions->npairs; ++q)
+      own[q] = regions->sides + regions->vtx_base[q] + 2ll * q;
+    vertex_sides = own.data();
   }
   if (regions->V != partition->V || regions->k != partition->k) {
     set_error("the regions were built for another hypergraph or k (V %d / %d, k %d / %d)",

@@ -30,6 +30,7 @@
 #include <cstring>
 #include <algorithm>
 #include <memory>
+#include <new>
 #include <vector>
 
 #include <rocprim/device/device_radix_sort.hpp>
@@ -644,6 +645,80 @@ __global__ void k_rg_last_offsets(int npairs, const long long* nbase, const long
 }  // namespace hf
 
 // ---------------------------------------------------------------------------
+// the kept pairs' problems as one disjoint-union network, straight from the
+// regions' arrays: kept pair i (pair ids[i]) owns union vertices
+// [voff[i], voff[i+1]) (its n region vertices, then s and t), nets
+// [eoff[i], eoff[i+1]) and pins [poff[i], poff[i+1])
+// ---------------------------------------------------------------------------
+
+namespace hf {
+
+struct RgUnion {
+  int32_t n;
+  const int32_t* ids;
+  const int32_t* voff;
+  const int32_t* eoff;
+  const int32_t* poff;
+  const long long* nbase;  // per pair (all pairs): first net / pin / vertex in the regions
+  const long long* pbase;
+  const long long* vbase;
+};
+
+__device__ __forceinline__ int rg_part(const int32_t* off, int n, int x) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_ru_nets(RgUnion m, const int32_t* off, const int32_t* w, int32_t E,
+                          int32_t* off_u, int32_t* w_u) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t <= E; t += gridDim.x * blockDim.x) {
+    if (t == E) {
+      off_u[E] = m.poff[m.n];
+      continue;
+    }
+    const int i = rg_part(m.eoff, m.n, t);
+    const int q = m.ids[i];
+    const int r = t - m.eoff[i];
+    off_u[t] = m.poff[i] + off[m.nbase[q] + q + r];
+    w_u[t] = w[m.nbase[q] + r];
+  }
+}
+
+__global__ void k_ru_pins(RgUnion m, const int32_t* pins, int32_t P, int32_t* pins_u) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+    const int i = rg_part(m.poff, m.n, p);
+    const int q = m.ids[i];
+    pins_u[p] = pins[m.pbase[q] + (p - m.poff[i])] + m.voff[i];
+  }
+}
+
+// flows of the kept pairs (weight of their nets cut by the union's minimal
+// source side) and their vertex sides scattered into the regions' buffer
+__global__ void __launch_bounds__(256) k_ru_flows(RgUnion m, const int32_t* w_u,
+                                                  const uint8_t* ns_u, unsigned long long* flows) {
+  const int i = blockIdx.x;
+  unsigned long long sum = 0ull;
+  for (int e = m.eoff[i] + threadIdx.x; e < m.eoff[i + 1]; e += blockDim.x)
+    if ((ns_u[e] & 3u) == 1u) sum += (unsigned long long)w_u[e];
+  block_add_u64(&flows[i], sum);
+}
+
+__global__ void k_ru_sides(RgUnion m, int32_t V, const uint8_t* vs_u, uint8_t* sides) {
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < V; v += gridDim.x * blockDim.x) {
+    const int i = rg_part(m.voff, m.n, v);
+    const int q = m.ids[i];
+    sides[m.vbase[q] + 2ll * q + (v - m.voff[i])] = vs_u[v];
+  }
+}
+
+}  // namespace hf
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 
@@ -1116,9 +1191,142 @@ fp_status regions_build(int32_t V, int32_t E, const int32_t* off_in, const int32
   return FP_OK;
 }
 
+// Solve the kept pairs as disjoint-union networks (split where 31-bit ids
+// or the INT32_MAX bound of a network's weight sum would be exceeded); flows
+// of skipped pairs are -1.  The minimal source sides are kept in r->sides.
+fp_status regions_solve(fp_regions* r, const uint8_t* skip, hipStream_t s, int64_t* flows) {
+  const int npairs = r->npairs;
+  if (npairs == 0) return FP_OK;
+  if (!r->sides) {
+    long long nb = 0;
+    for (int q = 0; q < npairs; ++q) nb += r->nloc[q] + 2;
+    RG_TRY(hipMalloc(&r->sides, (size_t)nb + 1), "allocating the source sides");
+  }
+  if (r->wsum.empty()) {
+    // net weight sum of every pair
+    r->wsum.assign(npairs, 0);
+    std::vector<int32_t> w((size_t)std::max<long long>(r->net_base.back() + r->info[(size_t)(npairs - 1) * kInfoLen + 2], 1));
+    const long long ne_tot = r->net_base.back() + r->info[(size_t)(npairs - 1) * kInfoLen + 2];
+    if (ne_tot)
+      RG_TRY(hipMemcpyAsync(w.data(), r->w, ne_tot * 4ull, hipMemcpyDeviceToHost, s), "reading");
+    RG_TRY(hipStreamSynchronize(s), "reading the net weights");
+    for (int q = 0; q < npairs; ++q) {
+      long long acc = 0;
+      const long long b = r->net_base[q], ne = r->info[(size_t)q * kInfoLen + 2];
+      for (long long e = 0; e < ne; ++e) acc += w[b + e];
+      r->wsum[q] = acc;
+    }
+  }
+  Scratch sc;
+  long long *nbase_d, *pbase_d, *vbase_d;
+  RG_TRY(sc.get((size_t)npairs, &nbase_d), "allocating");
+  RG_TRY(sc.get((size_t)npairs, &pbase_d), "allocating");
+  RG_TRY(sc.get((size_t)npairs, &vbase_d), "allocating");
+  RG_TRY(hipMemcpyAsync(nbase_d, r->net_base.data(), npairs * 8ull, hipMemcpyHostToDevice, s),
+         "copy");
+  RG_TRY(hipMemcpyAsync(pbase_d, r->pin_base.data(), npairs * 8ull, hipMemcpyHostToDevice, s),
+         "copy");
+  RG_TRY(hipMemcpyAsync(vbase_d, r->vtx_base.data(), npairs * 8ull, hipMemcpyHostToDevice, s),
+         "copy");
+  for (int q = 0; q < npairs; ++q) flows[q] = -1;
+  const long long kLimit = (1ll << 30);
+  int q = 0;
+  while (q < npairs) {
+    // next chunk of kept pairs
+    std::vector<int32_t> ids, voff(1, 0), eoff(1, 0), poff(1, 0), src, snk;
+    long long V = 0, E = 0, P = 0, W = 0;
+    for (; q < npairs; ++q) {
+      if (skip && skip[q]) continue;
+      const int64_t* in = &r->info[(size_t)q * kInfoLen];
+      const long long nv = in[1], ne = in[2], np = in[3];
+      if (!ids.empty() && (V + nv + 2 * (E + ne) >= kLimit || P + np >= kLimit ||
+                           W + r->wsum[q] > 0x7fffffffll))
+        break;
+      ids.push_back(q);
+      src.push_back((int32_t)(V + in[0]));
+      snk.push_back((int32_t)(V + in[0] + 1));
+      V += nv;
+      E += ne;
+      P += np;
+      W += r->wsum[q];
+      voff.push_back((int32_t)V);
+      eoff.push_back((int32_t)E);
+      poff.push_back((int32_t)P);
+    }
+    if (ids.empty()) break;
+    const int n = (int)ids.size();
+    int32_t *ids_d, *voff_d, *eoff_d, *poff_d, *off_u, *w_u, *pins_u, *src_d, *snk_d;
+    uint8_t *vs_u, *ns_u;
+    unsigned long long* fl_d;
+    RG_TRY(sc.get((size_t)n, &ids_d), "allocating");
+    RG_TRY(sc.get(n + 1ull, &voff_d), "allocating");
+    RG_TRY(sc.get(n + 1ull, &eoff_d), "allocating");
+    RG_TRY(sc.get(n + 1ull, &poff_d), "allocating");
+    RG_TRY(sc.get(E + 1ull, &off_u), "allocating the union");
+    RG_TRY(sc.get(E + 1ull, &w_u), "allocating the union");
+    RG_TRY(sc.get(P + 1ull, &pins_u), "allocating the union");
+    RG_TRY(sc.get((size_t)n, &src_d), "allocating");
+    RG_TRY(sc.get((size_t)n, &snk_d), "allocating");
+    RG_TRY(sc.get(V + 1ull, &vs_u), "allocating");
+    RG_TRY(sc.get(E + 1ull, &ns_u), "allocating");
+    RG_TRY(sc.get((size_t)n, &fl_d), "allocating");
+    RG_TRY(hipMemcpyAsync(ids_d, ids.data(), n * 4ull, hipMemcpyHostToDevice, s), "copy");
+    RG_TRY(hipMemcpyAsync(voff_d, voff.data(), (n + 1) * 4ull, hipMemcpyHostToDevice, s), "copy");
+    RG_TRY(hipMemcpyAsync(eoff_d, eoff.data(), (n + 1) * 4ull, hipMemcpyHostToDevice, s), "copy");
+    RG_TRY(hipMemcpyAsync(poff_d, poff.data(), (n + 1) * 4ull, hipMemcpyHostToDevice, s), "copy");
+    RG_TRY(hipMemcpyAsync(src_d, src.data(), n * 4ull, hipMemcpyHostToDevice, s), "copy");
+    RG_TRY(hipMemcpyAsync(snk_d, snk.data(), n * 4ull, hipMemcpyHostToDevice, s), "copy");
+    k_rg_zero<<<rg_grid(2ll * n), 256, 0, s>>>(reinterpret_cast<uint32_t*>(fl_d), 2ll * n);
+    RgUnion m{n, ids_d, voff_d, eoff_d, poff_d, nbase_d, pbase_d, vbase_d};
+    k_ru_nets<<<rg_grid(E + 1), 256, 0, s>>>(m, r->off, r->w, (int32_t)E, off_u, w_u);
+    if (P) k_ru_pins<<<rg_grid(P), 256, 0, s>>>(m, r->pins, (int32_t)P, pins_u);
+    fp_problem* u = new (std::nothrow) fp_problem();
+    if (!u) {
+      set_error("host allocation failed");
+      return FP_ERR_OOM;
+    }
+    u->device = r->device;
+    u->V = (int32_t)V;
+    u->E = (int32_t)E;
+    fp_options o{};
+    o.group_lanes = 8;
+    o.gr_interval = 8;
+    u->opt = resolve_options(&o);
+    fp_status st = build_problem(u, off_u, pins_u, w_u, src_d, n, snk_d, n, 1, s);
+    int64_t F = 0;
+    if (st == FP_OK) st = solve_problem(u, s, &F);
+    if (st == FP_OK) st = cut_problem(u, s, 1, vs_u, ns_u);
+    std::vector<unsigned long long> fh(n, 0ull);
+    if (st == FP_OK) {
+      k_ru_flows<<<n, 256, 0, s>>>(m, u->dev.w, ns_u, fl_d);
+      k_ru_sides<<<rg_grid(V), 256, 0, s>>>(m, (int32_t)V, vs_u, r->sides);
+      hipError_t he = hipMemcpyAsync(fh.data(), fl_d, n * 8ull, hipMemcpyDeviceToHost, s);
+      if (he == hipSuccess) he = hipStreamSynchronize(s);
+      if (he != hipSuccess) st = hip_fail(he, "splitting the union's flow");
+    }
+    if (st != FP_OK) (void)hipStreamSynchronize(s);
+    release_problem(u);
+    delete u;
+    if (st != FP_OK) return st;
+    unsigned long long tot = 0ull;
+    for (int i = 0; i < n; ++i) {
+      flows[ids[i]] = (int64_t)fh[i];
+      tot += fh[i];
+    }
+    if ((int64_t)tot != F) {
+      set_error("internal check: the pairs' cut weights sum to %llu, the union's flow is %lld",
+                tot, (long long)F);
+      return FP_ERR_DEVICE;
+    }
+    r->solved = true;
+  }
+  return FP_OK;
+}
+
 void release_regions(fp_regions* r) {
   if (!r) return;
   if (r->mem) (void)hipFree(r->mem);
+  if (r->sides) (void)hipFree(r->sides);
   delete r;
 }
 
@@ -1259,6 +1467,45 @@ fp_status flow_regions_problem(const fp_regions* regions, int32_t pair, const fp
   return flow_problem_create((int32_t)in[1], (int32_t)in[2], regions->off + nb + pair,
                              regions->pins + pb, regions->w + nb, regions->terms + 2 * pair, 1,
                              regions->terms + 2 * pair + 1, 1, 1, opts, hip_stream, out);
+}
+
+fp_status flow_regions_solve(fp_regions* regions, const uint8_t* skip, void* hip_stream,
+                             int64_t* flow_values) {
+  set_error("");
+  if (!regions || (regions->npairs > 0 && !flow_values)) {
+    set_error("NULL argument");
+    return FP_ERR_INVALID;
+  }
+  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const fp_status st = regions_solve(regions, skip, s, flow_values);
+  if (st != FP_OK) (void)hipStreamSynchronize(s);
+  return st;
+}
+
+fp_status flow_regions_source_side(const fp_regions* regions, int32_t pair, int32_t mem_kind,
+                                   void* hip_stream, uint8_t* vertex_side) {
+  set_error("");
+  if (!regions || !vertex_side) {
+    set_error("NULL argument");
+    return FP_ERR_INVALID;
+  }
+  if (pair < 0 || pair >= regions->npairs) {
+    set_error("pair %d out of range [0, %d)", pair, regions->npairs);
+    return FP_ERR_INVALID;
+  }
+  if (!regions->solved) {
+    set_error("the regions have not been solved");
+    return FP_ERR_STATE;
+  }
+  const long long n = regions->nloc[pair];
+  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipSuccess;
+  if (n) e = hipMemcpyAsync(vertex_side, regions->sides + regions->vtx_base[pair] + 2ll * pair,
+                            (size_t)n, mem_kind ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                            s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "copying a source side");
+  return FP_OK;
 }
 
 void flow_regions_destroy(fp_regions* regions) { release_regions(regions); }

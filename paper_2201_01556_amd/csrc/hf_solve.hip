@@ -17,6 +17,7 @@ namespace hf {
 constexpr int kThreads = 256;  // plain element-wise kernels
 constexpr int kBlock = 1024;   // frontier, sweep and single-workgroup kernels
 constexpr int kMaxFrontierBlocks = 512;
+static_assert(kMaxFrontierBlocks <= kMaxSliceGroups, "one slice segment per scan workgroup");
 constexpr int kMaxSweepBlocks = 512;
 constexpr long long kRoundGuard = 200000000ll;  // rounds per solve before giving up
 
@@ -90,6 +91,35 @@ k_bfs_rev_flat(Dev g, int level, int big_min, int pull_min, int tail) {
   else if (nf >= big_min)
     phase_bfs_rev_flat<false>(g, level, blockIdx.x, gridDim.x, KC_BFS_REV, lds);
   else phase_bfs_rev_node<G, true>(g, level, blockIdx.x, gridDim.x, KC_BFS_REV, lds);
+}
+
+// As k_bfs_rev_flat, with expanded levels split in two (XCD-local labels):
+// this kernel scans the level's arcs and hands each head that is not
+// labelled yet to its slice; k_bfs_slices then labels the heads of each
+// slice on the XCD that owns it.
+template <int G>
+__global__ void __launch_bounds__(kBlock) HF_TWO_WORKGROUPS_PER_CU
+k_bfs_rev_xflat(Dev g, int level, int big_min, int pull_min, int tail) {
+  HF_QUEUE_LDS;
+  const int c3 = level % 3;
+  const int nf = count_all(g.ctl->bcnt[c3]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (nf > tail) atomicMax(&g.ctl->big_last, level);
+    if (level < kLvlHist) g.ctl->lvl_nf[level] = nf;
+  }
+  if (nf >= pull_min)
+    phase_bfs_rev_pull(g, level, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x,
+                       KC_BFS_REV);
+  else if (nf >= big_min)
+    phase_bfs_rev_flat<false, true>(g, level, blockIdx.x, gridDim.x, KC_BFS_REV, lds);
+  else phase_bfs_rev_node<G, true>(g, level, blockIdx.x, gridDim.x, KC_BFS_REV, lds);
+}
+
+// nseg: the grid of the k_bfs_rev_xflat launch of this level.
+__global__ void __launch_bounds__(kBlock) k_bfs_slices(Dev g, int level, int big_min,
+                                                       int pull_min, int nseg) {
+  const int nf = count_all(g.ctl->bcnt[level % 3]);
+  if (nf >= big_min && nf < pull_min) phase_bfs_slices(g, level, nseg);
 }
 
 // Expanded and pulled levels list their new nodes by a sweep over the labels.
@@ -410,10 +440,16 @@ static void launch_levels(fp_problem* pb, hipStream_t s, int ep, int ep_tmp, int
         if (2 * p < big_min) bmin = off;
         if (2 * p < pull_min) pmin = off;
       }
+      const bool xcd = g.xbuf && g.bfs_flat && !g.bfs_arc;
       {
         Launch L(pb, s, KK_BFS_REV);
-        if (g.bfs_flat && !g.bfs_arc) k_bfs_rev_flat<G><<<grid, kBlock, 0, s>>>(g, lv, bmin, pmin, cap);
+        if (xcd) k_bfs_rev_xflat<G><<<grid, kBlock, 0, s>>>(g, lv, bmin, pmin, cap);
+        else if (g.bfs_flat && !g.bfs_arc) k_bfs_rev_flat<G><<<grid, kBlock, 0, s>>>(g, lv, bmin, pmin, cap);
         else k_bfs_rev<G><<<grid, kBlock, 0, s>>>(g, lv, bmin, pmin, cap);
+      }
+      if (xcd && bmin != off) {
+        Launch L(pb, s, KK_BFS_REV);
+        k_bfs_slices<<<kSlices * 64, kBlock, 0, s>>>(g, lv, bmin, pmin, grid);
       }
       if (bmin != off || pmin != off) {
         Launch L(pb, s, KK_BFS_COLLECT);

@@ -62,6 +62,7 @@ class Options(ctypes.Structure):
         ("bfs_flat", ctypes.c_int32),
         ("bfs_marks", ctypes.c_int32),
         ("relabel_blocking", ctypes.c_int32),
+        ("bfs_xcd", ctypes.c_int32),
     ]
 
 
@@ -152,6 +153,8 @@ EXPORTED = [
     "flow_regions_info",
     "flow_regions_export",
     "flow_regions_problem",
+    "flow_regions_solve",
+    "flow_regions_source_side",
     "flow_regions_destroy",
     "flow_partition_create",
     "flow_partition_apply",
@@ -241,6 +244,10 @@ def load_library(path: str = LIB_PATH):
     lib.flow_regions_export.restype = ctypes.c_int
     lib.flow_regions_problem.argtypes = [vp, i32, ctypes.POINTER(Options), vp, ctypes.POINTER(vp)]
     lib.flow_regions_problem.restype = ctypes.c_int
+    lib.flow_regions_solve.argtypes = [vp, vp, vp, vp]
+    lib.flow_regions_solve.restype = ctypes.c_int
+    lib.flow_regions_source_side.argtypes = [vp, i32, i32, vp, vp]
+    lib.flow_regions_source_side.restype = ctypes.c_int
     lib.flow_regions_destroy.argtypes = [vp]
     lib.flow_regions_destroy.restype = None
     lib.flow_partition_create.argtypes = [i32, i32, vp, vp, vp, vp, vp, i32, i32, vp,
@@ -699,6 +706,29 @@ class FlowRegions:
     def export(self, pair) -> dict:
         return flow_regions_export(self.handle, pair, self.stream)
 
+    def solve(self, skip=None):
+        """Minimum cuts of the pairs not skipped, as union networks built from
+        the regions (flow_regions_solve); flows of skipped pairs are -1."""
+        lib = load_library()
+        flows = np.zeros(max(self.count, 1), np.int64)
+        sk = None
+        if skip is not None:
+            sk = np.ascontiguousarray(skip, dtype=np.uint8)
+            if sk.shape[0] != self.count:
+                raise ValueError("one skip flag per pair")
+        _check(lib.flow_regions_solve(self.handle, sk.ctypes.data if sk is not None else None,
+                                      _stream_ptr(self.stream), flows.ctypes.data))
+        return flows[:self.count]
+
+    def source_side(self, pair):
+        """Pair ``pair``'s minimal source side of the last solve (host)."""
+        lib = load_library()
+        n = self.info(pair)["n"]
+        out = np.zeros(max(n, 1), np.uint8)
+        _check(lib.flow_regions_source_side(self.handle, int(pair), 0, _stream_ptr(self.stream),
+                                            out.ctypes.data))
+        return out[:n]
+
     def problem(self, pair, options: Options | None = None, **opts) -> "FlowProblem":
         if options is None and opts:
             options = Options(**opts)
@@ -765,12 +795,15 @@ class FlowPartition:
 
     def apply(self, regions: "FlowRegions", vertex_sides, expected_gains, lmax):
         """Apply pair q's source side ``vertex_sides[q]`` (device uint8
-        tensors) in pair order; returns (status, gains, moved) arrays."""
+        tensors; None = the sides of the regions' last solve) in pair order;
+        returns (status, gains, moved) arrays."""
         lib = load_library()
         n = regions.count
-        ptrs = (ctypes.c_void_p * max(n, 1))()
-        for q in range(n):
-            ptrs[q] = _ptr(vertex_sides[q], np.uint8)[0]
+        ptrs = None
+        if vertex_sides is not None:
+            ptrs = (ctypes.c_void_p * max(n, 1))()
+            for q in range(n):
+                ptrs[q] = _ptr(vertex_sides[q], np.uint8)[0]
         g = np.ascontiguousarray(expected_gains, dtype=np.int64)
         if g.shape[0] != n:
             raise ValueError("one expected gain per pair")

@@ -61,7 +61,7 @@ def test_missing_library_fails_loudly(tmp_path):
 
 def test_options_struct_matches_header():
     from paper_2201_01556_amd import hyperflow
-    assert ctypes.sizeof(hyperflow.Options) == 16 * 4
+    assert ctypes.sizeof(hyperflow.Options) == 17 * 4
     assert ctypes.sizeof(hyperflow.Stats) == 16 * 8
 
 
@@ -72,7 +72,9 @@ def test_binding_struct_layouts_match_the_header(tmp_path):
     structs = {"fp_options": hyperflow.Options, "fp_stats": hyperflow.Stats,
                "fp_batch_config": hyperflow.BatchConfig,
                "fp_cutter_result": hyperflow.CutterResult,
-               "fp_cutter_step": hyperflow.CutterStep}
+               "fp_cutter_step": hyperflow.CutterStep,
+               "fp_refine_config": hyperflow.RefineConfig,
+               "fp_refine_result": hyperflow.RefineResult}
     lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "hyperflow.h"',
              "int main(void) {"]
     for cname, cls in structs.items():

@@ -120,6 +120,8 @@ def test_debug_invariants_every_round(hf, oracle_mod):
     dict(bfs_marks=-1, bottom_up_min=1, tail_threshold=1), dict(bfs_flat=1, big_degree=2),
     dict(relabel_blocking=1), dict(relabel_blocking=1, tail_threshold=1),
     dict(relabel_blocking=1, gr_interval=-1, stale_rounds=-1),
+    dict(bfs_xcd=2), dict(bfs_xcd=2, bottom_up_min=1, tail_threshold=1),
+    dict(bfs_xcd=2, bottom_up_min=1, big_degree=2), dict(bfs_xcd=-1),
 ], ids=str)
 def test_schedule_invariance(hf, oracle_mod, opts):
     """Every tuning knob changes only the schedule, never the result."""
@@ -136,7 +138,10 @@ def test_schedule_invariance(hf, oracle_mod, opts):
                                   dict(bottom_up_min=1, tail_threshold=1, bfs_marks=-1),
                                   dict(bottom_up_min=-1, tail_threshold=1),
                                   dict(bfs_flat=-1, bfs_marks=-1, tail_threshold=1),
-                                  dict(relabel_blocking=1)], ids=str)
+                                  dict(relabel_blocking=1),
+                                  dict(bfs_xcd=2, bottom_up_min=1, tail_threshold=1),
+                                  dict(bfs_xcd=2, bottom_up_min=1, tail_threshold=1,
+                                       bfs_marks=1)], ids=str)
 def test_labels_and_preflow_certificate(hf, oracle_mod, opts):
     """After the solve the labels are exact residual distances of the final
     state (the terminating global relabel), the state is a feasible preflow

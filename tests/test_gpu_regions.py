@@ -264,3 +264,47 @@ def test_regions_full_block_pairs(hf, oreg):
         _say(f"full block pairs: {nets_removed} identical nets merged; oracle on one pair")
         vnets = oreg.vertex_nets(hg)
         _compare(oreg, hg, bp.block, rg, pairs, caps, True, vnets=vnets, sample=[len(pairs) - 1])
+
+
+def test_regions_solve_union(hf, oracle_mod):
+    """flow_regions_solve (union networks built from the regions, no handle
+    per pair): flows and minimal source sides equal the oracle's on the
+    exported problems and the per-handle batch's; skipped pairs report -1
+    and keep nothing; a solve before another keeps the latest sides."""
+    import torch
+    hg, block = _instance(8, 20_000, 6, 90_000, 100)
+    pairs, cuts = _heaviest_pairs(hg, block, 6, 10)
+    bw = np.bincount(block, weights=hg.vertex_weights, minlength=6).astype(np.int64)
+    caps = inputs.region_caps(bw, pairs, cuts)
+    with hf.FlowRegions(hg.num_vertices, hg.net_offsets, hg.pins, hg.net_weights,
+                        hg.vertex_weights, block, 6, pairs, caps) as rg:
+        with pytest.raises(hf.HyperflowError) as ei:
+            rg.source_side(0)
+        assert ei.value.name == "FP_ERR_STATE"
+        skip = np.zeros(len(pairs), np.uint8)
+        skip[::3] = 1
+        f_skip = rg.solve(skip)
+        assert all(f_skip[q] == -1 for q in range(len(pairs)) if skip[q])
+        flows = rg.solve()
+        probs = [rg.problem(q) for q in range(len(pairs))]
+        try:
+            with hf.FlowBatch(probs, with_cut=True) as plan:
+                fb = plan.run(with_cut=True)
+                torch.cuda.synchronize()
+                for q in range(len(pairs)):
+                    n = rg.info(q)["n"]
+                    assert (rg.source_side(q) == plan.vertex_sides[q].cpu().numpy()[:n]).all()
+        finally:
+            for p in probs:
+                p.close()
+        assert list(flows) == list(fb)
+        assert all(f_skip[q] == flows[q] for q in range(len(pairs)) if not skip[q])
+        for q in range(len(pairs)):
+            g = rg.export(q)
+            n = g["info"]["n"]
+            h = inputs.Hypergraph(n + 2, g["net_offsets"], g["pins"], g["net_weights"],
+                                  g["vertex_weights"], np.array([n], np.int32),
+                                  np.array([n + 1], np.int32), {})
+            ref = oracle_mod.maxflow(h)
+            assert flows[q] == ref.flow, q
+            assert (rg.source_side(q).astype(bool) == ref.vertex_side[:n].astype(bool)).all(), q
