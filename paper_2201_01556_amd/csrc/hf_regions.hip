@@ -420,34 +420,6 @@ __device__ __forceinline__ int rg_classify(const RgGraph& g, const RgSide& r, co
   return side == 0 ? 2 : 3;
 }
 
-__global__ void k_rg_count(RgGraph g, RgSide r, const int32_t* lmap, RgNets t) {
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < t.nt; k += gridDim.x * blockDim.x) {
-    const int q = t.tpair[k], e = t.tnet[k];
-    int nreg = 0;
-    bool has_s = false, has_t = false, in_i = false, in_j = false;
-    for (int p = g.off[e]; p < g.off[e + 1]; ++p) {
-      int lid = 0;
-      bool si = false;
-      const int c = rg_classify(g, r, lmap, q, g.pins[p], &lid, &si);
-      if (c == 1) {
-        ++nreg;
-        if (si) in_i = true;
-        else in_j = true;
-      } else if (c == 2) {
-        has_s = true;
-      } else if (c == 3) {
-        has_t = true;
-      }
-    }
-    const int size = nreg + (int)has_s + (int)has_t;
-    const bool keep = size >= 2 && !(has_s && has_t);
-    t.keep[k] = keep ? 1 : 0;
-    t.osz[k] = keep ? size : 0;
-    if (keep && (in_i || has_s) && (in_j || has_t))
-      atomicAdd(&t.cutb[q], (unsigned long long)g.w[e]);
-  }
-}
-
 struct RgKept {
   const int32_t* kidx;        // exclusive scan of keep
   const long long* opos;      // exclusive scan of osz
@@ -458,42 +430,169 @@ struct RgKept {
   int32_t* kgid;
   long long* kw;              // weights (summed over merged groups)
   int* unsorted;
-  unsigned long long* kcount; // kept nets per pair
 };
 
-__global__ void k_rg_write(RgGraph g, RgSide r, const int32_t* lmap, RgNets t, RgKept o) {
-  int bad = 0;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < t.nt; k += gridDim.x * blockDim.x) {
-    if (!t.keep[k]) continue;
-    const int q = t.tpair[k], e = t.tnet[k];
-    const int K = o.kidx[k];
-    long long pos = o.opos[k];
-    o.koff[K] = pos;
-    o.kpair[K] = q;
-    o.kgid[K] = e;
-    o.kw[K] = g.w[e];
-    atomicAdd(&o.kcount[q], 1ull);
-    bool has_s = false, has_t = false;
-    int prev = -1;
-    for (int p = g.off[e]; p < g.off[e + 1]; ++p) {
-      int lid = 0;
-      bool si = false;
-      const int c = rg_classify(g, r, lmap, q, g.pins[p], &lid, &si);
-      if (c == 1) {
-        if (lid < prev) bad = 1;
-        prev = lid;
-        o.kpins[pos++] = lid;
-      } else if (c == 2) {
-        has_s = true;
-      } else if (c == 3) {
-        has_t = true;
+// Flat versions of the two passes: a wave takes 64 touched nets and spreads
+// their pins evenly over its lanes (prefix sum of the sizes, each lane finds
+// its pin's net by binary search), so a 2,000-pin net does not hold 63 idle
+// lanes; per-net tallies live in LDS slots of the wave (64 per wave).
+constexpr int kFlatBlock = 256;
+
+struct RgWaveItem {
+  int k, e, q, deg, excl, A;
+};
+
+__device__ __forceinline__ RgWaveItem rg_wave_item(const RgGraph& g, const RgNets& t, int base) {
+  RgWaveItem it;
+  const int lane = __lane_id();
+  it.k = base + lane;
+  it.e = it.k < t.nt ? t.tnet[it.k] : 0;
+  it.q = it.k < t.nt ? t.tpair[it.k] : 0;
+  it.deg = it.k < t.nt ? g.off[it.e + 1] - g.off[it.e] : 0;
+  int incl = it.deg;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(incl, o);
+    if (lane >= o) incl += v;
+  }
+  it.excl = incl - it.deg;
+  it.A = __shfl(incl, 63);
+  return it;
+}
+
+__device__ __forceinline__ int rg_owner(int excl, int a) {
+  int lo = 0;
+#pragma unroll
+  for (int st = 32; st > 0; st >>= 1) {
+    const int c = lo + st;
+    if (__shfl(excl, c) <= a) lo = c;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(kFlatBlock) k_rg_count_flat(RgGraph g, RgSide r,
+                                                              const int32_t* lmap, RgNets t) {
+  __shared__ int cnt_s[kFlatBlock], flg_s[kFlatBlock];
+  const int lane = __lane_id(), wid = threadIdx.x >> 6;
+  int* cnt = cnt_s + wid * 64;
+  int* flg = flg_s + wid * 64;
+  const int nwaves = gridDim.x * (blockDim.x >> 6);
+  for (int base = (blockIdx.x * (blockDim.x >> 6) + wid) * 64; base < t.nt; base += nwaves * 64) {
+    const RgWaveItem it = rg_wave_item(g, t, base);
+    cnt[lane] = 0;
+    flg[lane] = 0;
+    for (int a0 = 0; a0 < it.A; a0 += 64) {
+      const int a = a0 + lane;
+      const int lo = rg_owner(it.excl, a);
+      const int eo = __shfl(it.e, lo), qo = __shfl(it.q, lo), xo = __shfl(it.excl, lo);
+      if (a < it.A) {
+        int lid = 0;
+        bool si = false;
+        const int c = rg_classify(g, r, lmap, qo, g.pins[g.off[eo] + (a - xo)], &lid, &si);
+        if (c == 1) {
+          atomicAdd(&cnt[lo], 1);
+          atomicOr(&flg[lo], si ? 4 : 8);
+        } else if (c == 2) {
+          atomicOr(&flg[lo], 1);
+        } else if (c == 3) {
+          atomicOr(&flg[lo], 2);
+        }
       }
     }
-    const int n = (int)o.nloc[q];
-    if (has_s) o.kpins[pos++] = n;
-    if (has_t) o.kpins[pos++] = n + 1;
+    bool keep = false, cut = false;
+    if (it.k < t.nt) {
+      const int f = flg[lane];
+      const bool has_s = f & 1, has_t = f & 2;
+      const int size = cnt[lane] + (int)has_s + (int)has_t;
+      keep = size >= 2 && !(has_s && has_t);
+      t.keep[it.k] = keep ? 1 : 0;
+      t.osz[it.k] = keep ? size : 0;
+      cut = keep && ((f & 4) || has_s) && ((f & 8) || has_t);
+    }
+    // cut weights per pair: one atomic per run of lanes of the same pair
+    unsigned long long w = cut ? (unsigned long long)g.w[it.e] : 0ull;
+    unsigned long long left = __ballot(cut);
+    while (left) {
+      const int lead = __builtin_ctzll(left);
+      const int q0 = __shfl(it.q, lead);
+      const bool mine = cut && it.q == q0;
+      unsigned long long v = mine ? w : 0ull;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+      if (lane == lead) atomicAdd(&t.cutb[q0], v);
+      left &= ~__ballot(mine);
+    }
   }
-  if (bad) atomicOr(o.unsorted, 1);
+}
+
+__global__ void __launch_bounds__(kFlatBlock) k_rg_write_flat(RgGraph g, RgSide r,
+                                                              const int32_t* lmap, RgNets t,
+                                                              RgKept o) {
+  __shared__ int cnt_s[kFlatBlock], flg_s[kFlatBlock];
+  const int lane = __lane_id(), wid = threadIdx.x >> 6;
+  int* cnt = cnt_s + wid * 64;
+  int* flg = flg_s + wid * 64;
+  const int nwaves = gridDim.x * (blockDim.x >> 6);
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  for (int base = (blockIdx.x * (blockDim.x >> 6) + wid) * 64; base < t.nt; base += nwaves * 64) {
+    const RgWaveItem it = rg_wave_item(g, t, base);
+    const int keep = it.k < t.nt ? t.keep[it.k] : 0;
+    const long long pos0 = keep ? o.opos[it.k] : 0;
+    cnt[lane] = 0;
+    flg[lane] = 0;
+    for (int a0 = 0; a0 < it.A; a0 += 64) {
+      const int a = a0 + lane;
+      const int lo = rg_owner(it.excl, a);
+      const int eo = __shfl(it.e, lo), qo = __shfl(it.q, lo), xo = __shfl(it.excl, lo);
+      const int ko = __shfl(keep, lo);
+      const long long po = __shfl(pos0, lo);
+      int lid = 0, c = 0;
+      bool si = false;
+      if (a < it.A && ko) c = rg_classify(g, r, lmap, qo, g.pins[g.off[eo] + (a - xo)], &lid, &si);
+      // rank of a region pin among its net's region pins: those in earlier
+      // steps (cnt) plus the lanes before it in this step (lanes of one net
+      // are contiguous, starting at max(0, xo - a0))
+      const unsigned long long reg = __ballot(c == 1);
+      const int first = max(0, xo - a0);
+      const unsigned long long from = first >= 64 ? 0ull : ~((1ull << first) - 1ull);
+      const int before = cnt[lo];
+      if (c == 1) o.kpins[po + before + __popcll(reg & lt & from)] = lid;
+      if (c == 1) atomicAdd(&cnt[lo], 1);
+      if (c == 2) atomicOr(&flg[lo], 1);
+      if (c == 3) atomicOr(&flg[lo], 2);
+    }
+    if (keep) {
+      const int K = o.kidx[it.k];
+      long long p = pos0 + cnt[lane];
+      const int n = (int)o.nloc[it.q];
+      if (flg[lane] & 1) o.kpins[p++] = n;
+      if (flg[lane] & 2) o.kpins[p++] = n + 1;
+      o.koff[K] = pos0;
+      o.kpair[K] = it.q;
+      o.kgid[K] = it.e;
+      o.kw[K] = g.w[it.e];
+    }
+  }
+}
+
+// kept nets per pair, from the scan of the keep flags at the pairs' bounds
+__global__ void k_rg_kept_per_pair(int npairs, const long long* tbase, int nt,
+                                   const int32_t* kidx, unsigned long long* kcount) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < npairs; q += gridDim.x * blockDim.x) {
+    const long long end = q + 1 < npairs ? tbase[q + 1] : nt;
+    kcount[q] = (unsigned long long)(kidx[end] - kidx[tbase[q]]);
+  }
+}
+
+// kept nets whose region pins are out of increasing local id
+__global__ void k_rg_check_sorted(long long nk, const long long* koff, const int32_t* kpins,
+                                  int* unsorted) {
+  int bad = 0;
+  for (long long K = blockIdx.x * (long long)blockDim.x + threadIdx.x; K < nk;
+       K += (long long)gridDim.x * blockDim.x)
+    for (long long p = koff[K] + 1; p < koff[K + 1]; ++p)
+      if (kpins[p] < kpins[p - 1]) bad = 1;
+  if (bad) atomicOr(unsorted, 1);
 }
 
 // sort keys (net << 32 | local id) of the kept nets' pins, and back
@@ -1006,7 +1105,7 @@ fp_status regions_build(int32_t V, int32_t E, const int32_t* off_in, const int32
   k_rg_zero<<<1, 64, 0, s>>>(reinterpret_cast<uint32_t*>(osz + nt), 2);
   k_rg_touch_list<<<npairs, kRegBlock, 0, s>>>(rs, tbase_d, tnet, tpair);
   RgNets tn{(int32_t)nt, tnet, tpair, keep, osz, cutb};
-  k_rg_count<<<rg_grid(nt), 256, 0, s>>>(g, rs, lmap, tn);
+  k_rg_count_flat<<<rg_grid(nt, kFlatBlock * 4), kFlatBlock, 0, s>>>(g, rs, lmap, tn);
   RG_TRY(rg_exclusive_scan<int32_t>(sc, keep, kidx, (size_t)nt + 1, s), "scanning the nets");
   RG_TRY(rg_exclusive_scan<long long>(sc, osz, opos, (size_t)nt + 1, s), "scanning the pins");
   int32_t nk32 = 0;
@@ -1031,11 +1130,11 @@ fp_status regions_build(int32_t V, int32_t E, const int32_t* off_in, const int32
   RG_TRY(sc.get(1, &unsorted), "allocating");
   RG_TRY(sc.get((size_t)npairs, &kcount), "allocating");
   k_rg_zero<<<1, 64, 0, s>>>(reinterpret_cast<uint32_t*>(unsorted), 1);
-  k_rg_zero<<<rg_grid(2ll * npairs), 256, 0, s>>>(reinterpret_cast<uint32_t*>(kcount),
-                                                   2ll * npairs);
+  k_rg_kept_per_pair<<<rg_grid(npairs), 256, 0, s>>>(npairs, tbase_d, (int)nt, kidx, kcount);
   RG_TRY(hipMemcpyAsync(koff + nk, &npk, 8, hipMemcpyHostToDevice, s), "copy");
-  RgKept kp{kidx, opos, nloc_d, koff, kpins, kpair, kgid, kw, unsorted, kcount};
-  k_rg_write<<<rg_grid(nt), 256, 0, s>>>(g, rs, lmap, tn, kp);
+  RgKept kp{kidx, opos, nloc_d, koff, kpins, kpair, kgid, kw, unsorted};
+  k_rg_write_flat<<<rg_grid(nt, kFlatBlock * 4), kFlatBlock, 0, s>>>(g, rs, lmap, tn, kp);
+  k_rg_check_sorted<<<rg_grid(nk), 256, 0, s>>>(nk, koff, kpins, unsorted);
   int hunsorted = 0;
   RG_TRY(hipMemcpyAsync(&hunsorted, unsorted, 4, hipMemcpyDeviceToHost, s), "reading");
   RG_TRY(hipStreamSynchronize(s), "writing the nets");
