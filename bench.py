@@ -57,9 +57,10 @@ def main():
     ap.add_argument("--no-cutter", action="store_true",
                     help="skip the incremental FlowCutter workload")
     ap.add_argument("--cutter-iterations", type=int, default=100000)
-    ap.add_argument("--cutter-single-cap", type=int, default=250000,
+    ap.add_argument("--cutter-single-cap", type=int, default=40000,
                     help="iteration cap of the one-vertex-per-iteration FlowCutter run "
-                         "(0 skips it)")
+                         "(0 skips it; 250000 runs the 200k-vertex region to balance, "
+                         "about 4 minutes)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-pruning workload")
     ap.add_argument("--learned-seeds", type=int, default=32,
