@@ -463,6 +463,11 @@ typedef struct {
  *   result          host out
  *   trace           host, max_iterations entries, or NULL
  *
+ * Schedule: unless the handle was created with these options set, the
+ * run's warm solves relabel globally every 8 rounds (gr_interval), every 16
+ * in the single-workgroup loop (tail_gr_interval), and claim every BFS level
+ * (bottom_up_min off); the handle keeps these settings afterwards.
+ *
  * The handle keeps the final terminals and flow.  Errors: FP_ERR_INVALID,
  * FP_ERR_ABORTED (a solve ran out of its round budget), FP_ERR_DEVICE.
  */

@@ -82,6 +82,7 @@ fp_status flow_problem_create(int32_t num_vertices, int32_t num_nets, const int3
   pb->V = num_vertices;
   pb->E = num_nets;
   pb->opt = resolve_options(opts);
+  if (opts) pb->opt_user = *opts;
   fp_status st = build_problem(pb, net_offsets, pins, net_weights, sources, num_sources, sinks,
                                num_sinks, mem_kind, static_cast<hipStream_t>(hip_stream));
   if (st != FP_OK) {

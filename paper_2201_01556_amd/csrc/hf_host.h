@@ -76,6 +76,7 @@ struct fp_problem {
   int32_t nS = 0, nT = 0;
   int64_t wsum = 0;          // sum of the net weights (at most INT32_MAX)
   fp_options opt{};
+  fp_options opt_user{};     // the options as the caller gave them (zeros = defaults)
   hf::Dev dev{};
   void* pool = nullptr;
   size_t pool_bytes = 0;     // capacity of the pool (a reused block may be larger)
