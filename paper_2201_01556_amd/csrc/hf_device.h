@@ -2163,42 +2163,56 @@ __device__ void phase_fc_weights(const Dev& g, const int32_t* cw, int ep_s, int 
   block_min_i32(&g.ctl->pierce[2], first_free, &g.ctl->pierce[2], kInf);
 }
 
-// Piercing candidates of both sides.  Side 0: nets cut by (S_r, V - S_r);
-// side 1: nets cut by (V - T_r, T_r) (net_cut_flags).  For side s,
-// pierce[3s] = smallest pin of such a net outside S_r and T_r, pierce[3s+1]
-// = smallest such pin on the opposite side that is not a terminal yet.
-// Lanes take one net each; the cut nets (a small part of all nets) are then
-// scanned by the whole wave, one after another, 64 pins at a time.
-__device__ void phase_fc_candidates(const Dev& g, int ep_s, int ep_t, int t0, int tstride) {
-  int free0 = kInf, aug0 = kInf, free1 = kInf, aug1 = kInf;
-  const int lane = lane_id();
-  for (int base = t0 - lane; base < g.E; base += tstride) {
-    const int e = base + lane;
-    bool2_t c{false, false};
-    if (e < g.E) c = net_cut_flags(g, e, ep_s, ep_t);
-    unsigned long long m = __ballot(c.a || c.b);
-    while (m) {
-      const int b = __builtin_ctzll(m);
-      m &= m - 1;
-      const bool cut0 = __shfl((int)c.a, b) != 0, cut1 = __shfl((int)c.b, b) != 0;
-      const int en = base + b;
-      const int beg = g.net_off[en], end = g.net_off[en + 1];
-      for (int p = beg + lane; p < end; p += 64) {
-        const int u = g.pin_v[p];
-        const int st = g.stamp[u];
-        if (st != ep_s && st != ep_t) {
-          if (cut0) free0 = min(free0, u);
-          if (cut1) free1 = min(free1, u);
-        } else if (st == ep_t) {
-          if (cut0 && g.role[u] != 2) aug0 = min(aug0, u);
-        } else if (cut1 && g.role[u] != 1) {
-          aug1 = min(aug1, u);
+// Piercing candidates of the side that is pierced next, the lighter one
+// (s = 0 when c(S_r) <= c(T_r), from the weights phase_fc_weights summed
+// before): pierce[3s] = the smallest vertex outside S_r and T_r on a net cut
+// by side s's bipartition; pierce[3s + 1] = the smallest vertex of the
+// opposite reachable set on such a net that is not a terminal yet.  The
+// second is only used when no vertex is outside both sets (pierce[2] =
+// kInf), so only then is it searched, and then the first has no candidate.
+// Vertex order, with the uncapped network's reachability: a vertex outside
+// S_r lies on a net cut by (S_r, V - S_r) exactly when one of its nets has
+// e_in in S_r (were e_out in S_r, its pins would be too); one outside T_r
+// lies on a net cut by (V - T_r, T_r) exactly when one of its nets has e_out
+// in T_r.  Workgroups take chunks of blockDim vertices in increasing order
+// (chunk b, b + gridDim, ...) and stop at the first chunk that starts above
+// the best candidate found so far: a vertex of that chunk or a later one
+// cannot be the smallest, and most free vertices next to a side are found
+// in the first chunks.
+__device__ void phase_fc_pick(const Dev& g, int ep_s, int ep_t) {
+  __shared__ int best_sh;
+  const unsigned long long cs = ld_vol64(&g.ctl->side_weight[0]);
+  const unsigned long long ct = ld_vol64(&g.ctl->side_weight[1]);
+  const int side = cs <= ct ? 0 : 1;
+  const bool aug = ld_vol(&g.ctl->pierce[2]) == kInf;
+  const int want = side == 0 ? ep_s : ep_t;  // stamp of the net node that makes a net cut
+  const int opp = side == 0 ? ep_t : ep_s;
+  const int opp_role = side == 0 ? 2 : 1;
+  int32_t* const out = &g.ctl->pierce[3 * side + (aug ? 1 : 0)];
+  const int nchunks = (g.V + (int)blockDim.x - 1) / (int)blockDim.x;
+  for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const int u = c * (int)blockDim.x + (int)threadIdx.x;
+    int found = kInf;
+    if (u < g.V) {
+      const int st = g.stamp[u];
+      const bool look = aug ? (st == opp && g.role[u] != opp_role) : (st != ep_s && st != ep_t);
+      if (look) {
+        const int end = g.vtx_off[u + 1];
+        for (int i = g.vtx_off[u]; i < end; ++i) {
+          if (g.stamp[g.NB + 2 * g.vinc[i].x + side] == want) {
+            found = u;
+            break;
+          }
         }
       }
     }
+    block_min_i32(out, found, out, kInf);
+    if (threadIdx.x == 0) best_sh = ld_vol(out);
+    __syncthreads();
+    const int best = best_sh;
+    __syncthreads();
+    if ((long long)(c + gridDim.x) * blockDim.x > (long long)best) break;
   }
-  block_min_i32(&g.ctl->pierce[0], free0, &g.ctl->pierce[1], aug0);
-  block_min_i32(&g.ctl->pierce[3], free1, &g.ctl->pierce[4], aug1);
 }
 
 // Every free vertex with stamp ep_s becomes a source.  The flows of its

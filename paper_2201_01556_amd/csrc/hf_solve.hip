@@ -16,6 +16,7 @@ namespace hf {
 
 constexpr int kThreads = 256;  // plain element-wise kernels
 constexpr int kBlock = 1024;   // frontier, sweep and single-workgroup kernels
+constexpr int kFcGrid = 128;   // FlowCutter weight and candidate sweeps
 constexpr int kMaxFrontierBlocks = 512;
 static_assert(kMaxFrontierBlocks <= kMaxSliceGroups, "one slice segment per scan workgroup");
 constexpr int kMaxSweepBlocks = 512;
@@ -197,8 +198,8 @@ __global__ void __launch_bounds__(kThreads) k_fc_weights(Dev g, const int32_t* c
   phase_fc_weights(g, cw, ep_s, ep_t, gthread(), gthreads());
 }
 
-__global__ void __launch_bounds__(kThreads) k_fc_candidates(Dev g, int ep_s, int ep_t) {
-  phase_fc_candidates(g, ep_s, ep_t, gthread(), gthreads());
+__global__ void __launch_bounds__(kThreads) k_fc_pick(Dev g, int ep_s, int ep_t) {
+  phase_fc_pick(g, ep_s, ep_t);
 }
 
 __global__ void __launch_bounds__(kThreads) k_fc_mark_augmenting(Dev g, int side, int ep_s,
@@ -1064,6 +1065,17 @@ fp_status terminals_problem(fp_problem* pb, hipStream_t s, int32_t mem_kind, uin
 
 // Up to `slice` more iterations of the FlowCutter run held in pb->fc (see
 // flowcutter_problem); trace[0 .. slice) receives this call's iterations.
+// The weights of S_r and T_r, the smallest vertex outside both and the
+// piercing candidates of the lighter side, into the control block (read
+// after the next round trip).  Both kernels fold workgroup results into the
+// same few counters, and same-address atomics from many workgroups
+// serialise, so their grids are kept small.
+static void fc_side_stats(fp_problem* pb, hipStream_t s, int ep_s, int ep_t) {
+  const int grid = std::min(sweep_grid(pb->V), kFcGrid);
+  k_fc_weights<<<grid, kThreads, 0, s>>>(pb->dev, pb->cw, ep_s, ep_t);
+  k_fc_pick<<<grid, kThreads, 0, s>>>(pb->dev, ep_s, ep_t);
+}
+
 static fp_status flowcutter_run(fp_problem* pb, int32_t slice, hipStream_t s, int32_t mem_kind,
                                 uint8_t* vside, fp_cutter_result* res, fp_cutter_step* trace) {
   Dev& g = pb->dev;
@@ -1122,8 +1134,7 @@ static fp_status flowcutter_run(fp_problem* pb, int32_t slice, hipStream_t s, in
     f.grow = -1;
     f.prev_ep_s = ep_s;
     f.prev_ep_t = ep_t;
-    k_fc_weights<<<sweep_grid(pb->V), kThreads, 0, s>>>(g, pb->cw, ep_s, ep_t);
-    k_fc_candidates<<<sweep_grid(pb->E), kThreads, 0, s>>>(g, ep_s, ep_t);
+    fc_side_stats(pb, s, ep_s, ep_t);
     st = sync_ctl(pb, s);
     if (st) return st;
     if (spec) {
@@ -1133,8 +1144,7 @@ static fp_status flowcutter_run(fp_problem* pb, int32_t slice, hipStream_t s, in
       if (nf > 0) {  // the growth outgrew the single-workgroup loop
         st = grow_side_finish(pb, s, grown, grown == 0 ? ep_s : ep_t, lv, nf);
         if (st) return st;
-        k_fc_weights<<<sweep_grid(pb->V), kThreads, 0, s>>>(g, pb->cw, ep_s, ep_t);
-        k_fc_candidates<<<sweep_grid(pb->E), kThreads, 0, s>>>(g, ep_s, ep_t);
+        fc_side_stats(pb, s, ep_s, ep_t);
         st = sync_ctl(pb, s);
         if (st) return st;
       }
