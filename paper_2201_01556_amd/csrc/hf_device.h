@@ -2024,6 +2024,14 @@ __device__ void phase_reset_bfs(const Dev& g) {
   }
 }
 
+// Clear the frontier counters of all three round slots (a solve that starts
+// from the labels it has, without a global relabel, gathers into one).
+__device__ void phase_clear_frontiers(const Dev& g) {
+  if (threadIdx.x == 0)
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < kNL; ++k) g.ctl->fcnt[i][k] = 0;
+}
+
 // One seed vertex p (already stamped by the caller) as BFS level 0.  The
 // BFS counters must be clear (phase_reset_bfs).
 __device__ void phase_seed_vertex(const Dev& g, int p) {
@@ -2219,7 +2227,11 @@ __device__ void phase_fc_pick(const Dev& g, int ep_s, int ep_t) {
 // pin arcs are cancelled (flow(u, e_in) back out of e_in's excess, flow
 // (e_out, u) back into e_out's excess), and a net that gains its first
 // source pin receives w(e) through its contracted source arc, so the state
-// stays a preflow of the new network with the same flow value.
+// stays a preflow of the new network with the same flow value.  The vertex
+// takes the sources' label N + 1.  No residual arc between non-terminal
+// nodes appears (the arcs that change all start or end at the new source),
+// so the other labels stay valid and the next solve may start from them
+// (paragraph "Maintain Distance Labels").
 // Incidence i (net e) of a vertex u that becomes a source: the flows of u's
 // pin arcs are cancelled -- e_in loses the flow u sent it and, when e gets its
 // first source pin, gains w(e) from the contracted source arc; e_out keeps as
@@ -2244,6 +2256,7 @@ __device__ void phase_pierce_sources(const Dev& g, int ep_s, int t0, int tstride
   for (int v = t0; v < g.V; v += tstride) {
     if (g.role[v] != 0 || g.stamp[v] != ep_s) continue;
     g.role[v] = 1;
+    g.d[v] = g.N + 1;  // a source's label: nothing is pushed into it
     for (int i = g.vtx_off[v]; i < g.vtx_off[v + 1]; ++i) cancel_source_pin(g, i);
   }
 }
@@ -2266,6 +2279,7 @@ __device__ void phase_pierce_sources_seed(const Dev& g, int ep_s, int tile0, int
     int beg = 0, end = 0;
     if (v < g.V && g.role[v] == 0 && g.stamp[v] == ep_s) {
       g.role[v] = 1;
+      g.d[v] = g.N + 1;
       beg = g.vtx_off[v];
       end = g.vtx_off[v + 1];
     }

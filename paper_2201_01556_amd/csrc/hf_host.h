@@ -87,6 +87,7 @@ struct fp_problem {
   int32_t gr_hist_levels = 0;
   bool inited = false;
   bool solved = false;
+  bool warm_labels = false;  // the labels are valid for the next solve (after a source pierce)
   int32_t* cw = nullptr;     // vertex weights of the last FlowCutter run (device)
   void* fc_mem = nullptr;    // FlowCutter scratch: candidate flags, tile counts, best side
   hf::FcRun fc;

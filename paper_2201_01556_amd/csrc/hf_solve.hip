@@ -132,6 +132,8 @@ __global__ void __launch_bounds__(kBlock) k_bfs_collect(Dev g, int level, int bi
   if (nf >= min(big_min, pull_min)) phase_bfs_collect(g, level, blockIdx.x, gridDim.x, lds);
 }
 
+__global__ void k_clear_frontiers(Dev g) { phase_clear_frontiers(g); }
+
 __global__ void __launch_bounds__(kBlock) k_gather(Dev g, int epoch) {
   HF_QUEUE_LDS;
   phase_gather(g, epoch, blockIdx.x, gridDim.x, lds);
@@ -590,7 +592,21 @@ static fp_status solve_impl(fp_problem* pb, hipStream_t s, int64_t* flow) {
     }
     pb->inited = true;
   }
-  st = global_relabel<G>(pb, s);
+  // After a source pierce the labels are still valid (paragraph "Maintain
+  // Distance Labels"): the solve only gathers the active nodes, and its end
+  // is confirmed by a global relabel as usual.  Otherwise it starts with one.
+  const bool warm = pb->warm_labels && pb->inited;
+  pb->warm_labels = false;
+  if (warm) {
+    {
+      Launch L(pb, s, KK_GATHER);
+      k_clear_frontiers<<<1, 64, 0, s>>>(g);
+      k_gather<<<sweep_blocks(g.N), kBlock, 0, s>>>(g, pb->epoch);
+    }
+    st = sync_ctl(pb, s, "gather");
+  } else {
+    st = global_relabel<G>(pb, s);
+  }
   if (st) return st;
   // global relabel triggers (paper: "after linear push and relabel work",
   // and the stale-flow rule of paragraph "Avoid Pushing Flow Back")
@@ -610,7 +626,7 @@ static fp_status solve_impl(fp_problem* pb, hipStream_t s, int64_t* flow) {
   unsigned long long last_flow = pb->ctl_h->flow;
   long long stale = 0;
   long long rounds_since_gr = 0;
-  bool fresh_gr = true;  // frontier was just gathered by a global relabel
+  bool fresh_gr = !warm;  // frontier was just gathered by a global relabel
   const int cap = pb->opt.tail_threshold;
   const int rounds_per_sync = pb->opt.debug_checks ? 1 : 8;
   int64_t rounds_this_solve = 0;
@@ -1080,6 +1096,12 @@ static fp_status flowcutter_run(fp_problem* pb, int32_t slice, hipStream_t s, in
                                 uint8_t* vside, fp_cutter_result* res, fp_cutter_step* trace) {
   Dev& g = pb->dev;
   FcRun& f = pb->fc;
+  // labels kept for a solve of this run only: whatever runs next on the
+  // handle (a continued run included) starts with a global relabel
+  struct WarmReset {
+    fp_problem* pb;
+    ~WarmReset() { pb->warm_labels = false; }
+  } warm_reset{pb};
   f.active = false;  // set again below if the slice ends at its limit
   const long long total = f.total;
   const int64_t max_src = f.max_src, max_snk = f.max_snk;
@@ -1306,6 +1328,8 @@ static fp_status flowcutter_run(fp_problem* pb, int32_t slice, hipStream_t s, in
         f.seeded = !aug && side == 0 && !pb->opt.debug_checks;
         st = apply_pierce(pb, s, side, ep, f.seeded);
         if (st) return st;
+        // an augmenting source pierce is followed by a solve that keeps the labels
+        pb->warm_labels = aug && side == 0;
       }
     }
     if (trace) trace[n] = step;

@@ -235,6 +235,23 @@ def test_flowcutter_uniform_vs_oracle(hf, oracle_mod, seed):
     assert res["status"] == "balanced"
 
 
+@pytest.mark.parametrize("seed", range(2))
+def test_flowcutter_kept_labels_checked(hf, oracle_mod, seed):
+    """A solve after an augmenting source pierce starts from the labels it
+    has (paragraph "Maintain Distance Labels"); with the invariant checker
+    after every round (preflow and label validity on every residual arc) the
+    run still equals the oracle's, on 2,000-vertex instances whose runs
+    pierce on both sides and augment."""
+    hg = inputs.uniform_hypergraph(10 + seed)
+    c = np.random.default_rng(seed).integers(1, 4, hg.num_vertices)
+    L = balance_limit(c.sum())
+    _say(f"kept labels, uniform {10 + seed}")
+    res = _compare_cutter(hf, oracle_mod, hg, c, L, L, 5000, f"kept labels {seed}",
+                          debug_checks=1)
+    _say(f"{res['iterations']} iterations, {res['augmenting']} augmenting")
+    assert res["augmenting"] > 0
+
+
 def test_flowcutter_block_pairs_vs_oracle(hf, oracle_mod):
     """Region problems of a partitioned hypergraph, balance = the k-way
     bound on both blocks (s and t carry the rest of their blocks)."""
