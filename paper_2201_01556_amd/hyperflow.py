@@ -695,7 +695,8 @@ class FlowRegions:
     def __init__(self, num_vertices, net_offsets, pins, net_weights, vertex_weights, blocks, k,
                  pairs, caps, merge_identical=True, stream=None):
         self.stream = stream
-        self.count = len(np.asarray(pairs).reshape(-1)) // 2
+        self.pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+        self.count = len(self.pairs)
         self.handle = flow_regions_build(num_vertices, net_offsets, pins, net_weights,
                                          vertex_weights, blocks, k, pairs, caps, merge_identical,
                                          stream)
@@ -705,6 +706,24 @@ class FlowRegions:
 
     def export(self, pair) -> dict:
         return flow_regions_export(self.handle, pair, self.stream)
+
+    def features(self, cuts, block_weights) -> np.ndarray:
+        """The learned scorer's 12 integer features of every pair (int64,
+        count x 12) from the statistics the device construction computed:
+        the pair's cut weight (``cuts``), region pins, boundary vertices, the
+        7 net-size bins, then c(V_i) and c(V_j) (``block_weights``)."""
+        cuts = np.asarray(cuts, dtype=np.int64).reshape(-1)
+        bw = np.asarray(block_weights, dtype=np.int64)
+        if len(cuts) != self.count:
+            raise ValueError("one cut weight per pair")
+        keys = ("num_pins", "boundary", "bin_2", "bin_4", "bin_8", "bin_16", "bin_64",
+                "bin_256", "bin_more")
+        out = np.empty((self.count, 12), dtype=np.int64)
+        for q in range(self.count):
+            inf = self.info(q)
+            i, j = self.pairs[q]
+            out[q] = [cuts[q], *[inf[k] for k in keys], bw[i], bw[j]]
+        return out
 
     def solve(self, skip=None):
         """Minimum cuts of the pairs not skipped, as union networks built from

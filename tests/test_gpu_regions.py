@@ -240,6 +240,8 @@ def test_regions_full_block_pairs(hf, oreg):
             assert (g["vertex_weights"] == p.vertex_weights).all(), q
             assert (g["vertex_ids"] == p.meta["gid"]).all(), q
             assert g["info"]["cut_before"] == p.meta["cut_before"], q
+        # the learned scorer's features from the device statistics
+        assert (rg.features(cuts, bp.block_weights) == inputs.scorer_features(bp.problems)).all()
     _say("full block pairs: unmerged equal to the host builder; merged flows")
     plain = [hf.FlowProblem.from_hypergraph(h, device=True) for h in bp.problems]
     try:

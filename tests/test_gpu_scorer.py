@@ -155,7 +155,7 @@ def test_trained_scorer_gain_on_planted_block_pairs(hf):
         cb = np.array([h.meta["cut_before"] for h in hgs], dtype=np.int64)
         probs = [hf.FlowProblem.from_hypergraph(h, device=True) for h in hgs]
         torch.cuda.synchronize()
-        return probs, feats, cb
+        return bp, probs, feats, cb
 
     def run(probs, skip=None):
         with hf.FlowBatch(probs, with_cut=True) as plan:
@@ -163,7 +163,7 @@ def test_trained_scorer_gain_on_planted_block_pairs(hf):
 
     X, Y = [], []
     for seed in range(6):
-        probs, feats, cb = instance(seed)
+        _, probs, feats, cb = instance(seed)
         try:
             gain = cb - run(probs)
         finally:
@@ -183,7 +183,7 @@ def test_trained_scorer_gain_on_planted_block_pairs(hf):
         theta = float(p[Y > 0].min())
         skipped = missed = total = negatives = 0
         for seed in (6, 7):
-            probs, feats, cb = instance(seed)
+            bp, probs, feats, cb = instance(seed)
             try:
                 flows = run(probs)
                 gain = cb - flows
@@ -194,6 +194,21 @@ def test_trained_scorer_gain_on_planted_block_pairs(hf):
             finally:
                 for p_ in probs:
                     p_.close()
+            # the same schedule end to end on the device: regions built there,
+            # the features from their statistics, inference, one union solve
+            # of the kept pairs
+            hg = bp.hypergraph
+            pairs = [h.meta["pair"] for h in bp.problems]
+            cuts = [h.meta["cut"] for h in bp.problems]
+            caps = inputs.region_caps(bp.block_weights, pairs, cuts)
+            with hf.FlowRegions(hg.num_vertices, hg.net_offsets, hg.pins, hg.net_weights,
+                                hg.vertex_weights, bp.block, 16, pairs, caps,
+                                merge_identical=False) as rg:
+                fd = rg.features(cuts, bp.block_weights)
+                assert (fd == feats).all()
+                skip_d = (sc.predict(fd) < theta).astype(np.uint8)
+                assert (skip_d == skip).all()
+                assert list(rg.solve(skip_d)) == list(kept)
             skipped += int(skip.sum())
             negatives += int((gain <= 0).sum())
             missed += int(gain[(skip > 0) & (gain > 0)].sum())
