@@ -236,7 +236,7 @@ fp_status flow_batch_solve(fp_problem *const *problems, int32_t count,
 /*
  * Batch plans: many independent problems solved at once, the pattern of
  * the paper's refinement scheduler (section "Parallel Active Block
- * Scheduling").  Two schedules:
+ * Scheduling").  Three schedules:
  *   1 (union, the default)  the kept problems are copied into one network,
  *                their disjoint union, and solved once with the device-wide
  *                kernels: every launch of the solve works on all problems
@@ -258,6 +258,18 @@ fp_status flow_batch_solve(fp_problem *const *problems, int32_t count,
  *                so the kernels and host round trips of different problems
  *                overlap; every solved handle then behaves as after
  *                maxflow_solve.
+ *   3 (workgroups)  one persistent launch, replayed from a captured HIP
+ *                graph: each workgroup takes the next problem (largest
+ *                first) from a device counter and solves it alone, from the
+ *                zero flow of its current terminals to the terminating
+ *                global relabel and, with with_cut, its source side, with
+ *                workgroup barriers only (no launches or host round trips
+ *                per problem: suited to many small problems).  The relabel
+ *                interval is gr_interval, else the first problem's interval
+ *                for single-workgroup rounds; relabel work and stale-flow
+ *                limits are the first problem's options.  Every solved
+ *                handle then behaves as after maxflow_solve; round budgets
+ *                and debug checks do not apply.
  */
 typedef struct fp_batch fp_batch; /* opaque, library-owned */
 
@@ -271,11 +283,13 @@ typedef struct {
   int32_t reserved1;     /* must be 0                                       */
   int32_t streams;       /* workers schedule: concurrent workers (streams),
                             1..64; 0 = 4                                   */
-  int32_t schedule;      /* 1 = union, 2 = workers; 0 = union              */
+  int32_t schedule;      /* 1 = union, 2 = workers, 3 = workgroups;
+                            0 = union                                      */
   int32_t union_pins;    /* union schedule: at most this many pins per
                             union (bounds its device memory); 0 = as many
                             as 31-bit ids allow                            */
-  int32_t reserved[1];
+  int32_t wg_threads;    /* workgroups schedule: threads per workgroup,
+                            256 or 1024; 0 = 256                           */
 } fp_batch_config;
 
 /*

@@ -41,12 +41,22 @@ struct fp_batch {
   std::vector<hipStream_t> workers;  // streams of the workers schedule
   void* umem = nullptr;              // scratch of the union schedule
   size_t umem_bytes = 0;
+  // workgroups schedule: [queue counter][order][skip flags][results] on the
+  // device, the results' pinned host copy, the captured launch and the
+  // stream it is captured on, with the arguments it was captured with
+  void* wmem = nullptr;
+  void* wres_h = nullptr;
+  hipStream_t wg_stream = nullptr;
+  hipGraph_t wg_graph = nullptr;
+  hipGraphExec_t wg_exec = nullptr;
+  int32_t wg_key[8] = {};
 };
 
 namespace hf {
 
 constexpr int32_t kScheduleUnion = 1;
 constexpr int32_t kScheduleWorkers = 2;
+constexpr int32_t kScheduleWorkgroups = 3;
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -57,13 +67,16 @@ static fp_batch_config resolve_batch_config(const fp_batch_config* c) {
   if (r.group_lanes == 0) r.group_lanes = 8;
   if (r.gr_interval == 0 && r.schedule == kScheduleUnion) r.gr_interval = 8;
   if (r.streams == 0) r.streams = 4;
+  if (r.wg_threads == 0) r.wg_threads = 256;
   return r;
 }
 
 static bool batch_config_valid(const fp_batch_config& c) {
   return (c.group_lanes == 4 || c.group_lanes == 8 || c.group_lanes == 16) &&
          c.gr_interval >= -1 && c.streams >= 1 && c.streams <= 64 &&
-         (c.schedule == kScheduleUnion || c.schedule == kScheduleWorkers) && c.union_pins >= 0 &&
+         (c.schedule == kScheduleUnion || c.schedule == kScheduleWorkers ||
+          c.schedule == kScheduleWorkgroups) &&
+         c.union_pins >= 0 && (c.wg_threads == 256 || c.wg_threads == 1024) &&
          c.reserved0 == 0 && c.reserved1 == 0;
 }
 
@@ -74,6 +87,15 @@ bool batch_config_ok(const fp_batch_config* c) {
 void release_batch(fp_batch* b) {
   for (hipStream_t w : b->workers) (void)hipStreamDestroy(w);
   b->workers.clear();
+  if (b->wg_exec) (void)hipGraphExecDestroy(b->wg_exec);
+  if (b->wg_graph) (void)hipGraphDestroy(b->wg_graph);
+  if (b->wg_stream) (void)hipStreamDestroy(b->wg_stream);
+  if (b->wmem) (void)hipFree(b->wmem);
+  if (b->wres_h) (void)hipHostFree(b->wres_h);
+  b->wg_exec = nullptr;
+  b->wg_graph = nullptr;
+  b->wg_stream = nullptr;
+  b->wmem = b->wres_h = nullptr;
   if (b->dmem) (void)hipFree(b->dmem);
   if (b->hmem) (void)hipHostFree(b->hmem);
   if (b->umem) (void)hipFree(b->umem);
@@ -482,6 +504,360 @@ static fp_status union_chunk(fp_batch* b, const std::vector<int32_t>& ids, int32
   return FP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// workgroups schedule: one persistent launch, a workgroup per problem
+//
+// Each workgroup takes the next problem of the plan's order (largest first)
+// from a device counter and solves it alone with the single-problem phases
+// in their one-workgroup form: init (zero flow of the current terminals), a
+// global relabel (reverse BFS whose levels claim, then the gather of the
+// active nodes), discharge rounds with the host loop's relabel triggers
+// (relabel work, interval, stale flow), the terminating relabel that
+// confirms an empty frontier (paper, section "A Bug in the Synchronous
+// Algorithm"), and on request the source side.  The waves of a workgroup
+// share one CU, so workgroup barriers order their memory traffic and no
+// device-wide synchronisation is needed; a problem costs no launches and no
+// host round trips of its own (the paper's many small flow problems at once,
+// section "Parallel Active Block Scheduling", paragraph "Parallelization").
+// The launch is replayed from a captured HIP graph.
+// ---------------------------------------------------------------------------
+
+constexpr long long kWgRoundGuard = 1000000ll;  // rounds per solve before giving up
+constexpr int kWgStaleFrontier = 1500;  // "only few active nodes" (paragraph "Avoid Pushing Flow Back")
+
+struct WgParams {
+  int32_t count;        // problems in the plan
+  int32_t epoch0;       // first stamp value of every solve (init clears the stamps)
+  int32_t gr_interval;  // rounds between global relabels; <= 0 off
+  int32_t stale_limit;  // rounds without a flow change (few active nodes); <= 0 off
+  int32_t relabel_x16;  // relabel work between global relabels: N * x / 16 relabels
+  int32_t with_cut;     // also write the minimal source side
+};
+
+struct WgResult {
+  unsigned long long flow;
+  long long rounds;
+  int32_t epoch;  // first stamp value not used by the solve
+  int32_t err;    // the problem's error flags
+  int32_t global_relabels;
+  int32_t restarts;
+};
+
+// Global relabel inside one workgroup: exact labels by the reverse BFS of
+// the capped network (levels claim their nodes), then the active nodes
+// gathered as round `epoch`'s frontier.  False (flagged ERR_GUARD) when a
+// level breaks the bounds of a BFS.  Block-uniform.
+__device__ bool wg_global_relabel(const Dev& g, int epoch, lds_int* lds) {
+  phase_gr_reset(g, 0, 1, lds);
+  __syncthreads();
+  bool ok = true;
+  for (int level = 0;; ++level) {
+    const int nf = count_all_vol(g.ctl->bcnt[level % 3]);
+    if (nf == 0) break;
+    if (nf > g.N || level > g.N) {  // a level holds distinct nodes; at most N levels
+      ok = false;
+      break;
+    }
+    __syncthreads();  // every wave has read the count before the level changes it
+    phase_bfs_rev_lb<true>(g, level, 0, 1, KC_LOOP_BFS, lds);
+    __syncthreads();
+  }
+  if (!ok) {
+    if (threadIdx.x == 0) atomicOr(&g.ctl->err, ERR_GUARD);
+    __syncthreads();
+    return false;
+  }
+  phase_gather(g, epoch, 0, 1, lds);
+  __syncthreads();
+  return true;
+}
+
+// Source side inside one workgroup: seeds, forward BFS levels of the
+// uncapped network, the bitmaps.  Block-uniform.
+__device__ void wg_cut(const Dev& g, int ep, uint8_t* vs, uint8_t* ns, lds_int* lds) {
+  phase_cut_seed(g, ep, false, 0, 1, lds);
+  __syncthreads();
+  for (int level = 0;; ++level) {
+    const int nf = count_all_vol(g.ctl->bcnt[level % 3]);
+    if (nf == 0) break;
+    if (nf > g.N || level > g.N) {
+      if (threadIdx.x == 0) atomicOr(&g.ctl->err, ERR_GUARD);
+      break;
+    }
+    __syncthreads();
+    phase_bfs_fwd_lb<true>(g, level, ep, 0, 0, 1, KC_LOOP_BFS, lds);
+    __syncthreads();
+  }
+  __syncthreads();
+  phase_cut_out(g, ep, vs, ns, threadIdx.x, blockDim.x);
+  __syncthreads();
+}
+
+// One problem, start to end, in one workgroup (the host loop of
+// solve_impl moved on the device).  Every decision reads counters after a
+// barrier that no wave passes before the next phase, so it is block-uniform.
+template <int G>
+__device__ void wg_solve(const Dev& g, const WgParams& p, uint8_t* vs, uint8_t* ns,
+                         lds_int* lds, WgResult* out) {
+  phase_init(g, threadIdx.x, blockDim.x);
+  __syncthreads();
+  int epoch = p.epoch0;
+  int ngr = 1, restarts = 0;
+  long long rounds = 0;
+  bool ok = wg_global_relabel(g, epoch, lds);
+  const unsigned long long budget =
+      (unsigned long long)g.N * (unsigned long long)p.relabel_x16 / 16ull + 1ull;
+  unsigned long long rel_at = ld_vol64(&g.ctl->relabels);
+  unsigned long long last_flow = ld_vol64(&g.ctl->flow);
+  int since = 0, stale = 0;
+  bool fresh = true;  // the frontier was just gathered by a global relabel
+  while (ok) {
+    const int nf = count_all_vol(g.ctl->fcnt[epoch % 3]);
+    if (ld_vol(&g.ctl->err) & ERR_LABEL) break;
+    bool gr = false;
+    if (nf == 0) {
+      if (fresh) break;
+      gr = true;  // apparent termination: confirm with exact labels
+    } else {
+      if (rounds >= kWgRoundGuard) {
+        __syncthreads();
+        if (threadIdx.x == 0) atomicOr(&g.ctl->err, ERR_GUARD);
+        ok = false;
+        break;
+      }
+      fresh = false;
+      __syncthreads();  // every wave has read the counters before they change
+      phase_push<G>(g, epoch, 0, 1, KC_LOOP_ROUNDS, lds);
+      __syncthreads();
+      phase_apply(g, epoch, 0, 1, KC_LOOP_ROUNDS, lds);
+      __syncthreads();
+      ++epoch;
+      ++rounds;
+      ++since;
+      const unsigned long long fl = ld_vol64(&g.ctl->flow);
+      if (fl != last_flow) {
+        last_flow = fl;
+        stale = 0;
+      } else if (nf < kWgStaleFrontier) {
+        ++stale;
+      } else {
+        stale = 0;
+      }
+      if (ld_vol64(&g.ctl->relabels) - rel_at >= budget) gr = true;
+      if (p.gr_interval > 0 && since >= p.gr_interval) gr = true;
+      if (p.stale_limit > 0 && stale >= p.stale_limit) gr = true;
+    }
+    if (gr) {
+      __syncthreads();  // every wave has read the counters before the relabel changes them
+      ok = wg_global_relabel(g, epoch, lds);
+      ++ngr;
+      if (ok && nf == 0 && count_all_vol(g.ctl->fcnt[epoch % 3]) > 0) ++restarts;
+      rel_at = ld_vol64(&g.ctl->relabels);
+      last_flow = ld_vol64(&g.ctl->flow);
+      since = 0;
+      stale = 0;
+      fresh = true;
+    }
+  }
+  __syncthreads();
+  if (ok && p.with_cut && vs != nullptr && !(ld_vol(&g.ctl->err) & ERR_LABEL)) {
+    const int ep = epoch++;
+    wg_cut(g, ep, vs, ns, lds);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out->flow = ld_vol64(&g.ctl->flow);
+    out->rounds = rounds;
+    out->epoch = epoch;
+    out->err = ld_vol(&g.ctl->err);
+    out->global_relabels = ngr;
+    out->restarts = restarts;
+  }
+  __syncthreads();
+}
+
+// The persistent launch: workgroups take problems from the counter `next`
+// until every problem of the order is taken.  Skipped problems are passed
+// over and keep their result slot.
+template <int G, int B>
+__global__ void __launch_bounds__(B) k_batch_wg(const Dev* devs, const int32_t* order,
+                                                         const uint8_t* skip,
+                                                         uint8_t* const* vs_ptrs,
+                                                         uint8_t* const* ns_ptrs, int32_t* next,
+                                                         WgParams p, WgResult* res) {
+  __shared__ int32_t bq[lds_words(B)];
+  lds_int* const lds = (lds_int*)bq;
+  __shared__ int32_t slot;
+  for (;;) {
+    if (threadIdx.x == 0) slot = atomicAdd(next, 1);
+    __syncthreads();
+    const int k = __builtin_amdgcn_readfirstlane(slot);
+    __syncthreads();  // every wave has read the slot before it is written again
+    if (k >= p.count) break;
+    const int i = __builtin_amdgcn_readfirstlane(order[k]);
+    if (skip[i]) continue;
+    uint8_t* vs = p.with_cut ? vs_ptrs[i] : nullptr;
+    uint8_t* ns = p.with_cut && ns_ptrs ? ns_ptrs[i] : nullptr;
+    // the layout is read where it lies (uniform address): a private copy
+    // would be indexed dynamically (list slots) and live in scratch
+    const Dev& g = devs[i];
+    wg_solve<G>(g, p, vs, ns, lds, res + i);
+  }
+}
+
+__global__ void k_wg_reset(int32_t* next) {
+  if (threadIdx.x == 0) *next = 0;
+}
+
+// Rounds between global relabels inside one workgroup: the configuration's,
+// else the problem's interval for rounds of the single-workgroup loop
+// (every round of this schedule is such a round).
+static int32_t wg_interval(const fp_batch* b) {
+  if (b->cfg.gr_interval != 0) return b->cfg.gr_interval < 0 ? 0 : b->cfg.gr_interval;
+  const fp_options& o = b->pbs[0]->opt;
+  if (o.tail_gr_interval > 0) return o.tail_gr_interval;
+  return o.tail_gr_interval < 0 ? o.gr_interval : 4 * o.gr_interval;
+}
+
+template <int G, int B>
+static int wg_grid_for(const fp_batch* b) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void*>(&k_batch_wg<G, B>), B, 0) != hipSuccess)
+    per_cu = 1;
+  hipDeviceProp_t prop{};
+  (void)hipGetDeviceProperties(&prop, b->device);
+  const long long grid = (long long)std::max(1, per_cu) * std::max(1, prop.multiProcessorCount);
+  return (int)std::max(1ll, std::min<long long>(grid, b->count));
+}
+
+template <int G, int B>
+static hipError_t wg_capture(fp_batch* b, int grid, const WgParams& p, int32_t* next,
+                             const int32_t* order, const uint8_t* skip_d, WgResult* res_d) {
+  hipStream_t ws = b->wg_stream;
+  hipError_t he = hipStreamBeginCapture(ws, hipStreamCaptureModeThreadLocal);
+  if (he != hipSuccess) return he;
+  k_wg_reset<<<1, 64, 0, ws>>>(next);
+  k_batch_wg<G, B><<<grid, B, 0, ws>>>(b->devs_d, order, skip_d, b->vs_d,
+                                       b->has_ns ? b->ns_d : nullptr, next, p, res_d);
+  hipGraph_t graph = nullptr;
+  const hipError_t launch = hipGetLastError();
+  he = hipStreamEndCapture(ws, &graph);
+  if (launch != hipSuccess) he = launch;
+  if (he == hipSuccess) he = hipGraphInstantiate(&b->wg_exec, graph, nullptr, nullptr, 0);
+  if (he == hipSuccess) b->wg_graph = graph;
+  else if (graph) (void)hipGraphDestroy(graph);
+  return he;
+}
+
+// Workgroups schedule: every kept problem solved from the zero flow of its
+// current terminals inside one workgroup of one persistent launch; every
+// solved handle then behaves as after maxflow_solve.
+static fp_status batch_workgroups(fp_batch* b, const uint8_t* skip, int32_t with_cut,
+                                  hipStream_t s, int64_t* flows, float* ms) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const int32_t n = b->count;
+  const size_t o_next = 0;
+  const size_t o_order = align_up(o_next + 4);
+  const size_t o_skip = align_up(o_order + (size_t)n * 4);
+  const size_t o_res = align_up(o_skip + (size_t)n);
+  const size_t bytes = align_up(o_res + (size_t)n * sizeof(WgResult));
+  hipError_t he = hipSuccess;
+  if (!b->wmem) {
+    he = hipMalloc(&b->wmem, bytes);
+    if (he == hipSuccess) he = hipHostMalloc(&b->wres_h, (size_t)n * sizeof(WgResult),
+                                             hipHostMallocDefault);
+    if (he == hipSuccess) he = hipStreamCreateWithFlags(&b->wg_stream, hipStreamNonBlocking);
+    if (he == hipSuccess)
+      he = hipMemcpyAsync(static_cast<char*>(b->wmem) + o_order, b->order.data(),
+                          (size_t)n * 4, hipMemcpyHostToDevice, s);
+    if (he != hipSuccess) return hip_fail(he, "allocating the workgroups schedule");
+  }
+  char* d = static_cast<char*>(b->wmem);
+  int32_t* next = reinterpret_cast<int32_t*>(d + o_next);
+  const int32_t* order = reinterpret_cast<const int32_t*>(d + o_order);
+  uint8_t* skip_d = reinterpret_cast<uint8_t*>(d + o_skip);
+  WgResult* res_d = reinterpret_cast<WgResult*>(d + o_res);
+  WgResult* res_h = static_cast<WgResult*>(b->wres_h);
+  for (int32_t i = 0; i < n; ++i) b->devs_h[i] = b->pbs[i]->dev;
+  he = hipMemcpyAsync(b->devs_d, b->devs_h, (size_t)n * sizeof(Dev), hipMemcpyHostToDevice, s);
+  if (he == hipSuccess) {
+    if (skip) he = hipMemcpyAsync(skip_d, skip, (size_t)n, hipMemcpyHostToDevice, s);
+    else he = hipMemsetAsync(skip_d, 0, (size_t)n, s);
+  }
+  if (he != hipSuccess) return hip_fail(he, "staging the workgroups schedule");
+  const fp_options& o = b->pbs[0]->opt;
+  WgParams p{};
+  p.count = n;
+  p.epoch0 = 1;
+  p.gr_interval = wg_interval(b);
+  p.stale_limit = o.stale_rounds;
+  p.relabel_x16 = o.relabel_factor_x16;
+  p.with_cut = with_cut ? 1 : 0;
+  const int G = b->cfg.group_lanes;
+  const bool big = b->cfg.wg_threads == 1024;
+  int grid = 0;
+  if (big) grid = G == 4 ? wg_grid_for<4, 1024>(b) : G == 16 ? wg_grid_for<16, 1024>(b)
+                                                          : wg_grid_for<8, 1024>(b);
+  else grid = G == 4 ? wg_grid_for<4, 256>(b) : G == 16 ? wg_grid_for<16, 256>(b)
+                                                       : wg_grid_for<8, 256>(b);
+  const int32_t key[8] = {G * (big ? -1 : 1), grid, p.gr_interval, p.stale_limit,
+                          p.relabel_x16, p.with_cut, b->has_ns ? 1 : 0, n};
+  if (!b->wg_exec || std::memcmp(key, b->wg_key, sizeof(key)) != 0) {
+    if (b->wg_exec) (void)hipGraphExecDestroy(b->wg_exec);
+    if (b->wg_graph) (void)hipGraphDestroy(b->wg_graph);
+    b->wg_exec = nullptr;
+    b->wg_graph = nullptr;
+    if (big)
+      he = G == 4    ? wg_capture<4, 1024>(b, grid, p, next, order, skip_d, res_d)
+           : G == 16 ? wg_capture<16, 1024>(b, grid, p, next, order, skip_d, res_d)
+                     : wg_capture<8, 1024>(b, grid, p, next, order, skip_d, res_d);
+    else
+      he = G == 4    ? wg_capture<4, 256>(b, grid, p, next, order, skip_d, res_d)
+           : G == 16 ? wg_capture<16, 256>(b, grid, p, next, order, skip_d, res_d)
+                     : wg_capture<8, 256>(b, grid, p, next, order, skip_d, res_d);
+    if (he != hipSuccess) {
+      b->wg_exec = nullptr;
+      return hip_fail(he, "capturing the workgroups launch");
+    }
+    std::memcpy(b->wg_key, key, sizeof(key));
+  }
+  he = hipGraphLaunch(b->wg_exec, s);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(res_h, res_d, (size_t)n * sizeof(WgResult), hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  if (he != hipSuccess) return hip_fail(he, "running the workgroups schedule");
+  fp_status st = FP_OK;
+  for (int32_t i = 0; i < n; ++i) {
+    if (skip && skip[i]) {
+      if (flows) flows[i] = -1;
+      continue;
+    }
+    const WgResult& r = res_h[i];
+    fp_problem* pb = b->pbs[i];
+    pb->st.rounds += r.rounds;
+    pb->st.tail_rounds += r.rounds;
+    pb->st.global_relabels += r.global_relabels;
+    pb->st.restarts += r.restarts;
+    pb->epoch = std::max(pb->epoch, r.epoch + 1);
+    const bool bad = r.err & (ERR_LABEL | ERR_GUARD | ERR_SINK_REACHED);
+    if (bad && st == FP_OK) {
+      set_error("problem %d: %s", i,
+                (r.err & ERR_LABEL)   ? "internal check: a relabel did not raise a label"
+                : (r.err & ERR_GUARD) ? "no convergence within the round or level bound"
+                                      : "internal check: a sink is reachable from the source side");
+      st = FP_ERR_DEVICE;
+    }
+    pb->inited = true;
+    pb->solved = !bad;
+    pb->st.flow_value = (int64_t)r.flow;
+    if (flows) flows[i] = bad ? -1 : (int64_t)r.flow;
+  }
+  if (ms)
+    *ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return st;
+}
+
 // The kept problems in unions that fit 31-bit ids (a handle holds fewer than
 // 2^30 pins and 2^31 network nodes), union_pins and a net-weight sum of at
 // most INT32_MAX, in index order.
@@ -525,6 +901,8 @@ static fp_status batch_union(fp_batch* b, const uint8_t* skip, int32_t with_cut,
 static fp_status batch_replay(fp_batch* b, const uint8_t* skip, int32_t with_cut, bool force_init,
                               hipStream_t s, int64_t* flows, float* ms) {
   if (b->cfg.schedule == kScheduleUnion) return batch_union(b, skip, with_cut, s, flows, ms);
+  if (b->cfg.schedule == kScheduleWorkgroups)
+    return batch_workgroups(b, skip, with_cut, s, flows, ms);
   return batch_concurrent(b, skip, with_cut, force_init, s, flows, ms);
 }
 
@@ -560,17 +938,18 @@ static bool cache_lookup(const char* path, const std::string& sig, fp_batch_conf
   FILE* f = fopen(path, "r");
   if (!f) return false;
   char line[512], key[256];
-  int g = 0, gr = 0, ns = 0, sc = 0;
+  int g = 0, gr = 0, ns = 0, sc = 0, wt = 0;
   bool found = false;
   while (fgets(line, sizeof(line), f)) {
     // lines of another layout are skipped
-    if (sscanf(line, "%255s v2 %d %d %d %d", key, &g, &gr, &ns, &sc) != 5) continue;
+    if (sscanf(line, "%255s v3 %d %d %d %d %d", key, &g, &gr, &ns, &sc, &wt) != 6) continue;
     if (sig == key) {  // the last entry for a signature wins
       *c = fp_batch_config{};
       c->group_lanes = g;
       c->gr_interval = gr;
       c->streams = ns;
       c->schedule = sc;
+      c->wg_threads = wt;
       found = batch_config_valid(*c);
     }
   }
@@ -582,8 +961,8 @@ static void cache_store(const char* path, const std::string& sig, const fp_batch
   if (!path) return;
   FILE* f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "%s v2 %d %d %d %d\n", sig.c_str(), c.group_lanes, c.gr_interval, c.streams,
-          c.schedule);
+  fprintf(f, "%s v3 %d %d %d %d %d\n", sig.c_str(), c.group_lanes, c.gr_interval, c.streams,
+          c.schedule, c.wg_threads);
   fclose(f);
 }
 
@@ -631,6 +1010,12 @@ fp_status tune_batch(fp_batch* b, hipStream_t s, const char* cache_path, fp_batc
     c.schedule = kScheduleUnion;
     fp_status st = trial(c);
     if (st) return st;
+    c.schedule = kScheduleWorkgroups;
+    for (int t : {256, 1024}) {
+      c.wg_threads = t;
+      st = trial(c);
+      if (st) return st;
+    }
   }
   const int lanes[3] = {4, 8, 16};
   const fp_batch_config conc = best;

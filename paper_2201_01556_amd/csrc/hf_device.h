@@ -65,6 +65,7 @@ enum : int32_t {
   ERR_INVARIANT = 4,     // debug invariant check failed
   ERR_SOURCE_REACHED = 8,  // sink-side BFS reached a source
   ERR_PIERCE_TERMINAL = 1024,  // a piercing vertex is a terminal of the other side
+  ERR_GUARD = 2048,  // a solve inside one workgroup passed its round or level bound
   ERR_BUILD_PIN = 16,
   ERR_BUILD_OFFSETS = 32,
   ERR_BUILD_WEIGHT = 64,

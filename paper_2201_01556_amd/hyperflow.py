@@ -90,7 +90,7 @@ class BatchConfig(ctypes.Structure):
         ("streams", ctypes.c_int32),
         ("schedule", ctypes.c_int32),
         ("union_pins", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 1),
+        ("wg_threads", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
