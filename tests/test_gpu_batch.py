@@ -113,7 +113,7 @@ def test_batch_relabel_intervals(hf, oracle_mod, gr):
     probs = [hf.FlowProblem.from_hypergraph(h) for h in hgs]
     try:
         _say(f"gr_interval={gr}")
-        for schedule in (1, 2):
+        for schedule in (1, 2, 3):
             with hf.FlowBatch(probs, with_cut=True, gr_interval=gr, schedule=schedule,
                               streams=5) as b:
                 flows = b.run(with_cut=True)
@@ -181,8 +181,9 @@ def test_batch_tune_and_cache(hf, oracle_mod):
             with hf.FlowBatch(probs, with_cut=True) as b:
                 cfg = b.tune(cache)
                 assert cfg["group_lanes"] in (4, 8, 16)
-                assert cfg["schedule"] in (1, 2)
+                assert cfg["schedule"] in (1, 2, 3)
                 assert 1 <= cfg["streams"] <= 64
+                assert cfg["wg_threads"] in (256, 1024)
                 assert b.config() == cfg
                 flows = b.run(with_cut=True)
                 assert list(flows) == [r.flow for r in refs]
@@ -308,7 +309,10 @@ def test_batch_errors(hf):
             hf.FlowBatch(probs, streams=65)
         assert ei.value.name == "FP_ERR_INVALID"
         with pytest.raises(hf.HyperflowError) as ei:
-            hf.FlowBatch(probs, schedule=3)
+            hf.FlowBatch(probs, schedule=4)
+        assert ei.value.name == "FP_ERR_INVALID"
+        with pytest.raises(hf.HyperflowError) as ei:
+            hf.FlowBatch(probs, schedule=3, wg_threads=512)
         assert ei.value.name == "FP_ERR_INVALID"
         with pytest.raises(hf.HyperflowError) as ei:
             hf.FlowBatch(probs, schedule=1, union_pins=-1)
