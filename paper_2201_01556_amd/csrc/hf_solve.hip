@@ -1118,6 +1118,7 @@ static fp_status flowcutter_run(fp_problem* pb, int32_t slice, hipStream_t s, in
   fp_cutter_result& r = f.r;
   r.status = 2;  // iteration limit unless a branch below decides
   int32_t done_here = 0;
+  bool side_written = false;  // the limit's result side, written before the last pierce
   for (int32_t n = 0; n < slice; ++n) {
     const int32_t it = ++f.it;
     ++done_here;
@@ -1283,6 +1284,17 @@ static fp_status flowcutter_run(fp_problem* pb, int32_t slice, hipStream_t s, in
         }
         done = true;
       } else {
+        if (n + 1 == slice) {
+          // the call stops at its limit after this iteration and returns
+          // this iteration's S_r: written now, before the pierce stamps the
+          // new sources with S_r's stamp
+          k_side_out<<<sweep_grid(pb->V), kThreads, 0, s>>>(g, ep_s, 0, vs);
+          he = hipGetLastError();
+          if (he == hipSuccess && mem_kind == 0)
+            he = hipMemcpyAsync(vside, vs, pb->V, hipMemcpyDeviceToHost, s);
+          if (he != hipSuccess) return hip_fail(he, "writing the FlowCutter side");
+          side_written = true;
+        }
         if (aug) r.augmenting++;
         else {
           f.grow = side;
@@ -1358,16 +1370,18 @@ static fp_status flowcutter_run(fp_problem* pb, int32_t slice, hipStream_t s, in
                         mem_kind == 0 ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s);
   } else {
     int invert = f.out_invert;
-    if (r.status == 2) {  // iteration limit: the last iteration's S_r (its stamps survive piercing)
+    if (r.status == 2) {  // iteration limit: the last iteration's S_r
       out.side = 0;
       out.source_weight = f.last_cs;
       out.sink_weight = total - f.last_cs;
       invert = 0;
     }
-    k_side_out<<<sweep_grid(pb->V), kThreads, 0, s>>>(g, f.out_ep, invert, vs);
-    he = hipGetLastError();
-    if (he == hipSuccess && mem_kind == 0)
-      he = hipMemcpyAsync(vside, vs, pb->V, hipMemcpyDeviceToHost, s);
+    if (!side_written) {
+      k_side_out<<<sweep_grid(pb->V), kThreads, 0, s>>>(g, f.out_ep, invert, vs);
+      he = hipGetLastError();
+      if (he == hipSuccess && mem_kind == 0)
+        he = hipMemcpyAsync(vside, vs, pb->V, hipMemcpyDeviceToHost, s);
+    }
   }
   if (he == hipSuccess) he = hipStreamSynchronize(s);
   if (he != hipSuccess) return hip_fail(he, "writing the FlowCutter side");

@@ -252,6 +252,30 @@ def test_flowcutter_kept_labels_checked(hf, oracle_mod, seed):
     assert res["augmenting"] > 0
 
 
+def test_flowcutter_limit_returns_last_source_side(hf, oracle_mod):
+    """A run stopped by its iteration limit returns the last iteration's
+    S_r, also when that iteration pierced on the source side (the pierced
+    vertex is not part of it): equal to the oracle's result at the same
+    limit, for limits ending on source and on sink pierces."""
+    hg = inputs.uniform_hypergraph(3)
+    c = np.random.default_rng(3).integers(1, 4, hg.num_vertices)
+    L = balance_limit(c.sum())
+    full = oracle_mod.flowcutter(hg, c, L, L, max_iterations=5000)
+    src = [i + 1 for i, t in enumerate(full.trace) if t[0] == 0][:2]
+    snk = [i + 1 for i, t in enumerate(full.trace) if t[0] == 1][:1]
+    assert src, "the run pierces on the source side"
+    for k in src + snk:
+        ref = oracle_mod.flowcutter(hg, c, L, L, max_iterations=k)
+        assert ref.status == "cap"
+        with hf.FlowProblem.from_hypergraph(hg) as p:
+            res, x, trace = p.flowcutter(c, L, L, max_iterations=k)
+        _say(f"limit {k}: last pierce on side {trace[-1][0]}")
+        assert res["status"] == "cap" and res["flow"] == ref.flow
+        assert [tuple(t) for t in trace] == [tuple(t) for t in ref.trace]
+        assert (x.astype(bool) == ref.vertex_side.astype(bool)).all(), k
+        assert oracle_mod.cut_weight(hg, x.astype(bool)) == res["flow"]
+
+
 def test_flowcutter_block_pairs_vs_oracle(hf, oracle_mod):
     """Region problems of a partitioned hypergraph, balance = the k-way
     bound on both blocks (s and t carry the rest of their blocks)."""
