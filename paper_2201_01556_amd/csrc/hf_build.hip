@@ -604,11 +604,11 @@ fp_status export_state(fp_problem* pb, hipStream_t s, int32_t* f_in, int32_t* f_
 
 void release_problem(fp_problem* pb) {
   if (!pb) return;
-  for (auto& t : pb->pending) {
-    hipEventDestroy(t.a);
-    hipEventDestroy(t.b);
+  for (auto& t : pb->pending) {  // recorded work has finished or is dropped with the handle
+    event_pool_put(pb->device, t.a);
+    event_pool_put(pb->device, t.b);
   }
-  for (auto e : pb->free_events) hipEventDestroy(e);
+  pb->pending.clear();
   pool_release(pb->device, pb->pool, pb->pool_bytes);
   if (pb->cw) hipFree(pb->cw);
   if (pb->fc_mem) hipFree(pb->fc_mem);

@@ -94,7 +94,6 @@ struct fp_problem {
   fp_stats st{};
   // profiling
   std::vector<hf::Timer> pending;
-  std::vector<hipEvent_t> free_events;
   int64_t k_launches[hf::KK_COUNT] = {};
   double k_ms[hf::KK_COUNT] = {};
   unsigned long long bytes_at_sync[hf::KC_N] = {};
@@ -185,5 +184,7 @@ void release_cached_memory();
 void prof_begin(fp_problem* pb, int kind, hipStream_t s, Timer* t);
 void prof_end(fp_problem* pb, Timer* t, hipStream_t s);
 void prof_collect(fp_problem* pb);
+// timing events go back to the process-wide pool of their device
+void event_pool_put(int device, hipEvent_t e);
 
 }  // namespace hf

@@ -10,6 +10,11 @@
 #include <cstdlib>
 #include <cstring>
 
+#include <hip/hip_ext.h>
+
+#include <map>
+#include <mutex>
+
 #include "hf_host.h"
 
 namespace hf {
@@ -366,6 +371,26 @@ static int sweep_blocks(long long n) {
   return (int)b;
 }
 
+static hipEvent_t get_event(fp_problem* pb);
+
+// Launch of the reverse-BFS level kernel.  With its timing on, the start and
+// stop events are recorded by the dispatch itself (hipExtLaunchKernel): the
+// time is the kernel's own, and no marker packets sit between the launches
+// of a batch of levels.
+template <typename... KArgs, typename... Args>
+static void launch_timed(fp_problem* pb, hipStream_t s, void (*kernel)(KArgs...), dim3 grid,
+                         dim3 block, Args... args) {
+  const bool on = pb->opt.profile == 1 || pb->opt.profile == 2;
+  hipEvent_t a = on ? get_event(pb) : nullptr;
+  hipEvent_t b = on ? get_event(pb) : nullptr;
+  if (!a || !b) {
+    hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+    return;
+  }
+  hipExtLaunchKernelGGL(kernel, grid, block, 0, s, a, b, 0, args...);
+  pb->pending.push_back(Timer{KK_BFS_REV, a, b});
+}
+
 struct Launch {
   fp_problem* pb;
   hipStream_t s;
@@ -444,12 +469,10 @@ static void launch_levels(fp_problem* pb, hipStream_t s, int ep, int ep_tmp, int
         if (2 * p < pull_min) pmin = off;
       }
       const bool xcd = g.xbuf && g.bfs_flat && !g.bfs_arc;
-      {
-        Launch L(pb, s, KK_BFS_REV);
-        if (xcd) k_bfs_rev_xflat<G><<<grid, kBlock, 0, s>>>(g, lv, bmin, pmin, cap);
-        else if (g.bfs_flat && !g.bfs_arc) k_bfs_rev_flat<G><<<grid, kBlock, 0, s>>>(g, lv, bmin, pmin, cap);
-        else k_bfs_rev<G><<<grid, kBlock, 0, s>>>(g, lv, bmin, pmin, cap);
-      }
+      if (xcd) launch_timed(pb, s, k_bfs_rev_xflat<G>, dim3(grid), dim3(kBlock), g, lv, bmin, pmin, cap);
+      else if (g.bfs_flat && !g.bfs_arc)
+        launch_timed(pb, s, k_bfs_rev_flat<G>, dim3(grid), dim3(kBlock), g, lv, bmin, pmin, cap);
+      else launch_timed(pb, s, k_bfs_rev<G>, dim3(grid), dim3(kBlock), g, lv, bmin, pmin, cap);
       if (xcd && bmin != off) {
         Launch L(pb, s, KK_BFS_REV);
         k_bfs_slices<<<kSlices * 64, kBlock, 0, s>>>(g, lv, bmin, pmin, grid);
@@ -1483,11 +1506,27 @@ int kernel_kind_class(int k) {
   }
 }
 
+// Timing events are kept per device for the whole process and shared by
+// every handle: a handle's run records a few hundred of them, and creating
+// and destroying that many per handle costs more than the kernels they time.
+static std::mutex g_event_mu;
+static std::map<int, std::vector<hipEvent_t>> g_events;
+
+void event_pool_put(int device, hipEvent_t e) {
+  if (!e) return;
+  std::lock_guard<std::mutex> lock(g_event_mu);
+  g_events[device].push_back(e);
+}
+
 static hipEvent_t get_event(fp_problem* pb) {
-  if (!pb->free_events.empty()) {
-    hipEvent_t e = pb->free_events.back();
-    pb->free_events.pop_back();
-    return e;
+  {
+    std::lock_guard<std::mutex> lock(g_event_mu);
+    std::vector<hipEvent_t>& pool = g_events[pb->device];
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
   }
   hipEvent_t e;
   if (hipEventCreate(&e) != hipSuccess) return nullptr;
@@ -1513,8 +1552,8 @@ void prof_collect(fp_problem* pb) {
       pb->k_ms[t.kind] += ms;
       pb->k_launches[t.kind]++;
     }
-    pb->free_events.push_back(t.a);
-    pb->free_events.push_back(t.b);
+    event_pool_put(pb->device, t.a);
+    event_pool_put(pb->device, t.b);
   }
   pb->pending.clear();
 }
