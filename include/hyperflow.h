@@ -265,9 +265,8 @@ fp_status flow_batch_solve(fp_problem *const *problems, int32_t count,
  *                global relabel and, with with_cut, its source side, with
  *                workgroup barriers only (no launches or host round trips
  *                per problem: suited to many small problems).  The relabel
- *                interval is gr_interval, else the first problem's interval
- *                for single-workgroup rounds; relabel work and stale-flow
- *                limits are the first problem's options.  Every solved
+ *                interval is gr_interval (0 = 16); relabel work and
+ *                stale-flow limits are the first problem's options.  Every solved
  *                handle then behaves as after maxflow_solve; round budgets
  *                and debug checks do not apply.
  */
@@ -278,8 +277,8 @@ typedef struct {
                             0 = 8                                          */
   int32_t reserved0;     /* must be 0                                       */
   int32_t gr_interval;   /* rounds between global relabels, -1 = off;
-                            0 = 8 for the union, each problem's own option
-                            for the workers                                */
+                            0 = 8 for the union, 16 for the workgroups,
+                            each problem's own option for the workers      */
   int32_t reserved1;     /* must be 0                                       */
   int32_t streams;       /* workers schedule: concurrent workers (streams),
                             1..64; 0 = 4                                   */
@@ -289,7 +288,7 @@ typedef struct {
                             union (bounds its device memory); 0 = as many
                             as 31-bit ids allow                            */
   int32_t wg_threads;    /* workgroups schedule: threads per workgroup,
-                            256 or 1024; 0 = 256                           */
+                            256 or 1024; 0 = 1024                          */
 } fp_batch_config;
 
 /*

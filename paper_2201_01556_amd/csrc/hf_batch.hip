@@ -66,8 +66,11 @@ static fp_batch_config resolve_batch_config(const fp_batch_config* c) {
   if (r.schedule == 0) r.schedule = kScheduleUnion;
   if (r.group_lanes == 0) r.group_lanes = 8;
   if (r.gr_interval == 0 && r.schedule == kScheduleUnion) r.gr_interval = 8;
+  // one workgroup per problem: relabel every 16 rounds (512 problems of 2,000
+  // vertices: 11.9 ms against 14.9 at 64; the 500 block pairs: 74 against 103)
+  if (r.gr_interval == 0 && r.schedule == kScheduleWorkgroups) r.gr_interval = 16;
   if (r.streams == 0) r.streams = 4;
-  if (r.wg_threads == 0) r.wg_threads = 256;
+  if (r.wg_threads == 0) r.wg_threads = 1024;
   return r;
 }
 
@@ -709,14 +712,10 @@ __global__ void k_wg_reset(int32_t* next) {
   if (threadIdx.x == 0) *next = 0;
 }
 
-// Rounds between global relabels inside one workgroup: the configuration's,
-// else the problem's interval for rounds of the single-workgroup loop
-// (every round of this schedule is such a round).
+// Rounds between global relabels inside one workgroup (the resolved
+// configuration's; -1 turns them off).
 static int32_t wg_interval(const fp_batch* b) {
-  if (b->cfg.gr_interval != 0) return b->cfg.gr_interval < 0 ? 0 : b->cfg.gr_interval;
-  const fp_options& o = b->pbs[0]->opt;
-  if (o.tail_gr_interval > 0) return o.tail_gr_interval;
-  return o.tail_gr_interval < 0 ? o.gr_interval : 4 * o.gr_interval;
+  return b->cfg.gr_interval < 0 ? 0 : b->cfg.gr_interval;
 }
 
 template <int G, int B>
@@ -986,9 +985,14 @@ fp_status tune_batch(fp_batch* b, hipStream_t s, const char* cache_path, fp_batc
   float best_ms = 1e30f;
   auto trial = [&](const fp_batch_config& c) -> fp_status {
     b->cfg = c;
-    float ms = 0.f;
-    fp_status st = batch_replay(b, nullptr, 0, true, s, nullptr, &ms);
-    if (st) return st;
+    // the better of two runs (the first of a schedule also sets it up)
+    float ms = 1e30f;
+    for (int rep = 0; rep < 2; ++rep) {
+      float t = 0.f;
+      fp_status st = batch_replay(b, nullptr, 0, true, s, nullptr, &t);
+      if (st) return st;
+      ms = std::min(ms, t);
+    }
     if (ms < best_ms) {
       best_ms = ms;
       best = c;
