@@ -344,7 +344,8 @@ def _cut_weight(hg, side):
 @pytest.mark.slow
 def test_batch_full_block_pairs_vs_oracle(hf, oracle_mod):
     """The 2M-vertex, 10M-pin, k=64 instance as the benchmark runs it: all
-    500 problems in one union plan with the cut, every problem's flow value,
+    500 problems in one union plan with the cut, then in one persistent
+    launch with a workgroup per problem, every problem's flow value,
     vertex side and net side compared with the oracle (run on a process
     pool), and every side a minimum cut certificate (cut weight = flow <=
     cut before)."""
@@ -357,18 +358,21 @@ def test_batch_full_block_pairs_vs_oracle(hf, oracle_mod):
     _say("creating on the device")
     probs = [hf.FlowProblem.from_hypergraph(h, device=True) for h in hgs]
     try:
-        with hf.FlowBatch(probs, with_cut=True, schedule=1, group_lanes=8,
-                          gr_interval=8) as b:
-            _say("union solve + cut")
-            flows = b.run(with_cut=True)
-            torch.cuda.synchronize()
-            for i, (h, (F, rvs, rns)) in enumerate(zip(hgs, refs)):
-                vs, ns = b.sides(i)
-                assert flows[i] == F, f"problem {i}: flow {flows[i]} != oracle {F}"
-                assert (vs.astype(bool) == rvs.astype(bool)).all(), f"problem {i}: vertex side"
-                assert (ns == rns).all(), f"problem {i}: net side"
-                assert _cut_weight(h, vs) == flows[i], f"problem {i}"
-                assert 0 <= flows[i] <= h.meta["cut_before"]
+        # the union, and the workgroups schedule as the tuner keeps it here
+        for cfg in (dict(schedule=1, group_lanes=8, gr_interval=8),
+                    dict(schedule=3, group_lanes=4, gr_interval=8)):
+            with hf.FlowBatch(probs, with_cut=True, **cfg) as b:
+                _say(f"solve + cut, {cfg}")
+                flows = b.run(with_cut=True)
+                torch.cuda.synchronize()
+                for i, (h, (F, rvs, rns)) in enumerate(zip(hgs, refs)):
+                    vs, ns = b.sides(i)
+                    assert flows[i] == F, f"{cfg} problem {i}: flow {flows[i]} != oracle {F}"
+                    assert (vs.astype(bool) == rvs.astype(bool)).all(), \
+                        f"{cfg} problem {i}: vertex side"
+                    assert (ns == rns).all(), f"{cfg} problem {i}: net side"
+                    assert _cut_weight(h, vs) == flows[i], f"{cfg} problem {i}"
+                    assert 0 <= flows[i] <= h.meta["cut_before"]
     finally:
         for p in probs:
             p.close()
