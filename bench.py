@@ -89,9 +89,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the max-flow path is single-device, see DESIGN.md for how it would shard",
-              file=sys.stderr)
+        print(f"bench.py: the max-flow path runs on one GPU (asked for --gpus {args.gpus}); "
+              "no run on several GPUs is measured", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -179,6 +178,7 @@ def main():
     ms_per_step = 1e3 * total / args.steps
     value = P * args.steps / total
 
+    step_traffic = measured_step_traffic()
     roofline = None
     kernels = None
     if profile:
@@ -296,6 +296,11 @@ def main():
         # whole step: algorithmic bytes of all counted kernels over the step time
         "step_alg_bytes": st["alg_bytes"],
         "step_alg_GBps": round(st["alg_bytes"] / (ms_per_step / 1e3) / 1e9, 3),
+        # whole step: counter bytes of every kernel of a profiled step (L2 to
+        # fabric, so an upper bound of HBM traffic) over this run's step time
+        "step_traffic": (None if step_traffic is None else dict(
+            bytes=step_traffic, GBps=round(step_traffic / (ms_per_step / 1e3) / 1e9, 1),
+            source="profiles/zipf1M_bfs_rev_traffic.md")),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity_vs_oracle": parity,
@@ -421,11 +426,10 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, calibrated by a plain copy), or None when the
-    kernel sources changed since the counters were taken."""
-    if kernel != "bfs_rev" or not os.path.exists(TRAFFIC_FILE):
+def _traffic_values():
+    """Machine-readable lines of the committed counter summary, or None when
+    the kernel sources changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
     with open(TRAFFIC_FILE) as f:
@@ -434,6 +438,26 @@ def measured_traffic(kernel):
                 k, v = line.strip()[2:].split(":", 1)
                 vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return vals
+
+
+def measured_step_traffic():
+    """Counter bytes (FETCH_SIZE + WRITE_SIZE, calibrated by a plain copy)
+    of every kernel of one whole step, or None (see _traffic_values)."""
+    vals = _traffic_values()
+    try:
+        return float(vals["step_traffic_bytes"]) if vals else None
+    except (KeyError, ValueError):
+        return None
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated by a plain copy), or None when the
+    kernel sources changed since the counters were taken."""
+    vals = _traffic_values() if kernel == "bfs_rev" else None
+    if not vals:
         return None
     try:
         return float(vals["traffic_bytes_per_launch"])

@@ -1102,8 +1102,6 @@ fp_status terminals_problem(fp_problem* pb, hipStream_t s, int32_t mem_kind, uin
   return FP_OK;
 }
 
-// Up to `slice` more iterations of the FlowCutter run held in pb->fc (see
-// flowcutter_problem); trace[0 .. slice) receives this call's iterations.
 // The weights of S_r and T_r, the smallest vertex outside both and the
 // piercing candidates of the lighter side, into the control block (read
 // after the next round trip).  Both kernels fold workgroup results into the
@@ -1115,6 +1113,8 @@ static void fc_side_stats(fp_problem* pb, hipStream_t s, int ep_s, int ep_t) {
   k_fc_pick<<<grid, kThreads, 0, s>>>(pb->dev, ep_s, ep_t);
 }
 
+// Up to `slice` more iterations of the FlowCutter run held in pb->fc (see
+// flowcutter_problem); trace[0 .. slice) receives this call's iterations.
 static fp_status flowcutter_run(fp_problem* pb, int32_t slice, hipStream_t s, int32_t mem_kind,
                                 uint8_t* vside, fp_cutter_result* res, fp_cutter_step* trace) {
   Dev& g = pb->dev;
