@@ -237,6 +237,7 @@ fp_status flow_problem_reset(fp_problem* problem) {
   }
   problem->inited = false;
   problem->solved = false;
+  problem->labels_exact = false;
   return FP_OK;
 }
 

@@ -225,6 +225,7 @@ static fp_status batch_concurrent(fp_batch* b, const uint8_t* skip, int32_t with
       if (force_init) {
         pb->inited = false;
         pb->solved = false;
+        pb->labels_exact = false;
       }
       const fp_options saved = pb->opt;
       pb->opt.group_lanes = cfg.group_lanes;
@@ -849,6 +850,7 @@ static fp_status batch_workgroups(fp_batch* b, const uint8_t* skip, int32_t with
     }
     pb->inited = true;
     pb->solved = !bad;
+    pb->labels_exact = false;
     pb->st.flow_value = (int64_t)r.flow;
     if (flows) flows[i] = bad ? -1 : (int64_t)r.flow;
   }

@@ -1942,6 +1942,47 @@ __device__ void phase_sink_seed(const Dev& g, int ep, int tile0, int tstride, ld
   bq_flush(q);
 }
 
+// The same sink side from exact labels of the capped network (the labels
+// of a global relabel that found no active node): a node reaches a sink in
+// the capped residual network exactly when its label is below N, and that
+// set D lies in T_r, the uncapped network having every residual arc of the
+// capped one.  The two networks differ only in the pin arcs u -> e_in,
+// residual in the uncapped network even when saturated, so a residual path
+// from outside D enters D by such an arc: its tail u (label N or more, arc
+// saturated into an e_in of D) is a seed, and the reverse BFS of the
+// uncapped network continues from the seeds through the nodes outside D.
+// Stamps D with ep and lists the seeds as level 0 (counters clear).  A
+// source's pin arcs carry no flow, so none qualifies; one that did would
+// reach a sink (ERR_SOURCE_REACHED).
+__device__ void phase_sink_seed_labels(const Dev& g, int ep, int tile0, int tstride,
+                                       lds_int* lds) {
+  const int ntiles = sweep_tiles(g);
+  for (int tile = tile0; tile < ntiles; tile += tstride) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int v = (2 * tile + j) * blockDim.x + threadIdx.x;
+      if (v < g.N && g.d[v] < g.N) g.stamp[v] = ep;
+    }
+  }
+  const BlockQ q = bq_bind(lds, g.ctl->bcnt[0], g.list[0]);
+  const int ptiles = (g.P + (int)blockDim.x - 1) / (int)blockDim.x;
+  for (int tile = tile0; tile < ptiles; tile += tstride) {
+    const int p = tile * (int)blockDim.x + (int)threadIdx.x;
+    int u = 0;
+    bool seed = false;
+    if (p < g.P && g.fpin[2 * p] == 0) {  // u -> e_in saturated (flow w(e))
+      u = g.pin_v[p];
+      if (g.d[g.NB + 2 * g.pin_net[p]] < g.N && g.d[u] >= g.N) {
+        if (g.role[u] == 1) atomicOr(&g.ctl->err, ERR_SOURCE_REACHED);
+        else seed = stamp_first(g, u, ep);
+      }
+    }
+    qpush(g, q, u, seed);
+    bq_tile_end(q, (int)blockDim.x);
+  }
+  bq_flush(q);
+}
+
 __device__ void phase_bfs_sink_lb(const Dev& g, int level, int ep, int tile0, int tstride, int kc,
                                   lds_int* lds) {
   const int c3 = level % 3, n3 = (level + 1) % 3, z3 = (level + 2) % 3;

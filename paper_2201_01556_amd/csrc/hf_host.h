@@ -88,6 +88,7 @@ struct fp_problem {
   bool inited = false;
   bool solved = false;
   bool warm_labels = false;  // the labels are valid for the next solve (after a source pierce)
+  bool labels_exact = false;  // the labels are exact distances of the current flow (a solve ended)
   int32_t* cw = nullptr;     // vertex weights of the last FlowCutter run (device)
   void* fc_mem = nullptr;    // FlowCutter scratch: candidate flags, tile counts, best side
   hf::FcRun fc;

@@ -192,6 +192,11 @@ __global__ void __launch_bounds__(kBlock) k_sink_seed(Dev g, int ep) {
   phase_sink_seed(g, ep, blockIdx.x, gridDim.x, lds);
 }
 
+__global__ void __launch_bounds__(kBlock) k_sink_seed_labels(Dev g, int ep) {
+  HF_QUEUE_LDS;
+  phase_sink_seed_labels(g, ep, blockIdx.x, gridDim.x, lds);
+}
+
 __global__ void k_reset_bfs(Dev g) { phase_reset_bfs(g); }
 
 __global__ void k_seed_vertex(Dev g, int p) { phase_seed_vertex(g, p); }
@@ -620,6 +625,7 @@ static fp_status solve_impl(fp_problem* pb, hipStream_t s, int64_t* flow) {
   // is confirmed by a global relabel as usual.  Otherwise it starts with one.
   const bool warm = pb->warm_labels && pb->inited;
   pb->warm_labels = false;
+  pb->labels_exact = false;
   if (warm) {
     {
       Launch L(pb, s, KK_GATHER);
@@ -774,6 +780,7 @@ static fp_status solve_impl(fp_problem* pb, hipStream_t s, int64_t* flow) {
   pb->st.relabels = (int64_t)pb->ctl_h->relabels;
   pb->st.flow_value = (int64_t)pb->ctl_h->flow;
   pb->solved = true;
+  pb->labels_exact = true;  // the loop ends right after a global relabel
   *flow = (int64_t)pb->ctl_h->flow;
   return FP_OK;
 }
@@ -877,8 +884,11 @@ static fp_status sink_side_stamps(fp_problem* pb, hipStream_t s, int* ep_out) {
   const int ep = pb->epoch++;
   k_reset_bfs<<<1, 64, 0, s>>>(g);
   {
+    // after a solve the labels give most of T_r at once (phase_sink_seed_labels)
     Launch L(pb, s, KK_CUT_SEED);
-    k_sink_seed<<<sweep_blocks(g.N), kBlock, 0, s>>>(g, ep);
+    if (pb->labels_exact)
+      k_sink_seed_labels<<<sweep_blocks(std::max(g.N, g.P)), kBlock, 0, s>>>(g, ep);
+    else k_sink_seed<<<sweep_blocks(g.N), kBlock, 0, s>>>(g, ep);
   }
   int levels = 0;
   fp_status st = run_bfs<G>(pb, s, ep, 2, &levels);
@@ -1022,6 +1032,7 @@ fp_status sink_side_problem(fp_problem* pb, hipStream_t s, int32_t mem_kind, uin
 static fp_status apply_pierce(fp_problem* pb, hipStream_t s, int side, int ep,
                               bool seed_growth = false) {
   Dev& g = pb->dev;
+  pb->labels_exact = false;  // flows and terminals change
   if (side == 0 && seed_growth) {
     k_reset_bfs<<<1, 64, 0, s>>>(g);
     const long long tiles = ((long long)g.V + kBlock - 1) / kBlock;
