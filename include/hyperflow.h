@@ -322,8 +322,10 @@ fp_status flow_batch_run(fp_batch *batch, const uint8_t *skip, int32_t with_cut,
 
 /*
  * flow_batch_tune: time candidate configurations (schedule and number of
- * streams, lanes per node, global relabel interval) on this batch, each run
- * from the zero flow, and keep the fastest.  With a cache_path (or NULL), a
+ * streams or threads per workgroup, lanes per node, global relabel
+ * interval) on this batch, each run from the zero flow (the better of two
+ * runs; with the source sides when the plan has vertex_sides), and keep the
+ * fastest.  With a cache_path (or NULL), a
  * configuration stored under the batch's signature (device, problem count,
  * total pins, total network nodes) is reused without timing, and a newly
  * timed one is appended.  Ends with a run of the chosen configuration (with

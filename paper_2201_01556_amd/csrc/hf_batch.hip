@@ -987,11 +987,13 @@ fp_status tune_batch(fp_batch* b, hipStream_t s, const char* cache_path, fp_batc
   float best_ms = 1e30f;
   auto trial = [&](const fp_batch_config& c) -> fp_status {
     b->cfg = c;
-    // the better of two runs (the first of a schedule also sets it up)
+    // the better of two runs (the first of a schedule also sets it up), with
+    // the source sides when the plan has buffers for them (the union always
+    // extracts them to split its flow; the other schedules only on request)
     float ms = 1e30f;
     for (int rep = 0; rep < 2; ++rep) {
       float t = 0.f;
-      fp_status st = batch_replay(b, nullptr, 0, true, s, nullptr, &t);
+      fp_status st = batch_replay(b, nullptr, b->has_vs ? 1 : 0, true, s, nullptr, &t);
       if (st) return st;
       ms = std::min(ms, t);
     }
