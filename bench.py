@@ -405,11 +405,41 @@ def bench_small(args, hyperflow, inputs, torch, np):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
     n = reps * len(hgs)
-    return dict(workload="uniform single flows: 2000 vertices, 3000 nets, sizes U{2..8}, "
-                         "weights U{1..4}, 100 sources, 100 sinks, seeds 0..9",
-                us_per_solve=round(1e6 * dt / n, 1), solves_per_s=round(n / dt, 1),
-                pins_per_s=round(sum(h.num_pins for h in hgs) * reps / dt, 1),
-                flows=flows[:len(hgs)])
+    out = dict(workload="uniform single flows: 2000 vertices, 3000 nets, sizes U{2..8}, "
+                        "weights U{1..4}, 100 sources, 100 sinks, seeds 0..9",
+               us_per_solve=round(1e6 * dt / n, 1), solves_per_s=round(n / dt, 1),
+               pins_per_s=round(sum(h.num_pins for h in hgs) * reps / dt, 1),
+               flows=flows[:len(hgs)])
+    # many such flows at once: the union schedule against the workgroups
+    # schedule (one persistent launch, a workgroup per problem), flows and
+    # source sides included, best of three runs each
+    many = [inputs.uniform_hypergraph(sd) for sd in range(512)]
+    probs = [hyperflow.FlowProblem.from_hypergraph(h, device=True) for h in many]
+    try:
+        res = {}
+        for name, cfg in (("union", dict(schedule=1)), ("workgroups", dict(schedule=3))):
+            with hyperflow.FlowBatch(probs, with_cut=True, **cfg) as b:
+                b.run(with_cut=True)
+                torch.cuda.synchronize()
+                best = None
+                for _ in range(3):
+                    t = time.perf_counter()
+                    f = b.run(with_cut=True)
+                    torch.cuda.synchronize()
+                    best = min(best or 1e9, time.perf_counter() - t)
+                res[name] = (f, best)
+        out["batch_512"] = dict(
+            workload="512 of these flows (seeds 0..511) in one batch plan with the source sides",
+            union_ms=round(1e3 * res["union"][1], 2),
+            workgroups_ms=round(1e3 * res["workgroups"][1], 2),
+            workgroups_solves_per_s=round(512 / res["workgroups"][1], 1),
+            flows_equal=bool((res["union"][0] == res["workgroups"][0]).all()),
+            flows_match_single=[int(x) for x in res["workgroups"][0][:len(hgs)]] ==
+            flows[:len(hgs)])
+    finally:
+        for p_ in probs:
+            p_.close()
+    return out
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "zipf1M_bfs_rev_traffic.md")
