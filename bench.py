@@ -614,14 +614,49 @@ def _pairs(inputs, seed, max_problems):
 
 def _gen_pairs(job):
     """One seed's block-pair problems, built in a worker process (one
-    builder thread each)."""
-    kind, seed, nprob = job
+    builder thread each); with `graph`, also the partitioned hypergraph they
+    come from (for the device construction of the same problems)."""
+    kind, seed, nprob, graph = job
     from paper_2201_01556_amd import inputs
     gen = inputs.planted_block_pair_problems if kind == "planted" else inputs.block_pair_problems
     bp = gen(seed, max_problems=nprob, threads=1)
     for h in bp.problems:
         h.meta.pop("gid", None)
-    return seed, bp.problems
+    g = None
+    if graph:
+        hg = bp.hypergraph
+        g = dict(num_vertices=hg.num_vertices, net_offsets=hg.net_offsets, pins=hg.pins,
+                 net_weights=hg.net_weights, vertex_weights=hg.vertex_weights, block=bp.block,
+                 block_weights=bp.block_weights, k=int(len(bp.block_weights)))
+    return seed, bp.problems, g
+
+
+def _device_pipeline(hyperflow, inputs, torch, np, graph, pairs, cuts, scorer, theta):
+    """Plain and learned schedules on device-built regions of one seed:
+    (plain flows, learned flows with -1 for skipped pairs, plain seconds,
+    learned seconds)."""
+    dv = [torch.from_numpy(np.ascontiguousarray(graph[k])).to("cuda")
+          for k in ("net_offsets", "pins", "net_weights", "vertex_weights", "block")]
+    caps = inputs.region_caps(graph["block_weights"], pairs, cuts)
+    torch.cuda.synchronize()
+
+    def run(learned):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        with hyperflow.FlowRegions(graph["num_vertices"], *dv, graph["k"], pairs, caps,
+                                   merge_identical=False) as rg:
+            skip = None
+            if learned and scorer is not None:
+                skip = (scorer.predict(rg.features(cuts, graph["block_weights"])) <
+                        theta).astype(np.uint8)
+            f = rg.solve(skip)
+        torch.cuda.synchronize()
+        return f, time.perf_counter() - t
+
+    run(False)  # first construction of this shape: allocations
+    f_plain, t_plain = run(False)
+    f_learn, t_learn = run(True)
+    return f_plain, f_learn, t_plain, t_learn
 
 
 # thresholds that give up this fraction of the improving training problems
@@ -666,17 +701,19 @@ def bench_learned(args, hyperflow, inputs, torch, np, config):
         t0 = time.perf_counter()
         Xtr, ytr = [], []
         ev = dict(problems=0, positive=0, plain_s=0.0, learned_s=0.0, rule_s=0.0, skipped=0,
-                  missed_gain=0, total_gain=0, rule_skipped=0, rule_missed_gain=0)
+                  missed_gain=0, total_gain=0, rule_skipped=0, rule_missed_gain=0,
+                  dev_plain_s=0.0, dev_learned_s=0.0, dev_equal=True)
         sc = None
         theta, usable, thetas = 1.0, False, {}
         try:
             with cf.ProcessPoolExecutor(max_workers=workers,
                                         mp_context=mp.get_context("spawn")) as ex:
-                jobs = [(kind, sd, args.batch_problems) for sd in range(K)]
-                for seed, hgs in ex.map(_gen_pairs, jobs):
+                jobs = [(kind, sd, args.batch_problems, sd >= n_train) for sd in range(K)]
+                for seed, hgs, graph in ex.map(_gen_pairs, jobs):
                     feats = inputs.scorer_features(hgs)
                     cb = np.array([h.meta["cut_before"] for h in hgs], dtype=np.int64)
                     pair_cut = np.array([h.meta["cut"] for h in hgs], dtype=np.int64)
+                    pairs_l = [h.meta["pair"] for h in hgs]
                     probs = [hyperflow.FlowProblem.from_hypergraph(h, device=True) for h in hgs]
                     del hgs
                     torch.cuda.synchronize()
@@ -719,6 +756,21 @@ def bench_learned(args, hyperflow, inputs, torch, np, config):
                                 ev["total_gain"] += int(gain[gain > 0].sum())
                                 ev["rule_skipped"] += int(rule.sum())
                                 ev["rule_missed_gain"] += int(gain[(rule > 0) & (gain > 0)].sum())
+                                if graph is not None:
+                                    # the same schedules end to end on the device:
+                                    # regions built there (inputs resident), then
+                                    # all pairs solved, or the scorer on the
+                                    # regions' own features and the kept pairs
+                                    f_dev, f_learn, t_dp, t_dl = _device_pipeline(
+                                        hyperflow, inputs, torch, np, graph, pairs_l, pair_cut,
+                                        sc if usable else None, theta)
+                                    ev["dev_plain_s"] += t_dp
+                                    ev["dev_learned_s"] += t_dl
+                                    kept = f_learn >= 0
+                                    ev["dev_equal"] = ev["dev_equal"] and bool(
+                                        (f_dev == flows).all() and
+                                        (f_learn[kept] == flows[kept]).all() and
+                                        (~kept == (skip > 0)).all())
                                 _log(f"  {kind} eval seed {seed}: {int((gain > 0).sum())} "
                                      f"improve, skipped {int(skip.sum())} of {len(gain)}")
                     finally:
@@ -771,6 +823,14 @@ def bench_learned(args, hyperflow, inputs, torch, np, config):
                    skip_rate=round(ev["skipped"] / max(n, 1), 4),
                    missed_gain=ev["missed_gain"], total_gain=ev["total_gain"],
                    missed_gain_pct=round(100.0 * ev["missed_gain"] / max(ev["total_gain"], 1), 3),
+                   device_pipeline=dict(
+                       note="eval seeds: regions built on the device from the resident "
+                            "hypergraph, then all pairs solved (plain) or the scorer on the "
+                            "regions' device features and the kept pairs (learned)",
+                       plain_value=round(n / ev["dev_plain_s"], 2) if ev["dev_plain_s"] else None,
+                       learned_value=(round(n / ev["dev_learned_s"], 2)
+                                      if ev["dev_learned_s"] else None),
+                       flows_and_skips_equal_host_built=ev["dev_equal"]),
                    value=round(n / ev["learned_s"], 2) if ev["learned_s"] else None,
                    plain_value=round(n / ev["plain_s"], 2) if ev["plain_s"] else None,
                    rule_value=round(n / ev["rule_s"], 2) if ev["rule_s"] else None,
