@@ -22,6 +22,7 @@ namespace hf {
 constexpr int kThreads = 256;  // plain element-wise kernels
 constexpr int kBlock = 1024;   // frontier, sweep and single-workgroup kernels
 constexpr int kFcGrid = 128;   // FlowCutter weight and candidate sweeps
+constexpr int kLoopBlock = 512;  // the single-workgroup round loop (1024 threads spill 48 bytes a lane)
 constexpr int kMaxFrontierBlocks = 512;
 static_assert(kMaxFrontierBlocks <= kMaxSliceGroups, "one slice segment per scan workgroup");
 constexpr int kMaxSweepBlocks = 512;
@@ -294,10 +295,12 @@ __global__ void __launch_bounds__(kThreads) k_check(Dev g) {
 // wave writes between the barrier and the test, so every wave takes the same
 // decision.
 template <int G>
-__global__ void __launch_bounds__(kBlock) k_round_loop(Dev g, int epoch0, int max_rounds, int cap,
-                                                       unsigned long long relabel_limit,
-                                                       int stale_limit) {
-  HF_QUEUE_LDS;
+__global__ void __launch_bounds__(kLoopBlock) k_round_loop(Dev g, int epoch0, int max_rounds,
+                                                           int cap,
+                                                           unsigned long long relabel_limit,
+                                                           int stale_limit) {
+  __shared__ int32_t hf_bq[lds_words(kLoopBlock)];
+  lds_int* const lds = (lds_int*)hf_bq;
   int epoch = epoch0;
   int r = 0;
   int why = 0;
@@ -703,7 +706,7 @@ static fp_status solve_impl(fp_problem* pb, hipStream_t s, int64_t* flow) {
       const int stale_left = stale_limit > 0 ? (int)std::max<long long>(1, stale_limit - stale) : 0;
       {
         Launch L(pb, s, KK_ROUND_LOOP);
-        k_round_loop<G><<<1, kBlock, 0, s>>>(g, pb->epoch, (int)max_rounds, cap,
+        k_round_loop<G><<<1, kLoopBlock, 0, s>>>(g, pb->epoch, (int)max_rounds, cap,
                                                   rel_at_gr + budget, stale_left);
       }
       st = sync_ctl(pb, s, "loop");
