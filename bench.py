@@ -80,6 +80,10 @@ def main():
     ap.add_argument("--gather-probe", type=int, default=0, metavar="READS",
                     help="only run one gather of READS random 4-byte words (counter "
                          "calibration for scattered reads) and exit")
+    ap.add_argument("--gr-interval", type=int, default=0,
+                    help="device-wide rounds between global relabels (0: the library default)")
+    ap.add_argument("--tail-gr-interval", type=int, default=0,
+                    help="single-workgroup rounds between global relabels (0: the default)")
     ap.add_argument("--relabel-blocking", type=int, default=0,
                     help="1: the blocking variant of the round (a node pushed to does not "
                          "relabel in that round)")
@@ -145,7 +149,9 @@ def main():
     def step(profile):
         opts = hyperflow.Options(profile=profile, bfs_flat=args.bfs_flat,
                                  bfs_marks=args.bfs_marks,
-                                 relabel_blocking=args.relabel_blocking, bfs_xcd=args.bfs_xcd)
+                                 relabel_blocking=args.relabel_blocking, bfs_xcd=args.bfs_xcd,
+                                 gr_interval=args.gr_interval,
+                                 tail_gr_interval=args.tail_gr_interval)
         h = hyperflow.flow_problem_create(V, *arrays, options=opts, stream=stream)
         try:
             F = hyperflow.maxflow_solve(h, stream)
