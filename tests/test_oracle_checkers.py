@@ -246,6 +246,84 @@ def test_residual_labels_vs_scipy(oracle_mod):
     assert _labels_agree(oracle_mod.residual_labels)
 
 
+def _uncapped_reach(st):
+    """Nodes that reach the sink set in the residual graph of the uncapped
+    network (the pin arcs u -> e_in without the cap w(e)), source vertices
+    removed: one bool per node of the explicit graph."""
+    hg, V, E = st.hg, st.hg.num_vertices, st.hg.num_nets
+    n = V + 2 * E
+    src = lambda x: x < V and st.role[x] == 1  # noqa: E731
+    into = [[] for _ in range(n)]
+    for tail, head, res, kind, _, sign in st.arcs():
+        if kind == "in" and sign == +1:
+            res = INF  # uncapped
+        if res > 0 and not src(tail) and not src(head):
+            into[head].append(tail)
+    seen = np.zeros(n, dtype=bool)
+    stack = [int(t) for t in np.nonzero(st.role == 2)[0]]
+    seen[stack] = True
+    while stack:
+        x = stack.pop()
+        for y in into[x]:
+            if not seen[y]:
+                seen[y] = True
+                stack.append(y)
+    return seen
+
+
+def test_sink_side_from_capped_labels():
+    """The reading behind the sink side derived from exact labels: the nodes
+    with a finite residual distance in the capped network (set D) all reach
+    the sinks in the uncapped network, and the uncapped network's sink side
+    is D plus what reaches a seed through its residual arcs, a seed being a
+    non-source vertex outside D with a saturated arc u -> e_in into an e_in
+    of D (the only arcs the two networks differ in).  Distances by scipy on
+    the explicit graph, the uncapped side by search on the explicit graph,
+    over random preflows."""
+    # a state where they differ: the source 0 sends one unit through net 0
+    # to vertex 1, which pushes it into net 1 (its arc into e_in saturated);
+    # net 1's e_in reaches the sink 2 over the bridge, vertex 1 only through
+    # that saturated arc
+    hand = _State(inputs.hypergraph_from_nets(3, [[0, 1], [1, 2]], [1, 1], [0], [2]))
+    hand.f_b[0] = 1
+    hand.f_out[1] = 1     # slot 1 = (net 0, vertex 1)
+    hand.f_in[2] = 1      # slot 2 = (net 1, vertex 1)
+    grew = 0
+    for k, st in enumerate([hand] + _states()):
+        hg, V, E = st.hg, st.hg.num_vertices, st.hg.num_nets
+        dv, din, dout = _scipy_distances(st)
+        D = np.concatenate([dv >= 0, din >= 0, dout >= 0])
+        T = _uncapped_reach(st)
+        assert not (D & ~T).any()
+        seeds = set()
+        for p in range(hg.num_pins):
+            e, u = int(st.net_of[p]), int(hg.pins[p])
+            if st.f_in[p] == st.w[e] and D[V + e] and not D[u] and st.role[u] != 1:
+                seeds.add(u)
+        # reverse search of the uncapped residual graph from the seeds
+        into = [[] for _ in range(V + 2 * E)]
+        src = lambda x: x < V and st.role[x] == 1  # noqa: E731
+        for tail, head, res, kind, _, sign in st.arcs():
+            if kind == "in" and sign == +1:
+                res = INF
+            if res > 0 and not src(tail) and not src(head):
+                into[head].append(tail)
+        got = D.copy()
+        stack = sorted(seeds)
+        got[stack] = True
+        while stack:
+            x = stack.pop()
+            for y in into[x]:
+                if not got[y]:
+                    got[y] = True
+                    stack.append(y)
+        assert (got == T).all()
+        if k == 0:  # vertex 1 and net 0's e_out (node 5), which reaches it
+            assert np.nonzero(T & ~D)[0].tolist() == [1, 5] and seeds == {1}
+        grew += int((T & ~D).sum() > 0)
+    assert grew >= 1
+
+
 CHECK_MUTANTS = {
     "contracted source arc ignored": ("+ np.where(has_s, w, 0) - f_b", "- f_b"),
     "cap off by one": ("(f_in > w[net_of]).any()", "(f_in > w[net_of] + 1).any()"),
