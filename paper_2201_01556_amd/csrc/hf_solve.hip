@@ -1279,6 +1279,7 @@ static fp_status flowcutter_run(fp_problem* pb, int32_t slice, hipStream_t s, in
       int p = pb->ctl_h->pierce[3 * side];  // a free boundary pin, else any free vertex
       if (p == kInf) p = pb->ctl_h->pierce[2];
       if (p == kInf) {
+        r.status = 0;  // finished: the best cut kept is the result, nothing to resume
         done = true;
       } else {
         step.side = side;
