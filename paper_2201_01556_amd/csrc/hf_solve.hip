@@ -392,6 +392,8 @@ static void launch_timed(fp_problem* pb, hipStream_t s, void (*kernel)(KArgs...)
   hipEvent_t a = on ? get_event(pb) : nullptr;
   hipEvent_t b = on ? get_event(pb) : nullptr;
   if (!a || !b) {
+    event_pool_put(pb->device, a);  // a null event is ignored
+    event_pool_put(pb->device, b);
     hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
     return;
   }
