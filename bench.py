@@ -708,12 +708,12 @@ def bench_learned(args, hyperflow, inputs, torch, np, config):
     n_train = max(1, (3 * K) // 4)
     workers = max(1, min(16, len(os.sched_getaffinity(0)) - 1))
     out = {}
-    for kind in ("c4", "planted"):
+    for kind in ("random_blocks", "planted"):
         _log(f"learned pruning, {kind} workload: {K} seeds, built on {workers} processes")
         res = dict(workload=(
             "block pairs of a random k=64 partition refined by 3 label-propagation sweeps "
             "(2M vertices, 10M pins, Zipf(2.2) sizes clamped to [2,2000], 500 heaviest pairs)"
-            if kind == "c4" else
+            if kind == "random_blocks" else
             "block pairs of a planted 64-block hypergraph (2M vertices, 10M pins, Zipf(2.2) "
             "sizes clamped to [2,2000], 98% of the nets inside one block), the planted "
             "partition with 2% of the vertices swapped across 150 random block pairs, 3 "
@@ -808,7 +808,7 @@ def bench_learned(args, hyperflow, inputs, torch, np, config):
                         init = inputs.scorer_init_params(0)
                         sc = hyperflow.Scorer(init)
                         sc.fit_normalization(Xtr)
-                        if kind == "c4" and not args.no_cpu_baseline:
+                        if kind == "random_blocks" and not args.no_cpu_baseline:
                             # the oracle's inputs never come from the device path:
                             # the check uses the training features with seeded
                             # coin-flip labels
@@ -975,7 +975,7 @@ def bench_refine(args, hyperflow, inputs, torch, np):
     perturbed pairs), timed from the partition on the device to the refined
     partition."""
     out = {}
-    for kind, gen in (("c4", inputs.block_pair_problems),
+    for kind, gen in (("random_blocks", inputs.block_pair_problems),
                       ("planted", inputs.planted_block_pair_problems)):
         _log(f"refinement rounds, {kind} workload")
         bp = gen(args.seed, max_problems=1, threads=0)
