@@ -54,6 +54,9 @@ def main():
                     help="skip the side-by-side of the two relabel variants")
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--batch-problems", type=int, default=500)
+    ap.add_argument("--batch-schedule", type=int, default=0,
+                    help="0: tune the batch plan; 1 union or 3 workgroups with 4 lanes and a "
+                         "relabel every 8 rounds, untuned (no host worker threads start)")
     ap.add_argument("--no-cutter", action="store_true",
                     help="skip the incremental FlowCutter workload")
     ap.add_argument("--cutter-iterations", type=int, default=100000)
@@ -888,12 +891,18 @@ def bench_batch(args, hyperflow, inputs, torch, np):
                problems=n, pins=pins, generate_s=round(gen_s, 2), unit="refinements/s")
     try:
         plain = hyperflow.FlowBatch(probs, with_cut=True, schedule=2, streams=1)
-        batched = hyperflow.FlowBatch(probs, with_cut=True)
-        _log("tuning the batch plan")
-        t0 = time.perf_counter()
-        cfg = batched.tune()
-        out["tune_s"] = round(time.perf_counter() - t0, 2)
-        out["config"] = cfg
+        if args.batch_schedule:
+            batched = hyperflow.FlowBatch(probs, with_cut=True, schedule=args.batch_schedule,
+                                          group_lanes=4, gr_interval=8)
+            out["tune_s"] = None
+            out["config"] = batched.config()
+        else:
+            batched = hyperflow.FlowBatch(probs, with_cut=True)
+            _log("tuning the batch plan")
+            t0 = time.perf_counter()
+            cfg = batched.tune()
+            out["tune_s"] = round(time.perf_counter() - t0, 2)
+            out["config"] = cfg
 
         def timed(plan, steps):
             ts = []
